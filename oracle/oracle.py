@@ -1,0 +1,235 @@
+"""ctypes front end of the plain C FP64 oracle (``tsvd_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: see the package docstring.  Every function takes and
+returns numpy float64 arrays in column-major (Fortran) order, so that a tensor
+of shape (n1, n2, n3) has X(i,j,k) at flat index i + n1*j + n1*n2*k, the layout
+the paper's MATLAB notation implies.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tsvd_oracle.c")
+_OUT_DIR = os.path.join(_HERE, "_build")
+_LIB = os.path.join(_OUT_DIR, "libtsvd_oracle.so")
+_lib = None
+
+_dp = C.POINTER(C.c_double)
+_i64 = C.c_int64
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no vendor math, no BLAS)."""
+    os.makedirs(_OUT_DIR, exist_ok=True)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build(force=False)
+    lib = C.CDLL(_LIB)
+    lib.or_dct_matrix.argtypes = [C.c_int, _dp]
+    for name in ("or_dct_tubes", "or_idct_tubes", "or_split_shift", "or_bt", "or_bh", "or_btph",
+                 "or_unfold", "or_fold"):
+        getattr(lib, name).argtypes = [_i64, _i64, _i64, _dp, _dp]
+    lib.or_btph_product.argtypes = [_i64, _i64, _i64, _i64, _dp, _dp, _dp]
+    lib.or_tprod_dct.argtypes = [_i64, _i64, _i64, _i64, _dp, _dp, _dp]
+    lib.or_jacobi_svd.argtypes = [_i64, _i64, _dp, _i64, _dp, _dp, _dp, C.c_int]
+    lib.or_jacobi_svd.restype = C.c_int
+    lib.or_tsvd_dct.argtypes = [_i64, _i64, _i64, _dp, _dp, _dp, _dp, C.c_int]
+    lib.or_tsvd_dct.restype = C.c_int
+    lib.or_tsvt_dct.argtypes = [_i64, _i64, _i64, _dp, C.c_double, _dp, C.POINTER(C.c_int32), C.c_int]
+    lib.or_tsvt_dct.restype = C.c_int
+    lib.or_tnn_c.argtypes = [_i64, _i64, _i64, _dp, C.c_int]
+    lib.or_tnn_c.restype = C.c_double
+    lib.or_complete.argtypes = [_i64, _i64, _i64, _dp, C.POINTER(C.c_uint8), C.c_int, _dp, _dp, C.c_double,
+                                C.c_int, _dp, _dp, _dp]
+    lib.or_complete.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.asfortranarray(np.asarray(a, dtype=np.float64))
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _as3(a) -> np.ndarray:
+    a = _f64(a)
+    if a.ndim == 2:
+        a = a.reshape(a.shape[0], a.shape[1], 1, order="F")
+    assert a.ndim == 3
+    return a
+
+
+MAX_SWEEPS = 100
+
+
+def dct_matrix(n: int) -> np.ndarray:
+    """Orthonormal DCT-II matrix, C[k, t] (row = frequency)."""
+    out = np.empty(n * n)
+    _load().or_dct_matrix(n, _p(out))
+    return out.reshape(n, n)  # stored row-major C[k*n+t]
+
+
+def _tube_op(name, X):
+    X = _as3(X)
+    out = np.empty_like(X, order="F")
+    getattr(_load(), name)(*X.shape, _p(X), _p(out))
+    return out
+
+
+def dct_tubes(X):
+    """Xbar = dct(X,[],3): orthonormal DCT-II along every mode-3 tube."""
+    return _tube_op("or_dct_tubes", X)
+
+
+def idct_tubes(Xbar):
+    """Inverse of dct_tubes."""
+    return _tube_op("or_idct_tubes", Xbar)
+
+
+def split_shift(X):
+    """A with X = A + sigma(A) (Section 3)."""
+    return _tube_op("or_split_shift", X)
+
+
+def _block_matrix(name, A):
+    A = _as3(A)
+    n1, n2, n3 = A.shape
+    out = np.empty((n1 * n3, n2 * n3), order="F")
+    getattr(_load(), name)(n1, n2, n3, _p(A), _p(out))
+    return out
+
+
+def bt(A):
+    """Block Toeplitz matrix of the slices of A (Section 3)."""
+    return _block_matrix("or_bt", A)
+
+
+def bh(A):
+    """Block Hankel matrix of the slices of A (Section 3)."""
+    return _block_matrix("or_bh", A)
+
+
+def btph(A):
+    """Block Toeplitz-plus-Hankel matrix bt(A) + bh(A) (Section 3)."""
+    return _block_matrix("or_btph", A)
+
+
+def unfold(X):
+    X = _as3(X)
+    n1, n2, n3 = X.shape
+    out = np.empty((n1 * n3, n2), order="F")
+    _load().or_unfold(n1, n2, n3, _p(X), _p(out))
+    return out
+
+
+def fold(U, n1, n2, n3):
+    U = _f64(U)
+    out = np.empty((n1, n2, n3), order="F")
+    _load().or_fold(n1, n2, n3, _p(U), _p(out))
+    return out
+
+
+def btph_product(X, Y):
+    """Z = fold(btph(A) unfold(Y)), the definition-level DCT t-product."""
+    X, Y = _as3(X), _as3(Y)
+    n1, n2, n3 = X.shape
+    assert Y.shape[0] == n2 and Y.shape[2] == n3
+    n4 = Y.shape[1]
+    out = np.empty((n1, n4, n3), order="F")
+    _load().or_btph_product(n1, n2, n4, n3, _p(X), _p(Y), _p(out))
+    return out
+
+
+def tprod_dct(X, Y):
+    """Z = idct(slice-wise Xbar^(k) Ybar^(k)), the transform-domain t-product."""
+    X, Y = _as3(X), _as3(Y)
+    n1, n2, n3 = X.shape
+    assert Y.shape[0] == n2 and Y.shape[2] == n3
+    n4 = Y.shape[1]
+    out = np.empty((n1, n4, n3), order="F")
+    _load().or_tprod_dct(n1, n2, n4, n3, _p(X), _p(Y), _p(out))
+    return out
+
+
+def jacobi_svd(A, max_sweeps: int = MAX_SWEEPS):
+    """Thin SVD of one matrix by one-sided Jacobi.  Returns (U, s, V, sweeps)."""
+    A = _f64(A)
+    m, n = A.shape
+    p = min(m, n)
+    U = np.empty((m, p), order="F")
+    V = np.empty((n, p), order="F")
+    s = np.empty(p)
+    sw = _load().or_jacobi_svd(m, n, _p(A), m, _p(U), _p(s), _p(V), max_sweeps)
+    return U, s, V, sw
+
+
+def tsvd_dct(X, max_sweeps: int = MAX_SWEEPS):
+    """DCT t-SVD, transform-domain thin factors (Ubar, Sbar, Vbar, sweeps).
+
+    Ubar: n1 x p x n3, Sbar: p x n3 (descending per column), Vbar: n2 x p x n3.
+    """
+    X = _as3(X)
+    n1, n2, n3 = X.shape
+    p = min(n1, n2)
+    U = np.empty((n1, p, n3), order="F")
+    V = np.empty((n2, p, n3), order="F")
+    S = np.empty((p, n3), order="F")
+    sw = _load().or_tsvd_dct(n1, n2, n3, _p(X), _p(U), _p(S), _p(V), max_sweeps)
+    return U, S, V, sw
+
+
+def tsvt_dct(Z, tau: float, max_sweeps: int = MAX_SWEEPS, return_ranks: bool = False):
+    """t-SVT (Theorem 5) with threshold tau on the orthonormal-DCT slices."""
+    Z = _as3(Z)
+    n1, n2, n3 = Z.shape
+    Y = np.empty_like(Z, order="F")
+    ranks = np.empty(n3, dtype=np.int32)
+    sw = _load().or_tsvt_dct(n1, n2, n3, _p(Z), float(tau), _p(Y), ranks.ctypes.data_as(C.POINTER(C.c_int32)),
+                             max_sweeps)
+    if return_ranks:
+        return Y, ranks, sw
+    return Y
+
+
+def tnn_c(X, max_sweeps: int = MAX_SWEEPS) -> float:
+    """TNN-C: (1/n3) * sum of nuclear norms of the DCT-domain slices."""
+    X = _as3(X)
+    return float(_load().or_tnn_c(*X.shape, _p(X), max_sweeps))
+
+
+def complete(B, mask, betas, taus=None, tol: float = 0.0, X0=None, M0=None, max_sweeps: int = MAX_SWEEPS):
+    """Algorithm 1 (ADMM for TNN-C completion) with a per-iteration penalty.
+
+    betas: length-L array of beta_l; taus: thresholds (default 1/beta_l, as in
+    Algorithm 1).  X0 defaults to B on the observed set, M0 to zero.
+    Returns (X, M, iters, relchange).
+    """
+    B = _as3(B)
+    n1, n2, n3 = B.shape
+    mask = np.asfortranarray(np.asarray(mask, dtype=np.uint8).reshape(B.shape, order="F"))
+    betas = np.ascontiguousarray(betas, dtype=np.float64)
+    L = betas.shape[0]
+    taus = 1.0 / betas if taus is None else np.ascontiguousarray(taus, dtype=np.float64)
+    X = _f64(np.where(mask != 0, B, 0.0)) if X0 is None else _as3(X0).copy(order="F")
+    M = np.zeros_like(B, order="F") if M0 is None else _as3(M0).copy(order="F")
+    rc = C.c_double(0.0)
+    it = _load().or_complete(n1, n2, n3, _p(B), mask.ctypes.data_as(C.POINTER(C.c_uint8)), L, _p(betas), _p(taus),
+                             float(tol), max_sweeps, _p(X), _p(M), C.byref(rc))
+    return X, M, it, rc.value

@@ -1,0 +1,418 @@
+/*
+ * Plain FP64 CPU oracle for cosine-transform t-SVD, t-SVT and TNN-C tensor
+ * completion (Xu, Zhao, Ng, "A Fast Algorithm for Cosine Transform Based
+ * Tensor Singular Value Decomposition", arXiv 1902.03070).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it.  It shares
+ * no code, header, table or helper with the GPU library, and the GPU library
+ * never calls it.
+ *
+ * Conventions (all functions):
+ *   - A real tensor X of size n1 x n2 x n3 is stored column-major with frontal
+ *     slices contiguous: X(i,j,k) lives at X[i + n1*j + n1*n2*k], 0-based.
+ *   - Matrices are column-major: M(r,c) at M[r + ld*c].
+ *   - C is the orthonormal DCT-II matrix of size n, stored row-major
+ *     C[k*n + t] (row k = frequency, column t = tube position).
+ *   - Everything is double precision; there is no blocking, no fusion and no
+ *     reordering beyond the textbook definitions cited at each function.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define X3(i, j, k, n1, n2) ((int64_t)(i) + (int64_t)(n1) * ((int64_t)(j) + (int64_t)(n2) * (int64_t)(k)))
+
+/* ------------------------------------------------------------------------- */
+/* Section 3: the cosine transform along tubes.                              */
+/* The paper writes dct(X,[],3), MATLAB's orthonormal DCT-II, and never       */
+/* prints the matrix; this is the standard orthonormal DCT-II matrix:         */
+/*   C[k][t] = s_k cos(pi (2t+1) k / (2n)),  s_0 = sqrt(1/n), s_k = sqrt(2/n). */
+/* ------------------------------------------------------------------------- */
+void or_dct_matrix(int n, double* C) {
+    const double pi = acos(-1.0);
+    for (int k = 0; k < n; ++k) {
+        double s = (k == 0) ? sqrt(1.0 / n) : sqrt(2.0 / n);
+        for (int t = 0; t < n; ++t) C[(int64_t)k * n + t] = s * cos(pi * (2.0 * t + 1.0) * k / (2.0 * n));
+    }
+}
+
+/* Xbar(:,:,k) = sum_t C[k][t] X(:,:,t)   (Section 3, Xbar = dct(X,[],3)). */
+void or_dct_tubes(int64_t n1, int64_t n2, int64_t n3, const double* X, double* Xbar) {
+    double* C = (double*)malloc(sizeof(double) * n3 * n3);
+    or_dct_matrix((int)n3, C);
+    for (int64_t j = 0; j < n2; ++j)
+        for (int64_t i = 0; i < n1; ++i)
+            for (int64_t k = 0; k < n3; ++k) {
+                double acc = 0.0;
+                for (int64_t t = 0; t < n3; ++t) acc += C[k * n3 + t] * X[X3(i, j, t, n1, n2)];
+                Xbar[X3(i, j, k, n1, n2)] = acc;
+            }
+    free(C);
+}
+
+/* Inverse: X(:,:,t) = sum_k C[k][t] Xbar(:,:,k)  (C orthonormal, so C^{-1} = C^T). */
+void or_idct_tubes(int64_t n1, int64_t n2, int64_t n3, const double* Xbar, double* X) {
+    double* C = (double*)malloc(sizeof(double) * n3 * n3);
+    or_dct_matrix((int)n3, C);
+    for (int64_t j = 0; j < n2; ++j)
+        for (int64_t i = 0; i < n1; ++i)
+            for (int64_t t = 0; t < n3; ++t) {
+                double acc = 0.0;
+                for (int64_t k = 0; k < n3; ++k) acc += C[k * n3 + t] * Xbar[X3(i, j, k, n1, n2)];
+                X[X3(i, j, t, n1, n2)] = acc;
+            }
+    free(C);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Section 3: the split X = A + sigma(A), where sigma shifts the frontal      */
+/* slices up by one and appends a zero slice.  Solving slice by slice from   */
+/* the last one: A^(n3) = X^(n3), A^(k) = X^(k) - A^(k+1).                    */
+/* ------------------------------------------------------------------------- */
+void or_split_shift(int64_t n1, int64_t n2, int64_t n3, const double* X, double* A) {
+    int64_t s = n1 * n2;
+    for (int64_t k = n3 - 1; k >= 0; --k)
+        for (int64_t e = 0; e < s; ++e) A[k * s + e] = (k == n3 - 1) ? X[k * s + e] : X[k * s + e] - A[(k + 1) * s + e];
+}
+
+/* Section 3, block Toeplitz bt(A): block (r,c) = A^(|r-c|+1) (1-based slices).
+ * Output is (n1*n3) x (n2*n3), column-major, leading dimension n1*n3. */
+void or_bt(int64_t n1, int64_t n2, int64_t n3, const double* A, double* M) {
+    int64_t ld = n1 * n3, s = n1 * n2;
+    for (int64_t bc = 0; bc < n3; ++bc)
+        for (int64_t br = 0; br < n3; ++br) {
+            int64_t k = br > bc ? br - bc : bc - br; /* 0-based slice index */
+            for (int64_t j = 0; j < n2; ++j)
+                for (int64_t i = 0; i < n1; ++i) M[(br * n1 + i) + ld * (bc * n2 + j)] = A[k * s + i + n1 * j];
+        }
+}
+
+/* Section 3, block Hankel bh(A): first block row A^(2),...,A^(n3),O and
+ * last block row O,A^(n3),...,A^(2).  With q = r+c+2 for the 0-based block
+ * (r,c), the block is A^(q) (1-based) when q <= n3, O when q = n3+1, and the
+ * reflected slice A^(2 n3 + 2 - q) beyond. */
+void or_bh(int64_t n1, int64_t n2, int64_t n3, const double* A, double* M) {
+    int64_t ld = n1 * n3, s = n1 * n2;
+    for (int64_t bc = 0; bc < n3; ++bc)
+        for (int64_t br = 0; br < n3; ++br) {
+            int64_t q = br + bc + 2;        /* 1-based index along the anti-diagonal */
+            int64_t k1;                      /* 1-based slice index, 0 = zero block */
+            if (q <= n3) k1 = q;
+            else if (q == n3 + 1) k1 = 0;
+            else k1 = 2 * n3 + 2 - q;
+            for (int64_t j = 0; j < n2; ++j)
+                for (int64_t i = 0; i < n1; ++i)
+                    M[(br * n1 + i) + ld * (bc * n2 + j)] = (k1 == 0) ? 0.0 : A[(k1 - 1) * s + i + n1 * j];
+        }
+}
+
+/* Section 3: btph(A) = bt(A) + bh(A). */
+void or_btph(int64_t n1, int64_t n2, int64_t n3, const double* A, double* M) {
+    int64_t ld = n1 * n3, cols = n2 * n3;
+    double* H = (double*)malloc(sizeof(double) * ld * cols);
+    or_bt(n1, n2, n3, A, M);
+    or_bh(n1, n2, n3, A, H);
+    for (int64_t e = 0; e < ld * cols; ++e) M[e] += H[e];
+    free(H);
+}
+
+/* Section 2, unfold: stack the frontal slices vertically into an
+ * (n1*n3) x n2 column-major matrix; fold is its inverse. */
+void or_unfold(int64_t n1, int64_t n2, int64_t n3, const double* X, double* U) {
+    int64_t ld = n1 * n3;
+    for (int64_t k = 0; k < n3; ++k)
+        for (int64_t j = 0; j < n2; ++j)
+            for (int64_t i = 0; i < n1; ++i) U[(k * n1 + i) + ld * j] = X[X3(i, j, k, n1, n2)];
+}
+void or_fold(int64_t n1, int64_t n2, int64_t n3, const double* U, double* X) {
+    int64_t ld = n1 * n3;
+    for (int64_t k = 0; k < n3; ++k)
+        for (int64_t j = 0; j < n2; ++j)
+            for (int64_t i = 0; i < n1; ++i) X[X3(i, j, k, n1, n2)] = U[(k * n1 + i) + ld * j];
+}
+
+/* Plain column-major matrix product C(m x n) = A(m x k) B(k x n). */
+static void matmul(int64_t m, int64_t n, int64_t kk, const double* A, int64_t lda, const double* B, int64_t ldb,
+                   double* C, int64_t ldc) {
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t r = 0; r < m; ++r) {
+            double acc = 0.0;
+            for (int64_t t = 0; t < kk; ++t) acc += A[r + lda * t] * B[t + ldb * c];
+            C[r + ldc * c] = acc;
+        }
+}
+
+/* Definition (DCT-based t-product), the form built from the definition:
+ * Z = fold(btph(A) unfold(Y)) with X = A + sigma(A).
+ * X: n1 x n2 x n3, Y: n2 x n4 x n3, Z: n1 x n4 x n3. */
+void or_btph_product(int64_t n1, int64_t n2, int64_t n4, int64_t n3, const double* X, const double* Y, double* Z) {
+    double* A = (double*)malloc(sizeof(double) * n1 * n2 * n3);
+    double* M = (double*)malloc(sizeof(double) * n1 * n3 * n2 * n3);
+    double* UY = (double*)malloc(sizeof(double) * n2 * n3 * n4);
+    double* UZ = (double*)malloc(sizeof(double) * n1 * n3 * n4);
+    or_split_shift(n1, n2, n3, X, A);
+    or_btph(n1, n2, n3, A, M);
+    or_unfold(n2, n4, n3, Y, UY);
+    matmul(n1 * n3, n4, n2 * n3, M, n1 * n3, UY, n2 * n3, UZ, n1 * n3);
+    or_fold(n1, n4, n3, UZ, Z);
+    free(A); free(M); free(UY); free(UZ);
+}
+
+/* Equation (tproduct dct), the transform-domain form used by Theorem 4,
+ * TNN-C and Algorithm 1: Zbar^(k) = Xbar^(k) Ybar^(k), then Z = idct(Zbar). */
+void or_tprod_dct(int64_t n1, int64_t n2, int64_t n4, int64_t n3, const double* X, const double* Y, double* Z) {
+    double* Xb = (double*)malloc(sizeof(double) * n1 * n2 * n3);
+    double* Yb = (double*)malloc(sizeof(double) * n2 * n4 * n3);
+    double* Zb = (double*)malloc(sizeof(double) * n1 * n4 * n3);
+    or_dct_tubes(n1, n2, n3, X, Xb);
+    or_dct_tubes(n2, n4, n3, Y, Yb);
+    for (int64_t k = 0; k < n3; ++k)
+        matmul(n1, n4, n2, Xb + k * n1 * n2, n1, Yb + k * n2 * n4, n2, Zb + k * n1 * n4, n1);
+    or_idct_tubes(n1, n4, n3, Zb, Z);
+    free(Xb); free(Yb); free(Zb);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Thin SVD of one real matrix by the one-sided Jacobi method of Hestenes    */
+/* (1958), as presented by Demmel and Veselic (1992) and Golub and Van Loan. */
+/* The paper takes the SVD of each transformed frontal slice (Theorem 4 and  */
+/* Algorithm 1) with a library routine and fixes no method; this is the     */
+/* textbook cyclic-by-row one-sided Jacobi:                                  */
+/*   for each pair i<j of columns of W: alpha=|w_i|^2, beta=|w_j|^2,          */
+/*   gamma=w_i.w_j; if |gamma| > tol*sqrt(alpha*beta) rotate so that the two  */
+/*   columns become orthogonal; stop after a sweep with no rotation.          */
+/* A is m x n with leading dimension lda.  p = min(m,n).  Outputs:            */
+/*   U: m x p, s: p (descending), V: n x p, all column-major; any may be NULL.*/
+/* Signs: each (u_j, v_j) is flipped so that the entry of u_j of largest     */
+/* magnitude (first one on ties) is positive.  A zero singular value gets a  */
+/* u_j completed by Gram-Schmidt against e_1, e_2, ...                        */
+/* Returns the number of sweeps, or -1 if max_sweeps was reached.             */
+/* ------------------------------------------------------------------------- */
+static int jacobi_tall(int64_t m, int64_t n, double* W, double* V, int max_sweeps, double tol) {
+    /* W: m x n (m >= n), rotated in place; V: n x n, starts as the identity. */
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t r = 0; r < n; ++r) V[r + n * c] = (r == c) ? 1.0 : 0.0;
+    for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
+        int64_t rotations = 0;
+        for (int64_t i = 0; i < n - 1; ++i)
+            for (int64_t j = i + 1; j < n; ++j) {
+                double* wi = W + m * i;
+                double* wj = W + m * j;
+                double alpha = 0.0, beta = 0.0, gamma = 0.0;
+                for (int64_t r = 0; r < m; ++r) {
+                    alpha += wi[r] * wi[r];
+                    beta += wj[r] * wj[r];
+                    gamma += wi[r] * wj[r];
+                }
+                if (gamma == 0.0 || fabs(gamma) <= tol * sqrt(alpha * beta)) continue;
+                double zeta = (beta - alpha) / (2.0 * gamma);
+                double sgn = (zeta >= 0.0) ? 1.0 : -1.0;
+                double t = sgn / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                double c = 1.0 / sqrt(1.0 + t * t);
+                double s = c * t;
+                for (int64_t r = 0; r < m; ++r) {
+                    double a = wi[r], b = wj[r];
+                    wi[r] = c * a - s * b;
+                    wj[r] = s * a + c * b;
+                }
+                double* vi = V + n * i;
+                double* vj = V + n * j;
+                for (int64_t r = 0; r < n; ++r) {
+                    double a = vi[r], b = vj[r];
+                    vi[r] = c * a - s * b;
+                    vj[r] = s * a + c * b;
+                }
+                ++rotations;
+            }
+        if (rotations == 0) return sweep;
+    }
+    return -1;
+}
+
+int or_jacobi_svd(int64_t m, int64_t n, const double* A, int64_t lda, double* U, double* s, double* V, int max_sweeps) {
+    int trans = m < n;
+    int64_t mm = trans ? n : m; /* rows of the tall working matrix */
+    int64_t p = trans ? m : n;  /* its columns = min(m,n) */
+    double* W = (double*)malloc(sizeof(double) * mm * p);
+    double* Q = (double*)malloc(sizeof(double) * p * p);
+    for (int64_t c = 0; c < p; ++c)
+        for (int64_t r = 0; r < mm; ++r) W[r + mm * c] = trans ? A[c + lda * r] : A[r + lda * c];
+    double tol = (double)mm * ldexp(1.0, -53);
+    int sweeps = jacobi_tall(mm, p, W, Q, max_sweeps, tol);
+
+    /* singular values = column norms; order descending (stable in index) */
+    double* sv = (double*)malloc(sizeof(double) * p);
+    int64_t* ord = (int64_t*)malloc(sizeof(int64_t) * p);
+    for (int64_t c = 0; c < p; ++c) {
+        double acc = 0.0;
+        for (int64_t r = 0; r < mm; ++r) acc += W[r + mm * c] * W[r + mm * c];
+        sv[c] = sqrt(acc);
+        ord[c] = c;
+    }
+    for (int64_t a = 1; a < p; ++a) { /* insertion sort */
+        int64_t key = ord[a], b = a - 1;
+        while (b >= 0 && sv[ord[b]] < sv[key]) { ord[b + 1] = ord[b]; --b; }
+        ord[b + 1] = key;
+    }
+    /* left vectors of the tall problem (mm x p) and its right vectors (p x p) */
+    double* Lt = (double*)malloc(sizeof(double) * mm * p);
+    double* Rt = (double*)malloc(sizeof(double) * p * p);
+    for (int64_t c = 0; c < p; ++c) {
+        int64_t o = ord[c];
+        for (int64_t r = 0; r < mm; ++r) Lt[r + mm * c] = (sv[o] > 0.0) ? W[r + mm * o] / sv[o] : 0.0;
+        for (int64_t r = 0; r < p; ++r) Rt[r + p * c] = Q[r + p * o];
+    }
+    /* zero singular values: complete the left vector by Gram-Schmidt (twice) */
+    for (int64_t c = 0; c < p; ++c) {
+        if (sv[ord[c]] > 0.0) continue;
+        for (int64_t e = 0; e < mm; ++e) {
+            double* u = Lt + mm * c;
+            for (int64_t r = 0; r < mm; ++r) u[r] = (r == e) ? 1.0 : 0.0;
+            for (int pass = 0; pass < 2; ++pass)
+                for (int64_t q = 0; q < p; ++q) {
+                    if (q == c || (sv[ord[q]] == 0.0 && q > c)) continue;
+                    double* w = Lt + mm * q;
+                    double d = 0.0;
+                    for (int64_t r = 0; r < mm; ++r) d += w[r] * u[r];
+                    for (int64_t r = 0; r < mm; ++r) u[r] -= d * w[r];
+                }
+            double nn = 0.0;
+            for (int64_t r = 0; r < mm; ++r) nn += u[r] * u[r];
+            nn = sqrt(nn);
+            if (nn > 0.5) { for (int64_t r = 0; r < mm; ++r) u[r] /= nn; break; }
+        }
+    }
+    /* Undo the transpose: A = Lt S Rt^T (tall) or A^T = Lt S Rt^T (wide). */
+    double* Uo = trans ? Rt : Lt; int64_t ldu = trans ? p : mm;
+    double* Vo = trans ? Lt : Rt; int64_t ldv = trans ? mm : p;
+    /* sign convention on the left vectors */
+    for (int64_t c = 0; c < p; ++c) {
+        int64_t best = 0;
+        for (int64_t r = 1; r < m; ++r)
+            if (fabs(Uo[r + ldu * c]) > fabs(Uo[best + ldu * c])) best = r;
+        if (Uo[best + ldu * c] < 0.0) {
+            for (int64_t r = 0; r < m; ++r) Uo[r + ldu * c] = -Uo[r + ldu * c];
+            for (int64_t r = 0; r < n; ++r) Vo[r + ldv * c] = -Vo[r + ldv * c];
+        }
+    }
+    if (U) for (int64_t c = 0; c < p; ++c) for (int64_t r = 0; r < m; ++r) U[r + m * c] = Uo[r + ldu * c];
+    if (V) for (int64_t c = 0; c < p; ++c) for (int64_t r = 0; r < n; ++r) V[r + n * c] = Vo[r + ldv * c];
+    if (s) for (int64_t c = 0; c < p; ++c) s[c] = sv[ord[c]];
+    free(W); free(Q); free(sv); free(ord); free(Lt); free(Rt);
+    return sweeps;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Theorem 4 (DCT-based t-SVD), computed as the paper prescribes: DCT along  */
+/* the tubes, then the SVD of every frontal slice of Xbar.  Thin factors,    */
+/* p = min(n1,n2), in the transform domain:                                  */
+/*   Ubar n1 x p x n3, Sbar p x n3 (column k = singular values of slice k),  */
+/*   Vbar n2 x p x n3.  Returns the largest sweep count, or -1.              */
+/* ------------------------------------------------------------------------- */
+int or_tsvd_dct(int64_t n1, int64_t n2, int64_t n3, const double* X, double* Ubar, double* Sbar, double* Vbar,
+                int max_sweeps) {
+    int64_t p = n1 < n2 ? n1 : n2;
+    double* Xb = (double*)malloc(sizeof(double) * n1 * n2 * n3);
+    or_dct_tubes(n1, n2, n3, X, Xb);
+    int worst = 0;
+    for (int64_t k = 0; k < n3; ++k) {
+        int sw = or_jacobi_svd(n1, n2, Xb + k * n1 * n2, n1, Ubar ? Ubar + k * n1 * p : NULL, Sbar + k * p,
+                               Vbar ? Vbar + k * n2 * p : NULL, max_sweeps);
+        if (sw < 0) worst = -1;
+        else if (worst >= 0 && sw > worst) worst = sw;
+    }
+    free(Xb);
+    return worst;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Theorem 5 (tensor singular value thresholding) with Algorithm 1's loop    */
+/* body: Zbar = dct(Z); per slice SVD; Dbar = (Sbar - tau)_+; rebuild         */
+/* Ubar Dbar Vbar^T; Y = idct.  ranks[k] = #{sigma > tau} (may be NULL).      */
+/* Returns the largest sweep count, or -1.                                    */
+/* ------------------------------------------------------------------------- */
+int or_tsvt_dct(int64_t n1, int64_t n2, int64_t n3, const double* Z, double tau, double* Y, int32_t* ranks,
+                int max_sweeps) {
+    int64_t p = n1 < n2 ? n1 : n2, s = n1 * n2;
+    double* Zb = (double*)malloc(sizeof(double) * s * n3);
+    double* Yb = (double*)malloc(sizeof(double) * s * n3);
+    double* U = (double*)malloc(sizeof(double) * n1 * p);
+    double* V = (double*)malloc(sizeof(double) * n2 * p);
+    double* sv = (double*)malloc(sizeof(double) * p);
+    or_dct_tubes(n1, n2, n3, Z, Zb);
+    int worst = 0;
+    for (int64_t k = 0; k < n3; ++k) {
+        int sw = or_jacobi_svd(n1, n2, Zb + k * s, n1, U, sv, V, max_sweeps);
+        if (sw < 0) worst = -1;
+        else if (worst >= 0 && sw > worst) worst = sw;
+        int32_t r = 0;
+        for (int64_t c = 0; c < p; ++c) if (sv[c] > tau) ++r;
+        if (ranks) ranks[k] = r;
+        double* Ybk = Yb + k * s;
+        for (int64_t j = 0; j < n2; ++j)
+            for (int64_t i = 0; i < n1; ++i) {
+                double acc = 0.0;
+                for (int64_t c = 0; c < p; ++c) {
+                    double d = sv[c] - tau;
+                    if (d > 0.0) acc += U[i + n1 * c] * d * V[j + n2 * c];
+                }
+                Ybk[i + n1 * j] = acc;
+            }
+    }
+    or_idct_tubes(n1, n2, n3, Yb, Y);
+    free(Zb); free(Yb); free(U); free(V); free(sv);
+    return worst;
+}
+
+/* Section 4, TNN-C: (1/n3) sum_k ||Xbar^(k)||_*  (nuclear norm of each slice). */
+double or_tnn_c(int64_t n1, int64_t n2, int64_t n3, const double* X, int max_sweeps) {
+    int64_t p = n1 < n2 ? n1 : n2;
+    double* Sb = (double*)malloc(sizeof(double) * p * n3);
+    or_tsvd_dct(n1, n2, n3, X, NULL, Sb, NULL, max_sweeps);
+    double acc = 0.0;
+    for (int64_t e = 0; e < p * n3; ++e) acc += Sb[e];
+    free(Sb);
+    return acc / (double)n3;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Algorithm 1 (ADMM for TNN-C completion), with the penalty given per       */
+/* iteration: iteration l uses beta[l] in Z = X - M/beta, in the X-update    */
+/* and in the multiplier update, and thresholds at tau[l] (Algorithm 1 uses  */
+/* tau = 1/beta).  mask[e] != 0 marks the observed set Omega.                */
+/* X, M: in = initial iterates (X normally B on Omega), out = final.          */
+/* Stops after iteration l when ||X_new - X_old||_F / ||X_old||_F <= tol      */
+/* (tol <= 0: run all L iterations).  Returns the number of iterations run;   */
+/* *relchg gets the last relative change.                                     */
+/* ------------------------------------------------------------------------- */
+int or_complete(int64_t n1, int64_t n2, int64_t n3, const double* B, const uint8_t* mask, int L,
+                const double* beta, const double* tau, double tol, int max_sweeps, double* X, double* M,
+                double* relchg) {
+    int64_t N = n1 * n2 * n3;
+    double* Z = (double*)malloc(sizeof(double) * N);
+    double* Y = (double*)malloc(sizeof(double) * N);
+    int it = 0;
+    double rc = 0.0;
+    for (int l = 0; l < L; ++l) {
+        double b = beta[l];
+        for (int64_t e = 0; e < N; ++e) Z[e] = X[e] - M[e] / b;                 /* line: Z = X - M/beta */
+        or_tsvt_dct(n1, n2, n3, Z, tau[l], Y, NULL, max_sweeps);                /* Y-subproblem, Theorem 5 */
+        double dn = 0.0, xn = 0.0;
+        for (int64_t e = 0; e < N; ++e) {
+            double xnew = mask[e] ? B[e] : Y[e] + M[e] / b;                     /* X-update closed form */
+            M[e] = M[e] + b * (Y[e] - xnew);                                    /* multiplier update */
+            dn += (xnew - X[e]) * (xnew - X[e]);
+            xn += X[e] * X[e];
+            X[e] = xnew;
+        }
+        ++it;
+        rc = (xn > 0.0) ? sqrt(dn / xn) : sqrt(dn);
+        if (tol > 0.0 && rc <= tol) break;
+    }
+    if (relchg) *relchg = rc;
+    free(Z); free(Y);
+    return it;
+}
