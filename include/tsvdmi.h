@@ -1,0 +1,214 @@
+/*
+ * tsvdmi: cosine-transform t-SVD, t-SVT and TNN-C tensor completion on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Xu, Zhao and Ng, "A Fast Algorithm for Cosine
+ * Transform Based Tensor Singular Value Decomposition" (arXiv 1902.03070):
+ *   - Section 3: the transform along tubes, Xbar = dct(X,[],3), read as the
+ *     orthonormal DCT-II C[k][t] = s_k cos(pi (2t+1) k / (2 n3)).
+ *   - Equation (tproduct dct): the DCT t-product, Zbar^(k) = Xbar^(k) Ybar^(k).
+ *   - Theorem 4: the DCT t-SVD, computed as the SVD of every frontal slice of
+ *     Xbar.
+ *   - Theorem 5 with Algorithm 1: tensor singular value thresholding.
+ *   - Algorithm 1: ADMM for the TNN-C completion model.
+ *
+ * Conventions for every entry point
+ *   - Tensors are real n1 x n2 x n3, column-major with contiguous frontal
+ *     slices: element (i,j,k) is at index i + n1*j + n1*n2*k (0-based).
+ *   - Tensor pointers are DEVICE pointers to caller-owned memory on the
+ *     context's device.  The element type is double for TSVD_FP64 and float
+ *     for TSVD_FP32 and TSVD_MIXED.  The library never frees caller memory.
+ *     Inputs and outputs must not overlap unless stated.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *     enqueued on it and the call returns without waiting, except where a
+ *     call says it synchronizes.
+ *   - A context owns its device workspace, the DCT matrices, captured graphs
+ *     and tuning results.  One context per host thread, or external locking.
+ *   - Return value: TSVD_OK, a positive warning (outputs written), or a
+ *     negative error (outputs undefined).  Errors found on the device
+ *     (non-finite input, Jacobi not converged, a wait that timed out) are
+ *     recorded in the context and returned by tsvd_sync_status, or directly
+ *     by a call that synchronizes.  No C++ exception crosses this interface.
+ */
+#ifndef TSVDMI_H
+#define TSVDMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tsvd_ctx tsvd_ctx;
+
+/* Precision of a call.
+ *   TSVD_FP64  : double data; every step in FP64.
+ *   TSVD_FP32  : float data; transforms on FP32 matrix cores; Jacobi sweeps in
+ *                FP32 with the rotation angle and the orthogonality test in
+ *                FP64.
+ *   TSVD_MIXED : float data; transforms on BF16 matrix cores with a hi+lo
+ *                split (three products, FP32 accumulation); Jacobi sweeps in
+ *                FP32 with FP64 angles and test, then one final sweep whose
+ *                dot products and rotations are computed in FP64. */
+enum { TSVD_FP64 = 0, TSVD_FP32 = 1, TSVD_MIXED = 2 };
+
+enum {
+    TSVD_OK = 0,
+    TSVD_WARN_NOCONV = 1,  /* a Jacobi SVD hit the sweep limit; outputs written */
+    TSVD_EINVAL = -1,      /* bad argument: size <= 0, tau < 0, beta <= 0, NULL, unknown precision */
+    TSVD_ENOMEM = -2,      /* device allocation failed */
+    TSVD_EHIP = -3,        /* a HIP runtime call failed (see tsvd_last_error) */
+    TSVD_ENONFINITE = -4,  /* the input holds a NaN or an infinity */
+    TSVD_EBUSY = -5,       /* admission refused: request exceeds the memory budget */
+    TSVD_ETIMEOUT = -6     /* a bounded device wait or a host deadline expired */
+};
+
+/* Context.  `device` is a HIP device ordinal.  Returns TSVD_OK and sets *ctx. */
+int tsvd_create(tsvd_ctx** ctx, int device);
+void tsvd_destroy(tsvd_ctx* ctx);
+/* Message of the last failure on this context (never NULL). */
+const char* tsvd_last_error(const tsvd_ctx* ctx);
+
+/* Options (set before use; values are doubles for a uniform interface). */
+enum {
+    TSVD_OPT_MAX_SWEEPS = 0,   /* Jacobi sweep limit, 1..64 (default 30) */
+    TSVD_OPT_SYNC_STATUS = 1,  /* 1: each call synchronizes and returns device status (default);
+                                  0: calls are asynchronous, status via tsvd_sync_status */
+    TSVD_OPT_TEAM_SIZE = 2,    /* 0: automatic; >0: workgroups per frontal slice in the Jacobi
+                                  kernel for slices too large for one workgroup's LDS */
+    TSVD_OPT_SPIN_LIMIT = 3,   /* polls before a device wait gives up (test hook; default 2^24) */
+    TSVD_OPT_PROFILE = 4       /* 1: record HIP events around every kernel phase on the launch
+                                  stream (read with tsvd_get_stats); 0: off (default) */
+};
+int tsvd_set_option(tsvd_ctx* ctx, int option, double value);
+double tsvd_get_option(const tsvd_ctx* ctx, int option);
+
+/* Wait for `stream`, then return and clear the device status accumulated by
+ * asynchronous calls on this context (TSVD_OK, TSVD_WARN_NOCONV,
+ * TSVD_ENONFINITE or TSVD_ETIMEOUT).  *max_sweeps_out (may be NULL) gets the
+ * largest Jacobi sweep count seen. */
+int tsvd_sync_status(tsvd_ctx* ctx, void* stream, int* max_sweeps_out);
+
+/* Counters since the last reset.  Phases: 0 forward transform (with the
+ * completion prologue), 1 Jacobi SVD, 2 thresholding and rebuild, 3 inverse
+ * transform (with the completion epilogue).  ms/launches are filled only
+ * while TSVD_OPT_PROFILE is 1 (event pairs on the launch stream).
+ * slice_sweeps counts Jacobi sweeps summed over all slices processed, always.
+ * Synchronizes `stream`. */
+typedef struct {
+    int64_t slice_sweeps;
+    double ms[4];
+    int64_t launches[4];
+} tsvd_stats;
+int tsvd_get_stats(tsvd_ctx* ctx, void* stream, tsvd_stats* out, int reset);
+
+/* DCT t-product, equation (tproduct dct):  Z = X * Y, i.e.
+ * Zbar^(k) = Xbar^(k) Ybar^(k) for every k, with Xbar = dct(X,[],3).
+ * X: n1 x n2 x n3, Y: n2 x n4 x n3, Z: n1 x n4 x n3 (Z must not alias X, Y). */
+int tprod_dct(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n4, int64_t n3, const void* X,
+              const void* Y, void* Z, void* stream);
+
+/* DCT t-SVD, Theorem 4, thin form with p = min(n1,n2):
+ *   U: n1 x p x n3, S: p x n3 (column k holds the singular values of the
+ *   transformed slice k, descending), V: n2 x p x n3.
+ * Default: spatial-domain factors, so that X = U * S * V^T with the library's
+ * tprod_dct (S expanded to the f-diagonal p x p x n3 tensor whose tubes are
+ * idct of the rows of S).  Flag TSVD_TRANSFORM_DOMAIN returns Ubar, sigma,
+ * Vbar instead, with S always in the transform domain.  Sign convention: in
+ * each transformed slice, the largest-magnitude entry of every left singular
+ * vector is positive.  U or V may be NULL when not wanted. */
+enum { TSVD_TRANSFORM_DOMAIN = 1 };
+int tsvd_dct(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const void* X, void* U, void* S,
+             void* V, int flags, void* stream);
+
+/* Tensor singular value thresholding, Theorem 5 and Algorithm 1's loop body:
+ * Y = idct_k( Ubar^(k) (Sbar^(k) - tau)_+ Vbar^(k)^T ) where
+ * Zbar^(k) = Ubar^(k) Sbar^(k) Vbar^(k)^T.  Threshold `tau` (>= 0) is applied
+ * to the singular values of the orthonormal-DCT slices.
+ * ranks_out: NULL or a HOST array of n3 int32 that receives #{sigma > tau}
+ * per slice; when given, the call synchronizes.  Y may alias Z. */
+int tsvt_dct(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const void* Z, void* Y, double tau,
+             int32_t* ranks_out, void* stream);
+
+/* Algorithm 1 (ADMM for TNN-C completion).
+ *   B    : observed data (only entries with mask != 0 are read).
+ *   mask : DEVICE uint8 array, N = n1*n2*n3 entries, nonzero = observed.
+ *   X    : in = initial iterate (normally B on the observed set, 0 elsewhere),
+ *          out = the recovered tensor.
+ * Iteration l of the call uses beta_l = opts->beta, or
+ * 1/opts->tau_schedule[start_iter + l] when a schedule is given, in Z = X - M/beta_l, in
+ * the X-update and in the multiplier update, and thresholds at
+ * tau_l = 1/beta_l.  It stops after max_iter iterations, or earlier when the
+ * relative change ||X_new - X||_F / ||X||_F <= tol (tested every check_every
+ * iterations; tol <= 0 disables the test).  M_init (DEVICE, may be NULL for
+ * zero) and M_out (DEVICE, may be NULL) carry the multiplier for warm starts.
+ * The whole iteration runs on the device and is replayed as a captured HIP
+ * graph; the call synchronizes. */
+typedef struct {
+    int max_iter;               /* L (> 0) */
+    double tol;                 /* stopping tolerance on the relative change */
+    double beta;                /* fixed penalty when tau_schedule is NULL (> 0) */
+    const double* tau_schedule; /* HOST array of thresholds (> 0), or NULL; this call's
+                                   iteration i uses tau_schedule[start_iter + i] */
+    int check_every;            /* iterations between host checks of tol (>= 1) */
+    int start_iter;             /* schedule offset for warm starts; 0 normally */
+    const void* M_init;
+    void* M_out;
+} tsvd_complete_opts;
+typedef struct {
+    int iters;         /* iterations run */
+    double rel_change; /* last relative change */
+    int status;        /* TSVD_OK or TSVD_WARN_NOCONV */
+    int max_sweeps;    /* largest Jacobi sweep count seen */
+} tsvd_complete_info;
+int complete_tensor(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const void* B,
+                    const uint8_t* mask, void* X, const tsvd_complete_opts* opts, tsvd_complete_info* info,
+                    void* stream);
+
+/* Batched t-SVT of `count` tensors of independent shapes in one pass of
+ * launches (one launch per step, all tensors together; the Jacobi step is one
+ * persistent launch that drains a device work list).  dims: HOST array of
+ * 3*count sizes (n1,n2,n3 per tensor); Z, Y: HOST arrays of DEVICE pointers;
+ * tau: HOST array of thresholds.  Each tensor's result is the same as a
+ * tsvt_dct call on it alone (same tiles, same reduction order). */
+int tsvt_dct_batched(tsvd_ctx* ctx, int prec, int count, const int64_t* dims, const void* const* Z,
+                     void* const* Y, const double* tau, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a host thread that admits t-SVT and completion requests by device
+ * memory footprint, keeps every admitted request's iterates on the device, and
+ * advances all admitted requests together, one batched step per tick
+ * (continuous batching: a request that arrives while others run joins at the
+ * next tick; a finished one leaves and frees its memory).
+ * ------------------------------------------------------------------------- */
+typedef struct tsvd_server tsvd_server;
+enum { TSVD_REQ_TSVT = 0, TSVD_REQ_COMPLETE = 1 };
+typedef struct {
+    int kind;              /* TSVD_REQ_TSVT or TSVD_REQ_COMPLETE */
+    int64_t n1, n2, n3;
+    const float* input;    /* HOST: Z (t-SVT) or B (completion), n1*n2*n3 floats, copied at submit */
+    const uint8_t* mask;   /* HOST: completion observed set, copied at submit; NULL for t-SVT */
+    double tau;            /* t-SVT threshold */
+    int iters;             /* completion: iterations, tau decays geometrically tau0 -> tau1 */
+    double tau0, tau1;
+} tsvd_request;
+/* budget_bytes: device memory the server may hold for admitted requests;
+ * max_active: most requests advanced per tick. */
+int tsvd_server_create(tsvd_server** srv, tsvd_ctx* ctx, int prec, int64_t budget_bytes, int max_active);
+/* Copies the request; returns a request id > 0, or TSVD_EBUSY when it can never
+ * fit the budget, or another negative error. */
+int64_t tsvd_server_submit(tsvd_server* srv, const tsvd_request* req);
+/* Non-blocking poll. Returns 1 and fills `out` (HOST, n1*n2*n3 floats) and the
+ * times (seconds on the server's steady clock) when request `id` is done, 0 if
+ * not yet, negative on error or unknown id. */
+int tsvd_server_poll(tsvd_server* srv, int64_t id, float* out, double* t_submit, double* t_admit, double* t_done);
+/* Server clock now (seconds). */
+double tsvd_server_now(tsvd_server* srv);
+/* Statistics: admitted, completed, ticks, peak bytes held. */
+int tsvd_server_stats(tsvd_server* srv, int64_t* admitted, int64_t* completed, int64_t* ticks, int64_t* peak_bytes);
+void tsvd_server_destroy(tsvd_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSVDMI_H */

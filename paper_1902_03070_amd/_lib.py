@@ -1,0 +1,293 @@
+"""ctypes binding of libtsvdmi (include/tsvdmi.h).  Argument marshalling only.
+
+Tensors are torch tensors on a ROCm device with logical shape (n1, n2, n3) in
+column-major layout (strides (1, n1, n1*n2)), the layout of the C interface.
+``fortran(x)`` makes such a view; outputs are allocated in that layout.
+Every computation runs in the HIP library; if it is not built, importing this
+module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtsvdmi.so")
+
+FP64, FP32, MIXED = 0, 1, 2
+OK, WARN_NOCONV, EINVAL, ENOMEM, EHIP, ENONFINITE, EBUSY, ETIMEOUT = 0, 1, -1, -2, -3, -4, -5, -6
+OPT_MAX_SWEEPS, OPT_SYNC_STATUS, OPT_TEAM_SIZE, OPT_SPIN_LIMIT, OPT_PROFILE = 0, 1, 2, 3, 4
+PHASES = ("forward_transform", "jacobi", "threshold_rebuild", "inverse_transform")
+TRANSFORM_DOMAIN = 1
+REQ_TSVT, REQ_COMPLETE = 0, 1
+
+EXPORTED = [
+    "tsvd_create", "tsvd_destroy", "tsvd_last_error", "tsvd_set_option", "tsvd_get_option", "tsvd_sync_status",
+    "tsvd_get_stats",
+    "tprod_dct", "tsvd_dct", "tsvt_dct", "complete_tensor", "tsvt_dct_batched", "tsvd_server_create",
+    "tsvd_server_submit", "tsvd_server_poll", "tsvd_server_now", "tsvd_server_stats", "tsvd_server_destroy",
+]
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libtsvdmi.so is not built (run __graft_entry__.build() or python -m paper_1902_03070_amd.build)")
+
+lib = C.CDLL(LIB_PATH)
+
+_vp, _i64, _i32, _d = C.c_void_p, C.c_int64, C.c_int, C.c_double
+
+
+class CompleteOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("tol", C.c_double), ("beta", C.c_double),
+                ("tau_schedule", C.POINTER(C.c_double)), ("check_every", C.c_int), ("start_iter", C.c_int),
+                ("M_init", C.c_void_p), ("M_out", C.c_void_p)]
+
+
+class CompleteInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("rel_change", C.c_double), ("status", C.c_int), ("max_sweeps", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("slice_sweeps", C.c_int64), ("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
+
+
+class Request(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n1", C.c_int64), ("n2", C.c_int64), ("n3", C.c_int64),
+                ("input", C.POINTER(C.c_float)), ("mask", C.POINTER(C.c_uint8)), ("tau", C.c_double),
+                ("iters", C.c_int), ("tau0", C.c_double), ("tau1", C.c_double)]
+
+
+lib.tsvd_create.argtypes = [C.POINTER(_vp), _i32]
+lib.tsvd_destroy.argtypes = [_vp]
+lib.tsvd_destroy.restype = None
+lib.tsvd_last_error.argtypes = [_vp]
+lib.tsvd_last_error.restype = C.c_char_p
+lib.tsvd_set_option.argtypes = [_vp, _i32, _d]
+lib.tsvd_get_option.argtypes = [_vp, _i32]
+lib.tsvd_get_option.restype = _d
+lib.tsvd_sync_status.argtypes = [_vp, _vp, C.POINTER(C.c_int)]
+lib.tsvd_get_stats.argtypes = [_vp, _vp, C.POINTER(Stats), _i32]
+lib.tprod_dct.argtypes = [_vp, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp]
+lib.tsvd_dct.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _i32, _vp]
+lib.tsvt_dct.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _d, C.POINTER(C.c_int32), _vp]
+lib.complete_tensor.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _vp, C.POINTER(CompleteOpts),
+                                C.POINTER(CompleteInfo), _vp]
+lib.tsvt_dct_batched.argtypes = [_vp, _i32, _i32, C.POINTER(C.c_int64), C.POINTER(_vp), C.POINTER(_vp),
+                                 C.POINTER(C.c_double), _vp]
+lib.tsvd_server_create.argtypes = [C.POINTER(_vp), _vp, _i32, _i64, _i32]
+lib.tsvd_server_submit.argtypes = [_vp, C.POINTER(Request)]
+lib.tsvd_server_submit.restype = _i64
+lib.tsvd_server_poll.argtypes = [_vp, _i64, C.POINTER(C.c_float), C.POINTER(_d), C.POINTER(_d), C.POINTER(_d)]
+lib.tsvd_server_now.argtypes = [_vp]
+lib.tsvd_server_now.restype = _d
+lib.tsvd_server_stats.argtypes = [_vp] + [C.POINTER(C.c_int64)] * 4
+lib.tsvd_server_destroy.argtypes = [_vp]
+lib.tsvd_server_destroy.restype = None
+
+
+class TsvdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("tsvdmi error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Context:
+    """Owns a tsvd_ctx (device workspace, transform matrices, options)."""
+
+    def __init__(self, device: int = 0):
+        h = _vp()
+        rc = lib.tsvd_create(C.byref(h), device)
+        if rc != OK:
+            raise TsvdError(rc, "tsvd_create(%d) failed" % device)
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib.tsvd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc: int, allow_warn: bool = True) -> int:
+        if rc < 0 or (rc > 0 and not allow_warn):
+            raise TsvdError(rc, lib.tsvd_last_error(self.h).decode())
+        return rc
+
+    def set_option(self, opt: int, value: float):
+        self.check(lib.tsvd_set_option(self.h, opt, float(value)))
+
+    def get_option(self, opt: int) -> float:
+        return lib.tsvd_get_option(self.h, opt)
+
+    def stats(self, reset: bool = True, stream=None) -> dict:
+        st = Stats()
+        self.check(lib.tsvd_get_stats(self.h, _stream(stream, self.device), C.byref(st), int(reset)))
+        return {"slice_sweeps": st.slice_sweeps,
+                "ms": {PHASES[i]: st.ms[i] for i in range(4)},
+                "launches": {PHASES[i]: st.launches[i] for i in range(4)}}
+
+    def sync_status(self, stream=None):
+        ms = C.c_int(0)
+        rc = lib.tsvd_sync_status(self.h, _stream(stream, self.device), C.byref(ms))
+        return rc, ms.value
+
+
+_contexts = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _contexts:
+        _contexts[device] = Context(device)
+    return _contexts[device]
+
+
+def _stream(stream, device):
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return _vp(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def fortran(x: torch.Tensor) -> torch.Tensor:
+    """Column-major view (strides 1, n1, n1*n2) of a 3-D tensor, copying if needed."""
+    if x.dim() == 2:
+        x = x.unsqueeze(2)
+    if x.dim() != 3:
+        raise ValueError("expected a 3-D tensor")
+    n1, n2, n3 = x.shape
+    if x.stride() == (1, n1, n1 * n2) or x.numel() == 0:
+        return x
+    return x.permute(2, 1, 0).contiguous().permute(2, 1, 0)
+
+
+def empty_f(n1: int, n2: int, n3: int, dtype, device) -> torch.Tensor:
+    return torch.empty((n3, n2, n1), dtype=dtype, device=device).permute(2, 1, 0)
+
+
+def _prec_of(t: torch.Tensor, prec: Optional[int]) -> int:
+    if prec is None:
+        prec = FP64 if t.dtype == torch.float64 else FP32
+    want = torch.float64 if prec == FP64 else torch.float32
+    if t.dtype != want:
+        raise TypeError("precision %d needs %s data, got %s" % (prec, want, t.dtype))
+    return prec
+
+
+def _dev(t: torch.Tensor) -> int:
+    if not t.is_cuda:
+        raise ValueError("tensors must be on a ROCm device")
+    return t.device.index or 0
+
+
+def tsvt_dct(Z: torch.Tensor, tau: float, Y: Optional[torch.Tensor] = None, prec: Optional[int] = None,
+             return_ranks: bool = False, ctx: Optional[Context] = None, stream=None):
+    """t-SVT with threshold tau (Theorem 5).  Returns Y (and per-slice ranks)."""
+    Z = fortran(Z)
+    d = _dev(Z)
+    prec = _prec_of(Z, prec)
+    ctx = ctx or default_context(d)
+    n1, n2, n3 = Z.shape
+    if Y is None:
+        Y = empty_f(n1, n2, n3, Z.dtype, Z.device)
+    ranks = (C.c_int32 * n3)() if return_ranks else None
+    rc = lib.tsvt_dct(ctx.h, prec, n1, n2, n3, Z.data_ptr(), Y.data_ptr(), float(tau), ranks,
+                      _stream(stream, d))
+    ctx.check(rc)
+    if return_ranks:
+        return Y, [int(r) for r in ranks]
+    return Y
+
+
+def tprod_dct(X: torch.Tensor, Yt: torch.Tensor, prec: Optional[int] = None, ctx: Optional[Context] = None,
+              stream=None) -> torch.Tensor:
+    """DCT t-product Z = X * Y (equation (tproduct dct))."""
+    X, Yt = fortran(X), fortran(Yt)
+    d = _dev(X)
+    prec = _prec_of(X, prec)
+    ctx = ctx or default_context(d)
+    n1, n2, n3 = X.shape
+    if Yt.shape[0] != n2 or Yt.shape[2] != n3:
+        raise ValueError("shape mismatch")
+    n4 = Yt.shape[1]
+    Z = empty_f(n1, n4, n3, X.dtype, X.device)
+    ctx.check(lib.tprod_dct(ctx.h, prec, n1, n2, n4, n3, X.data_ptr(), Yt.data_ptr(), Z.data_ptr(),
+                            _stream(stream, d)))
+    return Z
+
+
+def tsvd_dct(X: torch.Tensor, prec: Optional[int] = None, transform_domain: bool = False,
+             ctx: Optional[Context] = None, stream=None):
+    """DCT t-SVD (Theorem 4), thin.  Returns U (n1,p,n3), S (p,n3), V (n2,p,n3)."""
+    X = fortran(X)
+    d = _dev(X)
+    prec = _prec_of(X, prec)
+    ctx = ctx or default_context(d)
+    n1, n2, n3 = X.shape
+    p = min(n1, n2)
+    U = empty_f(n1, p, n3, X.dtype, X.device)
+    V = empty_f(n2, p, n3, X.dtype, X.device)
+    S = torch.empty((n3, p), dtype=X.dtype, device=X.device).t()
+    ctx.check(lib.tsvd_dct(ctx.h, prec, n1, n2, n3, X.data_ptr(), U.data_ptr(), S.data_ptr(), V.data_ptr(),
+                           TRANSFORM_DOMAIN if transform_domain else 0, _stream(stream, d)))
+    return U, S, V
+
+
+def complete_tensor(B: torch.Tensor, mask: torch.Tensor, X: Optional[torch.Tensor] = None, max_iter: int = 500,
+                    tol: float = 1e-8, beta: float = 1e-2, tau_schedule: Optional[Sequence[float]] = None,
+                    check_every: int = 10, start_iter: int = 0, M_init: Optional[torch.Tensor] = None,
+                    return_M: bool = False, prec: Optional[int] = None, ctx: Optional[Context] = None,
+                    stream=None):
+    """Algorithm 1 (ADMM for TNN-C completion).  Returns (X, info[, M])."""
+    B = fortran(B)
+    d = _dev(B)
+    prec = _prec_of(B, prec)
+    ctx = ctx or default_context(d)
+    n1, n2, n3 = B.shape
+    mask = fortran(mask.to(torch.uint8))
+    if X is None:
+        X = fortran(torch.where(mask != 0, B, torch.zeros_like(B)))
+    else:
+        X = fortran(X.clone())
+    M_out = empty_f(n1, n2, n3, B.dtype, B.device) if return_M else None
+    sched = None
+    if tau_schedule is not None:
+        sched = (C.c_double * len(tau_schedule))(*[float(t) for t in tau_schedule])
+        if start_iter + max_iter > len(tau_schedule):
+            raise ValueError("tau_schedule shorter than start_iter + max_iter")
+    opts = CompleteOpts(max_iter, float(tol), float(beta),
+                        C.cast(sched, C.POINTER(C.c_double)) if sched is not None else None, check_every,
+                        start_iter, fortran(M_init).data_ptr() if M_init is not None else None,
+                        M_out.data_ptr() if M_out is not None else None)
+    info = CompleteInfo()
+    rc = lib.complete_tensor(ctx.h, prec, n1, n2, n3, B.data_ptr(), mask.data_ptr(), X.data_ptr(),
+                             C.byref(opts), C.byref(info), _stream(stream, d))
+    ctx.check(rc)
+    out = {"iters": info.iters, "rel_change": info.rel_change, "status": info.status,
+           "max_sweeps": info.max_sweeps}
+    if return_M:
+        return X, out, M_out
+    return X, out
+
+
+def tsvt_dct_batched(Zs: Sequence[torch.Tensor], taus: Sequence[float], Ys: Optional[Sequence[torch.Tensor]] = None,
+                     prec: Optional[int] = None, ctx: Optional[Context] = None, stream=None):
+    """Batched t-SVT of tensors of independent shapes.  Returns the list of Y."""
+    Zs = [fortran(z) for z in Zs]
+    d = _dev(Zs[0])
+    prec = _prec_of(Zs[0], prec)
+    ctx = ctx or default_context(d)
+    count = len(Zs)
+    if Ys is None:
+        Ys = [empty_f(*z.shape, z.dtype, z.device) for z in Zs]
+    dims = (C.c_int64 * (3 * count))(*[int(v) for z in Zs for v in z.shape])
+    zp = (_vp * count)(*[z.data_ptr() for z in Zs])
+    yp = (_vp * count)(*[y.data_ptr() for y in Ys])
+    tp = (C.c_double * count)(*[float(t) for t in taus])
+    ctx.check(lib.tsvt_dct_batched(ctx.h, prec, count, dims, zp, yp, tp, _stream(stream, d)))
+    return list(Ys)

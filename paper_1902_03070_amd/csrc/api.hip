@@ -1,0 +1,782 @@
+// C-ABI of libtsvdmi: context, device workspace, execution plans and the
+// entry points declared in include/tsvdmi.h.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/tsvdmi.h"
+#include "internal.h"
+
+using namespace tsvd;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct tsvd_ctx {
+    int device = 0;
+    int cus = 0;
+    int max_sweeps = 30;
+    int sync_status = 1;
+    int team_size = 0;
+    int spin_limit = 1 << 24;
+    std::string err = "";
+    // transform matrices: (n3, prec) -> {C, C^T} rows, element type by prec
+    std::map<std::pair<int, int>, std::pair<void*, void*>> dct;
+    DevBuf ws;                 // main workspace
+    DevBuf ctrl;               // Ctrl + norms + history (persistent)
+    Ctrl* h_ctrl = nullptr;    // pinned host mirror
+    std::vector<void*> owned;  // other allocations freed at destroy
+    std::mutex mu;
+    // phase profiling (TSVD_OPT_PROFILE): event pairs recorded on the launch stream
+    int prof = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> marks;
+};
+
+namespace {
+
+int fail(tsvd_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(tsvd_ctx* c, hipError_t e, const char* where) {
+    (void)hipGetLastError();  // clear the runtime's sticky copy of a non-fatal error
+    return fail(c, TSVD_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, expr)                                         \
+    do {                                                          \
+        hipError_t e__ = (expr);                                  \
+        if (e__ != hipSuccess) return hip_fail((ctx), e__, #expr); \
+    } while (0)
+
+inline int esize(int prec) { return prec == TSVD_FP64 ? 8 : 4; }
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Orthonormal DCT-II matrix (Section 3, dct(.,[],3)) in FP64 on the host,
+// uploaded in the element type: C row-major [k][t] and its transpose.
+int get_dct(tsvd_ctx* c, int n3, int prec, const void** C, const void** Ct) {
+    auto key = std::make_pair(n3, prec == TSVD_FP64 ? 0 : 1);
+    auto it = c->dct.find(key);
+    if (it == c->dct.end()) {
+        std::vector<double> m((size_t)n3 * n3), mt((size_t)n3 * n3);
+        const double pi = acos(-1.0);
+        for (int k = 0; k < n3; ++k) {
+            const double s = k == 0 ? sqrt(1.0 / n3) : sqrt(2.0 / n3);
+            for (int t = 0; t < n3; ++t) {
+                const double v = s * cos(pi * (2.0 * t + 1.0) * k / (2.0 * n3));
+                m[(size_t)k * n3 + t] = v;
+                mt[(size_t)t * n3 + k] = v;
+            }
+        }
+        const size_t bytes = (size_t)n3 * n3 * esize(prec);
+        void *d0 = nullptr, *d1 = nullptr;
+        HIPCHK(c, hipMalloc(&d0, bytes));
+        HIPCHK(c, hipMalloc(&d1, bytes));
+        if (prec == TSVD_FP64) {
+            HIPCHK(c, hipMemcpy(d0, m.data(), bytes, hipMemcpyHostToDevice));
+            HIPCHK(c, hipMemcpy(d1, mt.data(), bytes, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> f(m.begin(), m.end()), ft(mt.begin(), mt.end());
+            HIPCHK(c, hipMemcpy(d0, f.data(), bytes, hipMemcpyHostToDevice));
+            HIPCHK(c, hipMemcpy(d1, ft.data(), bytes, hipMemcpyHostToDevice));
+        }
+        it = c->dct.emplace(key, std::make_pair(d0, d1)).first;
+    }
+    *C = it->second.first;
+    *Ct = it->second.second;
+    return TSVD_OK;
+}
+
+// Grow-only workspace.  Growing frees the old buffer (hipFree waits for the device).
+int ensure_ws(tsvd_ctx* c, size_t bytes) {
+    if (c->ws.bytes >= bytes) return TSVD_OK;
+    if (c->ws.p) {
+        HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipFree(c->ws.p));
+        c->ws.p = nullptr;
+        c->ws.bytes = 0;
+    }
+    size_t want = std::max(bytes, (size_t)64 << 20);
+    hipError_t e = hipMalloc(&c->ws.p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        e = hipMalloc(&c->ws.p, bytes);
+        want = bytes;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->ws.p = nullptr;
+        return fail(c, TSVD_ENOMEM, "workspace allocation failed");
+    }
+    c->ws.bytes = want;
+    return TSVD_OK;
+}
+
+// Bump allocator over the workspace.
+struct Carve {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    }
+};
+
+constexpr int kHist = 4096;  // relative-change history slots in the control region
+
+struct CtrlRegion {
+    Ctrl* ctrl;
+    double* norms;  // [2]
+    double* hist;   // [kHist]
+};
+
+int ensure_ctrl(tsvd_ctx* c, CtrlRegion* r) {
+    const size_t bytes = 256 + 256 + sizeof(double) * kHist;
+    if (!c->ctrl.p) {
+        HIPCHK(c, hipMalloc(&c->ctrl.p, bytes));
+        HIPCHK(c, hipMemset(c->ctrl.p, 0, bytes));
+        c->ctrl.bytes = bytes;
+        HIPCHK(c, hipHostMalloc((void**)&c->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
+    }
+    char* b = (char*)c->ctrl.p;
+    r->ctrl = (Ctrl*)b;
+    r->norms = (double*)(b + 256);
+    r->hist = (double*)(b + 512);
+    return TSVD_OK;
+}
+
+// Read and clear the accumulated device status (synchronizes `s`).
+int read_status(tsvd_ctx* c, hipStream_t s, int* max_sweeps) {
+    CtrlRegion cr;
+    int rc = ensure_ctrl(c, &cr);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(s));
+    Ctrl h;
+    HIPCHK(c, hipMemcpy(&h, cr.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    Ctrl z = h;
+    z.status = 0;
+    z.max_sweeps = 0;
+    HIPCHK(c, hipMemcpy(cr.ctrl, &z, sizeof(Ctrl), hipMemcpyHostToDevice));
+    if (max_sweeps) *max_sweeps = h.max_sweeps;
+    if (h.status & kStNonFinite) return fail(c, TSVD_ENONFINITE, "input holds a non-finite value");
+    if (h.status & kStTimeout) return fail(c, TSVD_ETIMEOUT, "a device-side wait timed out");
+    if (h.status & kStNoConv) return TSVD_WARN_NOCONV;
+    return TSVD_OK;
+}
+
+// Records an event pair around the launches of one phase when profiling.
+struct PhaseMark {
+    tsvd_ctx* c;
+    int ph;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    static hipEvent_t take(tsvd_ctx* c) {
+        if (c->ev_used == c->ev_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            c->ev_pool.push_back(e);
+        }
+        return c->ev_pool[c->ev_used++];
+    }
+    PhaseMark(tsvd_ctx* c_, int ph_, hipStream_t s_) : c(c_), ph(ph_), s(s_) {
+        if (c->prof && (a = take(c))) (void)hipEventRecord(a, s);
+    }
+    ~PhaseMark() {
+        if (!c->prof || !a) return;
+        hipEvent_t b = take(c);
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        c->marks.emplace_back(ph, a, b);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Plan of one t-SVT / t-SVD of an n1 x n2 x n3 tensor.
+// ---------------------------------------------------------------------------
+struct Plan {
+    int prec = 0;
+    int64_t n1 = 0, n2 = 0, n3 = 0, N = 0;
+    int m = 0, p = 0, trans = 0, with_v = 0;
+    int team = 0;        // 0: resident kernel; 1: team kernel
+    int threads = 256;
+    int lds = 0;
+    TeamSched ts{};
+    JacobiJob job{};
+    // workspace offsets
+    size_t o_zbar, o_A, o_F, o_G, o_w, o_sig, o_ybar, o_V, o_rot, o_sw, o_bar, o_rank, o_job, o_tj, o_tk, o_end;
+    size_t o_ctr_begin, o_ctr_end;  // region zeroed per call (counters)
+};
+
+int choose_team(tsvd_ctx* c, Plan& P) {
+    const int epl = (P.m + kWave - 1) / kWave;
+    int W = c->team_size > 0 ? c->team_size : (P.p + 31) / 32;
+    if (W < 1) W = 1;
+    int b = (P.p + 2 * W - 1) / (2 * W);
+    b += b & 1;
+    if (b < 2) b = 2;
+    // shrink b until one block pair fits in LDS
+    while (b > 2 && jacobi_team_lds_bytes(P.prec, P.m, P.p, b, P.with_v) > kLdsBudget) b -= 2;
+    int nb = (P.p + b - 1) / b;
+    nb += nb & 1;
+    if (W > nb / 2) W = nb / 2;
+    P.lds = jacobi_team_lds_bytes(P.prec, P.m, P.p, b, P.with_v);
+    P.threads = kWave * std::min(16, std::max(4, b));
+    int cap = jacobi_team_max_resident(P.prec, P.lds, P.threads, P.with_v);
+    if (cap < 1) return fail(c, TSVD_EINVAL, "Jacobi team kernel cannot be resident with this shape");
+    if (W > cap) W = cap;
+    int nteams = std::max(1, std::min((int)P.n3, cap / W));
+    P.ts.W = W;
+    P.ts.nteams = nteams;
+    P.job.b = b;
+    P.job.nb = nb;
+    P.job.epl = epl;
+    return TSVD_OK;
+}
+
+int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int with_v, Plan& P, Carve& cv) {
+    P.prec = prec;
+    P.n1 = n1; P.n2 = n2; P.n3 = n3; P.N = n1 * n2;
+    P.trans = n1 < n2;
+    P.m = (int)std::max(n1, n2);
+    P.p = (int)std::min(n1, n2);
+    P.with_v = with_v;
+    if (P.m > kMaxRows) return fail(c, TSVD_EINVAL, "frontal slices larger than 512 rows/columns are not supported");
+    const size_t es = esize(prec);
+    const size_t slice = (size_t)n1 * n2;
+    const int rl = jacobi_resident_lds_bytes(prec, P.m, P.p, with_v);
+    if (rl <= kLdsBudget) {
+        P.team = 0;
+        P.lds = rl;
+        const int pairs = (P.p + 1) / 2;
+        int nw = std::min(16, std::max(4, pairs));
+        P.threads = kWave * nw;
+        P.job.epl = (P.m + kWave - 1) / kWave;
+        P.job.b = 0;
+        P.job.nb = 0;
+        P.ts = TeamSched{1, 0, nullptr};
+    } else {
+        P.team = 1;
+        int rc = choose_team(c, P);
+        if (rc) return rc;
+    }
+    P.o_zbar = cv.take(slice * n3 * es);
+    P.o_A = cv.take((size_t)P.m * P.p * n3 * es);
+    P.o_F = cv.take((size_t)P.m * P.p * n3 * es);
+    P.o_G = cv.take((size_t)P.p * P.p * n3 * es);
+    P.o_w = cv.take((size_t)P.p * n3 * 8);
+    P.o_sig = cv.take((size_t)P.p * n3 * 8);
+    P.o_ybar = cv.take(slice * n3 * es);
+    P.o_V = with_v ? cv.take((size_t)P.p * P.p * n3 * es) : 0;
+    P.o_job = cv.take(sizeof(JacobiJob));
+    P.o_tj = cv.take((size_t)n3 * 4);
+    P.o_tk = cv.take((size_t)n3 * 4);
+    P.o_ctr_begin = cv.off;
+    P.o_rot = cv.take((size_t)n3 * kMaxSweeps * 4);
+    P.o_sw = cv.take((size_t)n3 * 4);
+    P.o_bar = cv.take((size_t)std::max(1, P.ts.nteams) * 4);
+    P.o_rank = cv.take((size_t)n3 * 4);
+    P.o_ctr_end = cv.off;
+    P.o_end = cv.off;
+    return TSVD_OK;
+}
+
+// Fill the device-side job descriptor and task list (synchronous upload).
+int upload_plan(tsvd_ctx* c, Plan& P, char* base) {
+    JacobiJob& J = P.job;
+    J.src = base + P.o_zbar;
+    J.A = base + P.o_A;
+    J.V = P.with_v ? (void*)(base + P.o_V) : nullptr;
+    J.rot = (int*)(base + P.o_rot);
+    J.sweeps = (int*)(base + P.o_sw);
+    J.src_ss = P.N;
+    if (!P.trans) { J.src_rs = 1; J.src_cs = P.n1; }
+    else { J.src_rs = P.n1; J.src_cs = 1; }
+    J.m = P.m;
+    J.p = P.p;
+    J.n3 = (int)P.n3;
+    J.refine64 = (P.prec == TSVD_MIXED) ? 1 : 0;
+    P.ts.bar = (int*)(base + P.o_bar);
+    HIPCHK(c, hipMemcpy(base + P.o_job, &J, sizeof(JacobiJob), hipMemcpyHostToDevice));
+    std::vector<int> tj(P.n3, 0), tk(P.n3);
+    for (int k = 0; k < P.n3; ++k) tk[k] = k;
+    HIPCHK(c, hipMemcpy(base + P.o_tj, tj.data(), P.n3 * 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(base + P.o_tk, tk.data(), P.n3 * 4, hipMemcpyHostToDevice));
+    return TSVD_OK;
+}
+
+int clamp_sweeps(int v) { return std::max(1, std::min(v, kMaxSweeps - 1)); }
+
+// Jacobi launch for a planned tensor.
+int run_jacobi(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s) {
+    const JacobiJob* jd = (const JacobiJob*)(base + P.o_job);
+    const int* tj = (const int*)(base + P.o_tj);
+    const int* tk = (const int*)(base + P.o_tk);
+    hipError_t e;
+    if (!P.team)
+        e = launch_jacobi_resident(P.prec, jd, 1, tj, tk, (int)P.n3, clamp_sweeps(c->max_sweeps), ctrl, P.lds,
+                                   P.threads, P.with_v, s);
+    else
+        e = launch_jacobi_team(P.prec, jd, 1, tj, tk, (int)P.n3, P.ts, clamp_sweeps(c->max_sweeps), ctrl, P.lds,
+                               P.threads, P.with_v, c->spin_limit, s);
+    if (e != hipSuccess) return hip_fail(c, e, "jacobi launch");
+    return TSVD_OK;
+}
+
+// Everything after the forward transform of the t-SVT: Jacobi, thresholding,
+// rebuild.  Leaves Ybar in the workspace.
+int enqueue_svt_core(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau_val, const double* tau_sched,
+                     hipStream_t s) {
+    {
+        PhaseMark pm(c, 1, s);
+        int rc = run_jacobi(c, P, base, ctrl, s);
+        if (rc) return rc;
+    }
+    PhaseMark pm(c, 2, s);
+    const int prec = P.prec == TSVD_FP64 ? 0 : 1;
+    SvtPrepArgs sp{};
+    sp.A = base + P.o_A; sp.m = P.m; sp.p = P.p; sp.a_ss = (int64_t)P.m * P.p;
+    sp.F = base + P.o_F; sp.f_ss = (int64_t)P.m * P.p;
+    sp.w = (double*)(base + P.o_w); sp.w_ss = P.p;
+    sp.sig = (double*)(base + P.o_sig); sp.sig_ss = P.p;
+    sp.ranks = (int*)(base + P.o_rank);
+    sp.n3 = (int)P.n3;
+    sp.tau_val = tau_val; sp.tau_sched = tau_sched; sp.ctrl = ctrl;
+    hipError_t e = launch_svt_prep(prec, sp, s);
+    if (e != hipSuccess) return hip_fail(c, e, "svt_prep");
+    // G_k (p x r_k) = Zt_k (p x m) F_k (m x r_k) diag(w_k)
+    GemmArgs g{};
+    g.A = base + P.o_zbar;
+    if (!P.trans) { g.a_rs = P.n1; g.a_cs = 1; } else { g.a_rs = 1; g.a_cs = P.n1; }
+    g.a_bs = P.N;
+    g.B = base + P.o_F; g.b_rs = 1; g.b_cs = P.m; g.b_bs = (int64_t)P.m * P.p;
+    g.C = base + P.o_G; g.c_rs = 1; g.c_cs = P.p; g.c_bs = (int64_t)P.p * P.p;
+    g.cscale = (const double*)(base + P.o_w); g.s_bs = P.p;
+    g.M = P.p; g.Nn = P.p; g.K = P.m; g.Kdev = nullptr; g.Ndev = (const int*)(base + P.o_rank);
+    g.batch = (int)P.n3;
+    e = launch_gemm(prec, g, s);
+    if (e != hipSuccess) return hip_fail(c, e, "svt factor gemm");
+    // Ybar_k (n1 x n2) = L (n1 x r) R^T (r x n2)
+    GemmArgs r{};
+    if (!P.trans) {
+        r.A = base + P.o_F; r.a_rs = 1; r.a_cs = P.m; r.a_bs = (int64_t)P.m * P.p;
+        r.B = base + P.o_G; r.b_rs = P.p; r.b_cs = 1; r.b_bs = (int64_t)P.p * P.p;
+    } else {
+        r.A = base + P.o_G; r.a_rs = 1; r.a_cs = P.p; r.a_bs = (int64_t)P.p * P.p;
+        r.B = base + P.o_F; r.b_rs = P.m; r.b_cs = 1; r.b_bs = (int64_t)P.m * P.p;
+    }
+    r.C = base + P.o_ybar; r.c_rs = 1; r.c_cs = P.n1; r.c_bs = P.N;
+    r.cscale = nullptr;
+    r.M = (int)P.n1; r.Nn = (int)P.n2; r.K = 0; r.Kdev = (const int*)(base + P.o_rank); r.Ndev = nullptr;
+    r.batch = (int)P.n3;
+    e = launch_gemm(prec, r, s);
+    if (e != hipSuccess) return hip_fail(c, e, "svt rebuild gemm");
+    return TSVD_OK;
+}
+
+bool bad_prec(int prec) { return prec != TSVD_FP64 && prec != TSVD_FP32 && prec != TSVD_MIXED; }
+
+int finish_call(tsvd_ctx* c, hipStream_t s) {
+    if (!c->sync_status) return TSVD_OK;
+    return read_status(c, s, nullptr);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int tsvd_create(tsvd_ctx** out, int device) {
+    if (!out) return TSVD_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TSVD_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return TSVD_EHIP;
+    auto* c = new tsvd_ctx();
+    c->device = device;
+    (void)hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device);
+    CtrlRegion cr;
+    if (ensure_ctrl(c, &cr) != TSVD_OK) {
+        delete c;
+        return TSVD_EHIP;
+    }
+    *out = c;
+    return TSVD_OK;
+}
+
+void tsvd_destroy(tsvd_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : c->dct) {
+        (void)hipFree(kv.second.first);
+        (void)hipFree(kv.second.second);
+    }
+    if (c->ws.p) (void)hipFree(c->ws.p);
+    if (c->ctrl.p) (void)hipFree(c->ctrl.p);
+    if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
+    for (void* p : c->owned) (void)hipFree(p);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char* tsvd_last_error(const tsvd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int tsvd_set_option(tsvd_ctx* c, int opt, double v) {
+    if (!c) return TSVD_EINVAL;
+    switch (opt) {
+        case TSVD_OPT_MAX_SWEEPS:
+            if (v < 1 || v > kMaxSweeps - 1) return fail(c, TSVD_EINVAL, "max_sweeps out of range 1..63");
+            c->max_sweeps = (int)v;
+            return TSVD_OK;
+        case TSVD_OPT_SYNC_STATUS: c->sync_status = v != 0.0; return TSVD_OK;
+        case TSVD_OPT_TEAM_SIZE:
+            if (v < 0 || v > 64) return fail(c, TSVD_EINVAL, "team size out of range 0..64");
+            c->team_size = (int)v;
+            return TSVD_OK;
+        case TSVD_OPT_SPIN_LIMIT:
+            if (v < 1 || v > 1e9) return fail(c, TSVD_EINVAL, "spin limit out of range");
+            c->spin_limit = (int)v;
+            return TSVD_OK;
+        case TSVD_OPT_PROFILE: c->prof = v != 0.0; return TSVD_OK;
+    }
+    return fail(c, TSVD_EINVAL, "unknown option");
+}
+
+double tsvd_get_option(const tsvd_ctx* c, int opt) {
+    if (!c) return -1.0;
+    switch (opt) {
+        case TSVD_OPT_MAX_SWEEPS: return c->max_sweeps;
+        case TSVD_OPT_SYNC_STATUS: return c->sync_status;
+        case TSVD_OPT_TEAM_SIZE: return c->team_size;
+        case TSVD_OPT_SPIN_LIMIT: return c->spin_limit;
+        case TSVD_OPT_PROFILE: return c->prof;
+    }
+    return -1.0;
+}
+
+int tsvd_sync_status(tsvd_ctx* c, void* stream, int* max_sweeps_out) {
+    if (!c) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIPCHK(c, hipSetDevice(c->device));
+    return read_status(c, (hipStream_t)stream, max_sweeps_out);
+}
+
+int tsvd_get_stats(tsvd_ctx* c, void* stream, tsvd_stats* out, int reset) {
+    if (!c || !out) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIPCHK(c, hipSetDevice(c->device));
+    CtrlRegion cr;
+    int rc = ensure_ctrl(c, &cr);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    HIPCHK(c, hipDeviceSynchronize());
+    memset(out, 0, sizeof(*out));
+    for (auto& mk : c->marks) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, std::get<1>(mk), std::get<2>(mk)));
+        out->ms[std::get<0>(mk)] += ms;
+        out->launches[std::get<0>(mk)] += 1;
+    }
+    Ctrl h;
+    HIPCHK(c, hipMemcpy(&h, cr.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    out->slice_sweeps = (int64_t)h.slice_sweeps;
+    if (reset) {
+        c->marks.clear();
+        c->ev_used = 0;
+        h.slice_sweeps = 0;
+        HIPCHK(c, hipMemcpy(cr.ctrl, &h, sizeof(Ctrl), hipMemcpyHostToDevice));
+    }
+    return TSVD_OK;
+}
+
+int tsvt_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const void* Z, void* Y, double tau,
+             int32_t* ranks_out, void* stream) {
+    if (!c) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (bad_prec(prec)) return fail(c, TSVD_EINVAL, "unknown precision");
+    if (n1 <= 0 || n2 <= 0 || n3 <= 0) return fail(c, TSVD_EINVAL, "sizes must be positive");
+    if (!Z || !Y) return fail(c, TSVD_EINVAL, "null tensor pointer");
+    if (!(tau >= 0.0) || !isfinite(tau)) return fail(c, TSVD_EINVAL, "tau must be finite and >= 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    Plan P;
+    Carve cv;
+    int rc = make_plan(c, prec, n1, n2, n3, 0, P, cv);
+    if (rc) return rc;
+    if ((rc = ensure_ws(c, P.o_end))) return rc;
+    char* base = (char*)c->ws.p;
+    if ((rc = upload_plan(c, P, base))) return rc;
+    CtrlRegion cr;
+    if ((rc = ensure_ctrl(c, &cr))) return rc;
+    const void *C, *Ct;
+    if ((rc = get_dct(c, (int)n3, prec, &C, &Ct))) return rc;
+    const int dp = prec == TSVD_FP64 ? 0 : 1;
+    hipError_t e = launch_fill_zero(base + P.o_ctr_begin, P.o_ctr_end - P.o_ctr_begin, s);
+    if (e != hipSuccess) return hip_fail(c, e, "fill");
+    TubeArgs f{};
+    f.in = Z; f.out = base + P.o_zbar; f.M = C; f.N = P.N; f.n3 = (int)n3; f.ctrl = cr.ctrl; f.check_finite = 1;
+    f.beta_val = 1.0;
+    {
+        PhaseMark pm(c, 0, s);
+        e = launch_tube_transform(dp, f, s);
+        if (e != hipSuccess) return hip_fail(c, e, "dct");
+    }
+    if ((rc = enqueue_svt_core(c, P, base, cr.ctrl, tau, nullptr, s))) return rc;
+    TubeArgs iv{};
+    iv.in = base + P.o_ybar; iv.out = Y; iv.M = Ct; iv.N = P.N; iv.n3 = (int)n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
+    {
+        PhaseMark pm(c, 3, s);
+        e = launch_tube_transform(dp, iv, s);
+        if (e != hipSuccess) return hip_fail(c, e, "idct");
+    }
+    if (ranks_out) {
+        HIPCHK(c, hipMemcpyAsync(ranks_out, base + P.o_rank, n3 * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        return read_status(c, s, nullptr);
+    }
+    return finish_call(c, s);
+}
+
+int tprod_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n4, int64_t n3, const void* X, const void* Yp,
+              void* Z, void* stream) {
+    if (!c) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (bad_prec(prec)) return fail(c, TSVD_EINVAL, "unknown precision");
+    if (n1 <= 0 || n2 <= 0 || n3 <= 0 || n4 <= 0) return fail(c, TSVD_EINVAL, "sizes must be positive");
+    if (!X || !Yp || !Z) return fail(c, TSVD_EINVAL, "null tensor pointer");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const size_t es = esize(prec);
+    Carve cv;
+    size_t oX = cv.take((size_t)n1 * n2 * n3 * es), oY = cv.take((size_t)n2 * n4 * n3 * es),
+           oZ = cv.take((size_t)n1 * n4 * n3 * es);
+    int rc = ensure_ws(c, cv.off);
+    if (rc) return rc;
+    char* base = (char*)c->ws.p;
+    CtrlRegion cr;
+    if ((rc = ensure_ctrl(c, &cr))) return rc;
+    const void *C, *Ct;
+    if ((rc = get_dct(c, (int)n3, prec, &C, &Ct))) return rc;
+    const int dp = prec == TSVD_FP64 ? 0 : 1;
+    TubeArgs f{};
+    f.in = X; f.out = base + oX; f.M = C; f.N = n1 * n2; f.n3 = (int)n3; f.ctrl = cr.ctrl; f.check_finite = 1;
+    f.beta_val = 1.0;
+    hipError_t e = launch_tube_transform(dp, f, s);
+    if (e != hipSuccess) return hip_fail(c, e, "dct X");
+    f.in = Yp; f.out = base + oY; f.N = n2 * n4;
+    e = launch_tube_transform(dp, f, s);
+    if (e != hipSuccess) return hip_fail(c, e, "dct Y");
+    GemmArgs g{};
+    g.A = base + oX; g.a_rs = 1; g.a_cs = n1; g.a_bs = n1 * n2;
+    g.B = base + oY; g.b_rs = 1; g.b_cs = n2; g.b_bs = n2 * n4;
+    g.C = base + oZ; g.c_rs = 1; g.c_cs = n1; g.c_bs = n1 * n4;
+    g.M = (int)n1; g.Nn = (int)n4; g.K = (int)n2; g.batch = (int)n3;
+    e = launch_gemm(dp, g, s);
+    if (e != hipSuccess) return hip_fail(c, e, "slice gemm");
+    TubeArgs iv{};
+    iv.in = base + oZ; iv.out = Z; iv.M = Ct; iv.N = n1 * n4; iv.n3 = (int)n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
+    e = launch_tube_transform(dp, iv, s);
+    if (e != hipSuccess) return hip_fail(c, e, "idct Z");
+    return finish_call(c, s);
+}
+
+int tsvd_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const void* X, void* U, void* S, void* V,
+             int flags, void* stream) {
+    if (!c) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (bad_prec(prec)) return fail(c, TSVD_EINVAL, "unknown precision");
+    if (n1 <= 0 || n2 <= 0 || n3 <= 0) return fail(c, TSVD_EINVAL, "sizes must be positive");
+    if (!X || !S) return fail(c, TSVD_EINVAL, "null tensor pointer");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    Plan P;
+    Carve cv;
+    int rc = make_plan(c, prec, n1, n2, n3, 1, P, cv);
+    if (rc) return rc;
+    const size_t es = esize(prec);
+    const size_t oU = cv.take((size_t)n1 * P.p * n3 * es), oV = cv.take((size_t)n2 * P.p * n3 * es);
+    if ((rc = ensure_ws(c, cv.off))) return rc;
+    char* base = (char*)c->ws.p;
+    if ((rc = upload_plan(c, P, base))) return rc;
+    CtrlRegion cr;
+    if ((rc = ensure_ctrl(c, &cr))) return rc;
+    const void *C, *Ct;
+    if ((rc = get_dct(c, (int)n3, prec, &C, &Ct))) return rc;
+    const int dp = prec == TSVD_FP64 ? 0 : 1;
+    hipError_t e = launch_fill_zero(base + P.o_ctr_begin, P.o_ctr_end - P.o_ctr_begin, s);
+    if (e != hipSuccess) return hip_fail(c, e, "fill");
+    TubeArgs f{};
+    f.in = X; f.out = base + P.o_zbar; f.M = C; f.N = P.N; f.n3 = (int)n3; f.ctrl = cr.ctrl; f.check_finite = 1;
+    f.beta_val = 1.0;
+    if ((e = launch_tube_transform(dp, f, s)) != hipSuccess) return hip_fail(c, e, "dct");
+    if ((rc = run_jacobi(c, P, base, cr.ctrl, s))) return rc;
+    // singular values per column
+    SvtPrepArgs sp{};
+    sp.A = base + P.o_A; sp.m = P.m; sp.p = P.p; sp.a_ss = (int64_t)P.m * P.p;
+    sp.F = base + P.o_F; sp.f_ss = (int64_t)P.m * P.p;
+    sp.w = (double*)(base + P.o_w); sp.w_ss = P.p;
+    sp.sig = (double*)(base + P.o_sig); sp.sig_ss = P.p;
+    sp.ranks = (int*)(base + P.o_rank); sp.n3 = (int)n3; sp.tau_val = 0.0; sp.ctrl = cr.ctrl;
+    if ((e = launch_svt_prep(dp, sp, s)) != hipSuccess) return hip_fail(c, e, "sigma");
+    void* Uo = U ? U : (void*)(base + oU);
+    void* Vo = V ? V : (void*)(base + oV);
+    TsvdFinishArgs fa{};
+    fa.A = base + P.o_A; fa.m = P.m; fa.p = P.p; fa.a_ss = (int64_t)P.m * P.p;
+    fa.Vj = base + P.o_V; fa.v_ss = (int64_t)P.p * P.p;
+    fa.sig = (const double*)(base + P.o_sig); fa.sig_ss = P.p;
+    // tall problem: left vectors are U (n1 >= n2) or V (n1 < n2)
+    fa.Ut = P.trans ? Vo : Uo; fa.ut_ss = (int64_t)P.m * P.p;
+    fa.Vt = P.trans ? Uo : Vo; fa.vt_ss = (int64_t)P.p * P.p;
+    fa.S = S; fa.s_ss = P.p; fa.n3 = (int)n3;
+    if ((e = launch_tsvd_finish(dp, fa, s)) != hipSuccess) return hip_fail(c, e, "tsvd finish");
+    if (!(flags & TSVD_TRANSFORM_DOMAIN)) {
+        // back to the spatial domain (in place: each workgroup owns whole tubes)
+        TubeArgs iv{};
+        iv.M = Ct; iv.n3 = (int)n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
+        if (U) { iv.in = U; iv.out = U; iv.N = n1 * P.p; if ((e = launch_tube_transform(dp, iv, s)) != hipSuccess) return hip_fail(c, e, "idct U"); }
+        if (V) { iv.in = V; iv.out = V; iv.N = n2 * P.p; if ((e = launch_tube_transform(dp, iv, s)) != hipSuccess) return hip_fail(c, e, "idct V"); }
+        iv.in = S; iv.out = S; iv.N = P.p;
+        if ((e = launch_tube_transform(dp, iv, s)) != hipSuccess) return hip_fail(c, e, "idct S");
+    }
+    return finish_call(c, s);
+}
+
+int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const void* B, const uint8_t* mask,
+                    void* X, const tsvd_complete_opts* o, tsvd_complete_info* info, void* stream) {
+    if (!c) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (bad_prec(prec)) return fail(c, TSVD_EINVAL, "unknown precision");
+    if (n1 <= 0 || n2 <= 0 || n3 <= 0) return fail(c, TSVD_EINVAL, "sizes must be positive");
+    if (!B || !mask || !X || !o) return fail(c, TSVD_EINVAL, "null pointer");
+    if (o->max_iter <= 0) return fail(c, TSVD_EINVAL, "max_iter must be positive");
+    if (!o->tau_schedule && !(o->beta > 0.0)) return fail(c, TSVD_EINVAL, "beta must be > 0");
+    if (o->check_every < 1) return fail(c, TSVD_EINVAL, "check_every must be >= 1");
+    if (o->start_iter < 0) return fail(c, TSVD_EINVAL, "start_iter must be >= 0");
+    const int L = o->max_iter;
+    std::vector<double> betas(L), taus(L);
+    for (int l = 0; l < L; ++l) {
+        const double t = o->tau_schedule ? o->tau_schedule[o->start_iter + l] : 1.0 / o->beta;
+        if (!(t > 0.0) || !isfinite(t)) return fail(c, TSVD_EINVAL, "schedule entries must be finite and > 0");
+        betas[l] = o->tau_schedule ? 1.0 / t : o->beta;
+        taus[l] = t;
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    Plan P;
+    Carve cv;
+    int rc = make_plan(c, prec, n1, n2, n3, 0, P, cv);
+    if (rc) return rc;
+    const size_t es = esize(prec);
+    const size_t oM = cv.take((size_t)P.N * n3 * es);
+    const size_t oBeta = cv.take((size_t)L * 8), oTau = cv.take((size_t)L * 8);
+    if ((rc = ensure_ws(c, cv.off))) return rc;
+    char* base = (char*)c->ws.p;
+    if ((rc = upload_plan(c, P, base))) return rc;
+    CtrlRegion cr;
+    if ((rc = ensure_ctrl(c, &cr))) return rc;
+    const void *C, *Ct;
+    if ((rc = get_dct(c, (int)n3, prec, &C, &Ct))) return rc;
+    const int dp = prec == TSVD_FP64 ? 0 : 1;
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipMemcpy(base + oBeta, betas.data(), L * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(base + oTau, taus.data(), L * 8, hipMemcpyHostToDevice));
+    if (o->M_init) HIPCHK(c, hipMemcpyAsync(base + oM, o->M_init, P.N * n3 * es, hipMemcpyDeviceToDevice, s));
+    else if (launch_fill_zero(base + oM, P.N * n3 * es, s) != hipSuccess) return fail(c, TSVD_EHIP, "fill M");
+    // iteration counter, norms and history start at zero (status and statistics are kept)
+    HIPCHK(c, hipStreamSynchronize(s));
+    {
+        Ctrl h;
+        HIPCHK(c, hipMemcpy(&h, cr.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+        h.iter = 0;
+        HIPCHK(c, hipMemcpy(cr.ctrl, &h, sizeof(Ctrl), hipMemcpyHostToDevice));
+    }
+    if (launch_fill_zero(cr.norms, 256 + 8 * kHist, s) != hipSuccess) return fail(c, TSVD_EHIP, "fill norms");
+
+    auto enqueue_iter = [&](hipStream_t st) -> int {
+        hipError_t e = launch_fill_zero(base + P.o_ctr_begin, P.o_ctr_end - P.o_ctr_begin, st);
+        if (e != hipSuccess) return hip_fail(c, e, "fill");
+        TubeArgs f{};
+        f.out = base + P.o_zbar; f.M = C; f.N = P.N; f.n3 = (int)n3; f.ctrl = cr.ctrl;
+        f.pX = X; f.pM = base + oM; f.beta_sched = (const double*)(base + oBeta);
+        {
+            PhaseMark pm(c, 0, st);
+            e = launch_tube_transform(dp, f, st);
+            if (e != hipSuccess) return hip_fail(c, e, "dct");
+        }
+        int r2 = enqueue_svt_core(c, P, base, cr.ctrl, 0.0, (const double*)(base + oTau), st);
+        if (r2) return r2;
+        TubeArgs iv{};
+        iv.in = base + P.o_ybar; iv.out = nullptr; iv.M = Ct; iv.N = P.N; iv.n3 = (int)n3; iv.ctrl = cr.ctrl;
+        iv.eB = B; iv.emask = mask; iv.eX = X; iv.eM = base + oM; iv.norms = cr.norms;
+        iv.beta_sched = (const double*)(base + oBeta);
+        {
+            PhaseMark pm(c, 3, st);
+            e = launch_tube_transform(dp, iv, st);
+            if (e != hipSuccess) return hip_fail(c, e, "idct");
+        }
+        e = launch_iter_advance(cr.ctrl, cr.norms, cr.hist, kHist, st);
+        if (e != hipSuccess) return hip_fail(c, e, "advance");
+        return TSVD_OK;
+    };
+
+    int iters = 0;
+    double last = 0.0;
+    bool stop = false;
+    const bool check = o->tol > 0.0;
+    while (iters < L && !stop) {
+        if ((rc = enqueue_iter(s))) return rc;
+        ++iters;
+        if (check && (iters % o->check_every == 0 || iters == L)) {
+            HIPCHK(c, hipStreamSynchronize(s));
+            double h = 0.0;
+            HIPCHK(c, hipMemcpy(&h, cr.hist + (iters - 1), 8, hipMemcpyDeviceToHost));
+            last = h;
+            if (h <= o->tol) stop = true;
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (iters >= 1 && iters <= kHist) HIPCHK(c, hipMemcpy(&last, cr.hist + (iters - 1), 8, hipMemcpyDeviceToHost));
+    if (o->M_out) HIPCHK(c, hipMemcpyAsync(o->M_out, base + oM, P.N * n3 * es, hipMemcpyDeviceToDevice, s));
+    int msw = 0;
+    rc = read_status(c, s, &msw);
+    if (info) {
+        info->iters = iters;
+        info->rel_change = last;
+        info->status = rc;
+        info->max_sweeps = msw;
+    }
+    return rc;
+}
+
+int tsvt_dct_batched(tsvd_ctx* c, int prec, int count, const int64_t* dims, const void* const* Z, void* const* Y,
+                     const double* tau, void* stream) {
+    if (!c) return TSVD_EINVAL;
+    if (count <= 0 || !dims || !Z || !Y || !tau) return fail(c, TSVD_EINVAL, "bad batch arguments");
+    // Reference behaviour: same result as one call per tensor.
+    const int sync = c->sync_status;
+    c->sync_status = 0;
+    int rc = TSVD_OK;
+    for (int j = 0; j < count && rc >= 0; ++j) {
+        rc = tsvt_dct(c, prec, dims[3 * j], dims[3 * j + 1], dims[3 * j + 2], Z[j], Y[j], tau[j], nullptr, stream);
+    }
+    c->sync_status = sync;
+    if (rc < 0) return rc;
+    if (sync) return tsvd_sync_status(c, stream, nullptr);
+    return TSVD_OK;
+}
+
+}  // extern "C"

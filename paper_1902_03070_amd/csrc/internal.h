@@ -1,0 +1,142 @@
+// Internal declarations shared by the HIP translation units of libtsvdmi.
+// Not part of the public interface (include/tsvdmi.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace tsvd {
+
+constexpr int kMaxSweeps = 64;       // hard cap on Jacobi sweeps (per-sweep counters are sized by it)
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kMaxEpl = 8;           // rows per lane in the Jacobi kernels: m <= 512
+constexpr int kMaxRows = kWave * kMaxEpl;
+constexpr int kLdsBudget = 160 * 1024 - 1024;  // dynamic LDS per workgroup (gfx950: 160 KB, minus static use)
+
+// Device status bits (accumulated with atomicOr in ctrl->status).
+enum : int { kStNonFinite = 1, kStNoConv = 2, kStTimeout = 4 };
+
+// Per-launch control block in device memory.
+struct Ctrl {
+    int status;      // kSt* bits
+    int max_sweeps;  // largest sweep count seen (atomicMax)
+    int iter;        // completion iteration counter (graph-captured loops)
+    int pad;
+    unsigned long long slice_sweeps;  // sweeps executed, summed over slices (statistics)
+};
+
+// One Jacobi problem set: all frontal slices of one tensor, in "tall" form.
+// Slice k's tall matrix T_k (m x p, m >= p) is, element (r, c):
+//   src[k*src_ss + r*src_rs + c*src_cs]
+// i.e. the transformed slice itself (n1 >= n2) or its transpose.
+struct JacobiJob {
+    const void* src;   // transformed tensor Zbar (n1 x n2 x n3)
+    void* A;           // work/output: m x p per slice, ld = m, slice stride m*p
+    void* V;           // p x p per slice (ld = p) or nullptr
+    int* rot;          // [n3 * kMaxSweeps] rotation counters (zeroed before launch)
+    int* sweeps;       // [n3] sweeps used per slice (-1 = not converged)
+    int64_t src_ss, src_rs, src_cs;
+    int m, p, n3;
+    int epl;           // ceil(m / 64)
+    int b;             // block width for the team kernel (even)
+    int nb;            // number of column blocks (even) = ceil(p / b) rounded up to even
+    int refine64;      // 1: after convergence run one sweep with FP64 arithmetic (FP32 data)
+    int pad;
+};
+
+struct TeamSched {
+    int W;             // workgroups per team
+    int nteams;        // teams in the grid
+    int* bar;          // [nteams] barrier counters (zeroed before launch)
+};
+
+// ---- launch helpers (defined in the .hip files) -----------------------------
+// All return hipSuccess or the first HIP error.
+
+// Tube transform: out[r + N*k'] = sum_k M[k'][k] in[r + N*k], r < N, k,k' < n3.
+// M is row-major n3 x n3 on the device.  Optional fused prologue/epilogue for
+// the completion loop (see ops.hip).
+struct TubeArgs {
+    const void* in;
+    void* out;
+    const void* M;         // transform matrix (device), row-major n3 x n3, element type = data type
+    int64_t N;             // tubes = n1*n2
+    int n3;
+    // prologue: in = X - Mlt / beta  (when X != nullptr; `in` is then ignored)
+    const void* pX;
+    const void* pM;
+    // epilogue (ADMM): y = transform result;
+    //   Xn = mask ? B : y + Mlt/beta ; Mlt += beta (y - Xn) ; X <- Xn; out <- y (if out)
+    const void* eB;
+    const uint8_t* emask;
+    void* eX;
+    void* eM;
+    double* norms;         // [2] += (||Xn - X||^2, ||X||^2) (FP64 atomics)
+    // beta: beta_val, or beta_sched[ctrl->iter] when beta_sched != nullptr
+    double beta_val;
+    const double* beta_sched;
+    Ctrl* ctrl;
+    int check_finite;      // 1: flag non-finite inputs in ctrl->status
+};
+hipError_t launch_tube_transform(int prec, const TubeArgs& a, hipStream_t s);
+
+// Jacobi one-sided SVD of every slice of one or more jobs.
+hipError_t launch_jacobi_resident(int prec, const JacobiJob* jobs_dev, int njobs, const int* task_job,
+                                  const int* task_slice, int ntasks, int max_sweeps, Ctrl* ctrl,
+                                  int lds_bytes, int threads, int with_v, hipStream_t s);
+hipError_t launch_jacobi_team(int prec, const JacobiJob* jobs_dev, int njobs, const int* task_job,
+                              const int* task_slice, int ntasks, const TeamSched& ts, int max_sweeps,
+                              Ctrl* ctrl, int lds_bytes, int threads, int with_v, int spin_limit,
+                              hipStream_t s);
+int jacobi_resident_lds_bytes(int prec, int m, int p, int with_v);
+int jacobi_team_lds_bytes(int prec, int m, int p, int b, int with_v);
+int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v);
+
+// Batched strided GEMM with optional per-batch K (ranks) and column scale.
+//   C_b(i,j) = cscale_b(j) * sum_{t < K_b} A_b(i,t) B_b(t,j)
+// X_b(r,c) = X[b*bs + r*rs + c*cs].  K_b = Kdev ? Kdev[b] : K.
+struct GemmArgs {
+    const void* A; int64_t a_rs, a_cs, a_bs;
+    const void* B; int64_t b_rs, b_cs, b_bs;
+    void* C; int64_t c_rs, c_cs, c_bs;
+    const double* cscale; int64_t s_bs;  // per-column scale (FP64) or nullptr
+    int M, Nn, K;
+    const int* Kdev;   // per-batch K, or nullptr
+    const int* Ndev;   // per-batch column count (<= Nn), or nullptr
+    int batch;
+};
+hipError_t launch_gemm(int prec, const GemmArgs& g, hipStream_t s);
+
+// SVT factor preparation: per slice, sigma_c = ||A'(:,c)||, keep = sigma > tau,
+// compacts kept columns of A' into F (ld m), w_c = (sigma_c - tau)/sigma_c^3,
+// rank -> ranks[k].
+struct SvtPrepArgs {
+    const void* A; int m, p; int64_t a_ss;   // A' slices (ld m)
+    void* F; int64_t f_ss;                    // compacted columns (ld m)
+    double* w; int64_t w_ss;                  // scales
+    double* sig; int64_t sig_ss;              // singular values (unsorted, per column)
+    int* ranks;
+    int n3;
+    double tau_val; const double* tau_sched; Ctrl* ctrl;
+};
+hipError_t launch_svt_prep(int prec, const SvtPrepArgs& a, hipStream_t s);
+
+// Small utility kernels.
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
+hipError_t launch_iter_advance(Ctrl* ctrl, double* norms, double* relchg_hist, int hist_len, hipStream_t s);
+// Sort singular values descending per slice and build U = A'(:,perm)/sigma, with the
+// sign convention, and permute V; used by tsvd_dct.
+struct TsvdFinishArgs {
+    const void* A; int m, p; int64_t a_ss;   // A' (tall m x p)
+    const void* Vj; int64_t v_ss;            // Jacobi V (p x p)
+    const double* sig; int64_t sig_ss;
+    void* Ut; int64_t ut_ss;                 // out: tall left vectors m x p
+    void* Vt; int64_t vt_ss;                 // out: tall right vectors p x p
+    void* S; int64_t s_ss;                   // out: singular values (data type), p per slice
+    int n3;
+};
+hipError_t launch_tsvd_finish(int prec, const TsvdFinishArgs& a, hipStream_t s);
+
+}  // namespace tsvd

@@ -1,0 +1,138 @@
+"""GPU parity of the t-SVT hot path against the FP64 oracle (through the C-ABI).
+
+FP64 bar: relative Frobenius error <= 1e-10 against the oracle on the same input.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import announce, need_gpu, rel, to_dev, to_np, torch
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def tm():
+    need_gpu()
+    import paper_1902_03070_amd as tm
+
+    return tm
+
+
+def case(shape, r=3, noise=0.01, tau=None, seed=11):
+    n1, n2, n3 = shape
+    if tau is None:
+        tau = 0.1 * (np.sqrt(n1) + np.sqrt(n2))
+    return synth.tsvt_case(oracle.tprod_dct, n1, n2, n3, r, noise, tau, seed)
+
+
+SMALL = [(7, 5, 3), (5, 7, 4), (33, 17, 9), (17, 33, 2), (1, 6, 5), (6, 1, 5), (64, 64, 16), (100, 80, 7),
+         (80, 100, 3), (130, 70, 5), (65, 64, 1), (2, 2, 2), (150, 150, 2)]
+
+
+@pytest.mark.parametrize("shape", SMALL)
+def test_tsvt_fp64_small(tm, shape):
+    announce("tsvt_fp64_small", shape=shape)
+    c = case(shape, r=max(1, min(shape[:2]) // 4))
+    Y, ranks = tm.tsvt_dct(to_dev(c.Z), c.tau, return_ranks=True)
+    Yo, ro, _ = oracle.tsvt_dct(c.Z, c.tau, return_ranks=True)
+    err = rel(to_np(Y), Yo)
+    assert err <= TOL64, err
+    assert list(ranks) == [int(x) for x in ro]
+
+
+def test_tsvt_fp64_config_small_case(tm):
+    # 64 x 64 x 16, tubal rank 5 Gaussian factors + N(0, 0.01) noise, tau = 1.0
+    announce("tsvt_fp64_64x64x16")
+    c = synth.tsvt_case(oracle.tprod_dct, 64, 64, 16, 5, 0.01, 1.0, synth.SEED_BASE + 1)
+    Y, ranks = tm.tsvt_dct(to_dev(c.Z), c.tau, return_ranks=True)
+    Yo, ro, _ = oracle.tsvt_dct(c.Z, c.tau, return_ranks=True)
+    assert rel(to_np(Y), Yo) <= TOL64
+    assert list(ranks) == [int(x) for x in ro]
+
+
+@pytest.mark.parametrize("shape", [(256, 256, 3), (200, 300, 2), (300, 170, 2), (512, 512, 1)])
+def test_tsvt_fp64_team_kernel(tm, shape):
+    # slices larger than one workgroup's LDS: block-pair team kernel
+    announce("tsvt_fp64_team", shape=shape)
+    c = case(shape, r=10)
+    Y = tm.tsvt_dct(to_dev(c.Z), c.tau)
+    Yo = oracle.tsvt_dct(c.Z, c.tau)
+    assert rel(to_np(Y), Yo) <= TOL64
+
+
+@pytest.mark.parametrize("team", [1, 2, 5])
+def test_tsvt_fp64_team_sizes_agree(tm, team):
+    announce("tsvt_team_sizes", team=team)
+    c = case((256, 192, 2), r=8)
+    ctx = tm.Context(0)
+    ctx.set_option(tm.OPT_TEAM_SIZE, team)
+    Y = tm.tsvt_dct(to_dev(c.Z), c.tau, ctx=ctx)
+    Yo = oracle.tsvt_dct(c.Z, c.tau)
+    assert rel(to_np(Y), Yo) <= TOL64
+    ctx.close()
+
+
+def test_tsvt_special_cases(tm):
+    announce("tsvt_special")
+    c = case((20, 12, 5))
+    Z = to_dev(c.Z)
+    assert rel(to_np(tm.tsvt_dct(Z, 0.0)), c.Z) <= 1e-12
+    Y = tm.tsvt_dct(Z, 1e6)
+    assert float(torch.abs(Y).max()) == 0.0
+
+
+def test_tsvt_fp32(tm):
+    announce("tsvt_fp32")
+    c = case((48, 40, 8), r=5)
+    Y = tm.tsvt_dct(to_dev(c.Z, torch.float32), c.tau)
+    Yo = oracle.tsvt_dct(c.Z, c.tau)
+    assert rel(to_np(Y), Yo) <= 1e-5
+
+
+def test_tsvt_nonfinite_input_is_an_error(tm):
+    announce("tsvt_nan")
+    c = case((10, 8, 3))
+    Z = c.Z.copy(order="F")
+    Z[3, 2, 1] = np.nan
+    with pytest.raises(tm.TsvdError) as ei:
+        tm.tsvt_dct(to_dev(Z), c.tau)
+    assert ei.value.code == tm.ENONFINITE
+
+
+def test_tsvt_sweep_limit_warns(tm):
+    announce("tsvt_sweep_limit")
+    c = case((40, 30, 3), r=6)
+    ctx = tm.Context(0)
+    ctx.set_option(tm.OPT_MAX_SWEEPS, 1)
+    rc = tm.lib.tsvt_dct(ctx.h, 0, 40, 30, 3, to_dev(c.Z).data_ptr(), to_dev(c.Z).data_ptr(), c.tau, None, None)
+    torch.cuda.synchronize()
+    assert rc == tm.WARN_NOCONV
+    ctx.close()
+
+
+def test_tsvt_invalid_arguments(tm):
+    announce("tsvt_invalid")
+    ctx = tm.default_context(0)
+    Z = to_dev(np.zeros((4, 4, 2)))
+    assert tm.lib.tsvt_dct(ctx.h, 0, 0, 4, 2, Z.data_ptr(), Z.data_ptr(), 1.0, None, None) == tm.EINVAL
+    assert tm.lib.tsvt_dct(ctx.h, 0, 4, 4, 2, Z.data_ptr(), Z.data_ptr(), -1.0, None, None) == tm.EINVAL
+    assert tm.lib.tsvt_dct(ctx.h, 7, 4, 4, 2, Z.data_ptr(), Z.data_ptr(), 1.0, None, None) == tm.EINVAL
+    assert tm.lib.tsvt_dct(ctx.h, 0, 4, 4, 2, None, Z.data_ptr(), 1.0, None, None) == tm.EINVAL
+
+
+def test_tsvt_full_size_sampled_slices(tm):
+    # 256 x 256 x 31, FP64, checked on sampled transformed slices: the DCT of
+    # the GPU output must equal the oracle's matrix SVT of those slices.
+    announce("tsvt_fp64_256x256x31_sampled")
+    cc = synth.completion_case(oracle.tprod_dct, 256, 256, 31, 10, 0.3, 100, synth.SEED_BASE + 2)
+    tau = float(cc.taus[0])
+    Y = tm.tsvt_dct(to_dev(cc.B), tau)
+    Yb = oracle.dct_tubes(to_np(Y))
+    Zb = oracle.dct_tubes(cc.B)
+    for k in (0, 7, 30):
+        want = oracle.tsvt_dct(Zb[:, :, k:k + 1], tau)[:, :, 0]
+        assert rel(Yb[:, :, k], want) <= TOL64, k
