@@ -220,28 +220,35 @@ struct Plan {
 };
 
 int choose_team(tsvd_ctx* c, Plan& P) {
-    const int epl = (P.m + kWave - 1) / kWave;
-    int W = c->team_size > 0 ? c->team_size : (P.p + 31) / 32;
+    int G, R, ldv;
+    jacobi_geometry(P.m, P.p, &G, &R, &ldv);
+    const int bstep = std::max(2, kWave / G);  // b * G must fill whole wavefronts
+    const int bmax = kTeamMaxThreads / G;
+    int W = c->team_size > 0 ? c->team_size : (P.p + 63) / 64;
     if (W < 1) W = 1;
     int b = (P.p + 2 * W - 1) / (2 * W);
-    b += b & 1;
-    if (b < 2) b = 2;
-    // shrink b until one block pair fits in LDS
-    while (b > 2 && jacobi_team_lds_bytes(P.prec, P.m, P.p, b, P.with_v) > kLdsBudget) b -= 2;
+    b = (b + bstep - 1) / bstep * bstep;
+    b = std::min(b, bmax);
+    while (b > bstep && jacobi_team_lds_bytes(P.prec, P.m, P.p, b, P.with_v) > kLdsBudget) b -= bstep;
+    if (jacobi_team_lds_bytes(P.prec, P.m, P.p, b, P.with_v) > kLdsBudget)
+        return fail(c, TSVD_EINVAL, "slice too large for the Jacobi team kernel");
     int nb = (P.p + b - 1) / b;
     nb += nb & 1;
     if (W > nb / 2) W = nb / 2;
     P.lds = jacobi_team_lds_bytes(P.prec, P.m, P.p, b, P.with_v);
-    P.threads = kWave * std::min(16, std::max(4, b));
-    int cap = jacobi_team_max_resident(P.prec, P.lds, P.threads, P.with_v);
-    if (cap < 1) return fail(c, TSVD_EINVAL, "Jacobi team kernel cannot be resident with this shape");
-    if (W > cap) W = cap;
-    int nteams = std::max(1, std::min((int)P.n3, cap / W));
+    P.threads = b * G;
+    const int cap = jacobi_team_max_resident(P.prec, P.lds, P.threads, P.with_v, R, G);
+    if (cap < 8) return fail(c, TSVD_EINVAL, "Jacobi team kernel cannot be resident with this shape");
+    // whole teams on every XCD: the grid is a multiple of 8 W workgroups
+    W = std::min(W, cap / 8);
+    int per_xcd = std::max(1, std::min(((int)P.n3 + 7) / 8, cap / (8 * W)));
     P.ts.W = W;
-    P.ts.nteams = nteams;
+    P.ts.nwg = 8 * W * per_xcd;
     P.job.b = b;
     P.job.nb = nb;
-    P.job.epl = epl;
+    P.job.G = G;
+    P.job.R = R;
+    P.job.ldv = ldv;
     return TSVD_OK;
 }
 
@@ -259,10 +266,15 @@ int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int wit
     if (rl <= kLdsBudget) {
         P.team = 0;
         P.lds = rl;
-        const int pairs = (P.p + 1) / 2;
-        int nw = std::min(16, std::max(4, pairs));
-        P.threads = kWave * nw;
-        P.job.epl = (P.m + kWave - 1) / kWave;
+        int G, R, ldv;
+        jacobi_geometry(P.m, P.p, &G, &R, &ldv);
+        const int per_wave = kWave / G;
+        int ngrp = std::min((P.p + 1) / 2, 1024 / G);
+        ngrp = (ngrp + per_wave - 1) / per_wave * per_wave;
+        P.threads = std::max(kWave, ngrp * G);
+        P.job.G = G;
+        P.job.R = R;
+        P.job.ldv = ldv;
         P.job.b = 0;
         P.job.nb = 0;
         P.ts = TeamSched{1, 0, nullptr};
@@ -285,7 +297,7 @@ int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int wit
     P.o_ctr_begin = cv.off;
     P.o_rot = cv.take((size_t)n3 * kMaxSweeps * 4);
     P.o_sw = cv.take((size_t)n3 * 4);
-    P.o_bar = cv.take((size_t)std::max(1, P.ts.nteams) * 4);
+    P.o_bar = cv.take((size_t)(kTeamCtlInts + std::max(1, P.ts.nwg)) * 4);
     P.o_rank = cv.take((size_t)n3 * 4);
     P.o_ctr_end = cv.off;
     P.o_end = cv.off;
@@ -307,7 +319,7 @@ int upload_plan(tsvd_ctx* c, Plan& P, char* base) {
     J.p = P.p;
     J.n3 = (int)P.n3;
     J.refine64 = (P.prec == TSVD_MIXED) ? 1 : 0;
-    P.ts.bar = (int*)(base + P.o_bar);
+    P.ts.ctl = (int*)(base + P.o_bar);
     HIPCHK(c, hipMemcpy(base + P.o_job, &J, sizeof(JacobiJob), hipMemcpyHostToDevice));
     std::vector<int> tj(P.n3, 0), tk(P.n3);
     for (int k = 0; k < P.n3; ++k) tk[k] = k;
@@ -329,7 +341,7 @@ int run_jacobi(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s) {
                                    P.threads, P.with_v, s);
     else
         e = launch_jacobi_team(P.prec, jd, 1, tj, tk, (int)P.n3, P.ts, clamp_sweeps(c->max_sweeps), ctrl, P.lds,
-                               P.threads, P.with_v, c->spin_limit, s);
+                               P.threads, P.with_v, c->spin_limit, P.job.R, P.job.G, s);
     if (e != hipSuccess) return hip_fail(c, e, "jacobi launch");
     return TSVD_OK;
 }
@@ -641,7 +653,7 @@ int tsvd_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
     // tall problem: left vectors are U (n1 >= n2) or V (n1 < n2)
     fa.Ut = P.trans ? Vo : Uo; fa.ut_ss = (int64_t)P.m * P.p;
     fa.Vt = P.trans ? Uo : Vo; fa.vt_ss = (int64_t)P.p * P.p;
-    fa.S = S; fa.s_ss = P.p; fa.n3 = (int)n3;
+    fa.S = S; fa.s_ss = P.p; fa.n3 = (int)n3; fa.sign_from_v = P.trans;
     if ((e = launch_tsvd_finish(dp, fa, s)) != hipSuccess) return hip_fail(c, e, "tsvd finish");
     if (!(flags & TSVD_TRANSFORM_DOMAIN)) {
         // back to the spatial domain (in place: each workgroup owns whole tubes)

@@ -13,7 +13,8 @@ constexpr int kMaxSweeps = 64;       // hard cap on Jacobi sweeps (per-sweep cou
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kMaxEpl = 8;           // rows per lane in the Jacobi kernels: m <= 512
 constexpr int kMaxRows = kWave * kMaxEpl;
-constexpr int kLdsBudget = 160 * 1024 - 1024;  // dynamic LDS per workgroup (gfx950: 160 KB, minus static use)
+constexpr int kTeamMaxThreads = 512;  // launch bound of the Jacobi team kernel
+constexpr int kLdsBudget = 160 * 1024 - 8 * 1024;  // dynamic LDS per workgroup (gfx950: 160 KB, minus static use)
 
 // Device status bits (accumulated with atomicOr in ctrl->status).
 enum : int { kStNonFinite = 1, kStNoConv = 2, kStTimeout = 4 };
@@ -39,18 +40,20 @@ struct JacobiJob {
     int* sweeps;       // [n3] sweeps used per slice (-1 = not converged)
     int64_t src_ss, src_rs, src_cs;
     int m, p, n3;
-    int epl;           // ceil(m / 64)
+    int G;             // lanes per column pair (16 or 32)
+    int R;             // rows per lane (4, 8, 12 or 16): R*G >= m
+    int ldv;           // LDS leading dimension of V columns (multiple of G, >= p)
     int b;             // block width for the team kernel (even)
     int nb;            // number of column blocks (even) = ceil(p / b) rounded up to even
     int refine64;      // 1: after convergence run one sweep with FP64 arithmetic (FP32 data)
-    int pad;
 };
 
 struct TeamSched {
     int W;             // workgroups per team
-    int nteams;        // teams in the grid
-    int* bar;          // [nteams] barrier counters (zeroed before launch)
+    int nwg;           // workgroups in the grid (a multiple of 8 W: whole teams on each XCD)
+    int* ctl;          // team formation and barrier counters, kTeamCtlInts + nwg / W ints, zeroed
 };
+constexpr int kTeamCtlInts = 32;
 
 // ---- launch helpers (defined in the .hip files) -----------------------------
 // All return hipSuccess or the first HIP error.
@@ -88,11 +91,12 @@ hipError_t launch_jacobi_resident(int prec, const JacobiJob* jobs_dev, int njobs
                                   int lds_bytes, int threads, int with_v, hipStream_t s);
 hipError_t launch_jacobi_team(int prec, const JacobiJob* jobs_dev, int njobs, const int* task_job,
                               const int* task_slice, int ntasks, const TeamSched& ts, int max_sweeps,
-                              Ctrl* ctrl, int lds_bytes, int threads, int with_v, int spin_limit,
+                              Ctrl* ctrl, int lds_bytes, int threads, int with_v, int spin_limit, int R, int G,
                               hipStream_t s);
+void jacobi_geometry(int m, int p, int* G, int* R, int* ldv);
 int jacobi_resident_lds_bytes(int prec, int m, int p, int with_v);
 int jacobi_team_lds_bytes(int prec, int m, int p, int b, int with_v);
-int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v);
+int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v, int R, int G);
 
 // Batched strided GEMM with optional per-batch K (ranks) and column scale.
 //   C_b(i,j) = cscale_b(j) * sum_{t < K_b} A_b(i,t) B_b(t,j)
@@ -136,6 +140,7 @@ struct TsvdFinishArgs {
     void* Vt; int64_t vt_ss;                 // out: tall right vectors p x p
     void* S; int64_t s_ss;                   // out: singular values (data type), p per slice
     int n3;
+    int sign_from_v;                         // 1: the slice's left vectors are the Jacobi V (n1 < n2)
 };
 hipError_t launch_tsvd_finish(int prec, const TsvdFinishArgs& a, hipStream_t s);
 

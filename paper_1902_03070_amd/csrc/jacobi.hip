@@ -6,21 +6,29 @@
 // Columns of T are rotated in pairs until every pair is orthogonal to
 // tol = m * u (u = unit roundoff of the sweep arithmetic):
 //     alpha = |x|^2, beta = |y|^2, gamma = x.y        (FP64 sums)
+//     rotate iff gamma^2 > tol^2 alpha beta
 //     zeta = (beta - alpha) / (2 gamma),  t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2))
 //     c = 1 / sqrt(1 + t^2),  s = c t,  x' = c x - s y,  y' = s x + c y.
 // On exit A holds T V (columns = sigma_j u_j); V is accumulated only when asked.
 //
-// Two kernels share the pair routine:
-//  * resident: one workgroup per slice, the whole slice (and V) in LDS, parallel
-//    round-robin ordering over all columns (p/2 disjoint pairs per round, one
-//    wavefront per pair, 64-lane shuffle reductions).
-//  * team: slices too large for LDS.  Columns are cut into nb blocks of b; a
-//    round-robin tournament over blocks gives nb/2 disjoint block pairs per
-//    step.  W workgroups of a team each hold one block pair in LDS per step,
-//    orthogonalize it (intra-block pairs on the first step of a sweep, then all
-//    b*b cross pairs), write it back, and meet at a team barrier.  The grid is
-//    launched cooperatively, so every workgroup of a team is resident; the
-//    barrier's wait is bounded and reports a timeout instead of hanging.
+// Work decomposition.  A column pair is handled by a group of G lanes (G = 16
+// for m <= 256, 32 above), each lane holding R rows (rows l, l+G, ..., so LDS
+// accesses of a group are contiguous).  The three dot products are reduced
+// inside the group with DPP row operations (plus one lane swizzle for G = 32);
+// a wavefront therefore works on 64/G pairs at once.
+//
+//  * resident kernel: one workgroup per slice, the whole slice (and V) in LDS,
+//    circle-method round robin over all columns (p/2 disjoint pairs per round).
+//  * team kernel: slices too large for LDS.  Columns are cut into nb blocks of
+//    b; a round-robin tournament over blocks gives nb/2 disjoint block pairs
+//    per step.  Each of the W workgroups of a team holds one block pair: the J
+//    block in LDS and, during the b cross rounds, each I column in the
+//    registers of its own lane group (only J columns move through LDS).  The
+//    first step of a sweep also orthogonalizes the pairs inside each block.
+//    Blocks go back to global memory after each step and the team meets at a
+//    barrier.  The grid is launched cooperatively, so every workgroup of a team
+//    is resident; the barrier's wait is bounded and reports a timeout instead
+//    of hanging.
 #include "internal.h"
 
 namespace tsvd {
@@ -29,10 +37,25 @@ template <typename T> struct Unit;
 template <> struct Unit<double> { static constexpr double v = 1.1102230246251565e-16; };  // 2^-53
 template <> struct Unit<float> { static constexpr double v = 5.9604644775390625e-08; };    // 2^-24
 
-__device__ __forceinline__ double wave_sum(double v) {
-    // Butterfly: every lane ends with the same bits (the adds are symmetric).
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+// DPP move of a double (two 32-bit halves).  CTRL: 0xB1 = quad_perm [1,0,3,2],
+// 0x4E = quad_perm [2,3,0,1], 0x141 = row_half_mirror, 0x140 = row_mirror.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over a group of G lanes (G = 16: one DPP row; G = 32: two rows).  Each
+// step adds a value to its mirror image, so every lane of the group ends with
+// the same bits.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    if (G == 32) v += __shfl_xor(v, 16, kWave);
     return v;
 }
 
@@ -51,73 +74,163 @@ __device__ __forceinline__ void rr_pair(int s, int q, int n, int& i, int& j) {
     j = a < b ? b : a;
 }
 
-// Orthogonalize columns x, y (LDS, EPL*64 rows, zero padded) and rotate the V
-// columns vx, vy (vrows rows, 0 = none).  f64 selects FP64 dots and rotation
-// for float data (the refinement sweep).  Returns 1 if a rotation was applied.
-template <typename T, int EPL>
-__device__ __forceinline__ int jpair(T* __restrict__ x, T* __restrict__ y, T* __restrict__ vx,
-                                     T* __restrict__ vy, int vrows, int lane, double tol, bool f64) {
-    T xr[EPL], yr[EPL];
-#pragma unroll
-    for (int q = 0; q < EPL; ++q) {
-        xr[q] = x[lane + kWave * q];
-        yr[q] = y[lane + kWave * q];
-    }
-    double a, b, g;
-    if (sizeof(T) == 8 || f64) {
-        double pa = 0.0, pb = 0.0, pg = 0.0;
-#pragma unroll
-        for (int q = 0; q < EPL; ++q) {
-            double xd = (double)xr[q], yd = (double)yr[q];
-            pa = fma(xd, xd, pa);
-            pb = fma(yd, yd, pb);
-            pg = fma(xd, yd, pg);
-        }
-        a = pa; b = pb; g = pg;
+// Reciprocal and reciprocal square root: hardware estimate plus one Newton
+// step (close to full FP64 precision).
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    return r * fma(-x, r, 2.0);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    return y * fma(-0.5 * x * y, y, 1.5);
+}
+
+// Rotation parameters from the column norms a = |x|^2, b = |y|^2 and the
+// group-reduced g = x.y.  Returns false when the pair is already orthogonal
+// to tol.  The angle may carry a few ulps of error; c and s are computed from
+// the same t with c = 1/sqrt(1 + t^2) to working precision, so the rotation
+// itself is orthogonal.  After it, |x'|^2 = a - t g and |y'|^2 = b + t g.
+__device__ __forceinline__ bool rotation(double a, double b, double g, double tol, double& c, double& s,
+                                         double& t) {
+    if (g == 0.0 || g * g <= (tol * tol) * (a * b)) return false;
+    const double zeta = (b - a) * (0.5 * rcp_nr(g));
+    const double az = fabs(zeta);
+    double tt;
+    if (az < 1e150) {
+        const double w = fma(zeta, zeta, 1.0);
+        const double sq = w * rsq_nr(w);  // sqrt(1 + zeta^2)
+        tt = rcp_nr(az + sq);
     } else {
-        T pa = 0, pb = 0, pg = 0;
-#pragma unroll
-        for (int q = 0; q < EPL; ++q) {
-            pa = fmaf(xr[q], xr[q], pa);
-            pb = fmaf(yr[q], yr[q], pb);
-            pg = fmaf(xr[q], yr[q], pg);
-        }
-        a = (double)pa; b = (double)pb; g = (double)pg;
+        tt = 0.5 * rcp_nr(az);
     }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    g = wave_sum(g);
-    if (g == 0.0 || fabs(g) <= tol * sqrt(a) * sqrt(b)) return 0;
-    const double zeta = (b - a) / (2.0 * g);
-    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-    const double c = 1.0 / sqrt(1.0 + t * t);
-    const double s = c * t;
+    t = zeta >= 0.0 ? tt : -tt;
+    c = rsq_nr(fma(t, t, 1.0));
+    s = c * t;
+    return true;
+}
+
+// Partial inner product of a lane's R rows of x and y (and, when norms is
+// set, the partial squared norms).  FP32 data accumulate their R products in
+// FP32 unless f64 (refinement sweep) asks for FP64.
+template <typename T, int R>
+__device__ __forceinline__ double partial_dot(const T (&x)[R], const T (&y)[R], bool f64) {
+    if (sizeof(T) == 8 || f64) {
+        double pg = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) pg = fma((double)x[q], (double)y[q], pg);
+        return pg;
+    }
+    float pg = 0.f;
+#pragma unroll
+    for (int q = 0; q < R; ++q) pg = fmaf((float)x[q], (float)y[q], pg);
+    return (double)pg;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ double partial_norm(const T (&x)[R]) {
+    double pa = 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) pa = fma((double)x[q], (double)x[q], pa);
+    return pa;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void rotate_regs(T (&x)[R], T (&y)[R], double c, double s, bool f64) {
     if (sizeof(T) == 8 || f64) {
 #pragma unroll
-        for (int q = 0; q < EPL; ++q) {
-            double xd = (double)xr[q], yd = (double)yr[q];
-            x[lane + kWave * q] = (T)(c * xd - s * yd);
-            y[lane + kWave * q] = (T)(s * xd + c * yd);
+        for (int q = 0; q < R; ++q) {
+            const double xd = (double)x[q], yd = (double)y[q];
+            x[q] = (T)(c * xd - s * yd);
+            y[q] = (T)(s * xd + c * yd);
         }
-        for (int r = lane; r < vrows; r += kWave) {
-            double xd = (double)vx[r], yd = (double)vy[r];
+    } else {
+        const T cc = (T)c, ss = (T)s;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const T xd = x[q], yd = y[q];
+            x[q] = cc * xd - ss * yd;
+            y[q] = ss * xd + cc * yd;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void rotate_lds_col(T* vx, T* vy, int n, int gl, int G, double c, double s, bool f64) {
+    if (sizeof(T) == 8 || f64) {
+        for (int r = gl; r < n; r += G) {
+            const double xd = (double)vx[r], yd = (double)vy[r];
             vx[r] = (T)(c * xd - s * yd);
             vy[r] = (T)(s * xd + c * yd);
         }
     } else {
         const T cc = (T)c, ss = (T)s;
-#pragma unroll
-        for (int q = 0; q < EPL; ++q) {
-            x[lane + kWave * q] = cc * xr[q] - ss * yr[q];
-            y[lane + kWave * q] = ss * xr[q] + cc * yr[q];
-        }
-        for (int r = lane; r < vrows; r += kWave) {
-            T xd = vx[r], yd = vy[r];
+        for (int r = gl; r < n; r += G) {
+            const T xd = vx[r], yd = vy[r];
             vx[r] = cc * xd - ss * yd;
             vy[r] = ss * xd + cc * yd;
         }
     }
+}
+
+// Pair with both columns in LDS (rows gl + G q); na, nb are their tracked
+// squared norms (LDS, updated by lane 0 of the group).  Returns 1 if rotated.
+template <typename T, int R, int G>
+__device__ __forceinline__ int gpair_lds(T* __restrict__ x, T* __restrict__ y, double* na, double* nb,
+                                         T* __restrict__ vx, T* __restrict__ vy, int vrows, int gl, double tol,
+                                         bool f64) {
+    T xr[R], yr[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        xr[q] = x[gl + G * q];
+        yr[q] = y[gl + G * q];
+    }
+    const double g = group_sum<G>(partial_dot<T, R>(xr, yr, f64));
+    const double a = *na, b = *nb;
+    double c, s, t;
+    if (!rotation(a, b, g, tol, c, s, t)) return 0;
+    rotate_regs<T, R>(xr, yr, c, s, f64);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        x[gl + G * q] = xr[q];
+        y[gl + G * q] = yr[q];
+    }
+    if (vrows) rotate_lds_col<T>(vx, vy, vrows, gl, G, c, s, f64);
+    if (gl == 0) {
+        *na = a - t * g;
+        *nb = b + t * g;
+    }
     return 1;
+}
+
+// Pair with x in registers (squared norm na, uniform in the group) and y in
+// LDS (squared norm *nb).
+template <typename T, int R, int G>
+__device__ __forceinline__ int gpair_reg(T (&xr)[R], double& na, T* __restrict__ y, double* nb,
+                                         T* __restrict__ vx, T* __restrict__ vy, int vrows, int gl, double tol,
+                                         bool f64) {
+    T yr[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) yr[q] = y[gl + G * q];
+    const double g = group_sum<G>(partial_dot<T, R>(xr, yr, f64));
+    const double a = na, b = *nb;
+    double c, s, t;
+    if (!rotation(a, b, g, tol, c, s, t)) return 0;
+    rotate_regs<T, R>(xr, yr, c, s, f64);
+#pragma unroll
+    for (int q = 0; q < R; ++q) y[gl + G * q] = yr[q];
+    if (vrows) rotate_lds_col<T>(vx, vy, vrows, gl, G, c, s, f64);
+    na = a - t * g;
+    if (gl == 0) *nb = b + t * g;
+    return 1;
+}
+
+// Squared norm of an LDS column (rows gl + G q), reduced over the group.
+template <typename T, int R, int G>
+__device__ __forceinline__ double lds_col_norm(const T* __restrict__ x, int gl) {
+    T xr[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) xr[q] = x[gl + G * q];
+    return group_sum<G>(partial_norm<T, R>(xr));
 }
 
 // Element (r, c) of slice k's tall matrix in the source tensor.
@@ -126,93 +239,123 @@ __device__ __forceinline__ T src_at(const JacobiJob& J, int k, int r, int c) {
     return ((const T*)J.src)[(int64_t)k * J.src_ss + (int64_t)r * J.src_rs + (int64_t)c * J.src_cs];
 }
 
-__device__ __forceinline__ int block_sum_int(int v, int* s_scratch) {
-    // v is per-wave (uniform within a wave); lane 0 of each wave contributes.
+// Sum of one value per lane group (uniform within the group) over the block.
+__device__ __forceinline__ int block_sum_groups(int v, int gl, int* s_scratch) {
     if (threadIdx.x == 0) *s_scratch = 0;
     __syncthreads();
-    if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicAdd(s_scratch, v);
+    if (gl == 0 && v) atomicAdd(s_scratch, v);
     __syncthreads();
-    int tot = *s_scratch;
+    const int tot = *s_scratch;
     __syncthreads();
     return tot;
 }
 
+__device__ __forceinline__ void record_slice(const JacobiJob& J, int k, int sweeps, int executed, Ctrl* ctrl) {
+    J.sweeps[k] = sweeps;
+    if (sweeps < 0) atomicOr(&ctrl->status, kStNoConv);
+    else atomicMax(&ctrl->max_sweeps, sweeps);
+    atomicAdd(&ctrl->slice_sweeps, (unsigned long long)executed);
+}
+
 // ---------------------------------------------------------------------------
-// Resident kernel: one workgroup per (job, slice) task, whole slice in LDS.
-// LDS: pp columns of ldl = 64*EPL rows of A, then (with V) pp columns of p rows.
+// Resident kernel.  LDS: pp columns of ldl = R*G rows of A, then (with V) pp
+// columns of ldv rows (ldv >= p).
 // ---------------------------------------------------------------------------
-template <typename T, int EPL, bool WV>
-__device__ void resident_task(const JacobiJob& J, int k, int max_sweeps, Ctrl* ctrl, T* lds, int* s_scratch) {
-    const int m = J.m, p = J.p;
-    const int ldl = kWave * EPL;
+template <typename T, int R, int G, bool WV>
+__device__ void resident_task(const JacobiJob& J, int k, int max_sweeps, Ctrl* ctrl, T* lds, int* s_scratch,
+                              double* s_nrm) {
+    constexpr int ldl = R * G;
+    const int m = J.m, p = J.p, ldv = J.ldv;
     const int pp = p + (p & 1);
     T* As = lds;
     T* Vs = lds + (int64_t)pp * ldl;
     const int tid = threadIdx.x, nth = blockDim.x;
-    const int wave = tid / kWave, lane = tid % kWave, NW = nth / kWave;
+    const int grp = tid / G, gl = tid % G, ngrp = nth / G;
 
     if (J.src_rs == 1) {
         for (int e = tid; e < pp * ldl; e += nth) {
-            int c = e / ldl, r = e - c * ldl;
+            const int c = e / ldl, r = e - c * ldl;
             As[e] = (c < p && r < m) ? src_at<T>(J, k, r, c) : (T)0;
         }
     } else {  // transposed source: walk columns fastest for contiguous reads
         for (int e = tid; e < pp * ldl; e += nth) {
-            int r = e / pp, c = e - r * pp;
+            const int r = e / pp, c = e - r * pp;
             As[c * ldl + r] = (c < p && r < m) ? src_at<T>(J, k, r, c) : (T)0;
         }
     }
     if (WV)
-        for (int e = tid; e < pp * p; e += nth) {
-            int c = e / p, r = e - c * p;
+        for (int e = tid; e < pp * ldv; e += nth) {
+            const int c = e / ldv, r = e - c * ldv;
             Vs[e] = (r == c) ? (T)1 : (T)0;
         }
     __syncthreads();
 
     const double tol = (double)m * Unit<T>::v;
     int sweeps = -1, executed = 0;
-    bool refine = J.refine64 != 0;
+    const bool refine = J.refine64 != 0;
     for (int sw = 0; sw < max_sweeps + (refine ? 1 : 0); ++sw) {
-        const bool f64 = refine && sw == max_sweeps;  // only reached via the refinement path below
+        const bool f64 = refine && sw == max_sweeps;  // reached only through the refinement path
+        const double tl = f64 ? (double)m * Unit<double>::v : tol;
         int rot = 0;
         ++executed;
+        // exact squared column norms at the start of each sweep, tracked after
+        for (int c = grp; c < p; c += ngrp) {
+            const double nn = lds_col_norm<T, R, G>(As + c * ldl, gl);
+            if (gl == 0) s_nrm[c] = nn;
+        }
+        __syncthreads();
         for (int s = 0; s < pp - 1; ++s) {
-            for (int q = wave; q < pp / 2; q += NW) {
+            for (int q = grp; q < pp / 2; q += ngrp) {
                 int i, j;
                 rr_pair(s, q, pp, i, j);
                 if (j < p)
-                    rot += jpair<T, EPL>(As + i * ldl, As + j * ldl, WV ? Vs + i * p : nullptr,
-                                         WV ? Vs + j * p : nullptr, WV ? p : 0, lane,
-                                         f64 ? (double)m * Unit<double>::v : tol, f64);
+                    rot += gpair_lds<T, R, G>(As + i * ldl, As + j * ldl, s_nrm + i, s_nrm + j,
+                                              WV ? Vs + i * ldv : nullptr, WV ? Vs + j * ldv : nullptr, WV ? p : 0,
+                                              gl, tl, f64);
             }
             __syncthreads();
         }
-        int tot = block_sum_int(rot, s_scratch);
+        const int tot = block_sum_groups(rot, gl, s_scratch);
         if (f64) break;
         if (tot == 0) {
             sweeps = sw + 1;
             if (!refine) break;
-            // one refinement sweep in FP64 arithmetic, then stop
-            sw = max_sweeps - 1;
+            sw = max_sweeps - 1;  // one more sweep, in FP64 arithmetic
         }
     }
-    // write back A (and V)
     T* Ag = (T*)J.A + (int64_t)k * m * p;
     for (int e = tid; e < p * m; e += nth) {
-        int c = e / m, r = e - c * m;
+        const int c = e / m, r = e - c * m;
         Ag[e] = As[c * ldl + r];
     }
     if (WV) {
         T* Vg = (T*)J.V + (int64_t)k * p * p;
-        for (int e = tid; e < p * p; e += nth) Vg[e] = Vs[e];
+        for (int e = tid; e < p * p; e += nth) {
+            const int c = e / p, r = e - c * p;
+            Vg[e] = Vs[c * ldv + r];
+        }
     }
-    if (tid == 0) {
-        J.sweeps[k] = sweeps;
-        if (sweeps < 0) atomicOr(&ctrl->status, kStNoConv);
-        else atomicMax(&ctrl->max_sweeps, sweeps);
-        atomicAdd(&ctrl->slice_sweeps, (unsigned long long)executed);
-    }
+    if (tid == 0) record_slice(J, k, sweeps, executed, ctrl);
 }
+
+#define TSVD_DISPATCH_RG(J, CALL)                          \
+    do {                                                   \
+        if ((J).G == 16) {                                 \
+            switch ((J).R) {                               \
+                case 4: CALL(4, 16); break;                \
+                case 8: CALL(8, 16); break;                \
+                case 12: CALL(12, 16); break;              \
+                default: CALL(16, 16); break;              \
+            }                                              \
+        } else {                                           \
+            switch ((J).R) {                               \
+                case 4: CALL(4, 32); break;                \
+                case 8: CALL(8, 32); break;                \
+                case 12: CALL(12, 32); break;              \
+                default: CALL(16, 32); break;              \
+            }                                              \
+        }                                                  \
+    } while (0)
 
 template <typename T, bool WV>
 __global__ __launch_bounds__(1024) void k_jacobi_resident(const JacobiJob* __restrict__ jobs,
@@ -221,20 +364,14 @@ __global__ __launch_bounds__(1024) void k_jacobi_resident(const JacobiJob* __res
                                                           int max_sweeps, Ctrl* ctrl) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_scratch;
+    __shared__ double s_nrm[kMaxRows];
     T* lds = (T*)smem_raw;
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const JacobiJob& J = jobs[task_job[t]];
         const int k = task_slice[t];
-        switch (J.epl) {
-            case 1: resident_task<T, 1, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch); break;
-            case 2: resident_task<T, 2, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch); break;
-            case 3: resident_task<T, 3, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch); break;
-            case 4: resident_task<T, 4, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch); break;
-            case 5: resident_task<T, 5, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch); break;
-            case 6: resident_task<T, 6, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch); break;
-            case 7: resident_task<T, 7, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch); break;
-            default: resident_task<T, 8, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch); break;
-        }
+#define TSVD_RES_CALL(RR, GG) resident_task<T, RR, GG, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch, s_nrm)
+        TSVD_DISPATCH_RG(J, TSVD_RES_CALL);
+#undef TSVD_RES_CALL
         __syncthreads();
     }
 }
@@ -250,94 +387,123 @@ struct TeamState {
     Ctrl* ctrl;
 };
 
-// Returns false when the wait gave up (the caller then abandons the launch).
+// XCD (accelerator complex die) of the executing workgroup: hardware register
+// XCC_ID, read with s_getreg_b32 (id 20, bits [3:0]).
+__device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg((15 << 11) | 20) & 0xF; }
+
+// Team barrier.  Each wavefront first waits for its own global stores to be
+// acknowledged (vmcnt(0)); then one lane per workgroup performs a device-scope
+// release, arrives on the team counter, waits for the team with a bounded
+// spin, and performs a device-scope acquire (which invalidates the CU's L1)
+// before the workgroup proceeds.  Teams are formed on one XCD, so the blocks
+// they exchange stay in that XCD's L2.  Returns false when the wait gave up.
 __device__ bool team_barrier(TeamState& ts, int* s_flag) {
-    __threadfence();  // release this thread's global writes at device scope
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's stores are complete
     __syncthreads();
     ts.passed += 1;
     if (threadIdx.x == 0) {
         *s_flag = 0;
         if (ts.W > 1) {
-            __hip_atomic_fetch_add(ts.bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(ts.bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const int target = ts.passed * ts.W;
             int it = 0;
-            while (__hip_atomic_load(ts.bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            while (__hip_atomic_load(ts.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 if (++it > ts.spin_limit) {
                     atomicOr(&ts.ctrl->status, kStTimeout);
                     *s_flag = 1;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(1);
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const bool ok = (*s_flag == 0);
     __syncthreads();
     return ok;
 }
 
-template <typename T, int EPL, bool WV>
+// Load b columns of block `blk` into LDS (ld ldl); from the source tensor on
+// the first step of the first sweep, else from A.  Zero padding beyond m / p.
+template <typename T, int R, int G, bool WV>
 __device__ __forceinline__ void team_load_block(const JacobiJob& J, int k, int blk, bool first, T* As, T* Vs) {
-    const int m = J.m, p = J.p, b = J.b, ldl = kWave * EPL;
+    constexpr int ldl = R * G;
+    const int m = J.m, p = J.p, b = J.b, ldv = J.ldv;
     const int tid = threadIdx.x, nth = blockDim.x;
     const T* Ag = (const T*)J.A + (int64_t)k * m * p;
     if (first && J.src_rs != 1) {
         for (int e = tid; e < b * ldl; e += nth) {
-            int r = e / b, cl = e - r * b, c = blk * b + cl;
+            const int r = e / b, cl = e - r * b, c = blk * b + cl;
             As[cl * ldl + r] = (c < p && r < m) ? src_at<T>(J, k, r, c) : (T)0;
         }
     } else {
-        for (int e = tid; e < b * ldl; e += nth) {
-            int cl = e / ldl, r = e - cl * ldl, c = blk * b + cl;
-            T v = (T)0;
-            if (c < p && r < m) v = first ? src_at<T>(J, k, r, c) : Ag[(int64_t)c * m + r];
-            As[e] = v;
+        // eight independent loads in flight per lane before the LDS stores
+        constexpr int U = 8;
+        const int total = b * ldl;
+        for (int e0 = tid; e0 < total; e0 += nth * U) {
+            T v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * nth;
+                const int cl = e / ldl, r = e - cl * ldl, c = blk * b + cl;
+                v[u] = (T)0;
+                if (e < total && c < p && r < m) v[u] = first ? src_at<T>(J, k, r, c) : Ag[(int64_t)c * m + r];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * nth;
+                if (e < total) As[e] = v[u];
+            }
         }
     }
     if (WV) {
         const T* Vg = (const T*)J.V + (int64_t)k * p * p;
-        for (int e = tid; e < b * p; e += nth) {
-            int cl = e / p, r = e - cl * p, c = blk * b + cl;
+        for (int e = tid; e < b * ldv; e += nth) {
+            const int cl = e / ldv, r = e - cl * ldv, c = blk * b + cl;
             T v = (T)0;
-            if (c < p) v = first ? (T)(r == c ? 1 : 0) : Vg[(int64_t)c * p + r];
+            if (c < p && r < p) v = first ? (T)(r == c ? 1 : 0) : Vg[(int64_t)c * p + r];
             Vs[e] = v;
         }
     }
 }
 
-template <typename T, int EPL, bool WV>
+template <typename T, int R, int G, bool WV>
 __device__ __forceinline__ void team_store_block(const JacobiJob& J, int k, int blk, const T* As, const T* Vs) {
-    const int m = J.m, p = J.p, b = J.b, ldl = kWave * EPL;
+    constexpr int ldl = R * G;
+    const int m = J.m, p = J.p, b = J.b, ldv = J.ldv;
     const int tid = threadIdx.x, nth = blockDim.x;
     T* Ag = (T*)J.A + (int64_t)k * m * p;
     for (int e = tid; e < b * m; e += nth) {
-        int cl = e / m, r = e - cl * m, c = blk * b + cl;
+        const int cl = e / m, r = e - cl * m, c = blk * b + cl;
         if (c < p) Ag[(int64_t)c * m + r] = As[cl * ldl + r];
     }
     if (WV) {
         T* Vg = (T*)J.V + (int64_t)k * p * p;
         for (int e = tid; e < b * p; e += nth) {
-            int cl = e / p, r = e - cl * p, c = blk * b + cl;
-            if (c < p) Vg[(int64_t)c * p + r] = Vs[e];
+            const int cl = e / p, r = e - cl * p, c = blk * b + cl;
+            if (c < p) Vg[(int64_t)c * p + r] = Vs[cl * ldv + r];
         }
     }
 }
 
-// Returns false if a barrier timed out.
-template <typename T, int EPL, bool WV>
+// One slice by one team.  Returns false if a barrier timed out.
+template <typename T, int R, int G, bool WV>
 __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, int max_sweeps, T* lds,
-                          int* s_scratch, int* s_flag) {
-    const int m = J.m, p = J.p, b = J.b, nb = J.nb, ldl = kWave * EPL;
-    const int tid = threadIdx.x;
-    const int wave = tid / kWave, lane = tid % kWave, NW = blockDim.x / kWave;
-    T* As = lds;                            // 2b columns x ldl
-    T* Vs = lds + (int64_t)2 * b * ldl;     // 2b columns x p
+                          int* s_scratch, int* s_flag, double* nI, double* nJ) {
+    constexpr int ldl = R * G;
+    const int m = J.m, p = J.p, b = J.b, nb = J.nb, ldv = J.ldv;
+    const int tid = threadIdx.x, grp = tid / G, gl = tid % G;  // one lane group per I column (b groups)
+    T* Is = lds;                           // b columns x ldl (first step of a sweep)
+    T* Js = lds + (int64_t)b * ldl;        // b columns x ldl
+    T* Vi = lds + (int64_t)2 * b * ldl;    // b columns x ldv
+    T* Vj = Vi + (int64_t)b * ldv;         // b columns x ldv
     const double tol = (double)m * Unit<T>::v;
     const bool refine = J.refine64 != 0;
     int sweeps = -1, executed = 0;
     int* rot_g = J.rot + (int64_t)k * kMaxSweeps;
+    T* Ag = (T*)J.A + (int64_t)k * m * p;
     for (int sw = 0; sw < max_sweeps + (refine ? 1 : 0); ++sw) {
         const bool f64 = refine && sw == max_sweeps;
         const double tl = f64 ? (double)m * Unit<double>::v : tol;
@@ -348,43 +514,75 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                 int BI, BJ;
                 rr_pair(s, q, nb, BI, BJ);
                 const bool first = (sw == 0 && s == 0);
-                team_load_block<T, EPL, WV>(J, k, BI, first, As, Vs);
-                team_load_block<T, EPL, WV>(J, k, BJ, first, As + b * ldl, Vs + b * p);
+                const int ci = BI * b + grp;  // this group's I column
+                T xr[R];
+                double na;
+                team_load_block<T, R, G, WV>(J, k, BJ, first, Js, Vj);
+                if (s == 0 || WV) team_load_block<T, R, G, WV>(J, k, BI, first, Is, Vi);
+                __syncthreads();
+                {
+                    const double nn = lds_col_norm<T, R, G>(Js + grp * ldl, gl);
+                    if (gl == 0) nJ[grp] = nn;
+                    if (s == 0) {
+                        const double ni = lds_col_norm<T, R, G>(Is + grp * ldl, gl);
+                        if (gl == 0) nI[grp] = ni;
+                    }
+                }
                 __syncthreads();
                 if (s == 0) {
-                    // intra-block pairs of both blocks: b-1 rounds of b pairs
+                    // pairs inside each block: b-1 rounds, b/2 pairs per block per round
                     for (int r = 0; r < b - 1; ++r) {
-                        for (int q2 = wave; q2 < b; q2 += NW) {
-                            const int half = q2 < b / 2 ? 0 : 1;
-                            int i, j;
-                            rr_pair(r, q2 - half * (b / 2), b, i, j);
-                            const int blk = half ? BJ : BI;
-                            if (blk * b + j < p) {
-                                const int off = half * b;
-                                rot += jpair<T, EPL>(As + (off + i) * ldl, As + (off + j) * ldl,
-                                                     WV ? Vs + (off + i) * p : nullptr,
-                                                     WV ? Vs + (off + j) * p : nullptr, WV ? p : 0, lane, tl, f64);
-                            }
-                        }
+                        const int half = grp < b / 2 ? 0 : 1;
+                        int i, j;
+                        rr_pair(r, grp - half * (b / 2), b, i, j);
+                        const int blk = half ? BJ : BI;
+                        T* base = half ? Js : Is;
+                        T* vb = half ? Vj : Vi;
+                        double* nb_ = half ? nJ : nI;
+                        if (blk * b + j < p)
+                            rot += gpair_lds<T, R, G>(base + i * ldl, base + j * ldl, nb_ + i, nb_ + j,
+                                                      WV ? vb + i * ldv : nullptr, WV ? vb + j * ldv : nullptr,
+                                                      WV ? p : 0, gl, tl, f64);
                         __syncthreads();
                     }
-                }
-                // cross pairs: b rounds of b disjoint pairs (I[i], J[(i + r) % b])
-                for (int r = 0; r < b; ++r) {
-                    for (int i = wave; i < b; i += NW) {
-                        const int j = (i + r) % b;
-                        if (BI * b + i < p && BJ * b + j < p)
-                            rot += jpair<T, EPL>(As + i * ldl, As + (b + j) * ldl, WV ? Vs + i * p : nullptr,
-                                                 WV ? Vs + (b + j) * p : nullptr, WV ? p : 0, lane, tl, f64);
+#pragma unroll
+                    for (int q2 = 0; q2 < R; ++q2) xr[q2] = Is[grp * ldl + gl + G * q2];
+                    na = nI[grp];
+                } else {
+#pragma unroll
+                    for (int q2 = 0; q2 < R; ++q2) {
+                        const int r = gl + G * q2;
+                        xr[q2] = (ci < p && r < m) ? Ag[(int64_t)ci * m + r] : (T)0;
                     }
+                    na = group_sum<G>(partial_norm<T, R>(xr));
+                }
+                // cross pairs: b rounds, group g pairs I[g] with J[(g + r) % b]
+                for (int r = 0; r < b; ++r) {
+                    const int j = (grp + r) % b;
+                    if (ci < p && BJ * b + j < p)
+                        rot += gpair_reg<T, R, G>(xr, na, Js + j * ldl, nJ + j, WV ? Vi + grp * ldv : nullptr,
+                                                  WV ? Vj + j * ldv : nullptr, WV ? p : 0, gl, tl, f64);
                     __syncthreads();
                 }
-                team_store_block<T, EPL, WV>(J, k, BI, As, Vs);
-                team_store_block<T, EPL, WV>(J, k, BJ, As + b * ldl, Vs + b * p);
+                if (ci < p) {
+#pragma unroll
+                    for (int q2 = 0; q2 < R; ++q2) {
+                        const int r = gl + G * q2;
+                        if (r < m) Ag[(int64_t)ci * m + r] = xr[q2];
+                    }
+                }
+                team_store_block<T, R, G, WV>(J, k, BJ, Js, Vj);
+                if (WV) {
+                    T* Vg = (T*)J.V + (int64_t)k * p * p;
+                    for (int e = tid; e < b * p; e += blockDim.x) {
+                        const int cl = e / p, rr = e - cl * p, c = BI * b + cl;
+                        if (c < p) Vg[(int64_t)c * p + rr] = Vi[cl * ldv + rr];
+                    }
+                }
                 __syncthreads();
             }
             if (s == nb - 2) {
-                int tot = block_sum_int(rot, s_scratch);
+                const int tot = block_sum_groups(rot, gl, s_scratch);
                 if (tid == 0 && tot) atomicAdd(rot_g + sw, tot);
             }
             if (!team_barrier(ts, s_flag)) return false;
@@ -397,43 +595,63 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
             sw = max_sweeps - 1;
         }
     }
-    if (tid == 0 && rank == 0) {
-        J.sweeps[k] = sweeps;
-        if (sweeps < 0) atomicOr(&ts.ctrl->status, kStNoConv);
-        else atomicMax(&ts.ctrl->max_sweeps, sweeps);
-        atomicAdd(&ts.ctrl->slice_sweeps, (unsigned long long)executed);
-    }
+    if (tid == 0 && rank == 0) record_slice(J, k, sweeps, executed, ts.ctrl);
     return true;
 }
 
-template <typename T, bool WV>
-__global__ __launch_bounds__(1024) void k_jacobi_team(const JacobiJob* __restrict__ jobs,
-                                                      const int* __restrict__ task_job,
-                                                      const int* __restrict__ task_slice, int ntasks,
-                                                      TeamSched sched, int max_sweeps, Ctrl* ctrl,
-                                                      int spin_limit) {
+// Team formation: every workgroup takes a slot on its own XCD; once all have
+// arrived, slots [W t, W t + W) of an XCD form team t there, and a workgroup
+// left over on an XCD without a full team exits.  Teams are numbered across
+// XCDs and take slices t, t + nteams, ...  ctl layout (ints, zeroed before the
+// launch): [0, 16) slot counter per XCD, [16] arrivals, [32 + i] barrier of
+// team i.
+template <typename T, bool WV, int R, int G>
+__global__ __launch_bounds__(512) void k_jacobi_team(const JacobiJob* __restrict__ jobs,
+                                                     const int* __restrict__ task_job,
+                                                     const int* __restrict__ task_slice, int ntasks,
+                                                     TeamSched sched, int max_sweeps, Ctrl* ctrl,
+                                                     int spin_limit) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int s_scratch, s_flag;
+    __shared__ int s_scratch, s_flag, s_team, s_rank, s_nteams;
+    __shared__ double s_nI[kTeamMaxThreads / 16], s_nJ[kTeamMaxThreads / 16];
     T* lds = (T*)smem_raw;
     const int W = sched.W;
-    const int team = blockIdx.x / W, rank = blockIdx.x % W;
-    if (team >= sched.nteams) return;
-    TeamState ts{sched.bar + team, 0, W, spin_limit, ctrl};
-    for (int t = team; t < ntasks; t += sched.nteams) {
+    int* ctl = sched.ctl;
+    if (threadIdx.x == 0) {
+        const int x = xcc_id();
+        const int slot = __hip_atomic_fetch_add(ctl + x, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(ctl + 16, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int it = 0;
+        bool ok = true;
+        while (__hip_atomic_load(ctl + 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (int)gridDim.x) {
+            if (++it > spin_limit) {
+                atomicOr(&ctrl->status, kStTimeout);
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        int before = 0, total = 0;
+        for (int xx = 0; xx < 16; ++xx) {
+            const int full = __hip_atomic_load(ctl + xx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / W;
+            if (xx < x) before += full;
+            total += full;
+        }
+        const int local = slot / W;
+        const int full_here = __hip_atomic_load(ctl + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / W;
+        s_team = (ok && local < full_here) ? before + local : -1;
+        s_rank = slot % W;
+        s_nteams = total;
+        if (ok && total == 0 && blockIdx.x == 0) atomicOr(&ctrl->status, kStTimeout);
+    }
+    __syncthreads();
+    const int team = s_team, rank = s_rank, nteams = s_nteams;
+    if (team < 0) return;
+    TeamState ts{ctl + 32 + team, 0, W, spin_limit, ctrl};
+    for (int t = team; t < ntasks; t += nteams) {
         const JacobiJob& J = jobs[task_job[t]];
         const int k = task_slice[t];
-        bool ok;
-        switch (J.epl) {
-            case 1: ok = team_task<T, 1, WV>(J, k, rank, ts, max_sweeps, lds, &s_scratch, &s_flag); break;
-            case 2: ok = team_task<T, 2, WV>(J, k, rank, ts, max_sweeps, lds, &s_scratch, &s_flag); break;
-            case 3: ok = team_task<T, 3, WV>(J, k, rank, ts, max_sweeps, lds, &s_scratch, &s_flag); break;
-            case 4: ok = team_task<T, 4, WV>(J, k, rank, ts, max_sweeps, lds, &s_scratch, &s_flag); break;
-            case 5: ok = team_task<T, 5, WV>(J, k, rank, ts, max_sweeps, lds, &s_scratch, &s_flag); break;
-            case 6: ok = team_task<T, 6, WV>(J, k, rank, ts, max_sweeps, lds, &s_scratch, &s_flag); break;
-            case 7: ok = team_task<T, 7, WV>(J, k, rank, ts, max_sweeps, lds, &s_scratch, &s_flag); break;
-            default: ok = team_task<T, 8, WV>(J, k, rank, ts, max_sweeps, lds, &s_scratch, &s_flag); break;
-        }
-        if (!ok) return;
+        if (!team_task<T, R, G, WV>(J, k, rank, ts, max_sweeps, lds, &s_scratch, &s_flag, s_nI, s_nJ)) return;
     }
 }
 
@@ -442,94 +660,101 @@ __global__ __launch_bounds__(1024) void k_jacobi_team(const JacobiJob* __restric
 // ---------------------------------------------------------------------------
 static int elem_size(int prec) { return prec == 0 ? 8 : 4; }
 
+void jacobi_geometry(int m, int p, int* G, int* R, int* ldv) {
+    *G = m <= 256 ? 16 : 32;
+    int r = (m + *G - 1) / *G;
+    r = (r + 3) / 4 * 4;
+    if (r < 4) r = 4;
+    *R = r;
+    *ldv = ((p + *G - 1) / *G) * *G;
+}
+
 int jacobi_resident_lds_bytes(int prec, int m, int p, int with_v) {
-    const int epl = (m + kWave - 1) / kWave;
+    int G, R, ldv;
+    jacobi_geometry(m, p, &G, &R, &ldv);
     const int pp = p + (p & 1);
-    int64_t elems = (int64_t)pp * epl * kWave + (with_v ? (int64_t)pp * p : 0);
+    const int64_t elems = (int64_t)pp * R * G + (with_v ? (int64_t)pp * ldv : 0);
     return (int)(elems * elem_size(prec));
 }
 
 int jacobi_team_lds_bytes(int prec, int m, int p, int b, int with_v) {
-    const int epl = (m + kWave - 1) / kWave;
-    int64_t elems = (int64_t)2 * b * epl * kWave + (with_v ? (int64_t)2 * b * p : 0);
+    int G, R, ldv;
+    jacobi_geometry(m, p, &G, &R, &ldv);
+    const int64_t elems = (int64_t)2 * b * R * G + (with_v ? (int64_t)2 * b * ldv : 0);
     return (int)(elems * elem_size(prec));
 }
 
 template <typename T, bool WV>
-static hipError_t set_lds_attr_team(int lds) {
-    return hipFuncSetAttribute((const void*)k_jacobi_team<T, WV>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+static const void* team_fn_rg(int R, int G) {
+    if (G == 16) {
+        switch (R) {
+            case 4: return (const void*)k_jacobi_team<T, WV, 4, 16>;
+            case 8: return (const void*)k_jacobi_team<T, WV, 8, 16>;
+            case 12: return (const void*)k_jacobi_team<T, WV, 12, 16>;
+            default: return (const void*)k_jacobi_team<T, WV, 16, 16>;
+        }
+    }
+    switch (R) {
+        case 4: return (const void*)k_jacobi_team<T, WV, 4, 32>;
+        case 8: return (const void*)k_jacobi_team<T, WV, 8, 32>;
+        case 12: return (const void*)k_jacobi_team<T, WV, 12, 32>;
+        default: return (const void*)k_jacobi_team<T, WV, 16, 32>;
+    }
+}
+static const void* team_fn(int prec, int with_v, int R, int G) {
+    return prec == 0 ? (with_v ? team_fn_rg<double, true>(R, G) : team_fn_rg<double, false>(R, G))
+                     : (with_v ? team_fn_rg<float, true>(R, G) : team_fn_rg<float, false>(R, G));
 }
 template <typename T, bool WV>
-static hipError_t set_lds_attr_res(int lds) {
-    return hipFuncSetAttribute((const void*)k_jacobi_resident<T, WV>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               lds);
-}
+static const void* res_fn() { return (const void*)k_jacobi_resident<T, WV>; }
 
 hipError_t launch_jacobi_resident(int prec, const JacobiJob* jobs_dev, int njobs, const int* task_job,
                                   const int* task_slice, int ntasks, int max_sweeps, Ctrl* ctrl, int lds_bytes,
                                   int threads, int with_v, hipStream_t s) {
     (void)njobs;
     if (ntasks <= 0) return hipSuccess;
+    const void* f = prec == 0 ? (with_v ? res_fn<double, true>() : res_fn<double, false>())
+                              : (with_v ? res_fn<float, true>() : res_fn<float, false>());
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
     dim3 grid(ntasks), block(threads);
-    hipError_t e;
     if (prec == 0) {
-        if (with_v) {
-            if ((e = set_lds_attr_res<double, true>(lds_bytes)) != hipSuccess) return e;
+        if (with_v)
             hipLaunchKernelGGL((k_jacobi_resident<double, true>), grid, block, lds_bytes, s, jobs_dev, task_job,
                                task_slice, ntasks, max_sweeps, ctrl);
-        } else {
-            if ((e = set_lds_attr_res<double, false>(lds_bytes)) != hipSuccess) return e;
+        else
             hipLaunchKernelGGL((k_jacobi_resident<double, false>), grid, block, lds_bytes, s, jobs_dev, task_job,
                                task_slice, ntasks, max_sweeps, ctrl);
-        }
     } else {
-        if (with_v) {
-            if ((e = set_lds_attr_res<float, true>(lds_bytes)) != hipSuccess) return e;
+        if (with_v)
             hipLaunchKernelGGL((k_jacobi_resident<float, true>), grid, block, lds_bytes, s, jobs_dev, task_job,
                                task_slice, ntasks, max_sweeps, ctrl);
-        } else {
-            if ((e = set_lds_attr_res<float, false>(lds_bytes)) != hipSuccess) return e;
+        else
             hipLaunchKernelGGL((k_jacobi_resident<float, false>), grid, block, lds_bytes, s, jobs_dev, task_job,
                                task_slice, ntasks, max_sweeps, ctrl);
-        }
     }
     return hipGetLastError();
 }
 
-template <typename T, bool WV>
-static hipError_t coop_team(const JacobiJob* jobs_dev, const int* task_job, const int* task_slice, int ntasks,
-                            TeamSched ts, int max_sweeps, Ctrl* ctrl, int lds, int threads, int spin_limit,
-                            hipStream_t s) {
-    hipError_t e = set_lds_attr_team<T, WV>(lds);
-    if (e != hipSuccess) return e;
-    void* args[] = {(void*)&jobs_dev, (void*)&task_job, (void*)&task_slice, (void*)&ntasks,
-                    (void*)&ts,       (void*)&max_sweeps, (void*)&ctrl,     (void*)&spin_limit};
-    dim3 grid(ts.nteams * ts.W), block(threads);
-    return hipLaunchCooperativeKernel((const void*)k_jacobi_team<T, WV>, grid, block, args, (unsigned)lds, s);
-}
-
 hipError_t launch_jacobi_team(int prec, const JacobiJob* jobs_dev, int njobs, const int* task_job,
-                              const int* task_slice, int ntasks, const TeamSched& ts, int max_sweeps, Ctrl* ctrl,
-                              int lds_bytes, int threads, int with_v, int spin_limit, hipStream_t s) {
+                              const int* task_slice, int ntasks, const TeamSched& ts_in, int max_sweeps, Ctrl* ctrl,
+                              int lds_bytes, int threads, int with_v, int spin_limit, int R, int G, hipStream_t s) {
     (void)njobs;
     if (ntasks <= 0) return hipSuccess;
-    if (prec == 0)
-        return with_v ? coop_team<double, true>(jobs_dev, task_job, task_slice, ntasks, ts, max_sweeps, ctrl,
-                                                lds_bytes, threads, spin_limit, s)
-                      : coop_team<double, false>(jobs_dev, task_job, task_slice, ntasks, ts, max_sweeps, ctrl,
-                                                 lds_bytes, threads, spin_limit, s);
-    return with_v ? coop_team<float, true>(jobs_dev, task_job, task_slice, ntasks, ts, max_sweeps, ctrl, lds_bytes,
-                                           threads, spin_limit, s)
-                  : coop_team<float, false>(jobs_dev, task_job, task_slice, ntasks, ts, max_sweeps, ctrl, lds_bytes,
-                                            threads, spin_limit, s);
+    const void* f = team_fn(prec, with_v, R, G);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+    TeamSched ts = ts_in;
+    void* args[] = {(void*)&jobs_dev, (void*)&task_job, (void*)&task_slice, (void*)&ntasks,
+                    (void*)&ts,       (void*)&max_sweeps, (void*)&ctrl,     (void*)&spin_limit};
+    dim3 grid(ts.nwg), block(threads);
+    return hipLaunchCooperativeKernel(f, grid, block, args, (unsigned)lds_bytes, s);
 }
 
-int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v) {
+int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v, int R, int G) {
     int nb = 0;
-    hipError_t e;
-    const void* f = prec == 0 ? (with_v ? (const void*)k_jacobi_team<double, true> : (const void*)k_jacobi_team<double, false>)
-                              : (with_v ? (const void*)k_jacobi_team<float, true> : (const void*)k_jacobi_team<float, false>);
-    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    const void* f = team_fn(prec, with_v, R, G);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();  // do not leave a sticky error for the caller's runtime
         return 0;

@@ -298,11 +298,14 @@ __global__ __launch_bounds__(256) void k_tsvd_finish(TsvdFinishArgs a) {
     for (int c = wave; c < p; c += 4) {
         const double sc = s_sig[c];
         const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
-        // argmax |A(:,c)| with the first index on ties
+        // the slice's left singular vector is A(:,c) (tall) or V(:,c) (wide):
+        // argmax of its magnitudes, first index on ties, decides the sign
+        const T* L = a.sign_from_v ? Vj + (int64_t)c * p : A + (int64_t)c * m;
+        const int nl = a.sign_from_v ? p : m;
         double best = -1.0;
         int bi = 0x7fffffff;
-        for (int r = lane; r < m; r += kWave) {
-            const double v = fabs((double)A[(int64_t)c * m + r]);
+        for (int r = lane; r < nl; r += kWave) {
+            const double v = fabs((double)L[r]);
             if (v > best) { best = v; bi = r; }
         }
 #pragma unroll
@@ -311,7 +314,7 @@ __global__ __launch_bounds__(256) void k_tsvd_finish(TsvdFinishArgs a) {
             const int oi = __shfl_xor(bi, o, kWave);
             if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
         }
-        const double sgn = (bi < m && (double)A[(int64_t)c * m + bi] < 0.0) ? -1.0 : 1.0;
+        const double sgn = (bi < nl && (double)L[bi] < 0.0) ? -1.0 : 1.0;
         const int pos = s_pos[c];
         for (int r = lane; r < m; r += kWave) U[(int64_t)pos * m + r] = (T)(sgn * inv * (double)A[(int64_t)c * m + r]);
         for (int r = lane; r < p; r += kWave) V[(int64_t)pos * p + r] = (T)(sgn * (double)Vj[(int64_t)c * p + r]);
