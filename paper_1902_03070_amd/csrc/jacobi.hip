@@ -87,23 +87,23 @@ __device__ __forceinline__ double rsq_nr(double x) {
 
 // Rotation parameters from the column norms a = |x|^2, b = |y|^2 and the
 // group-reduced g = x.y.  Returns false when the pair is already orthogonal
-// to tol.  The angle may carry a few ulps of error; c and s are computed from
-// the same t with c = 1/sqrt(1 + t^2) to working precision, so the rotation
-// itself is orthogonal.  After it, |x'|^2 = a - t g and |y'|^2 = b + t g.
+// to tol.  With d = b - a the tangent
+//     t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),  zeta = d / (2 g),
+// is evaluated as t = sgn(zeta) |2g| / (|d| + sqrt(d^2 + 4 g^2)) (multiply
+// through by |2g|; sgn(0) = +1), which needs one reciprocal instead of two.
+// The angle may carry a few ulps of error; c and s are computed from the same
+// t with c = 1/sqrt(1 + t^2) to working precision, so the rotation itself is
+// orthogonal.  After it, |x'|^2 = a - t g and |y'|^2 = b + t g.
 __device__ __forceinline__ bool rotation(double a, double b, double g, double tol, double& c, double& s,
                                          double& t) {
-    if (g == 0.0 || g * g <= (tol * tol) * (a * b)) return false;
-    const double zeta = (b - a) * (0.5 * rcp_nr(g));
-    const double az = fabs(zeta);
-    double tt;
-    if (az < 1e150) {
-        const double w = fma(zeta, zeta, 1.0);
-        const double sq = w * rsq_nr(w);  // sqrt(1 + zeta^2)
-        tt = rcp_nr(az + sq);
-    } else {
-        tt = 0.5 * rcp_nr(az);
-    }
-    t = zeta >= 0.0 ? tt : -tt;
+    const double g2 = g * g;
+    if (g == 0.0 || g2 <= (tol * tol) * (a * b)) return false;
+    const double d = b - a;
+    const double w = fma(d, d, 4.0 * g2);
+    const double den = fabs(d) + w * rsq_nr(w);
+    const double ag2 = 2.0 * fabs(g);
+    // sgn(zeta) = + exactly when d g >= 0 (d = 0 gives +0 or -0, both >= 0): a select, no branch
+    t = (d * g >= 0.0 ? ag2 : -ag2) * rcp_nr(den);
     c = rsq_nr(fma(t, t, 1.0));
     s = c * t;
     return true;
@@ -114,16 +114,27 @@ __device__ __forceinline__ bool rotation(double a, double b, double g, double to
 // FP32 unless f64 (refinement sweep) asks for FP64.
 template <typename T, int R>
 __device__ __forceinline__ double partial_dot(const T (&x)[R], const T (&y)[R], bool f64) {
+    // four independent accumulators shorten the dependency chain
     if (sizeof(T) == 8 || f64) {
-        double pg = 0.0;
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
 #pragma unroll
-        for (int q = 0; q < R; ++q) pg = fma((double)x[q], (double)y[q], pg);
-        return pg;
+        for (int q = 0; q < R; q += 4) {
+            p0 = fma((double)x[q], (double)y[q], p0);
+            p1 = fma((double)x[q + 1], (double)y[q + 1], p1);
+            p2 = fma((double)x[q + 2], (double)y[q + 2], p2);
+            p3 = fma((double)x[q + 3], (double)y[q + 3], p3);
+        }
+        return (p0 + p1) + (p2 + p3);
     }
-    float pg = 0.f;
+    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
 #pragma unroll
-    for (int q = 0; q < R; ++q) pg = fmaf((float)x[q], (float)y[q], pg);
-    return (double)pg;
+    for (int q = 0; q < R; q += 4) {
+        p0 = fmaf((float)x[q], (float)y[q], p0);
+        p1 = fmaf((float)x[q + 1], (float)y[q + 1], p1);
+        p2 = fmaf((float)x[q + 2], (float)y[q + 2], p2);
+        p3 = fmaf((float)x[q + 3], (float)y[q + 3], p3);
+    }
+    return (double)((p0 + p1) + (p2 + p3));
 }
 
 template <typename T, int R>
@@ -184,8 +195,8 @@ __device__ __forceinline__ int gpair_lds(T* __restrict__ x, T* __restrict__ y, d
         xr[q] = x[gl + G * q];
         yr[q] = y[gl + G * q];
     }
-    const double g = group_sum<G>(partial_dot<T, R>(xr, yr, f64));
     const double a = *na, b = *nb;
+    const double g = group_sum<G>(partial_dot<T, R>(xr, yr, f64));
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
     rotate_regs<T, R>(xr, yr, c, s, f64);
@@ -208,11 +219,12 @@ template <typename T, int R, int G>
 __device__ __forceinline__ int gpair_reg(T (&xr)[R], double& na, T* __restrict__ y, double* nb,
                                          T* __restrict__ vx, T* __restrict__ vy, int vrows, int gl, double tol,
                                          bool f64) {
+    const double b = *nb;
     T yr[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) yr[q] = y[gl + G * q];
+    const double a = na;
     const double g = group_sum<G>(partial_dot<T, R>(xr, yr, f64));
-    const double a = na, b = *nb;
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
     rotate_regs<T, R>(xr, yr, c, s, f64);
@@ -264,7 +276,7 @@ __device__ __forceinline__ void record_slice(const JacobiJob& J, int k, int swee
 template <typename T, int R, int G, bool WV>
 __device__ void resident_task(const JacobiJob& J, int k, int max_sweeps, Ctrl* ctrl, T* lds, int* s_scratch,
                               double* s_nrm) {
-    constexpr int ldl = R * G;
+    constexpr int ldl = R * G + kLdsPad;
     const int m = J.m, p = J.p, ldv = J.ldv;
     const int pp = p + (p & 1);
     T* As = lds;
@@ -429,7 +441,7 @@ __device__ bool team_barrier(TeamState& ts, int* s_flag) {
 // the first step of the first sweep, else from A.  Zero padding beyond m / p.
 template <typename T, int R, int G, bool WV>
 __device__ __forceinline__ void team_load_block(const JacobiJob& J, int k, int blk, bool first, T* As, T* Vs) {
-    constexpr int ldl = R * G;
+    constexpr int ldl = R * G + kLdsPad;
     const int m = J.m, p = J.p, b = J.b, ldv = J.ldv;
     const int tid = threadIdx.x, nth = blockDim.x;
     const T* Ag = (const T*)J.A + (int64_t)k * m * p;
@@ -471,13 +483,26 @@ __device__ __forceinline__ void team_load_block(const JacobiJob& J, int k, int b
 
 template <typename T, int R, int G, bool WV>
 __device__ __forceinline__ void team_store_block(const JacobiJob& J, int k, int blk, const T* As, const T* Vs) {
-    constexpr int ldl = R * G;
+    constexpr int ldl = R * G + kLdsPad;
     const int m = J.m, p = J.p, b = J.b, ldv = J.ldv;
     const int tid = threadIdx.x, nth = blockDim.x;
     T* Ag = (T*)J.A + (int64_t)k * m * p;
-    for (int e = tid; e < b * m; e += nth) {
-        const int cl = e / m, r = e - cl * m, c = blk * b + cl;
-        if (c < p) Ag[(int64_t)c * m + r] = As[cl * ldl + r];
+    constexpr int U = 8;  // eight LDS reads in flight before the global stores
+    const int total = b * m;
+    for (int e0 = tid; e0 < total; e0 += nth * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * nth;
+            const int cl = e / m, r = e - cl * m;
+            v[u] = e < total ? As[cl * ldl + r] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * nth;
+            const int cl = e / m, r = e - cl * m, c = blk * b + cl;
+            if (e < total && c < p) Ag[(int64_t)c * m + r] = v[u];
+        }
     }
     if (WV) {
         T* Vg = (T*)J.V + (int64_t)k * p * p;
@@ -492,7 +517,7 @@ __device__ __forceinline__ void team_store_block(const JacobiJob& J, int k, int 
 template <typename T, int R, int G, bool WV>
 __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, int max_sweeps, T* lds,
                           int* s_scratch, int* s_flag, double* nI, double* nJ) {
-    constexpr int ldl = R * G;
+    constexpr int ldl = R * G + kLdsPad;
     const int m = J.m, p = J.p, b = J.b, nb = J.nb, ldv = J.ldv;
     const int tid = threadIdx.x, grp = tid / G, gl = tid % G;  // one lane group per I column (b groups)
     T* Is = lds;                           // b columns x ldl (first step of a sweep)
@@ -549,10 +574,13 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                     for (int q2 = 0; q2 < R; ++q2) xr[q2] = Is[grp * ldl + gl + G * q2];
                     na = nI[grp];
                 } else {
+                    // clamped addresses keep every load in bounds; padding reads as zero
+                    const T* xs = Ag + (int64_t)(ci < p ? ci : 0) * m;
 #pragma unroll
                     for (int q2 = 0; q2 < R; ++q2) {
                         const int r = gl + G * q2;
-                        xr[q2] = (ci < p && r < m) ? Ag[(int64_t)ci * m + r] : (T)0;
+                        const T v = xs[r < m ? r : m - 1];
+                        xr[q2] = (ci < p && r < m) ? v : (T)0;
                     }
                     na = group_sum<G>(partial_norm<T, R>(xr));
                 }
@@ -673,14 +701,14 @@ int jacobi_resident_lds_bytes(int prec, int m, int p, int with_v) {
     int G, R, ldv;
     jacobi_geometry(m, p, &G, &R, &ldv);
     const int pp = p + (p & 1);
-    const int64_t elems = (int64_t)pp * R * G + (with_v ? (int64_t)pp * ldv : 0);
+    const int64_t elems = (int64_t)pp * (R * G + kLdsPad) + (with_v ? (int64_t)pp * ldv : 0);
     return (int)(elems * elem_size(prec));
 }
 
 int jacobi_team_lds_bytes(int prec, int m, int p, int b, int with_v) {
     int G, R, ldv;
     jacobi_geometry(m, p, &G, &R, &ldv);
-    const int64_t elems = (int64_t)2 * b * R * G + (with_v ? (int64_t)2 * b * ldv : 0);
+    const int64_t elems = (int64_t)2 * b * (R * G + kLdsPad) + (with_v ? (int64_t)2 * b * ldv : 0);
     return (int)(elems * elem_size(prec));
 }
 
