@@ -77,8 +77,10 @@ enum {
     TSVD_OPT_TEAM_SIZE = 2,    /* 0: automatic; >0: workgroups per frontal slice in the Jacobi
                                   kernel for slices too large for one workgroup's LDS */
     TSVD_OPT_SPIN_LIMIT = 3,   /* polls before a device wait gives up (test hook; default 2^24) */
-    TSVD_OPT_PROFILE = 4       /* 1: record HIP events around every kernel phase on the launch
+    TSVD_OPT_PROFILE = 4,      /* 1: record HIP events around every kernel phase on the launch
                                   stream (read with tsvd_get_stats); 0: off (default) */
+    TSVD_OPT_GRAPHS = 5        /* 1: complete_tensor replays one captured iteration as a HIP graph
+                                  (default; not while profiling); 0: direct launches */
 };
 int tsvd_set_option(tsvd_ctx* ctx, int option, double value);
 double tsvd_get_option(const tsvd_ctx* ctx, int option);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libtsvdmi.so")
 
 FP64, FP32, MIXED = 0, 1, 2
 OK, WARN_NOCONV, EINVAL, ENOMEM, EHIP, ENONFINITE, EBUSY, ETIMEOUT = 0, 1, -1, -2, -3, -4, -5, -6
-OPT_MAX_SWEEPS, OPT_SYNC_STATUS, OPT_TEAM_SIZE, OPT_SPIN_LIMIT, OPT_PROFILE = 0, 1, 2, 3, 4
+OPT_MAX_SWEEPS, OPT_SYNC_STATUS, OPT_TEAM_SIZE, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_GRAPHS = 0, 1, 2, 3, 4, 5
 PHASES = ("forward_transform", "jacobi", "threshold_rebuild", "inverse_transform")
 TRANSFORM_DOMAIN = 1
 REQ_TSVT, REQ_COMPLETE = 0, 1

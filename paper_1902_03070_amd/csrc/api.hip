@@ -31,6 +31,8 @@ struct tsvd_ctx {
     std::string err = "";
     // transform matrices: (n3, prec) -> {C, C^T} rows, element type by prec
     std::map<std::pair<int, int>, std::pair<void*, void*>> dct;
+    // matrix-core fragments: (n3, engine, inverse) -> device buffer
+    std::map<std::tuple<int, int, int>, void*> frag;
     DevBuf ws;                 // main workspace
     DevBuf ctrl;               // Ctrl + norms + history (persistent)
     Ctrl* h_ctrl = nullptr;    // pinned host mirror
@@ -41,6 +43,10 @@ struct tsvd_ctx {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> marks;
+    // graph capture of the completion iteration
+    int use_graphs = 1;
+    int capturing = 0;
+    hipStream_t own = nullptr;  // context stream (capture cannot use the legacy default stream)
 };
 
 namespace {
@@ -96,6 +102,56 @@ int get_dct(tsvd_ctx* c, int n3, int prec, const void** C, const void** Ct) {
     }
     *C = it->second.first;
     *Ct = it->second.second;
+    return TSVD_OK;
+}
+
+int tube_engine(int prec) { return prec == TSVD_FP64 ? 0 : prec == TSVD_FP32 ? 1 : 2; }
+
+// C or C^T in fragment order for the matrix-core tube transform.
+int get_frag(tsvd_ctx* c, int n3, int prec, int inverse, const void** out) {
+    const int eng = tube_engine(prec);
+    auto key = std::make_tuple(n3, eng, inverse);
+    auto it = c->frag.find(key);
+    if (it == c->frag.end()) {
+        std::vector<double> m((size_t)n3 * n3);
+        const double pi = acos(-1.0);
+        for (int k = 0; k < n3; ++k) {
+            const double sk = k == 0 ? sqrt(1.0 / n3) : sqrt(2.0 / n3);
+            for (int t = 0; t < n3; ++t) {
+                const double v = sk * cos(pi * (2.0 * t + 1.0) * k / (2.0 * n3));
+                if (!inverse) m[(size_t)k * n3 + t] = v;   // out[k] = sum_t C[k][t] in[t]
+                else m[(size_t)t * n3 + k] = v;            // out[t] = sum_k C[k][t] in[k]
+            }
+        }
+        const size_t bytes = tube_fragment_bytes(eng, n3);
+        std::vector<unsigned char> h(bytes);
+        make_tube_fragments(eng, n3, m.data(), h.data());
+        void* d = nullptr;
+        HIPCHK(c, hipMalloc(&d, bytes));
+        HIPCHK(c, hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
+        it = c->frag.emplace(key, d).first;
+    }
+    *out = it->second;
+    return TSVD_OK;
+}
+
+// Tube transform along n3 (forward or inverse) on the matrix cores; tubes
+// longer than kMaxTube use the vector-ALU kernel with the dense matrix.
+int run_tube(tsvd_ctx* c, int prec, TubeArgs a, int inverse, hipStream_t s) {
+    hipError_t e;
+    if (a.n3 <= kMaxTube) {
+        const void* fr;
+        int rc = get_frag(c, a.n3, prec, inverse, &fr);
+        if (rc) return rc;
+        e = launch_tube_mfma(tube_engine(prec), a, fr, s);
+    } else {
+        const void *C, *Ct;
+        int rc = get_dct(c, a.n3, prec, &C, &Ct);
+        if (rc) return rc;
+        a.M = inverse ? Ct : C;
+        e = launch_tube_transform(prec == TSVD_FP64 ? 0 : 1, a, s);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, inverse ? "inverse tube transform" : "tube transform");
     return TSVD_OK;
 }
 
@@ -319,6 +375,8 @@ int upload_plan(tsvd_ctx* c, Plan& P, char* base) {
     J.p = P.p;
     J.n3 = (int)P.n3;
     J.refine64 = (P.prec == TSVD_MIXED) ? 1 : 0;
+    const double u64 = ldexp(1.0, -53), u32 = ldexp(1.0, -24);
+    J.tol = P.prec == TSVD_FP64 ? P.m * u64 : P.prec == TSVD_FP32 ? 2.0 * sqrt((double)P.m) * u32 : P.m * u32;
     P.ts.ctl = (int*)(base + P.o_bar);
     HIPCHK(c, hipMemcpy(base + P.o_job, &J, sizeof(JacobiJob), hipMemcpyHostToDevice));
     std::vector<int> tj(P.n3, 0), tk(P.n3);
@@ -341,7 +399,7 @@ int run_jacobi(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s) {
                                    P.threads, P.with_v, s);
     else
         e = launch_jacobi_team(P.prec, jd, 1, tj, tk, (int)P.n3, P.ts, clamp_sweeps(c->max_sweeps), ctrl, P.lds,
-                               P.threads, P.with_v, c->spin_limit, P.job.R, P.job.G, s);
+                               P.threads, P.with_v, c->spin_limit, P.job.R, P.job.G, c->capturing ? 0 : 1, s);
     if (e != hipSuccess) return hip_fail(c, e, "jacobi launch");
     return TSVD_OK;
 }
@@ -437,9 +495,11 @@ void tsvd_destroy(tsvd_ctx* c) {
         (void)hipFree(kv.second.first);
         (void)hipFree(kv.second.second);
     }
+    for (auto& kv : c->frag) (void)hipFree(kv.second);
     if (c->ws.p) (void)hipFree(c->ws.p);
     if (c->ctrl.p) (void)hipFree(c->ctrl.p);
     if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
+    if (c->own) (void)hipStreamDestroy(c->own);
     for (void* p : c->owned) (void)hipFree(p);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
@@ -464,6 +524,7 @@ int tsvd_set_option(tsvd_ctx* c, int opt, double v) {
             c->spin_limit = (int)v;
             return TSVD_OK;
         case TSVD_OPT_PROFILE: c->prof = v != 0.0; return TSVD_OK;
+        case TSVD_OPT_GRAPHS: c->use_graphs = v != 0.0; return TSVD_OK;
     }
     return fail(c, TSVD_EINVAL, "unknown option");
 }
@@ -476,6 +537,7 @@ double tsvd_get_option(const tsvd_ctx* c, int opt) {
         case TSVD_OPT_TEAM_SIZE: return c->team_size;
         case TSVD_OPT_SPIN_LIMIT: return c->spin_limit;
         case TSVD_OPT_PROFILE: return c->prof;
+        case TSVD_OPT_GRAPHS: return c->use_graphs;
     }
     return -1.0;
 }
@@ -536,7 +598,6 @@ int tsvt_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
     if ((rc = ensure_ctrl(c, &cr))) return rc;
     const void *C, *Ct;
     if ((rc = get_dct(c, (int)n3, prec, &C, &Ct))) return rc;
-    const int dp = prec == TSVD_FP64 ? 0 : 1;
     hipError_t e = launch_fill_zero(base + P.o_ctr_begin, P.o_ctr_end - P.o_ctr_begin, s);
     if (e != hipSuccess) return hip_fail(c, e, "fill");
     TubeArgs f{};
@@ -544,16 +605,14 @@ int tsvt_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
     f.beta_val = 1.0;
     {
         PhaseMark pm(c, 0, s);
-        e = launch_tube_transform(dp, f, s);
-        if (e != hipSuccess) return hip_fail(c, e, "dct");
+        if ((rc = run_tube(c, prec, f, 0, s))) return rc;
     }
     if ((rc = enqueue_svt_core(c, P, base, cr.ctrl, tau, nullptr, s))) return rc;
     TubeArgs iv{};
     iv.in = base + P.o_ybar; iv.out = Y; iv.M = Ct; iv.N = P.N; iv.n3 = (int)n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
     {
         PhaseMark pm(c, 3, s);
-        e = launch_tube_transform(dp, iv, s);
-        if (e != hipSuccess) return hip_fail(c, e, "idct");
+        if ((rc = run_tube(c, prec, iv, 1, s))) return rc;
     }
     if (ranks_out) {
         HIPCHK(c, hipMemcpyAsync(ranks_out, base + P.o_rank, n3 * 4, hipMemcpyDeviceToHost, s));
@@ -587,11 +646,10 @@ int tprod_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n4, int64_t
     TubeArgs f{};
     f.in = X; f.out = base + oX; f.M = C; f.N = n1 * n2; f.n3 = (int)n3; f.ctrl = cr.ctrl; f.check_finite = 1;
     f.beta_val = 1.0;
-    hipError_t e = launch_tube_transform(dp, f, s);
-    if (e != hipSuccess) return hip_fail(c, e, "dct X");
+    if ((rc = run_tube(c, prec, f, 0, s))) return rc;
     f.in = Yp; f.out = base + oY; f.N = n2 * n4;
-    e = launch_tube_transform(dp, f, s);
-    if (e != hipSuccess) return hip_fail(c, e, "dct Y");
+    if ((rc = run_tube(c, prec, f, 0, s))) return rc;
+    hipError_t e;
     GemmArgs g{};
     g.A = base + oX; g.a_rs = 1; g.a_cs = n1; g.a_bs = n1 * n2;
     g.B = base + oY; g.b_rs = 1; g.b_cs = n2; g.b_bs = n2 * n4;
@@ -601,8 +659,7 @@ int tprod_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n4, int64_t
     if (e != hipSuccess) return hip_fail(c, e, "slice gemm");
     TubeArgs iv{};
     iv.in = base + oZ; iv.out = Z; iv.M = Ct; iv.N = n1 * n4; iv.n3 = (int)n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
-    e = launch_tube_transform(dp, iv, s);
-    if (e != hipSuccess) return hip_fail(c, e, "idct Z");
+    if ((rc = run_tube(c, prec, iv, 1, s))) return rc;
     return finish_call(c, s);
 }
 
@@ -634,7 +691,7 @@ int tsvd_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
     TubeArgs f{};
     f.in = X; f.out = base + P.o_zbar; f.M = C; f.N = P.N; f.n3 = (int)n3; f.ctrl = cr.ctrl; f.check_finite = 1;
     f.beta_val = 1.0;
-    if ((e = launch_tube_transform(dp, f, s)) != hipSuccess) return hip_fail(c, e, "dct");
+    if ((rc = run_tube(c, prec, f, 0, s))) return rc;
     if ((rc = run_jacobi(c, P, base, cr.ctrl, s))) return rc;
     // singular values per column
     SvtPrepArgs sp{};
@@ -659,10 +716,10 @@ int tsvd_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
         // back to the spatial domain (in place: each workgroup owns whole tubes)
         TubeArgs iv{};
         iv.M = Ct; iv.n3 = (int)n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
-        if (U) { iv.in = U; iv.out = U; iv.N = n1 * P.p; if ((e = launch_tube_transform(dp, iv, s)) != hipSuccess) return hip_fail(c, e, "idct U"); }
-        if (V) { iv.in = V; iv.out = V; iv.N = n2 * P.p; if ((e = launch_tube_transform(dp, iv, s)) != hipSuccess) return hip_fail(c, e, "idct V"); }
+        if (U) { iv.in = U; iv.out = U; iv.N = n1 * P.p; if ((rc = run_tube(c, prec, iv, 1, s))) return rc; }
+        if (V) { iv.in = V; iv.out = V; iv.N = n2 * P.p; if ((rc = run_tube(c, prec, iv, 1, s))) return rc; }
         iv.in = S; iv.out = S; iv.N = P.p;
-        if ((e = launch_tube_transform(dp, iv, s)) != hipSuccess) return hip_fail(c, e, "idct S");
+        if ((rc = run_tube(c, prec, iv, 1, s))) return rc;
     }
     return finish_call(c, s);
 }
@@ -702,7 +759,6 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
     if ((rc = ensure_ctrl(c, &cr))) return rc;
     const void *C, *Ct;
     if ((rc = get_dct(c, (int)n3, prec, &C, &Ct))) return rc;
-    const int dp = prec == TSVD_FP64 ? 0 : 1;
     HIPCHK(c, hipStreamSynchronize(s));
     HIPCHK(c, hipMemcpy(base + oBeta, betas.data(), L * 8, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(base + oTau, taus.data(), L * 8, hipMemcpyHostToDevice));
@@ -726,8 +782,8 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
         f.pX = X; f.pM = base + oM; f.beta_sched = (const double*)(base + oBeta);
         {
             PhaseMark pm(c, 0, st);
-            e = launch_tube_transform(dp, f, st);
-            if (e != hipSuccess) return hip_fail(c, e, "dct");
+            int r0 = run_tube(c, prec, f, 0, st);
+            if (r0) return r0;
         }
         int r2 = enqueue_svt_core(c, P, base, cr.ctrl, 0.0, (const double*)(base + oTau), st);
         if (r2) return r2;
@@ -737,8 +793,8 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
         iv.beta_sched = (const double*)(base + oBeta);
         {
             PhaseMark pm(c, 3, st);
-            e = launch_tube_transform(dp, iv, st);
-            if (e != hipSuccess) return hip_fail(c, e, "idct");
+            int r3 = run_tube(c, prec, iv, 1, st);
+            if (r3) return r3;
         }
         e = launch_iter_advance(cr.ctrl, cr.norms, cr.hist, kHist, st);
         if (e != hipSuccess) return hip_fail(c, e, "advance");
@@ -749,17 +805,57 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
     double last = 0.0;
     bool stop = false;
     const bool check = o->tol > 0.0;
+    // Replay a captured iteration unless profiling (per-kernel events) is on.
+    hipGraphExec_t exec = nullptr;
+    hipStream_t run = s;
+    if (c->use_graphs && !c->prof) {
+        // everything the iteration allocates lazily must exist before capture
+        const void* tmp;
+        if (n3 <= kMaxTube) {
+            if ((rc = get_frag(c, (int)n3, prec, 0, &tmp)) || (rc = get_frag(c, (int)n3, prec, 1, &tmp))) return rc;
+        }
+        if (!c->own) HIPCHK(c, hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+        HIPCHK(c, hipStreamSynchronize(s));
+        run = c->own;
+        hipGraph_t graph = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal));
+        c->capturing = 1;
+        const int rc_cap = enqueue_iter(run);
+        c->capturing = 0;
+        const hipError_t ec = hipStreamEndCapture(run, &graph);
+        if (rc_cap) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc_cap;
+        }
+        if (ec != hipSuccess) return hip_fail(c, ec, "hipStreamEndCapture");
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return hip_fail(c, ei, "hipGraphInstantiate");
+    }
+    auto one_iter = [&]() -> int {
+        if (exec) {
+            hipError_t e = hipGraphLaunch(exec, run);
+            return e == hipSuccess ? TSVD_OK : hip_fail(c, e, "hipGraphLaunch");
+        }
+        return enqueue_iter(run);
+    };
     while (iters < L && !stop) {
-        if ((rc = enqueue_iter(s))) return rc;
+        if ((rc = one_iter())) break;
         ++iters;
         if (check && (iters % o->check_every == 0 || iters == L)) {
-            HIPCHK(c, hipStreamSynchronize(s));
+            if (hipStreamSynchronize(run) != hipSuccess) { rc = fail(c, TSVD_EHIP, "sync"); break; }
             double h = 0.0;
-            HIPCHK(c, hipMemcpy(&h, cr.hist + (iters - 1), 8, hipMemcpyDeviceToHost));
+            if (hipMemcpy(&h, cr.hist + (iters - 1), 8, hipMemcpyDeviceToHost) != hipSuccess) {
+                rc = fail(c, TSVD_EHIP, "history read");
+                break;
+            }
             last = h;
             if (h <= o->tol) stop = true;
         }
     }
+    if (run != s) (void)hipStreamSynchronize(run);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(s));
     if (iters >= 1 && iters <= kHist) HIPCHK(c, hipMemcpy(&last, cr.hist + (iters - 1), 8, hipMemcpyDeviceToHost));
     if (o->M_out) HIPCHK(c, hipMemcpyAsync(o->M_out, base + oM, P.N * n3 * es, hipMemcpyDeviceToDevice, s));

@@ -47,6 +47,7 @@ struct JacobiJob {
     int b;             // block width for the team kernel (even)
     int nb;            // number of column blocks (even) = ceil(p / b) rounded up to even
     int refine64;      // 1: after convergence run one sweep with FP64 arithmetic (FP32 data)
+    double tol;        // rotate a pair iff |x.y| > tol |x| |y| (precision dependent, set on the host)
 };
 
 struct TeamSched {
@@ -86,6 +87,15 @@ struct TubeArgs {
 };
 hipError_t launch_tube_transform(int prec, const TubeArgs& a, hipStream_t s);
 
+// The same transform on the matrix cores for tubes of length n3 <= kMaxTube.
+// eng: 0 FP64, 1 FP32, 2 BF16 hi+lo (FP32 data).  frag: M in fragment order,
+// built on the host by make_tube_fragments (tube_fragment_bytes bytes).
+constexpr int kMaxTube = 128;
+int tube_ks(int eng, int n3);
+size_t tube_fragment_bytes(int eng, int n3);
+void make_tube_fragments(int eng, int n3, const double* M, void* out);
+hipError_t launch_tube_mfma(int eng, const TubeArgs& a, const void* frag, hipStream_t s);
+
 // Jacobi one-sided SVD of every slice of one or more jobs.
 hipError_t launch_jacobi_resident(int prec, const JacobiJob* jobs_dev, int njobs, const int* task_job,
                                   const int* task_slice, int ntasks, int max_sweeps, Ctrl* ctrl,
@@ -93,7 +103,7 @@ hipError_t launch_jacobi_resident(int prec, const JacobiJob* jobs_dev, int njobs
 hipError_t launch_jacobi_team(int prec, const JacobiJob* jobs_dev, int njobs, const int* task_job,
                               const int* task_slice, int ntasks, const TeamSched& ts, int max_sweeps,
                               Ctrl* ctrl, int lds_bytes, int threads, int with_v, int spin_limit, int R, int G,
-                              hipStream_t s);
+                              int coop, hipStream_t s);
 void jacobi_geometry(int m, int p, int* G, int* R, int* ldv);
 int jacobi_resident_lds_bytes(int prec, int m, int p, int with_v);
 int jacobi_team_lds_bytes(int prec, int m, int p, int b, int with_v);

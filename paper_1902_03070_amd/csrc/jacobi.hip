@@ -3,8 +3,11 @@
 // The method takes the SVD of every frontal slice of Zbar = dct(Z,[],3)
 // (Theorem 4; Algorithm 1, per-slice SVD).  Each slice is handled in "tall"
 // form T (m x p, m >= p): the slice itself, or its transpose when n1 < n2.
-// Columns of T are rotated in pairs until every pair is orthogonal to
-// tol = m * u (u = unit roundoff of the sweep arithmetic):
+// Columns of T are rotated in pairs until every pair is orthogonal to a
+// tolerance tol (m u for FP64, u = 2^-53; 2 sqrt(m) u32 for FP32 sweeps, since
+// FP32 rounding of the stored columns bounds the attainable orthogonality;
+// m u32 for the FP32 sweeps of the mixed path, which ends with one sweep in
+// FP64 arithmetic at m u):
 //     alpha = |x|^2, beta = |y|^2, gamma = x.y        (FP64 sums)
 //     rotate iff gamma^2 > tol^2 alpha beta
 //     zeta = (beta - alpha) / (2 gamma),  t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2))
@@ -302,7 +305,7 @@ __device__ void resident_task(const JacobiJob& J, int k, int max_sweeps, Ctrl* c
         }
     __syncthreads();
 
-    const double tol = (double)m * Unit<T>::v;
+    const double tol = J.tol;
     int sweeps = -1, executed = 0;
     const bool refine = J.refine64 != 0;
     for (int sw = 0; sw < max_sweeps + (refine ? 1 : 0); ++sw) {
@@ -524,7 +527,7 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
     T* Js = lds + (int64_t)b * ldl;        // b columns x ldl
     T* Vi = lds + (int64_t)2 * b * ldl;    // b columns x ldv
     T* Vj = Vi + (int64_t)b * ldv;         // b columns x ldv
-    const double tol = (double)m * Unit<T>::v;
+    const double tol = J.tol;
     const bool refine = J.refine64 != 0;
     int sweeps = -1, executed = 0;
     int* rot_g = J.rot + (int64_t)k * kMaxSweeps;
@@ -766,7 +769,8 @@ hipError_t launch_jacobi_resident(int prec, const JacobiJob* jobs_dev, int njobs
 
 hipError_t launch_jacobi_team(int prec, const JacobiJob* jobs_dev, int njobs, const int* task_job,
                               const int* task_slice, int ntasks, const TeamSched& ts_in, int max_sweeps, Ctrl* ctrl,
-                              int lds_bytes, int threads, int with_v, int spin_limit, int R, int G, hipStream_t s) {
+                              int lds_bytes, int threads, int with_v, int spin_limit, int R, int G, int coop,
+                              hipStream_t s) {
     (void)njobs;
     if (ntasks <= 0) return hipSuccess;
     const void* f = team_fn(prec, with_v, R, G);
@@ -776,7 +780,10 @@ hipError_t launch_jacobi_team(int prec, const JacobiJob* jobs_dev, int njobs, co
     void* args[] = {(void*)&jobs_dev, (void*)&task_job, (void*)&task_slice, (void*)&ntasks,
                     (void*)&ts,       (void*)&max_sweeps, (void*)&ctrl,     (void*)&spin_limit};
     dim3 grid(ts.nwg), block(threads);
-    return hipLaunchCooperativeKernel(f, grid, block, args, (unsigned)lds_bytes, s);
+    if (coop) return hipLaunchCooperativeKernel(f, grid, block, args, (unsigned)lds_bytes, s);
+    // plain launch (inside stream capture): the grid fits the device, and the
+    // bounded team waits turn a non-resident team into an error, not a hang
+    return hipLaunchKernel(f, grid, block, args, (size_t)lds_bytes, s);
 }
 
 int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v, int R, int G) {

@@ -108,3 +108,25 @@ def test_complete_tolerance_stop(tm):
     Xo, _, it, _ = oracle.complete(cc.B, cc.mask, np.full(200, 10.0), tol=1e-6)
     assert info["iters"] == it
     assert rel(to_np(X), Xo) <= 1e-10
+
+
+@pytest.mark.parametrize("shape", [(20, 18, 6), (260, 200, 3)])
+def test_complete_graph_replays_match_direct_launches(tm, shape):
+    # The captured iteration is replayed L times with a host synchronization
+    # between replays (check_every = 1); every L must give the same bits as
+    # direct launches of the same kernels.
+    announce("complete_graph", shape=shape)
+    cc = small_case(L=5, shape=shape, r=3, sr=0.5)
+    B, mk = to_dev(cc.B), to_dev(cc.mask, torch.uint8)
+    for L in (1, 2, 3, 5):
+        outs = []
+        for graphs in (1, 0):
+            ctx = tm.Context(0)
+            ctx.set_option(tm.OPT_GRAPHS, graphs)
+            X, info, M = tm.complete_tensor(B, mk, max_iter=L, tol=1e-300, check_every=1, tau_schedule=cc.taus,
+                                            return_M=True, ctx=ctx)
+            torch.cuda.synchronize()
+            outs.append((to_np(X), to_np(M), info["iters"]))
+            ctx.close()
+        assert outs[0][2] == outs[1][2] == L
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
