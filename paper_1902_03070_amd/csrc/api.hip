@@ -271,7 +271,7 @@ struct Plan {
     TeamSched ts{};
     JacobiJob job{};
     // workspace offsets
-    size_t o_zbar, o_A, o_F, o_G, o_w, o_sig, o_ybar, o_V, o_rot, o_sw, o_bar, o_rank, o_job, o_tj, o_tk, o_end;
+    size_t o_zbar, o_A, o_F, o_G, o_w, o_sig, o_ybar, o_V, o_rot, o_sw, o_bar, o_rank, o_end;
     size_t o_ctr_begin, o_ctr_end;  // region zeroed per call (counters)
 };
 
@@ -308,7 +308,29 @@ int choose_team(tsvd_ctx* c, Plan& P) {
     return TSVD_OK;
 }
 
-int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int with_v, Plan& P, Carve& cv) {
+// Batched plans: a slice that does not fit in LDS gets a team of one
+// workgroup with b * G == kTeamMaxThreads (the batched kernel's block size).
+int choose_single_wg(tsvd_ctx* c, Plan& P) {
+    int G, R, ldv;
+    jacobi_geometry(P.m, P.p, &G, &R, &ldv);
+    const int b = kTeamMaxThreads / G;
+    if (jacobi_team_lds_bytes(P.prec, P.m, P.p, b, P.with_v) > kLdsBudget)
+        return fail(c, TSVD_EINVAL, "slice too large for the batched Jacobi kernel");
+    int nb = (P.p + b - 1) / b;
+    nb += nb & 1;
+    P.lds = jacobi_team_lds_bytes(P.prec, P.m, P.p, b, P.with_v);
+    P.threads = kTeamMaxThreads;
+    P.ts = TeamSched{1, 1, nullptr};
+    P.job.b = b;
+    P.job.nb = nb;
+    P.job.G = G;
+    P.job.R = R;
+    P.job.ldv = ldv;
+    return TSVD_OK;
+}
+
+int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int with_v, Plan& P, Carve& cv,
+              bool batched = false) {
     P.prec = prec;
     P.n1 = n1; P.n2 = n2; P.n3 = n3; P.N = n1 * n2;
     P.trans = n1 < n2;
@@ -336,7 +358,7 @@ int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int wit
         P.ts = TeamSched{1, 0, nullptr};
     } else {
         P.team = 1;
-        int rc = choose_team(c, P);
+        int rc = batched ? choose_single_wg(c, P) : choose_team(c, P);
         if (rc) return rc;
     }
     P.o_zbar = cv.take(slice * n3 * es);
@@ -347,9 +369,6 @@ int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int wit
     P.o_sig = cv.take((size_t)P.p * n3 * 8);
     P.o_ybar = cv.take(slice * n3 * es);
     P.o_V = with_v ? cv.take((size_t)P.p * P.p * n3 * es) : 0;
-    P.o_job = cv.take(sizeof(JacobiJob));
-    P.o_tj = cv.take((size_t)n3 * 4);
-    P.o_tk = cv.take((size_t)n3 * 4);
     P.o_ctr_begin = cv.off;
     P.o_rot = cv.take((size_t)n3 * kMaxSweeps * 4);
     P.o_sw = cv.take((size_t)n3 * 4);
@@ -360,8 +379,8 @@ int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int wit
     return TSVD_OK;
 }
 
-// Fill the device-side job descriptor and task list (synchronous upload).
-int upload_plan(tsvd_ctx* c, Plan& P, char* base) {
+// Point the plan's Jacobi descriptor at its workspace regions.
+void bind_plan(Plan& P, char* base) {
     JacobiJob& J = P.job;
     J.src = base + P.o_zbar;
     J.A = base + P.o_A;
@@ -378,11 +397,11 @@ int upload_plan(tsvd_ctx* c, Plan& P, char* base) {
     const double u64 = ldexp(1.0, -53), u32 = ldexp(1.0, -24);
     J.tol = P.prec == TSVD_FP64 ? P.m * u64 : P.prec == TSVD_FP32 ? 2.0 * sqrt((double)P.m) * u32 : P.m * u32;
     P.ts.ctl = (int*)(base + P.o_bar);
-    HIPCHK(c, hipMemcpy(base + P.o_job, &J, sizeof(JacobiJob), hipMemcpyHostToDevice));
-    std::vector<int> tj(P.n3, 0), tk(P.n3);
-    for (int k = 0; k < P.n3; ++k) tk[k] = k;
-    HIPCHK(c, hipMemcpy(base + P.o_tj, tj.data(), P.n3 * 4, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(base + P.o_tk, tk.data(), P.n3 * 4, hipMemcpyHostToDevice));
+}
+
+int upload_plan(tsvd_ctx* c, Plan& P, char* base) {
+    (void)c;
+    bind_plan(P, base);
     return TSVD_OK;
 }
 
@@ -390,22 +409,23 @@ int clamp_sweeps(int v) { return std::max(1, std::min(v, kMaxSweeps - 1)); }
 
 // Jacobi launch for a planned tensor.
 int run_jacobi(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s) {
-    const JacobiJob* jd = (const JacobiJob*)(base + P.o_job);
-    const int* tj = (const int*)(base + P.o_tj);
-    const int* tk = (const int*)(base + P.o_tk);
+    (void)base;
     hipError_t e;
     if (!P.team)
-        e = launch_jacobi_resident(P.prec, jd, 1, tj, tk, (int)P.n3, clamp_sweeps(c->max_sweeps), ctrl, P.lds,
-                                   P.threads, P.with_v, s);
+        e = launch_jacobi_resident(P.prec, P.job, nullptr, nullptr, nullptr, (int)P.n3, clamp_sweeps(c->max_sweeps),
+                                   ctrl, P.lds, P.threads, P.with_v, s);
     else
-        e = launch_jacobi_team(P.prec, jd, 1, tj, tk, (int)P.n3, P.ts, clamp_sweeps(c->max_sweeps), ctrl, P.lds,
-                               P.threads, P.with_v, c->spin_limit, P.job.R, P.job.G, c->capturing ? 0 : 1, s);
+        e = launch_jacobi_team(P.prec, P.job, (int)P.n3, P.ts, clamp_sweeps(c->max_sweeps), ctrl, P.lds, P.threads,
+                               P.with_v, c->spin_limit, P.job.R, P.job.G, c->capturing ? 0 : 1, s);
     if (e != hipSuccess) return hip_fail(c, e, "jacobi launch");
     return TSVD_OK;
 }
 
 // Everything after the forward transform of the t-SVT: Jacobi, thresholding,
 // rebuild.  Leaves Ybar in the workspace.
+int enqueue_after_jacobi(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau_val, const double* tau_sched,
+                         hipStream_t s);
+
 int enqueue_svt_core(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau_val, const double* tau_sched,
                      hipStream_t s) {
     {
@@ -413,6 +433,12 @@ int enqueue_svt_core(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau_va
         int rc = run_jacobi(c, P, base, ctrl, s);
         if (rc) return rc;
     }
+    return enqueue_after_jacobi(c, P, base, ctrl, tau_val, tau_sched, s);
+}
+
+// Thresholding and rebuild (Ybar in the workspace) once A' is ready.
+int enqueue_after_jacobi(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau_val, const double* tau_sched,
+                         hipStream_t s) {
     PhaseMark pm(c, 2, s);
     const int prec = P.prec == TSVD_FP64 ? 0 : 1;
     SvtPrepArgs sp{};
@@ -873,18 +899,95 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
 int tsvt_dct_batched(tsvd_ctx* c, int prec, int count, const int64_t* dims, const void* const* Z, void* const* Y,
                      const double* tau, void* stream) {
     if (!c) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (bad_prec(prec)) return fail(c, TSVD_EINVAL, "unknown precision");
     if (count <= 0 || !dims || !Z || !Y || !tau) return fail(c, TSVD_EINVAL, "bad batch arguments");
-    // Reference behaviour: same result as one call per tensor.
-    const int sync = c->sync_status;
-    c->sync_status = 0;
-    int rc = TSVD_OK;
-    for (int j = 0; j < count && rc >= 0; ++j) {
-        rc = tsvt_dct(c, prec, dims[3 * j], dims[3 * j + 1], dims[3 * j + 2], Z[j], Y[j], tau[j], nullptr, stream);
+    for (int j = 0; j < count; ++j) {
+        if (dims[3 * j] <= 0 || dims[3 * j + 1] <= 0 || dims[3 * j + 2] <= 0)
+            return fail(c, TSVD_EINVAL, "sizes must be positive");
+        if (!Z[j] || !Y[j]) return fail(c, TSVD_EINVAL, "null tensor pointer");
+        if (!(tau[j] >= 0.0) || !isfinite(tau[j])) return fail(c, TSVD_EINVAL, "tau must be finite and >= 0");
     }
-    c->sync_status = sync;
-    if (rc < 0) return rc;
-    if (sync) return tsvd_sync_status(c, stream, nullptr);
-    return TSVD_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<Plan> plans(count);
+    Carve cv;
+    int rc;
+    int64_t ntasks = 0;
+    for (int j = 0; j < count; ++j) {
+        if ((rc = make_plan(c, prec, dims[3 * j], dims[3 * j + 1], dims[3 * j + 2], 0, plans[j], cv, true))) return rc;
+        ntasks += dims[3 * j + 2];
+    }
+    const size_t o_jobs = cv.take(sizeof(JacobiJob) * count);
+    const size_t o_tj = cv.take(sizeof(int) * ntasks), o_tk = cv.take(sizeof(int) * ntasks);
+    const size_t o_queue = cv.take(256);  // one work counter per row geometry (8 x 32 bytes)
+    if ((rc = ensure_ws(c, cv.off))) return rc;
+    char* base = (char*)c->ws.p;
+    CtrlRegion cr;
+    if ((rc = ensure_ctrl(c, &cr))) return rc;
+    // job table; task lists grouped by row geometry (R, G), each sorted by
+    // estimated cost (m p^2 per slice), largest first
+    auto geo = [](const Plan& P) { return (P.job.G == 32 ? 4 : 0) + P.job.R / 4 - 1; };  // 0..7
+    std::vector<JacobiJob> jobs(count);
+    std::vector<std::pair<double, std::pair<int, int>>> order;
+    order.reserve(ntasks);
+    for (int j = 0; j < count; ++j) {
+        bind_plan(plans[j], base);
+        jobs[j] = plans[j].job;
+        const double cost = (double)plans[j].m * plans[j].p * plans[j].p;
+        for (int k = 0; k < plans[j].n3; ++k) order.push_back({geo(plans[j]) * 1e30 - cost, {j, k}});
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<double, std::pair<int, int>>& a, const std::pair<double, std::pair<int, int>>& b) {
+                         return a.first < b.first;
+                     });
+    std::vector<int> tj(ntasks), tk(ntasks);
+    int gbeg[9] = {0}, gcnt[8] = {0};
+    for (int64_t t = 0; t < ntasks; ++t) {
+        tj[t] = order[t].second.first;
+        tk[t] = order[t].second.second;
+        gcnt[geo(plans[tj[t]])]++;
+    }
+    for (int g = 0; g < 8; ++g) gbeg[g + 1] = gbeg[g] + gcnt[g];
+    int glds[8] = {0};
+    for (int j = 0; j < count; ++j) glds[geo(plans[j])] = std::max(glds[geo(plans[j])], plans[j].lds);
+    HIPCHK(c, hipStreamSynchronize(s));  // tables live in the shared workspace
+    HIPCHK(c, hipMemcpy(base + o_jobs, jobs.data(), sizeof(JacobiJob) * count, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(base + o_tj, tj.data(), sizeof(int) * ntasks, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(base + o_tk, tk.data(), sizeof(int) * ntasks, hipMemcpyHostToDevice));
+    hipError_t e = launch_fill_zero(base + o_queue, 256, s);
+    if (e != hipSuccess) return hip_fail(c, e, "fill");
+    for (int j = 0; j < count; ++j) {
+        Plan& P = plans[j];
+        if ((e = launch_fill_zero(base + P.o_ctr_begin, P.o_ctr_end - P.o_ctr_begin, s)) != hipSuccess)
+            return hip_fail(c, e, "fill");
+        TubeArgs f{};
+        f.in = Z[j]; f.out = base + P.o_zbar; f.N = P.N; f.n3 = (int)P.n3; f.ctrl = cr.ctrl; f.check_finite = 1;
+        f.beta_val = 1.0;
+        PhaseMark pm(c, 0, s);
+        if ((rc = run_tube(c, prec, f, 0, s))) return rc;
+    }
+    {
+        PhaseMark pm(c, 1, s);
+        for (int g = 0; g < 8; ++g) {
+            if (!gcnt[g]) continue;
+            const int G = g >= 4 ? 32 : 16, R = 4 * (g % 4 + 1);
+            e = launch_jacobi_batched(prec == TSVD_FP64 ? 0 : 1, R, G, (const JacobiJob*)(base + o_jobs),
+                                      (const int*)(base + o_tj) + gbeg[g], (const int*)(base + o_tk) + gbeg[g],
+                                      gcnt[g], (int*)(base + o_queue) + 8 * g, clamp_sweeps(c->max_sweeps), cr.ctrl,
+                                      glds[g], s);
+            if (e != hipSuccess) return hip_fail(c, e, "batched jacobi");
+        }
+    }
+    for (int j = 0; j < count; ++j) {
+        Plan& P = plans[j];
+        if ((rc = enqueue_after_jacobi(c, P, base, cr.ctrl, tau[j], nullptr, s))) return rc;
+        TubeArgs iv{};
+        iv.in = base + P.o_ybar; iv.out = Y[j]; iv.N = P.N; iv.n3 = (int)P.n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
+        PhaseMark pm(c, 3, s);
+        if ((rc = run_tube(c, prec, iv, 1, s))) return rc;
+    }
+    return finish_call(c, s);
 }
 
 }  // extern "C"

@@ -96,14 +96,20 @@ size_t tube_fragment_bytes(int eng, int n3);
 void make_tube_fragments(int eng, int n3, const double* M, void* out);
 hipError_t launch_tube_mfma(int eng, const TubeArgs& a, const void* frag, hipStream_t s);
 
-// Jacobi one-sided SVD of every slice of one or more jobs.
-hipError_t launch_jacobi_resident(int prec, const JacobiJob* jobs_dev, int njobs, const int* task_job,
-                                  const int* task_slice, int ntasks, int max_sweeps, Ctrl* ctrl,
-                                  int lds_bytes, int threads, int with_v, hipStream_t s);
-hipError_t launch_jacobi_team(int prec, const JacobiJob* jobs_dev, int njobs, const int* task_job,
-                              const int* task_slice, int ntasks, const TeamSched& ts, int max_sweeps,
-                              Ctrl* ctrl, int lds_bytes, int threads, int with_v, int spin_limit, int R, int G,
-                              int coop, hipStream_t s);
+// Jacobi one-sided SVD of every slice.  Single tensor: `job1` by value, task
+// t = slice t (jobs_dev == nullptr).  Batched: job table and task list in
+// device memory.
+hipError_t launch_jacobi_resident(int prec, const JacobiJob& job1, const JacobiJob* jobs_dev, const int* task_job,
+                                  const int* task_slice, int ntasks, int max_sweeps, Ctrl* ctrl, int lds_bytes,
+                                  int threads, int with_v, hipStream_t s);
+hipError_t launch_jacobi_team(int prec, const JacobiJob& job, int ntasks, const TeamSched& ts, int max_sweeps,
+                              Ctrl* ctrl, int lds_bytes, int threads, int with_v, int spin_limit, int R, int G, int coop,
+                              hipStream_t s);
+// One persistent launch over (tensor, slice) tasks drawn from *queue (zeroed).
+// One persistent launch per row geometry (R, G) present in the batch.
+hipError_t launch_jacobi_batched(int prec, int R, int G, const JacobiJob* jobs_dev, const int* task_job,
+                                 const int* task_slice, int ntasks, int* queue, int max_sweeps, Ctrl* ctrl,
+                                 int lds_bytes, hipStream_t s);
 void jacobi_geometry(int m, int p, int* G, int* R, int* ldv);
 int jacobi_resident_lds_bytes(int prec, int m, int p, int with_v);
 int jacobi_team_lds_bytes(int prec, int m, int p, int b, int with_v);

@@ -32,6 +32,8 @@
 //    barrier.  The grid is launched cooperatively, so every workgroup of a team
 //    is resident; the barrier's wait is bounded and reports a timeout instead
 //    of hanging.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace tsvd {
@@ -373,7 +375,7 @@ __device__ void resident_task(const JacobiJob& J, int k, int max_sweeps, Ctrl* c
     } while (0)
 
 template <typename T, bool WV>
-__global__ __launch_bounds__(1024) void k_jacobi_resident(const JacobiJob* __restrict__ jobs,
+__global__ __launch_bounds__(1024) void k_jacobi_resident(JacobiJob job1, const JacobiJob* __restrict__ jobs,
                                                           const int* __restrict__ task_job,
                                                           const int* __restrict__ task_slice, int ntasks,
                                                           int max_sweeps, Ctrl* ctrl) {
@@ -382,8 +384,9 @@ __global__ __launch_bounds__(1024) void k_jacobi_resident(const JacobiJob* __res
     __shared__ double s_nrm[kMaxRows];
     T* lds = (T*)smem_raw;
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
-        const JacobiJob& J = jobs[task_job[t]];
-        const int k = task_slice[t];
+        // one tensor: the job travels by value and task t is slice t
+        const JacobiJob J = jobs ? jobs[task_job[t]] : job1;
+        const int k = jobs ? task_slice[t] : t;
 #define TSVD_RES_CALL(RR, GG) resident_task<T, RR, GG, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch, s_nrm)
         TSVD_DISPATCH_RG(J, TSVD_RES_CALL);
 #undef TSVD_RES_CALL
@@ -637,11 +640,8 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
 // launch): [0, 16) slot counter per XCD, [16] arrivals, [32 + i] barrier of
 // team i.
 template <typename T, bool WV, int R, int G>
-__global__ __launch_bounds__(512) void k_jacobi_team(const JacobiJob* __restrict__ jobs,
-                                                     const int* __restrict__ task_job,
-                                                     const int* __restrict__ task_slice, int ntasks,
-                                                     TeamSched sched, int max_sweeps, Ctrl* ctrl,
-                                                     int spin_limit) {
+__global__ __launch_bounds__(512) void k_jacobi_team(JacobiJob J1, int ntasks, TeamSched sched, int max_sweeps,
+                                                     Ctrl* ctrl, int spin_limit) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_scratch, s_flag, s_team, s_rank, s_nteams;
     __shared__ double s_nI[kTeamMaxThreads / 16], s_nJ[kTeamMaxThreads / 16];
@@ -679,10 +679,45 @@ __global__ __launch_bounds__(512) void k_jacobi_team(const JacobiJob* __restrict
     const int team = s_team, rank = s_rank, nteams = s_nteams;
     if (team < 0) return;
     TeamState ts{ctl + 32 + team, 0, W, spin_limit, ctrl};
-    for (int t = team; t < ntasks; t += nteams) {
-        const JacobiJob& J = jobs[task_job[t]];
+    for (int t = team; t < ntasks; t += nteams)
+        if (!team_task<T, R, G, WV>(J1, t, rank, ts, max_sweeps, lds, &s_scratch, &s_flag, s_nI, s_nJ)) return;
+}
+
+// ---------------------------------------------------------------------------
+// Batched kernel: one persistent launch for the slices of many tensors of
+// different shapes.  Workgroups take (tensor, slice) tasks from a device work
+// counter in the order of the task list (the host sorts it by estimated cost,
+// largest first).  A slice that fits in LDS runs the resident algorithm; a
+// larger one runs the block-pair algorithm with a team of one workgroup that
+// streams its block pairs through the L2 (no inter-workgroup waits).  Each
+// task is done by one workgroup with a fixed algorithm, so a tensor's result
+// does not depend on what else is in the batch.  512 threads; a streamed task
+// needs b * G == 512.
+// ---------------------------------------------------------------------------
+template <typename T, int R, int G>
+__global__ __launch_bounds__(512) void k_jacobi_batched(const JacobiJob* __restrict__ jobs,
+                                                        const int* __restrict__ task_job,
+                                                        const int* __restrict__ task_slice, int ntasks, int* queue,
+                                                        int max_sweeps, Ctrl* ctrl) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_scratch, s_flag, s_task;
+    __shared__ double s_nrm[kMaxRows];
+    T* lds = (T*)smem_raw;
+    for (;;) {
+        if (threadIdx.x == 0) s_task = atomicAdd(queue, 1);
+        __syncthreads();
+        const int t = s_task;
+        __syncthreads();
+        if (t >= ntasks) break;
+        const JacobiJob J = jobs[task_job[t]];
         const int k = task_slice[t];
-        if (!team_task<T, R, G, WV>(J, k, rank, ts, max_sweeps, lds, &s_scratch, &s_flag, s_nI, s_nJ)) return;
+        if (J.nb == 0) {
+            resident_task<T, R, G, false>(J, k, max_sweeps, ctrl, lds, &s_scratch, s_nrm);
+        } else {
+            TeamState ts{nullptr, 0, 1, 0, ctrl};
+            (void)team_task<T, R, G, false>(J, k, 0, ts, max_sweeps, lds, &s_scratch, &s_flag, s_nrm, s_nrm + 64);
+        }
+        __syncthreads();
     }
 }
 
@@ -739,51 +774,71 @@ static const void* team_fn(int prec, int with_v, int R, int G) {
 template <typename T, bool WV>
 static const void* res_fn() { return (const void*)k_jacobi_resident<T, WV>; }
 
-hipError_t launch_jacobi_resident(int prec, const JacobiJob* jobs_dev, int njobs, const int* task_job,
+hipError_t launch_jacobi_resident(int prec, const JacobiJob& job1, const JacobiJob* jobs_dev, const int* task_job,
                                   const int* task_slice, int ntasks, int max_sweeps, Ctrl* ctrl, int lds_bytes,
                                   int threads, int with_v, hipStream_t s) {
-    (void)njobs;
     if (ntasks <= 0) return hipSuccess;
     const void* f = prec == 0 ? (with_v ? res_fn<double, true>() : res_fn<double, false>())
                               : (with_v ? res_fn<float, true>() : res_fn<float, false>());
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
-    dim3 grid(ntasks), block(threads);
-    if (prec == 0) {
-        if (with_v)
-            hipLaunchKernelGGL((k_jacobi_resident<double, true>), grid, block, lds_bytes, s, jobs_dev, task_job,
-                               task_slice, ntasks, max_sweeps, ctrl);
-        else
-            hipLaunchKernelGGL((k_jacobi_resident<double, false>), grid, block, lds_bytes, s, jobs_dev, task_job,
-                               task_slice, ntasks, max_sweeps, ctrl);
-    } else {
-        if (with_v)
-            hipLaunchKernelGGL((k_jacobi_resident<float, true>), grid, block, lds_bytes, s, jobs_dev, task_job,
-                               task_slice, ntasks, max_sweeps, ctrl);
-        else
-            hipLaunchKernelGGL((k_jacobi_resident<float, false>), grid, block, lds_bytes, s, jobs_dev, task_job,
-                               task_slice, ntasks, max_sweeps, ctrl);
-    }
-    return hipGetLastError();
+    JacobiJob j1 = job1;
+    void* args[] = {(void*)&j1, (void*)&jobs_dev, (void*)&task_job, (void*)&task_slice,
+                    (void*)&ntasks, (void*)&max_sweeps, (void*)&ctrl};
+    return hipLaunchKernel(f, dim3(ntasks), dim3(threads), args, (size_t)lds_bytes, s);
 }
 
-hipError_t launch_jacobi_team(int prec, const JacobiJob* jobs_dev, int njobs, const int* task_job,
-                              const int* task_slice, int ntasks, const TeamSched& ts_in, int max_sweeps, Ctrl* ctrl,
-                              int lds_bytes, int threads, int with_v, int spin_limit, int R, int G, int coop,
+hipError_t launch_jacobi_team(int prec, const JacobiJob& job, int ntasks, const TeamSched& ts_in, int max_sweeps,
+                              Ctrl* ctrl, int lds_bytes, int threads, int with_v, int spin_limit, int R, int G, int coop,
                               hipStream_t s) {
-    (void)njobs;
     if (ntasks <= 0) return hipSuccess;
     const void* f = team_fn(prec, with_v, R, G);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
     TeamSched ts = ts_in;
-    void* args[] = {(void*)&jobs_dev, (void*)&task_job, (void*)&task_slice, (void*)&ntasks,
-                    (void*)&ts,       (void*)&max_sweeps, (void*)&ctrl,     (void*)&spin_limit};
+    JacobiJob j1 = job;
+    void* args[] = {(void*)&j1, (void*)&ntasks, (void*)&ts, (void*)&max_sweeps, (void*)&ctrl, (void*)&spin_limit};
     dim3 grid(ts.nwg), block(threads);
     if (coop) return hipLaunchCooperativeKernel(f, grid, block, args, (unsigned)lds_bytes, s);
     // plain launch (inside stream capture): the grid fits the device, and the
     // bounded team waits turn a non-resident team into an error, not a hang
     return hipLaunchKernel(f, grid, block, args, (size_t)lds_bytes, s);
+}
+
+template <typename T>
+static const void* batched_fn_t(int R, int G) {
+    if (G == 16) {
+        switch (R) {
+            case 4: return (const void*)k_jacobi_batched<T, 4, 16>;
+            case 8: return (const void*)k_jacobi_batched<T, 8, 16>;
+            case 12: return (const void*)k_jacobi_batched<T, 12, 16>;
+            default: return (const void*)k_jacobi_batched<T, 16, 16>;
+        }
+    }
+    switch (R) {
+        case 4: return (const void*)k_jacobi_batched<T, 4, 32>;
+        case 8: return (const void*)k_jacobi_batched<T, 8, 32>;
+        case 12: return (const void*)k_jacobi_batched<T, 12, 32>;
+        default: return (const void*)k_jacobi_batched<T, 16, 32>;
+    }
+}
+
+hipError_t launch_jacobi_batched(int prec, int R, int G, const JacobiJob* jobs_dev, const int* task_job,
+                                 const int* task_slice, int ntasks, int* queue, int max_sweeps, Ctrl* ctrl,
+                                 int lds_bytes, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
+    const void* f = prec == 0 ? batched_fn_t<double>(R, G) : batched_fn_t<float>(R, G);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+    int per_cu = 0, dev = 0, cus = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kTeamMaxThreads, lds_bytes);
+    if (e != hipSuccess) return e;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int grid = std::max(1, std::min(ntasks, std::max(1, per_cu) * cus));
+    void* args[] = {(void*)&jobs_dev, (void*)&task_job, (void*)&task_slice, (void*)&ntasks,
+                    (void*)&queue,    (void*)&max_sweeps, (void*)&ctrl};
+    return hipLaunchKernel(f, dim3(grid), dim3(kTeamMaxThreads), args, (size_t)lds_bytes, s);
 }
 
 int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v, int R, int G) {
