@@ -291,3 +291,90 @@ def tsvt_dct_batched(Zs: Sequence[torch.Tensor], taus: Sequence[float], Ys: Opti
     tp = (C.c_double * count)(*[float(t) for t in taus])
     ctx.check(lib.tsvt_dct_batched(ctx.h, prec, count, dims, zp, yp, tp, _stream(stream, d)))
     return list(Ys)
+
+
+class Server:
+    """Continuous-batching server over a context (tsvd_server_* in the header).
+
+    Host arrays are float32, shape (n1, n2, n3), any layout (copied in
+    column-major order at submit)."""
+
+    def __init__(self, budget_bytes: int, max_active: int, prec: int = FP32, ctx: Optional[Context] = None,
+                 device: int = 0):
+        import numpy as np  # noqa: F401
+
+        self.ctx = ctx or Context(device)
+        self._own_ctx = ctx is None
+        h = _vp()
+        rc = lib.tsvd_server_create(C.byref(h), self.ctx.h, prec, int(budget_bytes), int(max_active))
+        if rc != OK:
+            raise TsvdError(rc, "tsvd_server_create failed")
+        self.h = h
+        self.shapes = {}
+
+    @staticmethod
+    def _host(a):
+        import numpy as np
+
+        return np.asfortranarray(np.asarray(a, dtype=np.float32))
+
+    def _submit(self, req: "Request", shape) -> int:
+        rid = lib.tsvd_server_submit(self.h, C.byref(req))
+        if rid < 0:
+            raise TsvdError(int(rid), "submit refused")
+        self.shapes[rid] = shape
+        return rid
+
+    def submit_tsvt(self, Z, tau: float) -> int:
+        Z = self._host(Z)
+        n1, n2, n3 = Z.shape
+        req = Request(REQ_TSVT, n1, n2, n3, Z.ctypes.data_as(C.POINTER(C.c_float)), None, float(tau), 0, 0.0, 0.0)
+        return self._submit(req, Z.shape)
+
+    def submit_complete(self, B, mask, iters: int, tau0: float, tau1: float) -> int:
+        import numpy as np
+
+        B = self._host(B)
+        mk = np.asfortranarray(np.asarray(mask, dtype=np.uint8))
+        n1, n2, n3 = B.shape
+        req = Request(REQ_COMPLETE, n1, n2, n3, B.ctypes.data_as(C.POINTER(C.c_float)),
+                      mk.ctypes.data_as(C.POINTER(C.c_uint8)), 0.0, int(iters), float(tau0), float(tau1))
+        return self._submit(req, B.shape)
+
+    def poll(self, rid: int):
+        """None while running; else (result array, (t_submit, t_admit, t_done))."""
+        import numpy as np
+
+        shape = self.shapes[rid]
+        out = np.empty(shape, dtype=np.float32, order="F")
+        ts, ta, td = C.c_double(), C.c_double(), C.c_double()
+        rc = lib.tsvd_server_poll(self.h, rid, out.ctypes.data_as(C.POINTER(C.c_float)), C.byref(ts), C.byref(ta),
+                                  C.byref(td))
+        if rc == 0:
+            return None
+        del self.shapes[rid]
+        if rc < 0:
+            raise TsvdError(rc, "request %d failed" % rid)
+        return out, (ts.value, ta.value, td.value)
+
+    def now(self) -> float:
+        return lib.tsvd_server_now(self.h)
+
+    def stats(self) -> dict:
+        v = [C.c_int64() for _ in range(4)]
+        lib.tsvd_server_stats(self.h, *[C.byref(x) for x in v])
+        return dict(zip(("admitted", "completed", "ticks", "peak_bytes"), [x.value for x in v]))
+
+    def close(self):
+        if self.h:
+            lib.tsvd_server_destroy(self.h)
+            self.h = None
+        if self._own_ctx and self.ctx:
+            self.ctx.close()
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -902,21 +902,34 @@ int tsvt_dct_batched(tsvd_ctx* c, int prec, int count, const int64_t* dims, cons
     std::lock_guard<std::mutex> lk(c->mu);
     if (bad_prec(prec)) return fail(c, TSVD_EINVAL, "unknown precision");
     if (count <= 0 || !dims || !Z || !Y || !tau) return fail(c, TSVD_EINVAL, "bad batch arguments");
+    std::vector<BatchJobSpec> jb(count);
     for (int j = 0; j < count; ++j) {
         if (dims[3 * j] <= 0 || dims[3 * j + 1] <= 0 || dims[3 * j + 2] <= 0)
             return fail(c, TSVD_EINVAL, "sizes must be positive");
         if (!Z[j] || !Y[j]) return fail(c, TSVD_EINVAL, "null tensor pointer");
         if (!(tau[j] >= 0.0) || !isfinite(tau[j])) return fail(c, TSVD_EINVAL, "tau must be finite and >= 0");
+        jb[j] = BatchJobSpec{dims[3 * j], dims[3 * j + 1], dims[3 * j + 2], Z[j], Y[j], nullptr, nullptr, nullptr,
+                             nullptr, 1.0, tau[j]};
     }
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
+    int rc = batched_step_locked(c, prec, count, jb.data(), s);
+    if (rc) return rc;
+    return finish_call(c, s);
+}
+
+}  // extern "C"
+
+// Batched step shared by tsvt_dct_batched and the serving loop.  Called with
+// the context lock held.
+int batched_step_locked(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb, hipStream_t s) {
     std::vector<Plan> plans(count);
     Carve cv;
     int rc;
     int64_t ntasks = 0;
     for (int j = 0; j < count; ++j) {
-        if ((rc = make_plan(c, prec, dims[3 * j], dims[3 * j + 1], dims[3 * j + 2], 0, plans[j], cv, true))) return rc;
-        ntasks += dims[3 * j + 2];
+        if ((rc = make_plan(c, prec, jb[j].n1, jb[j].n2, jb[j].n3, 0, plans[j], cv, true))) return rc;
+        ntasks += jb[j].n3;
     }
     const size_t o_jobs = cv.take(sizeof(JacobiJob) * count);
     const size_t o_tj = cv.take(sizeof(int) * ntasks), o_tk = cv.take(sizeof(int) * ntasks);
@@ -962,8 +975,9 @@ int tsvt_dct_batched(tsvd_ctx* c, int prec, int count, const int64_t* dims, cons
         if ((e = launch_fill_zero(base + P.o_ctr_begin, P.o_ctr_end - P.o_ctr_begin, s)) != hipSuccess)
             return hip_fail(c, e, "fill");
         TubeArgs f{};
-        f.in = Z[j]; f.out = base + P.o_zbar; f.N = P.N; f.n3 = (int)P.n3; f.ctrl = cr.ctrl; f.check_finite = 1;
-        f.beta_val = 1.0;
+        f.out = base + P.o_zbar; f.N = P.N; f.n3 = (int)P.n3; f.ctrl = cr.ctrl; f.check_finite = 1;
+        f.beta_val = jb[j].X ? jb[j].beta : 1.0;
+        if (jb[j].X) { f.pX = jb[j].X; f.pM = jb[j].M; } else { f.in = jb[j].Z; }
         PhaseMark pm(c, 0, s);
         if ((rc = run_tube(c, prec, f, 0, s))) return rc;
     }
@@ -981,13 +995,35 @@ int tsvt_dct_batched(tsvd_ctx* c, int prec, int count, const int64_t* dims, cons
     }
     for (int j = 0; j < count; ++j) {
         Plan& P = plans[j];
-        if ((rc = enqueue_after_jacobi(c, P, base, cr.ctrl, tau[j], nullptr, s))) return rc;
+        if ((rc = enqueue_after_jacobi(c, P, base, cr.ctrl, jb[j].tau, nullptr, s))) return rc;
         TubeArgs iv{};
-        iv.in = base + P.o_ybar; iv.out = Y[j]; iv.N = P.N; iv.n3 = (int)P.n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
+        iv.in = base + P.o_ybar; iv.N = P.N; iv.n3 = (int)P.n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
+        if (jb[j].X) {
+            iv.eB = jb[j].B; iv.emask = jb[j].mask; iv.eX = jb[j].X; iv.eM = jb[j].M; iv.beta_val = jb[j].beta;
+        } else {
+            iv.out = jb[j].Y;
+        }
         PhaseMark pm(c, 3, s);
         if ((rc = run_tube(c, prec, iv, 1, s))) return rc;
     }
-    return finish_call(c, s);
+    return TSVD_OK;
 }
 
-}  // extern "C"
+int tsvd_batched_step_sync(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = batched_step_locked(c, prec, count, jb, s);
+    if (rc) return rc;
+    return read_status(c, s, nullptr);
+}
+
+size_t tsvd_batched_workspace_bytes(int prec, int64_t n1, int64_t n2, int64_t n3) {
+    // mirrors make_plan's regions (upper bound: counters and alignment)
+    const size_t es = prec == TSVD_FP64 ? 8 : 4;
+    const size_t m = (size_t)std::max(n1, n2), p = (size_t)std::min(n1, n2), N = (size_t)n1 * n2;
+    return es * (2 * N * n3 + 2 * m * p * n3 + p * p * n3) + 16 * p * n3 + 4 * n3 * (kMaxSweeps + 3) + 16 * 256 +
+           sizeof(JacobiJob) + 8 * n3;
+}
+
+int tsvd_ctx_device(const tsvd_ctx* c) { return c->device; }
+

@@ -144,6 +144,20 @@ struct SvtPrepArgs {
 };
 hipError_t launch_svt_prep(int prec, const SvtPrepArgs& a, hipStream_t s);
 
+// One batched step over many tensors (used by tsvt_dct_batched and the serving
+// loop).  Per tensor: either a plain t-SVT Z -> Y, or one completion iteration
+// with the fused prologue Z = X - M/beta and epilogue (X, M updated in place).
+struct BatchJobSpec {
+    int64_t n1, n2, n3;
+    const void* Z;        // plain t-SVT input (nullptr when X is given)
+    void* Y;              // plain t-SVT output
+    void* X;              // completion iterate (prologue input, epilogue in/out)
+    void* M;              // completion multiplier (in/out)
+    const void* B;        // observed data
+    const uint8_t* mask;  // observed set
+    double beta, tau;
+};
+
 // Small utility kernels.
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
 hipError_t launch_iter_advance(Ctrl* ctrl, double* norms, double* relchg_hist, int hist_len, hipStream_t s);
@@ -162,3 +176,13 @@ struct TsvdFinishArgs {
 hipError_t launch_tsvd_finish(int prec, const TsvdFinishArgs& a, hipStream_t s);
 
 }  // namespace tsvd
+
+// Internal entry points of the library used by the serving loop (C++ linkage).
+struct tsvd_ctx;
+int batched_step_locked(tsvd_ctx* c, int prec, int count, const tsvd::BatchJobSpec* jb, hipStream_t s);
+// Takes the context lock, runs one batched step on `s`, waits for it and
+// returns the device status (as tsvd_sync_status).
+int tsvd_batched_step_sync(tsvd_ctx* c, int prec, int count, const tsvd::BatchJobSpec* jb, hipStream_t s);
+// Bytes of workspace one batched step needs for a tensor of this shape.
+size_t tsvd_batched_workspace_bytes(int prec, int64_t n1, int64_t n2, int64_t n3);
+int tsvd_ctx_device(const tsvd_ctx* c);
