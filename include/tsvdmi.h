@@ -79,8 +79,12 @@ enum {
     TSVD_OPT_SPIN_LIMIT = 3,   /* polls before a device wait gives up (test hook; default 2^24) */
     TSVD_OPT_PROFILE = 4,      /* 1: record HIP events around every kernel phase on the launch
                                   stream (read with tsvd_get_stats); 0: off (default) */
-    TSVD_OPT_GRAPHS = 5        /* 1: complete_tensor replays one captured iteration as a HIP graph
+    TSVD_OPT_GRAPHS = 5,       /* 1: complete_tensor replays one captured iteration as a HIP graph
                                   (default; not while profiling); 0: direct launches */
+    TSVD_OPT_AUTOTUNE = 6,     /* 1: choose Jacobi tiles by timing the candidates (default); 0: the
+                                  built-in heuristic.  See tsvd_get_tile. */
+    TSVD_OPT_GROUP_LANES = 7   /* 0: automatic; 16 or 32: lanes per column-pair group in the Jacobi
+                                  kernels (a forced setting, like TEAM_SIZE, disables tuning) */
 };
 int tsvd_set_option(tsvd_ctx* ctx, int option, double value);
 double tsvd_get_option(const tsvd_ctx* ctx, int option);
@@ -90,6 +94,25 @@ double tsvd_get_option(const tsvd_ctx* ctx, int option);
  * TSVD_ENONFINITE or TSVD_ETIMEOUT).  *max_sweeps_out (may be NULL) gets the
  * largest Jacobi sweep count seen. */
 int tsvd_sync_status(tsvd_ctx* ctx, void* stream, int* max_sweeps_out);
+
+/* Jacobi tile of a tensor shape (the one the next call with this shape uses).
+ * A slice of a t-SVT is the tall m x p matrix, m = max(n1,n2), p = min(n1,n2)
+ * (Theorem 4 takes one SVD per transformed frontal slice); its column pairs
+ * are handled by groups of G lanes, either with the whole slice resident in
+ * one workgroup's LDS or by a team of W workgroups exchanging column blocks.
+ * With TSVD_OPT_AUTOTUNE on and no forced option, the first request for a
+ * shape class times every candidate tile on synthetic slices of that shape on
+ * the context's own stream (synchronizing the device and allocating a
+ * temporary buffer) and caches the fastest for the process; the class is
+ * (precision, m, p, n3, with_v), or (precision, m, p, with_v) for batched
+ * calls (batched != 0).  If the environment variable TSVDMI_TILE_CACHE names
+ * a file, tuned tiles are read from and appended to it.  No tuning happens
+ * while `stream` of a call is being captured.  Results of different tiles
+ * agree to the precision's tolerance, not bitwise.
+ * out[5]: team (0 resident, 1 team), G, W (0 when resident), workgroup size,
+ * source (0 heuristic, 1 autotuned, 2 forced by options). */
+int tsvd_get_tile(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, int batched, int with_v,
+                  int32_t* out);
 
 /* Counters since the last reset.  Phases: 0 forward transform (with the
  * completion prologue), 1 Jacobi SVD, 2 thresholding and rebuild, 3 inverse
@@ -167,12 +190,15 @@ int complete_tensor(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3,
                     const uint8_t* mask, void* X, const tsvd_complete_opts* opts, tsvd_complete_info* info,
                     void* stream);
 
-/* Batched t-SVT of `count` tensors of independent shapes in one pass of
- * launches (one launch per step, all tensors together; the Jacobi step is one
- * persistent launch that drains a device work list).  dims: HOST array of
- * 3*count sizes (n1,n2,n3 per tensor); Z, Y: HOST arrays of DEVICE pointers;
- * tau: HOST array of thresholds.  Each tensor's result is the same as a
- * tsvt_dct call on it alone (same tiles, same reduction order). */
+/* Batched t-SVT (Theorem 5 per tensor) of `count` tensors of independent
+ * shapes.  The Jacobi step of all tensors is one persistent launch per row
+ * geometry present (at most 8; usually 1 or 2), each draining a device work
+ * list of (tensor, slice) tasks, largest first.  dims: HOST array of 3*count
+ * sizes (n1,n2,n3 per tensor); Z, Y: HOST arrays of DEVICE pointers; tau:
+ * HOST array of thresholds.  A tensor's tile depends only on its own shape
+ * and each task is done by one workgroup, so its result is bitwise the same
+ * as in a batched call holding it alone; it agrees with tsvt_dct on it to the
+ * precision's tolerance (tsvt_dct may use a multi-workgroup team). */
 int tsvt_dct_batched(tsvd_ctx* ctx, int prec, int count, const int64_t* dims, const void* const* Z,
                      void* const* Y, const double* tau, void* stream);
 

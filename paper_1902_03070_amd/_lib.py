@@ -20,13 +20,14 @@ LIB_PATH = os.path.join(HERE, "libtsvdmi.so")
 FP64, FP32, MIXED = 0, 1, 2
 OK, WARN_NOCONV, EINVAL, ENOMEM, EHIP, ENONFINITE, EBUSY, ETIMEOUT = 0, 1, -1, -2, -3, -4, -5, -6
 OPT_MAX_SWEEPS, OPT_SYNC_STATUS, OPT_TEAM_SIZE, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_GRAPHS = 0, 1, 2, 3, 4, 5
+OPT_AUTOTUNE, OPT_GROUP_LANES = 6, 7
 PHASES = ("forward_transform", "jacobi", "threshold_rebuild", "inverse_transform")
 TRANSFORM_DOMAIN = 1
 REQ_TSVT, REQ_COMPLETE = 0, 1
 
 EXPORTED = [
     "tsvd_create", "tsvd_destroy", "tsvd_last_error", "tsvd_set_option", "tsvd_get_option", "tsvd_sync_status",
-    "tsvd_get_stats",
+    "tsvd_get_stats", "tsvd_get_tile",
     "tprod_dct", "tsvd_dct", "tsvt_dct", "complete_tensor", "tsvt_dct_batched", "tsvd_server_create",
     "tsvd_server_submit", "tsvd_server_poll", "tsvd_server_now", "tsvd_server_stats", "tsvd_server_destroy",
 ]
@@ -69,6 +70,7 @@ lib.tsvd_get_option.argtypes = [_vp, _i32]
 lib.tsvd_get_option.restype = _d
 lib.tsvd_sync_status.argtypes = [_vp, _vp, C.POINTER(C.c_int)]
 lib.tsvd_get_stats.argtypes = [_vp, _vp, C.POINTER(Stats), _i32]
+lib.tsvd_get_tile.argtypes = [_vp, _i32, _i64, _i64, _i64, _i32, _i32, C.POINTER(C.c_int32)]
 lib.tprod_dct.argtypes = [_vp, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp]
 lib.tsvd_dct.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _i32, _vp]
 lib.tsvt_dct.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _d, C.POINTER(C.c_int32), _vp]
@@ -132,6 +134,12 @@ class Context:
         return {"slice_sweeps": st.slice_sweeps,
                 "ms": {PHASES[i]: st.ms[i] for i in range(4)},
                 "launches": {PHASES[i]: st.launches[i] for i in range(4)}}
+
+    def tile(self, prec: int, n1: int, n2: int, n3: int, batched: bool = False, with_v: bool = False) -> dict:
+        """Jacobi tile this context uses for the shape (tunes it if needed)."""
+        out = (C.c_int32 * 5)()
+        self.check(lib.tsvd_get_tile(self.h, prec, n1, n2, n3, int(batched), int(with_v), out))
+        return dict(zip(("team", "G", "W", "threads", "source"), list(out)))
 
     def sync_status(self, stream=None):
         ms = C.c_int(0)

@@ -27,6 +27,8 @@ struct tsvd_ctx {
     int max_sweeps = 30;
     int sync_status = 1;
     int team_size = 0;
+    int group_lanes = 0;
+    int autotune = 1;
     int spin_limit = 1 << 24;
     std::string err = "";
     // transform matrices: (n3, prec) -> {C, C^T} rows, element type by prec
@@ -267,6 +269,7 @@ struct Plan {
     int m = 0, p = 0, trans = 0, with_v = 0;
     int team = 0;        // 0: resident kernel; 1: team kernel
     int threads = 256;
+    int tile_source = 0, tile_W = 0;
     int lds = 0;
     TeamSched ts{};
     JacobiJob job{};
@@ -275,62 +278,356 @@ struct Plan {
     size_t o_ctr_begin, o_ctr_end;  // region zeroed per call (counters)
 };
 
-int choose_team(tsvd_ctx* c, Plan& P) {
-    int G, R, ldv;
-    jacobi_geometry(P.m, P.p, &G, &R, &ldv);
-    const int bstep = std::max(2, kWave / G);  // b * G must fill whole wavefronts
-    const int bmax = kTeamMaxThreads / G;
-    int W = c->team_size > 0 ? c->team_size : (P.p + 63) / 64;
-    if (W < 1) W = 1;
+// ---------------------------------------------------------------------------
+// Jacobi tiles: how one tensor's slices map onto workgroups.
+//   team 0: one workgroup per slice, the whole slice resident in LDS,
+//           `threads` lanes (threads / G column-pair groups);
+//   team 1: W workgroups per slice exchanging column blocks through the L2
+//           (batched plans: a team of one workgroup of kTeamMaxThreads lanes).
+// ---------------------------------------------------------------------------
+struct Tile {
+    int team = 0;
+    int G = 16;
+    int W = 0;
+    int threads = 0;
+    int source = 0;  // 0 default heuristic, 1 autotuned, 2 forced by options
+};
+
+// Resident workgroup size: one group of G lanes per column pair of a round
+// (at most 1024 lanes), or half as many groups (each takes two pairs).
+int resident_threads(int p, int G, int halve) {
+    const int per_wave = kWave / G;
+    int ngrp = std::min((p + 1) / 2, 1024 / G);
+    if (halve) ngrp = (ngrp + 1) / 2;
+    ngrp = (ngrp + per_wave - 1) / per_wave * per_wave;
+    return std::max(kWave, ngrp * G);
+}
+
+// Fill the Jacobi part of a plan from a tile.  Fails when the tile cannot
+// hold the slice (LDS, residency, row geometry).
+int apply_tile(tsvd_ctx* c, Plan& P, const Tile& t, bool batched) {
+    int R, ldv;
+    if (jacobi_geometry_g(P.m, P.p, t.G, &R, &ldv)) return fail(c, TSVD_EINVAL, "lane group cannot hold the slice rows");
+    P.job.G = t.G;
+    P.job.R = R;
+    P.job.ldv = ldv;
+    if (!t.team) {
+        const int rl = jacobi_resident_lds_bytes(P.prec, P.m, P.p, t.G, P.with_v);
+        if (rl > kLdsBudget) return fail(c, TSVD_EINVAL, "slice does not fit in LDS");
+        P.team = 0;
+        P.lds = rl;
+        P.threads = batched ? kTeamMaxThreads : t.threads;
+        if (P.threads < kWave || P.threads > 1024 || P.threads % t.G) return fail(c, TSVD_EINVAL, "bad workgroup size");
+        P.job.b = 0;
+        P.job.nb = 0;
+        P.ts = TeamSched{1, 0, nullptr};
+        return TSVD_OK;
+    }
+    P.team = 1;
+    if (batched) {
+        // a team of one workgroup with b G == kTeamMaxThreads
+        const int b = kTeamMaxThreads / t.G;
+        if (jacobi_team_lds_bytes(P.prec, P.m, P.p, t.G, b, P.with_v) > kLdsBudget)
+            return fail(c, TSVD_EINVAL, "slice too large for the batched Jacobi kernel");
+        int nb = (P.p + b - 1) / b;
+        nb += nb & 1;
+        P.lds = jacobi_team_lds_bytes(P.prec, P.m, P.p, t.G, b, P.with_v);
+        P.threads = kTeamMaxThreads;
+        P.ts = TeamSched{1, 1, nullptr};
+        P.job.b = b;
+        P.job.nb = nb;
+        return TSVD_OK;
+    }
+    const int bstep = std::max(2, kWave / t.G);  // b G must fill whole wavefronts
+    const int bmax = kTeamMaxThreads / t.G;
+    int W = std::max(1, t.W);
     int b = (P.p + 2 * W - 1) / (2 * W);
     b = (b + bstep - 1) / bstep * bstep;
     b = std::min(b, bmax);
-    while (b > bstep && jacobi_team_lds_bytes(P.prec, P.m, P.p, b, P.with_v) > kLdsBudget) b -= bstep;
-    if (jacobi_team_lds_bytes(P.prec, P.m, P.p, b, P.with_v) > kLdsBudget)
+    while (b > bstep && jacobi_team_lds_bytes(P.prec, P.m, P.p, t.G, b, P.with_v) > kLdsBudget) b -= bstep;
+    if (jacobi_team_lds_bytes(P.prec, P.m, P.p, t.G, b, P.with_v) > kLdsBudget)
         return fail(c, TSVD_EINVAL, "slice too large for the Jacobi team kernel");
     int nb = (P.p + b - 1) / b;
     nb += nb & 1;
     if (W > nb / 2) W = nb / 2;
-    P.lds = jacobi_team_lds_bytes(P.prec, P.m, P.p, b, P.with_v);
-    P.threads = b * G;
-    const int cap = jacobi_team_max_resident(P.prec, P.lds, P.threads, P.with_v, R, G);
+    P.lds = jacobi_team_lds_bytes(P.prec, P.m, P.p, t.G, b, P.with_v);
+    P.threads = b * t.G;
+    const int cap = jacobi_team_max_resident(P.prec, P.lds, P.threads, P.with_v, R, t.G);
     if (cap < 8) return fail(c, TSVD_EINVAL, "Jacobi team kernel cannot be resident with this shape");
     // whole teams on every XCD: the grid is a multiple of 8 W workgroups
     W = std::min(W, cap / 8);
-    int per_xcd = std::max(1, std::min(((int)P.n3 + 7) / 8, cap / (8 * W)));
+    const int per_xcd = std::max(1, std::min(((int)P.n3 + 7) / 8, cap / (8 * W)));
     P.ts.W = W;
     P.ts.nwg = 8 * W * per_xcd;
     P.job.b = b;
     P.job.nb = nb;
-    P.job.G = G;
-    P.job.R = R;
-    P.job.ldv = ldv;
     return TSVD_OK;
 }
 
-// Batched plans: a slice that does not fit in LDS gets a team of one
-// workgroup with b * G == kTeamMaxThreads (the batched kernel's block size).
-int choose_single_wg(tsvd_ctx* c, Plan& P) {
+// Lane-group widths worth trying: those with the fewest padded rows R G.
+std::vector<int> group_widths(int m, int p) {
+    std::vector<int> out;
+    int best = 1 << 30;
+    for (int G : {16, 32}) {
+        int R, ldv;
+        if (!jacobi_geometry_g(m, p, G, &R, &ldv)) best = std::min(best, R * G);
+    }
+    for (int G : {16, 32}) {
+        int R, ldv;
+        if (!jacobi_geometry_g(m, p, G, &R, &ldv) && R * G == best) out.push_back(G);
+    }
+    return out;
+}
+
+Tile default_tile(const Plan& P, int team_size, int group_lanes) {
+    Tile t;
     int G, R, ldv;
     jacobi_geometry(P.m, P.p, &G, &R, &ldv);
-    const int b = kTeamMaxThreads / G;
-    if (jacobi_team_lds_bytes(P.prec, P.m, P.p, b, P.with_v) > kLdsBudget)
-        return fail(c, TSVD_EINVAL, "slice too large for the batched Jacobi kernel");
-    int nb = (P.p + b - 1) / b;
-    nb += nb & 1;
-    P.lds = jacobi_team_lds_bytes(P.prec, P.m, P.p, b, P.with_v);
-    P.threads = kTeamMaxThreads;
-    P.ts = TeamSched{1, 1, nullptr};
-    P.job.b = b;
-    P.job.nb = nb;
-    P.job.G = G;
-    P.job.R = R;
-    P.job.ldv = ldv;
+    t.G = group_lanes ? group_lanes : G;
+    t.team = jacobi_resident_lds_bytes(P.prec, P.m, P.p, t.G, P.with_v) > kLdsBudget;
+    t.W = t.team ? (team_size > 0 ? team_size : std::max(1, (P.p + 63) / 64)) : 0;
+    t.threads = t.team ? 0 : resident_threads(P.p, t.G, 0);
+    return t;
+}
+
+std::vector<Tile> tile_candidates(const Plan& P, bool batched) {
+    std::vector<Tile> out;
+    for (int G : group_widths(P.m, P.p)) {
+        Tile t;
+        t.G = G;
+        t.team = jacobi_resident_lds_bytes(P.prec, P.m, P.p, G, P.with_v) > kLdsBudget;
+        if (batched) {
+            t.threads = kTeamMaxThreads;
+            out.push_back(t);
+        } else if (!t.team) {
+            for (int h = 0; h < 2; ++h) {
+                t.threads = resident_threads(P.p, G, h);
+                if (out.empty() || out.back().threads != t.threads || out.back().G != G) out.push_back(t);
+            }
+        } else {
+            for (int W : {1, 2, 3, 4, 6, 8}) {
+                t.W = W;
+                out.push_back(t);
+            }
+        }
+    }
+    return out;
+}
+
+// ---- process-wide tile cache -----------------------------------------------
+// Key: (batched, prec, m, p, n3, with_v); batched plans ignore n3.  When the
+// environment variable TSVDMI_TILE_CACHE names a file, it is read at first
+// use and every newly tuned tile is appended to it, one line per tile:
+//   tile <batched> <prec> <m> <p> <n3> <with_v> <team> <G> <W> <threads> <microseconds>
+typedef std::tuple<int, int, int, int, int, int> TileKey;
+std::mutex g_tile_mu;
+std::map<TileKey, Tile> g_tiles;
+bool g_tiles_loaded = false;
+
+void tile_cache_load_locked() {
+    if (g_tiles_loaded) return;
+    g_tiles_loaded = true;
+    const char* path = getenv("TSVDMI_TILE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        int k[6], team, G, W, th;
+        double us;
+        if (sscanf(line, "tile %d %d %d %d %d %d %d %d %d %d %lf", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &team, &G,
+                   &W, &th, &us) != 11)
+            continue;
+        Tile t;
+        t.team = team; t.G = G; t.W = W; t.threads = th; t.source = 1;
+        g_tiles[TileKey(k[0], k[1], k[2], k[3], k[4], k[5])] = t;
+    }
+    fclose(f);
+}
+
+bool tile_cache_get(const TileKey& k, Tile* t) {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    tile_cache_load_locked();
+    auto it = g_tiles.find(k);
+    if (it == g_tiles.end()) return false;
+    *t = it->second;
+    return true;
+}
+
+void tile_cache_put(const TileKey& k, const Tile& t, double us) {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    tile_cache_load_locked();
+    g_tiles[k] = t;
+    const char* path = getenv("TSVDMI_TILE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "tile %d %d %d %d %d %d %d %d %d %d %.1f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+            std::get<3>(k), std::get<4>(k), std::get<5>(k), t.team, t.G, t.W, t.threads, us);
+    fclose(f);
+}
+
+// ---- the tuner --------------------------------------------------------------
+// Times every candidate tile on synthetic slices of the plan's shape (a
+// deterministic pattern, kTuneSweeps sweeps with rotation threshold 0 so that
+// every candidate does the same work) on the context's own stream, and keeps
+// the fastest.  Runs once per key per process.
+constexpr int kTuneSweeps = 3;
+constexpr int kTuneReps = 3;
+constexpr int kTuneBatchTasks = 64;
+
+int ensure_own_stream(tsvd_ctx* c) {
+    if (!c->own) HIPCHK(c, hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+    return TSVD_OK;
+}
+
+// Time one candidate; returns microseconds per launch or a negative value.
+double time_tile(tsvd_ctx* c, const Plan& P0, const Tile& t, bool batched, char* tb, size_t o_src, size_t o_A,
+                 size_t o_V, size_t o_cnt, size_t cnt_bytes, size_t o_jobs, size_t o_tj, size_t o_tk, int ntasks,
+                 hipEvent_t e0, hipEvent_t e1) {
+    Plan P = P0;
+    if (apply_tile(c, P, t, batched)) return -1.0;
+    JacobiJob& J = P.job;
+    J.src = tb + o_src;
+    J.A = tb + o_A;
+    J.V = P.with_v ? (void*)(tb + o_V) : nullptr;
+    J.src_ss = (int64_t)P.m * P.p; J.src_rs = 1; J.src_cs = P.m;
+    J.m = P.m;
+    J.p = P.p;
+    J.n3 = ntasks;
+    J.tol = 0.0;
+    J.refine64 = 0;
+    // counters: [Ctrl 256][queue 256][sweeps 4 ntasks][rot 4 ntasks kMaxSweeps][team ctl]
+    char* cnt = tb + o_cnt;
+    Ctrl* ctrl = (Ctrl*)cnt;
+    int* queue = (int*)(cnt + 256);
+    J.sweeps = (int*)(cnt + 512);
+    J.rot = (int*)(cnt + 512 + align256((size_t)4 * ntasks));
+    P.ts.ctl = (int*)(cnt + 512 + align256((size_t)4 * ntasks) + align256((size_t)4 * ntasks * kMaxSweeps));
+    if (batched && hipMemcpy(tb + o_jobs, &J, sizeof(JacobiJob), hipMemcpyHostToDevice) != hipSuccess) return -1.0;
+    hipStream_t s = c->own;
+    double best = -1.0;
+    for (int rep = 0; rep <= kTuneReps; ++rep) {
+        if (launch_fill_zero(cnt, (int64_t)cnt_bytes, s) != hipSuccess) return -1.0;
+        if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
+        hipError_t e;
+        if (batched)
+            e = launch_jacobi_batched(P.prec == TSVD_FP64 ? 0 : 1, J.R, J.G, (const JacobiJob*)(tb + o_jobs),
+                                      (const int*)(tb + o_tj), (const int*)(tb + o_tk), ntasks, queue, kTuneSweeps,
+                                      ctrl, P.lds, s);
+        else if (!P.team)
+            e = launch_jacobi_resident(P.prec, J, nullptr, nullptr, nullptr, ntasks, kTuneSweeps, ctrl, P.lds,
+                                       P.threads, P.with_v, s);
+        else
+            e = launch_jacobi_team(P.prec, J, ntasks, P.ts, kTuneSweeps, ctrl, P.lds, P.threads, P.with_v,
+                                   c->spin_limit, J.R, J.G, 1, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return -1.0;
+        }
+        if (hipEventRecord(e1, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return -1.0;
+        Ctrl h;
+        if (hipMemcpy(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess) return -1.0;
+        // every slice must have run every sweep (threshold 0 never converges)
+        if ((h.status & (kStTimeout | kStNonFinite)) || h.slice_sweeps != (unsigned long long)ntasks * kTuneSweeps)
+            return -1.0;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
+        if (rep > 0 && (best < 0.0 || 1e3 * ms < best)) best = 1e3 * ms;  // first run warms up
+    }
+    return best;
+}
+
+int tune_tile(tsvd_ctx* c, const Plan& P, bool batched, Tile* out, double* us_out) {
+    std::vector<Tile> cands = tile_candidates(P, batched);
+    if (cands.size() < 2) return -1;
+    int rc = ensure_own_stream(c);
+    if (rc) return rc;
+    const size_t es = esize(P.prec);
+    const int ntasks = batched ? kTuneBatchTasks : (int)P.n3;
+    const size_t slice = (size_t)P.m * P.p;
+    Carve cv;
+    const size_t o_src = cv.take(slice * ntasks * es), o_A = cv.take(slice * ntasks * es);
+    const size_t o_V = cv.take(P.with_v ? (size_t)P.p * P.p * ntasks * es : 0);
+    const size_t o_jobs = cv.take(sizeof(JacobiJob)), o_tj = cv.take((size_t)4 * ntasks),
+                 o_tk = cv.take((size_t)4 * ntasks);
+    const size_t cnt_bytes = 512 + align256((size_t)4 * ntasks) + align256((size_t)4 * ntasks * kMaxSweeps) +
+                             (size_t)4 * (kTeamCtlInts + 8 * 64 * 64);
+    const size_t o_cnt = cv.take(cnt_bytes);
+    char* tb = nullptr;
+    if (hipMalloc((void**)&tb, cv.off) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double best_us = -1.0;
+    Tile best;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    if (ok) {
+        std::vector<int> tj(ntasks, 0), tk(ntasks);
+        for (int i = 0; i < ntasks; ++i) tk[i] = i;
+        ok = launch_fill_pattern(tb + o_src, (int64_t)slice * ntasks, P.prec == TSVD_FP64 ? 0 : 1, 12345u, c->own) ==
+                 hipSuccess &&
+             hipMemcpy(tb + o_tj, tj.data(), 4 * ntasks, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(tb + o_tk, tk.data(), 4 * ntasks, hipMemcpyHostToDevice) == hipSuccess &&
+             hipStreamSynchronize(c->own) == hipSuccess;
+    }
+    std::vector<std::tuple<int, int, int, int, int>> seen;  // (team, G, threads, b, nwg) of applied plans
+    for (size_t i = 0; ok && i < cands.size(); ++i) {
+        Plan Q = P;
+        if (apply_tile(c, Q, cands[i], batched)) continue;
+        auto sig = std::make_tuple(Q.team, Q.job.G, Q.threads, Q.job.b, Q.ts.nwg);
+        if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
+        seen.push_back(sig);
+        const double us = time_tile(c, P, cands[i], batched, tb, o_src, o_A, o_V, o_cnt, cnt_bytes, o_jobs, o_tj, o_tk,
+                                    ntasks, e0, e1);
+        if (us > 0.0 && (best_us < 0.0 || us < best_us)) {
+            best_us = us;
+            best = cands[i];
+        }
+    }
+    (void)hipStreamSynchronize(c->own);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(tb);
+    (void)hipGetLastError();
+    c->err.clear();
+    if (best_us < 0.0) return -1;
+    best.source = 1;
+    *out = best;
+    *us_out = best_us;
+    return TSVD_OK;
+}
+
+// The tile of a plan: forced by options, cached, autotuned, or the default.
+int pick_tile(tsvd_ctx* c, const Plan& P, bool batched, hipStream_t s, Tile* t) {
+    if (c->team_size > 0 || c->group_lanes > 0) {
+        *t = default_tile(P, c->team_size, c->group_lanes);
+        t->source = 2;
+        return TSVD_OK;
+    }
+    const TileKey key(batched ? 1 : 0, P.prec, P.m, P.p, batched ? 0 : (int)P.n3, P.with_v);
+    if (tile_cache_get(key, t)) return TSVD_OK;
+    *t = default_tile(P, 0, 0);
+    if (!c->autotune) return TSVD_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return TSVD_OK;  // no timing inside a capture: default tile, not cached
+    }
+    Tile tuned;
+    double us = 0.0;
+    if (tune_tile(c, P, batched, &tuned, &us) == TSVD_OK) {
+        tile_cache_put(key, tuned, us);
+        *t = tuned;
+    } else {
+        tile_cache_put(key, *t, 0.0);  // one candidate, or tuning failed: remember the default
+    }
     return TSVD_OK;
 }
 
 int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int with_v, Plan& P, Carve& cv,
-              bool batched = false) {
+              hipStream_t s, bool batched = false) {
     P.prec = prec;
     P.n1 = n1; P.n2 = n2; P.n3 = n3; P.N = n1 * n2;
     P.trans = n1 < n2;
@@ -340,27 +637,12 @@ int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int wit
     if (P.m > kMaxRows) return fail(c, TSVD_EINVAL, "frontal slices larger than 512 rows/columns are not supported");
     const size_t es = esize(prec);
     const size_t slice = (size_t)n1 * n2;
-    const int rl = jacobi_resident_lds_bytes(prec, P.m, P.p, with_v);
-    if (rl <= kLdsBudget) {
-        P.team = 0;
-        P.lds = rl;
-        int G, R, ldv;
-        jacobi_geometry(P.m, P.p, &G, &R, &ldv);
-        const int per_wave = kWave / G;
-        int ngrp = std::min((P.p + 1) / 2, 1024 / G);
-        ngrp = (ngrp + per_wave - 1) / per_wave * per_wave;
-        P.threads = std::max(kWave, ngrp * G);
-        P.job.G = G;
-        P.job.R = R;
-        P.job.ldv = ldv;
-        P.job.b = 0;
-        P.job.nb = 0;
-        P.ts = TeamSched{1, 0, nullptr};
-    } else {
-        P.team = 1;
-        int rc = batched ? choose_single_wg(c, P) : choose_team(c, P);
-        if (rc) return rc;
-    }
+    Tile t;
+    int rc = pick_tile(c, P, batched, s, &t);
+    if (rc) return rc;
+    if ((rc = apply_tile(c, P, t, batched))) return rc;
+    P.tile_source = t.source;
+    P.tile_W = t.W;
     P.o_zbar = cv.take(slice * n3 * es);
     P.o_A = cv.take((size_t)P.m * P.p * n3 * es);
     P.o_F = cv.take((size_t)P.m * P.p * n3 * es);
@@ -551,6 +833,11 @@ int tsvd_set_option(tsvd_ctx* c, int opt, double v) {
             return TSVD_OK;
         case TSVD_OPT_PROFILE: c->prof = v != 0.0; return TSVD_OK;
         case TSVD_OPT_GRAPHS: c->use_graphs = v != 0.0; return TSVD_OK;
+        case TSVD_OPT_AUTOTUNE: c->autotune = v != 0.0; return TSVD_OK;
+        case TSVD_OPT_GROUP_LANES:
+            if (v != 0 && v != 16 && v != 32) return fail(c, TSVD_EINVAL, "group lanes must be 0, 16 or 32");
+            c->group_lanes = (int)v;
+            return TSVD_OK;
     }
     return fail(c, TSVD_EINVAL, "unknown option");
 }
@@ -564,8 +851,29 @@ double tsvd_get_option(const tsvd_ctx* c, int opt) {
         case TSVD_OPT_SPIN_LIMIT: return c->spin_limit;
         case TSVD_OPT_PROFILE: return c->prof;
         case TSVD_OPT_GRAPHS: return c->use_graphs;
+        case TSVD_OPT_AUTOTUNE: return c->autotune;
+        case TSVD_OPT_GROUP_LANES: return c->group_lanes;
     }
     return -1.0;
+}
+
+int tsvd_get_tile(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int batched, int with_v,
+                  int32_t* out) {
+    if (!c || !out) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (bad_prec(prec)) return fail(c, TSVD_EINVAL, "unknown precision");
+    if (n1 <= 0 || n2 <= 0 || n3 <= 0) return fail(c, TSVD_EINVAL, "sizes must be positive");
+    HIPCHK(c, hipSetDevice(c->device));
+    Plan P;
+    Carve cv;
+    int rc = make_plan(c, prec, n1, n2, n3, with_v ? 1 : 0, P, cv, nullptr, batched != 0);
+    if (rc) return rc;
+    out[0] = P.team;
+    out[1] = P.job.G;
+    out[2] = P.team ? P.ts.W : 0;
+    out[3] = P.threads;
+    out[4] = P.tile_source;
+    return TSVD_OK;
 }
 
 int tsvd_sync_status(tsvd_ctx* c, void* stream, int* max_sweeps_out) {
@@ -615,7 +923,7 @@ int tsvt_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
     hipStream_t s = (hipStream_t)stream;
     Plan P;
     Carve cv;
-    int rc = make_plan(c, prec, n1, n2, n3, 0, P, cv);
+    int rc = make_plan(c, prec, n1, n2, n3, 0, P, cv, s);
     if (rc) return rc;
     if ((rc = ensure_ws(c, P.o_end))) return rc;
     char* base = (char*)c->ws.p;
@@ -700,7 +1008,7 @@ int tsvd_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
     hipStream_t s = (hipStream_t)stream;
     Plan P;
     Carve cv;
-    int rc = make_plan(c, prec, n1, n2, n3, 1, P, cv);
+    int rc = make_plan(c, prec, n1, n2, n3, 1, P, cv, s);
     if (rc) return rc;
     const size_t es = esize(prec);
     const size_t oU = cv.take((size_t)n1 * P.p * n3 * es), oV = cv.take((size_t)n2 * P.p * n3 * es);
@@ -773,7 +1081,7 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
     hipStream_t s = (hipStream_t)stream;
     Plan P;
     Carve cv;
-    int rc = make_plan(c, prec, n1, n2, n3, 0, P, cv);
+    int rc = make_plan(c, prec, n1, n2, n3, 0, P, cv, s);
     if (rc) return rc;
     const size_t es = esize(prec);
     const size_t oM = cv.take((size_t)P.N * n3 * es);
@@ -928,7 +1236,7 @@ int batched_step_locked(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb
     int rc;
     int64_t ntasks = 0;
     for (int j = 0; j < count; ++j) {
-        if ((rc = make_plan(c, prec, jb[j].n1, jb[j].n2, jb[j].n3, 0, plans[j], cv, true))) return rc;
+        if ((rc = make_plan(c, prec, jb[j].n1, jb[j].n2, jb[j].n3, 0, plans[j], cv, s, true))) return rc;
         ntasks += jb[j].n3;
     }
     const size_t o_jobs = cv.take(sizeof(JacobiJob) * count);

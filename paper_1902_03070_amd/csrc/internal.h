@@ -110,9 +110,14 @@ hipError_t launch_jacobi_team(int prec, const JacobiJob& job, int ntasks, const 
 hipError_t launch_jacobi_batched(int prec, int R, int G, const JacobiJob* jobs_dev, const int* task_job,
                                  const int* task_slice, int ntasks, int* queue, int max_sweeps, Ctrl* ctrl,
                                  int lds_bytes, hipStream_t s);
+// Row geometry of a tall m x p slice: G lanes per column pair (16 or 32), R
+// rows per lane (4, 8, 12 or 16, R G >= m), ldv the padded V column length.
+// jacobi_geometry picks the default G; jacobi_geometry_g returns -1 when G
+// cannot hold m rows.
 void jacobi_geometry(int m, int p, int* G, int* R, int* ldv);
-int jacobi_resident_lds_bytes(int prec, int m, int p, int with_v);
-int jacobi_team_lds_bytes(int prec, int m, int p, int b, int with_v);
+int jacobi_geometry_g(int m, int p, int G, int* R, int* ldv);
+int jacobi_resident_lds_bytes(int prec, int m, int p, int G, int with_v);
+int jacobi_team_lds_bytes(int prec, int m, int p, int G, int b, int with_v);
 int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v, int R, int G);
 
 // Batched strided GEMM with optional per-batch K (ranks) and column scale.
@@ -160,6 +165,8 @@ struct BatchJobSpec {
 
 // Small utility kernels.
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
+// n values of a deterministic pseudo-random pattern in [-1, 1) (prec 0: double, else float).
+hipError_t launch_fill_pattern(void* p, int64_t n, int prec, uint32_t seed, hipStream_t s);
 hipError_t launch_iter_advance(Ctrl* ctrl, double* norms, double* relchg_hist, int hist_len, hipStream_t s);
 // Sort singular values descending per slice and build U = A'(:,perm)/sigma, with the
 // sign convention, and permute V; used by tsvd_dct.

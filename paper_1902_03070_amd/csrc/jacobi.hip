@@ -410,11 +410,14 @@ struct TeamState {
 __device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg((15 << 11) | 20) & 0xF; }
 
 // Team barrier.  Each wavefront first waits for its own global stores to be
-// acknowledged (vmcnt(0)); then one lane per workgroup performs a device-scope
-// release, arrives on the team counter, waits for the team with a bounded
+// acknowledged by the L2 (vmcnt(0)); then one lane per workgroup arrives on
+// the team counter (a device-scope atomic), waits for the team with a bounded
 // spin, and performs a device-scope acquire (which invalidates the CU's L1)
-// before the workgroup proceeds.  Teams are formed on one XCD, so the blocks
-// they exchange stay in that XCD's L2.  Returns false when the wait gave up.
+// before the workgroup proceeds.  All workgroups of a team run on one XCD and
+// so share one L2: the exchanged blocks are visible to the partner as soon as
+// the stores are acknowledged, and the release needs no L2 write-back (a
+// device-scope release would write the XCD's dirty L2 lines back to memory at
+// every barrier).  Returns false when the wait gave up.
 __device__ bool team_barrier(TeamState& ts, int* s_flag) {
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's stores are complete
     __syncthreads();
@@ -422,7 +425,7 @@ __device__ bool team_barrier(TeamState& ts, int* s_flag) {
     if (threadIdx.x == 0) {
         *s_flag = 0;
         if (ts.W > 1) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // XCD-local team: see above
             __hip_atomic_fetch_add(ts.bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const int target = ts.passed * ts.W;
             int it = 0;
@@ -726,26 +729,33 @@ __global__ __launch_bounds__(512) void k_jacobi_batched(const JacobiJob* __restr
 // ---------------------------------------------------------------------------
 static int elem_size(int prec) { return prec == 0 ? 8 : 4; }
 
-void jacobi_geometry(int m, int p, int* G, int* R, int* ldv) {
-    *G = m <= 256 ? 16 : 32;
-    int r = (m + *G - 1) / *G;
+int jacobi_geometry_g(int m, int p, int G, int* R, int* ldv) {
+    if (G != 16 && G != 32) return -1;
+    int r = (m + G - 1) / G;
     r = (r + 3) / 4 * 4;
     if (r < 4) r = 4;
+    if (r > 16) return -1;
     *R = r;
-    *ldv = ((p + *G - 1) / *G) * *G;
+    *ldv = ((p + G - 1) / G) * G;
+    return 0;
 }
 
-int jacobi_resident_lds_bytes(int prec, int m, int p, int with_v) {
-    int G, R, ldv;
-    jacobi_geometry(m, p, &G, &R, &ldv);
+void jacobi_geometry(int m, int p, int* G, int* R, int* ldv) {
+    *G = m <= 256 ? 16 : 32;
+    (void)jacobi_geometry_g(m, p, *G, R, ldv);
+}
+
+int jacobi_resident_lds_bytes(int prec, int m, int p, int G, int with_v) {
+    int R, ldv;
+    if (jacobi_geometry_g(m, p, G, &R, &ldv)) return 1 << 30;
     const int pp = p + (p & 1);
     const int64_t elems = (int64_t)pp * (R * G + kLdsPad) + (with_v ? (int64_t)pp * ldv : 0);
     return (int)(elems * elem_size(prec));
 }
 
-int jacobi_team_lds_bytes(int prec, int m, int p, int b, int with_v) {
-    int G, R, ldv;
-    jacobi_geometry(m, p, &G, &R, &ldv);
+int jacobi_team_lds_bytes(int prec, int m, int p, int G, int b, int with_v) {
+    int R, ldv;
+    if (jacobi_geometry_g(m, p, G, &R, &ldv)) return 1 << 30;
     const int64_t elems = (int64_t)2 * b * (R * G + kLdsPad) + (with_v ? (int64_t)2 * b * ldv : 0);
     return (int)(elems * elem_size(prec));
 }

@@ -346,6 +346,35 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Deterministic test pattern in [-1, 1): a 32-bit integer hash of (index,
+// seed) (the "lowbias32" mixer: xorshift-multiply rounds), top 24 bits scaled.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+template <typename T>
+__global__ void k_fill_pattern(T* p, int64_t n, uint32_t seed) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t h = mix32((uint32_t)i ^ mix32(seed + (uint32_t)(i >> 32)));
+        p[i] = (T)((double)(h >> 8) * (1.0 / 8388608.0) - 1.0);
+    }
+}
+
+hipError_t launch_fill_pattern(void* p, int64_t n, int prec, uint32_t seed, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (prec == 0) hipLaunchKernelGGL(k_fill_pattern<double>, dim3((unsigned)blocks), dim3(256), 0, s, (double*)p, n, seed);
+    else hipLaunchKernelGGL(k_fill_pattern<float>, dim3((unsigned)blocks), dim3(256), 0, s, (float*)p, n, seed);
+    return hipGetLastError();
+}
+
 // End of one completion iteration: record the relative change, clear the
 // norm accumulators, advance the iteration counter.
 __global__ void k_iter_advance(Ctrl* ctrl, double* norms, double* hist, int hist_len) {

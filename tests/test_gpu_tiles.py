@@ -1,0 +1,86 @@
+"""Jacobi tiles: every tile the tuner may pick gives the oracle's result, and the
+tuned choice is stable within a process."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import announce, need_gpu, rel, to_dev, to_np, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tm():
+    need_gpu()
+    import paper_1902_03070_amd as tm
+
+    return tm
+
+
+def case(shape, seed):
+    n1, n2, n3 = shape
+    return synth.tsvt_case(oracle.tprod_dct, n1, n2, n3, max(1, min(n1, n2) // 10), 0.01,
+                           0.1 * (np.sqrt(n1) + np.sqrt(n2)), seed)
+
+
+# (shape, group widths, team sizes): resident slices, team slices with both
+# group widths, and a wide tensor whose 300-row slices need 32-lane groups
+FORCED = [
+    ((64, 48, 9), (16, 32), (0,)),
+    ((256, 200, 3), (16, 32), (1, 2, 3, 4)),
+    ((130, 300, 2), (32,), (1, 2, 4)),
+]
+
+
+@pytest.mark.parametrize("shape,widths,teams", FORCED)
+def test_forced_tiles_match_oracle(tm, shape, widths, teams):
+    c = case(shape, 700 + shape[0])
+    want = oracle.tsvt_dct(c.Z, c.tau)
+    Z = to_dev(c.Z)
+    for G in widths:
+        for W in teams:
+            announce("forced_tile", shape=shape, G=G, W=W)
+            ctx = tm.Context(0)
+            ctx.set_option(tm.OPT_GROUP_LANES, G)
+            ctx.set_option(tm.OPT_TEAM_SIZE, W)
+            t = ctx.tile(tm.FP64, *shape)
+            assert t["source"] == 2 and t["G"] == G
+            Y = tm.tsvt_dct(Z, c.tau, ctx=ctx)
+            err = rel(to_np(Y), want)
+            print("shape %s G %d W %d tile %s rel err %.2e" % (shape, G, W, t, err))
+            assert err <= 1e-10
+            ctx.close()
+
+
+@pytest.mark.parametrize("shape", [(64, 48, 9), (256, 200, 3), (200, 256, 5)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tuned_tile_matches_oracle_and_is_stable(tm, shape, prec):
+    announce("tuned_tile", shape=shape, prec=prec)
+    c = case(shape, 720 + shape[2])
+    ctx1, ctx2 = tm.Context(0), tm.Context(0)
+    t1 = ctx1.tile(prec, *shape)
+    t2 = ctx2.tile(prec, *shape)
+    print("tuned tile", shape, prec, t1)
+    assert t1 == t2 and t1["source"] in (0, 1)
+    dt = torch.float64 if prec == 0 else torch.float32
+    Zf = c.Z if prec == 0 else c.Z.astype(np.float32).astype(np.float64)
+    Y = tm.tsvt_dct(to_dev(Zf, dt), c.tau, prec=prec, ctx=ctx1)
+    err = rel(to_np(Y), oracle.tsvt_dct(Zf, c.tau))
+    assert err <= (1e-10 if prec == 0 else 1e-4)
+    ctx1.close()
+    ctx2.close()
+
+
+def test_batched_tiles_are_per_shape(tm):
+    # the batched tile of a shape is the same whichever context or batch asks
+    announce("batched_tiles")
+    ctx = tm.Context(0)
+    shapes = [(100, 90, 7), (256, 256, 3), (300, 40, 4)]
+    tiles = [ctx.tile(1, *s, batched=True) for s in shapes]
+    ctx2 = tm.Context(0)
+    assert tiles == [ctx2.tile(1, *s, batched=True) for s in shapes]
+    for t in tiles:
+        assert t["threads"] == 512
+    ctx.close()
+    ctx2.close()

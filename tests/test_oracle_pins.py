@@ -436,6 +436,31 @@ def test_complete_first_iteration_against_library(orc):
     assert np.abs(M - Mw).max() < 1e-12 * max(1, np.abs(Mw).max())
 
 
+def test_complete_iterations_from_warm_start_against_library(orc):
+    # Four iterations of Algorithm 1 from a random (X0, M0), each written with
+    # LAPACK's SVD and scipy's DCT: Z = X - M/beta, Y = t-SVT(Z, 1/beta),
+    # X = B on the observed set and Y + M/beta off it, M = M + beta (Y - X).
+    # A nonzero M exercises both multiplier terms and their signs.
+    case = small_completion(orc)
+    g = np.random.default_rng(82)
+    X = F(g.standard_normal(case.B.shape))
+    M = F(g.standard_normal(case.B.shape))
+    obs = case.mask != 0
+    L = 4
+    Xo, Mo, _, _ = orc.complete(case.B, case.mask, case.betas[:L], case.taus[:L], X0=X, M0=M)
+    for b, tau in zip(case.betas[:L], case.taus[:L]):
+        Zb = lib_dct(X - M / b)
+        Yb = np.zeros_like(Zb)
+        for k in range(Zb.shape[2]):
+            U, s, Vt = np.linalg.svd(Zb[:, :, k], full_matrices=False)
+            Yb[:, :, k] = U @ np.diag(np.maximum(s - tau, 0)) @ Vt
+        Y = lib_idct(Yb)
+        X = np.where(obs, case.B, Y + M / b)
+        M = M + b * (Y - X)
+    assert np.abs(Xo - X).max() <= 1e-11 * np.abs(X).max()
+    assert np.abs(Mo - M).max() <= 1e-11 * np.abs(M).max()
+
+
 def test_complete_resume_equals_straight_run(orc):
     case = small_completion(orc)
     X, M, _, _ = orc.complete(case.B, case.mask, case.betas[:10], case.taus[:10])
