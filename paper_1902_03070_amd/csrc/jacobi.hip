@@ -44,11 +44,24 @@ template <> struct Unit<float> { static constexpr double v = 5.9604644775390625e
 
 // DPP move of a double (two 32-bit halves).  CTRL: 0xB1 = quad_perm [1,0,3,2],
 // 0x4E = quad_perm [2,3,0,1], 0x141 = row_half_mirror, 0x140 = row_mirror.
+// These patterns read a valid lane for every lane, so the old value is never
+// used (passing the source keeps the compiler from materialising one).
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int l = __double2loint(v), h = __double2hiint(v);
+    const int lo = __builtin_amdgcn_update_dpp(l, l, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(h, h, CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
+}
+
+// Sum of the two 16-lane rows of each 32-lane half: v_permlane16_swap of a
+// value with itself leaves row 2r in one result and row 2r+1 in the other, in
+// both rows, so every lane adds the same two values in the same order.
+__device__ __forceinline__ double pair_rows_sum(double v) {
+    const unsigned l = (unsigned)__double2loint(v), h = (unsigned)__double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane16_swap(l, l, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(h, h, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
 }
 
 // Sum over a group of G lanes (G = 16: one DPP row; G = 32: two rows).  Each
@@ -60,23 +73,36 @@ __device__ __forceinline__ double group_sum(double v) {
     v += dpp_d<0x4E>(v);
     v += dpp_d<0x141>(v);
     v += dpp_d<0x140>(v);
-    if (G == 32) v += __shfl_xor(v, 16, kWave);
+    if (G == 32) v = pair_rows_sum(v);
     return v;
 }
 
 // Circle-method round robin on n (even) players: round s (0..n-2), pair q
 // (0..n/2-1) -> players (i < j).  Every pair meets exactly once in n-1 rounds.
+// (s + q and s - q stay within one period of n - 1, so a conditional add or
+// subtract replaces the remainder.)
 __device__ __forceinline__ void rr_pair(int s, int q, int n, int& i, int& j) {
     int a, b;
     if (q == 0) {
         a = n - 1;
         b = s;
     } else {
-        a = (s + q) % (n - 1);
-        b = (s - q + n - 1) % (n - 1);
+        a = s + q;
+        if (a >= n - 1) a -= n - 1;
+        b = s - q;
+        if (b < 0) b += n - 1;
     }
     i = a < b ? a : b;
     j = a < b ? b : a;
+}
+
+// Load of a value another workgroup of the team stored: a device-scope
+// relaxed load (sc1), which misses the CU's L1 and reads the XCD's L2, where
+// the partner's acknowledged stores are.  This replaces an acquire fence (an
+// L1 and L2 invalidation) at every team barrier.
+template <typename T>
+__device__ __forceinline__ T ld_team(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Reciprocal and reciprocal square root: hardware estimate plus one Newton
@@ -94,23 +120,29 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // group-reduced g = x.y.  Returns false when the pair is already orthogonal
 // to tol.  With d = b - a the tangent
 //     t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),  zeta = d / (2 g),
-// is evaluated as t = sgn(zeta) |2g| / (|d| + sqrt(d^2 + 4 g^2)) (multiply
-// through by |2g|; sgn(0) = +1), which needs one reciprocal instead of two.
-// The angle may carry a few ulps of error; c and s are computed from the same
-// t with c = 1/sqrt(1 + t^2) to working precision, so the rotation itself is
-// orthogonal.  After it, |x'|^2 = a - t g and |y'|^2 = b + t g.
+// is evaluated as t = sgn(zeta) |2g| / den, den = |d| + r, r = sqrt(d^2 + 4 g^2)
+// (multiply through by |2g|; sgn(0) = +1).  Since 1 + t^2 = 2 r / den, c and s
+// both follow from one reciprocal square root z = 1/sqrt(2 r den): c = den z,
+// s = sgn |2g| z, and t = s / c = sgn |2g| 2 r z^2.  Two reciprocal square
+// roots and no reciprocal; c^2 + s^2 = 1 to working precision, so the rotation
+// is orthogonal.  After it, |x'|^2 = a - t g and |y'|^2 = b + t g.
 __device__ __forceinline__ bool rotation(double a, double b, double g, double tol, double& c, double& s,
                                          double& t) {
     const double g2 = g * g;
     if (g == 0.0 || g2 <= (tol * tol) * (a * b)) return false;
     const double d = b - a;
-    const double w = fma(d, d, 4.0 * g2);
-    const double den = fabs(d) + w * rsq_nr(w);
+    const double w = fma(d, d, 4.0 * g2);    // r^2, r = sqrt(d^2 + 4 g^2)
+    const double r = w * rsq_nr(w);
+    const double den = fabs(d) + r;          // t = sgn 2|g| / den
+    // 1 + t^2 = 2 r / den, so with z = 1/sqrt(2 r den):  c = den z,  |s| = 2|g| z,
+    // and 1/den = 2 r z^2 gives t without a reciprocal
+    const double z = rsq_nr(2.0 * r * den);
     const double ag2 = 2.0 * fabs(g);
     // sgn(zeta) = + exactly when d g >= 0 (d = 0 gives +0 or -0, both >= 0): a select, no branch
-    t = (d * g >= 0.0 ? ag2 : -ag2) * rcp_nr(den);
-    c = rsq_nr(fma(t, t, 1.0));
-    s = c * t;
+    const double sg = d * g >= 0.0 ? ag2 : -ag2;
+    c = den * z;
+    s = sg * z;
+    t = sg * (2.0 * r * z * z);
     return true;
 }
 
@@ -411,13 +443,13 @@ __device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg((15 <
 
 // Team barrier.  Each wavefront first waits for its own global stores to be
 // acknowledged by the L2 (vmcnt(0)); then one lane per workgroup arrives on
-// the team counter (a device-scope atomic), waits for the team with a bounded
-// spin, and performs a device-scope acquire (which invalidates the CU's L1)
-// before the workgroup proceeds.  All workgroups of a team run on one XCD and
-// so share one L2: the exchanged blocks are visible to the partner as soon as
-// the stores are acknowledged, and the release needs no L2 write-back (a
-// device-scope release would write the XCD's dirty L2 lines back to memory at
-// every barrier).  Returns false when the wait gave up.
+// the team counter (a device-scope atomic) and waits for the team with a
+// bounded spin.  All workgroups of a team run on one XCD and so share one L2:
+// the exchanged blocks are there as soon as the stores are acknowledged, so
+// the release needs no L2 write-back (a device-scope release would write the
+// XCD's dirty L2 lines back to memory at every barrier), and the readers load
+// them with ld_team, which bypasses the L1, so no acquire invalidation is
+// needed either.  Returns false when the wait gave up.
 __device__ bool team_barrier(TeamState& ts, int* s_flag) {
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's stores are complete
     __syncthreads();
@@ -437,7 +469,6 @@ __device__ bool team_barrier(TeamState& ts, int* s_flag) {
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
     }
     __syncthreads();
@@ -455,69 +486,58 @@ __device__ __forceinline__ void team_load_block(const JacobiJob& J, int k, int b
     const int tid = threadIdx.x, nth = blockDim.x;
     const T* Ag = (const T*)J.A + (int64_t)k * m * p;
     if (first && J.src_rs != 1) {
+        // transposed source: consecutive lanes take consecutive columns (contiguous in memory)
         for (int e = tid; e < b * ldl; e += nth) {
             const int r = e / b, cl = e - r * b, c = blk * b + cl;
             As[cl * ldl + r] = (c < p && r < m) ? src_at<T>(J, k, r, c) : (T)0;
         }
     } else {
-        // eight independent loads in flight per lane before the LDS stores
-        constexpr int U = 8;
-        const int total = b * ldl;
-        for (int e0 = tid; e0 < total; e0 += nth * U) {
-            T v[U];
+        // group g (G lanes) takes column g of the block, rows gl + G q: R loads in flight per lane
+        const int grp = tid / G, gl = tid % G, c = blk * b + grp;
+        T v[R];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = e0 + u * nth;
-                const int cl = e / ldl, r = e - cl * ldl, c = blk * b + cl;
-                v[u] = (T)0;
-                if (e < total && c < p && r < m) v[u] = first ? src_at<T>(J, k, r, c) : Ag[(int64_t)c * m + r];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = e0 + u * nth;
-                if (e < total) As[e] = v[u];
-            }
+        for (int q = 0; q < R; ++q) {
+            const int r = gl + G * q;
+            v[q] = (T)0;
+            if (c < p && r < m) v[q] = first ? src_at<T>(J, k, r, c) : ld_team(Ag + (int64_t)c * m + r);
         }
+#pragma unroll
+        for (int q = 0; q < R; ++q) As[grp * ldl + gl + G * q] = v[q];
     }
     if (WV) {
         const T* Vg = (const T*)J.V + (int64_t)k * p * p;
         for (int e = tid; e < b * ldv; e += nth) {
             const int cl = e / ldv, r = e - cl * ldv, c = blk * b + cl;
             T v = (T)0;
-            if (c < p && r < p) v = first ? (T)(r == c ? 1 : 0) : Vg[(int64_t)c * p + r];
+            if (c < p && r < p) v = first ? (T)(r == c ? 1 : 0) : ld_team(Vg + (int64_t)c * p + r);
             Vs[e] = v;
         }
     }
 }
 
+// Write a block back to the work array (group g stores column g).
 template <typename T, int R, int G, bool WV>
 __device__ __forceinline__ void team_store_block(const JacobiJob& J, int k, int blk, const T* As, const T* Vs) {
     constexpr int ldl = R * G + kLdsPad;
     const int m = J.m, p = J.p, b = J.b, ldv = J.ldv;
     const int tid = threadIdx.x, nth = blockDim.x;
+    const int grp = tid / G, gl = tid % G, c = blk * b + grp;
     T* Ag = (T*)J.A + (int64_t)k * m * p;
-    constexpr int U = 8;  // eight LDS reads in flight before the global stores
-    const int total = b * m;
-    for (int e0 = tid; e0 < total; e0 += nth * U) {
-        T v[U];
+    T v[R];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * nth;
-            const int cl = e / m, r = e - cl * m;
-            v[u] = e < total ? As[cl * ldl + r] : (T)0;
-        }
+    for (int q = 0; q < R; ++q) v[q] = As[grp * ldl + gl + G * q];
+    if (c < p) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * nth;
-            const int cl = e / m, r = e - cl * m, c = blk * b + cl;
-            if (e < total && c < p) Ag[(int64_t)c * m + r] = v[u];
+        for (int q = 0; q < R; ++q) {
+            const int r = gl + G * q;
+            if (r < m) Ag[(int64_t)c * m + r] = v[q];
         }
     }
     if (WV) {
         T* Vg = (T*)J.V + (int64_t)k * p * p;
         for (int e = tid; e < b * p; e += nth) {
-            const int cl = e / p, r = e - cl * p, c = blk * b + cl;
-            if (c < p) Vg[(int64_t)c * p + r] = Vs[cl * ldv + r];
+            const int cl = e / p, r = e - cl * p, cc = blk * b + cl;
+            if (cc < p) Vg[(int64_t)cc * p + r] = Vs[cl * ldv + r];
         }
     }
 }
@@ -550,7 +570,19 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                 const bool first = (sw == 0 && s == 0);
                 const int ci = BI * b + grp;  // this group's I column
                 T xr[R];
-                double na;
+                double na = 0.0;
+                if (s != 0) {
+                    // this group's I column comes from the work array; its loads are issued
+                    // first so that they overlap with the J block's (the clamped column keeps
+                    // every load in bounds; rows beyond m read as zero)
+                    const T* xs = Ag + (int64_t)(ci < p ? ci : 0) * m;
+#pragma unroll
+                    for (int q2 = 0; q2 < R; ++q2) {
+                        const int r = gl + G * q2;
+                        xr[q2] = (T)0;
+                        if (r < m) xr[q2] = ld_team(xs + r);
+                    }
+                }
                 team_load_block<T, R, G, WV>(J, k, BJ, first, Js, Vj);
                 if (s == 0 || WV) team_load_block<T, R, G, WV>(J, k, BI, first, Is, Vi);
                 __syncthreads();
@@ -583,19 +615,11 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                     for (int q2 = 0; q2 < R; ++q2) xr[q2] = Is[grp * ldl + gl + G * q2];
                     na = nI[grp];
                 } else {
-                    // clamped addresses keep every load in bounds; padding reads as zero
-                    const T* xs = Ag + (int64_t)(ci < p ? ci : 0) * m;
-#pragma unroll
-                    for (int q2 = 0; q2 < R; ++q2) {
-                        const int r = gl + G * q2;
-                        const T v = xs[r < m ? r : m - 1];
-                        xr[q2] = (ci < p && r < m) ? v : (T)0;
-                    }
                     na = group_sum<G>(partial_norm<T, R>(xr));
                 }
-                // cross pairs: b rounds, group g pairs I[g] with J[(g + r) % b]
-                for (int r = 0; r < b; ++r) {
-                    const int j = (grp + r) % b;
+                // cross pairs: b rounds, group g pairs I[g] with J[(g + r) mod b]
+                int j = grp;
+                for (int r = 0; r < b; ++r, j = (j + 1 == b) ? 0 : j + 1) {
                     if (ci < p && BJ * b + j < p)
                         rot += gpair_reg<T, R, G>(xr, na, Js + j * ldl, nJ + j, WV ? Vi + grp * ldv : nullptr,
                                                   WV ? Vj + j * ldv : nullptr, WV ? p : 0, gl, tl, f64);
