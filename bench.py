@@ -123,17 +123,24 @@ def dct_roofline(res, prec_name):
             "bytes_per_launch": nbytes}
 
 
+def kernel_source_md5():
+    """Hash of the Jacobi kernel's sources (the counters are tied to them)."""
+    h = hashlib.md5()
+    for f in ("jacobi.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1902_03070_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def traffic_for(kernel, prec_name):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken with the library build that is running now; else None."""
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken with the kernel sources that are built now; else None."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_completion_256x256x31.json")
-    lib = os.path.join(ROOT, "paper_1902_03070_amd", "libtsvdmi.so")
     try:
         with open(path) as f:
             t = json.load(f)
-        h = hashlib.md5(open(lib, "rb").read()).hexdigest()
         ent = t.get("%s_%s" % (kernel, prec_name))
-        if ent and ent.get("lib_md5") == h:
+        if ent and ent.get("kernel_src_md5") == kernel_source_md5():
             return ent["bytes_per_launch"]
     except (OSError, ValueError):
         pass

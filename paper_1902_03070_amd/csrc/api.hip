@@ -581,7 +581,9 @@ int tune_tile(tsvd_ctx* c, const Plan& P, bool batched, Tile* out, double* us_ou
         seen.push_back(sig);
         const double us = time_tile(c, P, cands[i], batched, tb, o_src, o_A, o_V, o_cnt, cnt_bytes, o_jobs, o_tj, o_tk,
                                     ntasks, e0, e1);
-        if (us > 0.0 && (best_us < 0.0 || us < best_us)) {
+        // a later candidate must be 2% faster to replace an earlier one, so that
+        // near-ties resolve the same way from run to run
+        if (us > 0.0 && (best_us < 0.0 || us < 0.98 * best_us)) {
             best_us = us;
             best = cands[i];
         }
