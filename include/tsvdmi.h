@@ -83,8 +83,11 @@ enum {
                                   (default; not while profiling); 0: direct launches */
     TSVD_OPT_AUTOTUNE = 6,     /* 1: choose Jacobi tiles by timing the candidates (default); 0: the
                                   built-in heuristic.  See tsvd_get_tile. */
-    TSVD_OPT_GROUP_LANES = 7   /* 0: automatic; 16 or 32: lanes per column-pair group in the Jacobi
+    TSVD_OPT_GROUP_LANES = 7,  /* 0: automatic; 16 or 32: lanes per column-pair group in the Jacobi
                                   kernels (a forced setting, like TEAM_SIZE, disables tuning) */
+    TSVD_OPT_GROUP_COLUMNS = 8 /* 0: automatic; 1 or 2: columns each lane group of the multi-workgroup
+                                  Jacobi kernel holds (2: two independent rotations at a time; not
+                                  with V).  A forced setting disables tuning. */
 };
 int tsvd_set_option(tsvd_ctx* ctx, int option, double value);
 double tsvd_get_option(const tsvd_ctx* ctx, int option);
@@ -109,8 +112,9 @@ int tsvd_sync_status(tsvd_ctx* ctx, void* stream, int* max_sweeps_out);
  * a file, tuned tiles are read from and appended to it.  No tuning happens
  * while `stream` of a call is being captured.  Results of different tiles
  * agree to the precision's tolerance, not bitwise.
- * out[5]: team (0 resident, 1 team), G, W (0 when resident), workgroup size,
- * source (0 heuristic, 1 autotuned, 2 forced by options). */
+ * out[6]: team (0 resident, 1 team), G, W (0 when resident), workgroup size,
+ * source (0 heuristic, 1 autotuned, 2 forced by options), columns per lane
+ * group (0 when resident). */
 int tsvd_get_tile(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, int batched, int with_v,
                   int32_t* out);
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libtsvdmi.so")
 FP64, FP32, MIXED = 0, 1, 2
 OK, WARN_NOCONV, EINVAL, ENOMEM, EHIP, ENONFINITE, EBUSY, ETIMEOUT = 0, 1, -1, -2, -3, -4, -5, -6
 OPT_MAX_SWEEPS, OPT_SYNC_STATUS, OPT_TEAM_SIZE, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_GRAPHS = 0, 1, 2, 3, 4, 5
-OPT_AUTOTUNE, OPT_GROUP_LANES = 6, 7
+OPT_AUTOTUNE, OPT_GROUP_LANES, OPT_GROUP_COLUMNS = 6, 7, 8
 PHASES = ("forward_transform", "jacobi", "threshold_rebuild", "inverse_transform")
 TRANSFORM_DOMAIN = 1
 REQ_TSVT, REQ_COMPLETE = 0, 1
@@ -137,9 +137,9 @@ class Context:
 
     def tile(self, prec: int, n1: int, n2: int, n3: int, batched: bool = False, with_v: bool = False) -> dict:
         """Jacobi tile this context uses for the shape (tunes it if needed)."""
-        out = (C.c_int32 * 5)()
+        out = (C.c_int32 * 6)()
         self.check(lib.tsvd_get_tile(self.h, prec, n1, n2, n3, int(batched), int(with_v), out))
-        return dict(zip(("team", "G", "W", "threads", "source"), list(out)))
+        return dict(zip(("team", "G", "W", "threads", "source", "K"), list(out)))
 
     def sync_status(self, stream=None):
         ms = C.c_int(0)

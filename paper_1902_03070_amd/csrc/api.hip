@@ -28,6 +28,7 @@ struct tsvd_ctx {
     int sync_status = 1;
     int team_size = 0;
     int group_lanes = 0;
+    int group_cols = 0;
     int autotune = 1;
     int spin_limit = 1 << 24;
     std::string err = "";
@@ -270,6 +271,7 @@ struct Plan {
     int team = 0;        // 0: resident kernel; 1: team kernel
     int threads = 256;
     int tile_source = 0, tile_W = 0;
+    int K = 1;           // team kernel lane-group columns
     int lds = 0;
     TeamSched ts{};
     JacobiJob job{};
@@ -290,6 +292,7 @@ struct Tile {
     int G = 16;
     int W = 0;
     int threads = 0;
+    int K = 1;       // team: lane-group columns (2: two I columns per group, no V)
     int source = 0;  // 0 default heuristic, 1 autotuned, 2 forced by options
 };
 
@@ -338,6 +341,35 @@ int apply_tile(tsvd_ctx* c, Plan& P, const Tile& t, bool batched) {
         P.job.nb = nb;
         return TSVD_OK;
     }
+    if (t.K == 2) {
+        if (P.with_v) return fail(c, TSVD_EINVAL, "two columns per lane group need no V");
+        // block width B = 2 ng columns for ng groups; ng G must fill whole wavefronts
+        const int gstep = std::max(1, kWave / t.G), bstep = 2 * gstep;
+        const int bmax = 2 * (kTeamMaxThreads / t.G);
+        int W = std::max(1, t.W);
+        int B = (P.p + 2 * W - 1) / (2 * W);
+        B = (B + bstep - 1) / bstep * bstep;
+        B = std::min(B, bmax);
+        while (B > bstep && jacobi_team_lds_bytes(P.prec, P.m, P.p, t.G, B, 0) > kLdsBudget) B -= bstep;
+        if (jacobi_team_lds_bytes(P.prec, P.m, P.p, t.G, B, 0) > kLdsBudget)
+            return fail(c, TSVD_EINVAL, "slice too large for the Jacobi team kernel");
+        int nb = (P.p + B - 1) / B;
+        nb += nb & 1;
+        if (W > nb / 2) W = nb / 2;
+        P.lds = jacobi_team_lds_bytes(P.prec, P.m, P.p, t.G, B, 0);
+        P.threads = (B / 2) * t.G;
+        const int cap = jacobi_team_max_resident(P.prec, P.lds, P.threads, 0, R, t.G, 2);
+        if (cap < 8) return fail(c, TSVD_EINVAL, "Jacobi team kernel cannot be resident with this shape");
+        W = std::min(W, cap / 8);
+        const int per_xcd = std::max(1, std::min(((int)P.n3 + 7) / 8, cap / (8 * W)));
+        P.ts.W = W;
+        P.ts.nwg = 8 * W * per_xcd;
+        P.job.b = B;
+        P.job.nb = nb;
+        P.K = 2;
+        return TSVD_OK;
+    }
+    P.K = 1;
     const int bstep = std::max(2, kWave / t.G);  // b G must fill whole wavefronts
     const int bmax = kTeamMaxThreads / t.G;
     int W = std::max(1, t.W);
@@ -352,7 +384,7 @@ int apply_tile(tsvd_ctx* c, Plan& P, const Tile& t, bool batched) {
     if (W > nb / 2) W = nb / 2;
     P.lds = jacobi_team_lds_bytes(P.prec, P.m, P.p, t.G, b, P.with_v);
     P.threads = b * t.G;
-    const int cap = jacobi_team_max_resident(P.prec, P.lds, P.threads, P.with_v, R, t.G);
+    const int cap = jacobi_team_max_resident(P.prec, P.lds, P.threads, P.with_v, R, t.G, 1);
     if (cap < 8) return fail(c, TSVD_EINVAL, "Jacobi team kernel cannot be resident with this shape");
     // whole teams on every XCD: the grid is a multiple of 8 W workgroups
     W = std::min(W, cap / 8);
@@ -379,7 +411,7 @@ std::vector<int> group_widths(int m, int p) {
     return out;
 }
 
-Tile default_tile(const Plan& P, int team_size, int group_lanes) {
+Tile default_tile(const Plan& P, int team_size, int group_lanes, int group_cols, bool batched) {
     Tile t;
     int G, R, ldv;
     jacobi_geometry(P.m, P.p, &G, &R, &ldv);
@@ -387,6 +419,7 @@ Tile default_tile(const Plan& P, int team_size, int group_lanes) {
     t.team = jacobi_resident_lds_bytes(P.prec, P.m, P.p, t.G, P.with_v) > kLdsBudget;
     t.W = t.team ? (team_size > 0 ? team_size : std::max(1, (P.p + 63) / 64)) : 0;
     t.threads = t.team ? 0 : resident_threads(P.p, t.G, 0);
+    t.K = (t.team && !batched && !P.with_v && group_cols == 2) ? 2 : 1;
     return t;
 }
 
@@ -405,9 +438,13 @@ std::vector<Tile> tile_candidates(const Plan& P, bool batched) {
                 if (out.empty() || out.back().threads != t.threads || out.back().G != G) out.push_back(t);
             }
         } else {
-            for (int W : {1, 2, 3, 4, 6, 8}) {
-                t.W = W;
-                out.push_back(t);
+            for (int K : {1, 2}) {
+                if (K == 2 && P.with_v) continue;
+                t.K = K;
+                for (int W : {1, 2, 3, 4, 6, 8}) {
+                    t.W = W;
+                    out.push_back(t);
+                }
             }
         }
     }
@@ -418,7 +455,7 @@ std::vector<Tile> tile_candidates(const Plan& P, bool batched) {
 // Key: (batched, prec, m, p, n3, with_v); batched plans ignore n3.  When the
 // environment variable TSVDMI_TILE_CACHE names a file, it is read at first
 // use and every newly tuned tile is appended to it, one line per tile:
-//   tile <batched> <prec> <m> <p> <n3> <with_v> <team> <G> <W> <threads> <microseconds>
+//   tile <batched> <prec> <m> <p> <n3> <with_v> <team> <G> <W> <threads> <K> <microseconds>
 typedef std::tuple<int, int, int, int, int, int> TileKey;
 std::mutex g_tile_mu;
 std::map<TileKey, Tile> g_tiles;
@@ -433,13 +470,13 @@ void tile_cache_load_locked() {
     if (!f) return;
     char line[256];
     while (fgets(line, sizeof line, f)) {
-        int k[6], team, G, W, th;
+        int k[6], team, G, W, th, K;
         double us;
-        if (sscanf(line, "tile %d %d %d %d %d %d %d %d %d %d %lf", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &team, &G,
-                   &W, &th, &us) != 11)
+        if (sscanf(line, "tile %d %d %d %d %d %d %d %d %d %d %d %lf", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &team,
+                   &G, &W, &th, &K, &us) != 12)
             continue;
         Tile t;
-        t.team = team; t.G = G; t.W = W; t.threads = th; t.source = 1;
+        t.team = team; t.G = G; t.W = W; t.threads = th; t.K = K == 2 ? 2 : 1; t.source = 1;
         g_tiles[TileKey(k[0], k[1], k[2], k[3], k[4], k[5])] = t;
     }
     fclose(f);
@@ -462,8 +499,8 @@ void tile_cache_put(const TileKey& k, const Tile& t, double us) {
     if (!path || !*path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "tile %d %d %d %d %d %d %d %d %d %d %.1f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
-            std::get<3>(k), std::get<4>(k), std::get<5>(k), t.team, t.G, t.W, t.threads, us);
+    fprintf(f, "tile %d %d %d %d %d %d %d %d %d %d %d %.1f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+            std::get<3>(k), std::get<4>(k), std::get<5>(k), t.team, t.G, t.W, t.threads, t.K, us);
     fclose(f);
 }
 
@@ -496,14 +533,15 @@ double time_tile(tsvd_ctx* c, const Plan& P0, const Tile& t, bool batched, char*
     J.p = P.p;
     J.n3 = ntasks;
     J.tol = 0.0;
+    J.skip2 = 0.0;
     J.refine64 = 0;
-    // counters: [Ctrl 256][queue 256][sweeps 4 ntasks][rot 4 ntasks kMaxSweeps][team ctl]
+    // counters: [Ctrl 256][queue 256][sweeps 4 ntasks][rot 4 ntasks kRotStride][team ctl]
     char* cnt = tb + o_cnt;
     Ctrl* ctrl = (Ctrl*)cnt;
     int* queue = (int*)(cnt + 256);
     J.sweeps = (int*)(cnt + 512);
     J.rot = (int*)(cnt + 512 + align256((size_t)4 * ntasks));
-    P.ts.ctl = (int*)(cnt + 512 + align256((size_t)4 * ntasks) + align256((size_t)4 * ntasks * kMaxSweeps));
+    P.ts.ctl = (int*)(cnt + 512 + align256((size_t)4 * ntasks) + align256((size_t)4 * ntasks * kRotStride));
     if (batched && hipMemcpy(tb + o_jobs, &J, sizeof(JacobiJob), hipMemcpyHostToDevice) != hipSuccess) return -1.0;
     hipStream_t s = c->own;
     double best = -1.0;
@@ -520,7 +558,7 @@ double time_tile(tsvd_ctx* c, const Plan& P0, const Tile& t, bool batched, char*
                                        P.threads, P.with_v, s);
         else
             e = launch_jacobi_team(P.prec, J, ntasks, P.ts, kTuneSweeps, ctrl, P.lds, P.threads, P.with_v,
-                                   c->spin_limit, J.R, J.G, 1, s);
+                                   c->spin_limit, J.R, J.G, P.K, 1, s);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return -1.0;
@@ -551,7 +589,7 @@ int tune_tile(tsvd_ctx* c, const Plan& P, bool batched, Tile* out, double* us_ou
     const size_t o_V = cv.take(P.with_v ? (size_t)P.p * P.p * ntasks * es : 0);
     const size_t o_jobs = cv.take(sizeof(JacobiJob)), o_tj = cv.take((size_t)4 * ntasks),
                  o_tk = cv.take((size_t)4 * ntasks);
-    const size_t cnt_bytes = 512 + align256((size_t)4 * ntasks) + align256((size_t)4 * ntasks * kMaxSweeps) +
+    const size_t cnt_bytes = 512 + align256((size_t)4 * ntasks) + align256((size_t)4 * ntasks * kRotStride) +
                              (size_t)4 * (kTeamCtlInts + 8 * 64 * 64);
     const size_t o_cnt = cv.take(cnt_bytes);
     char* tb = nullptr;
@@ -572,11 +610,11 @@ int tune_tile(tsvd_ctx* c, const Plan& P, bool batched, Tile* out, double* us_ou
              hipMemcpy(tb + o_tk, tk.data(), 4 * ntasks, hipMemcpyHostToDevice) == hipSuccess &&
              hipStreamSynchronize(c->own) == hipSuccess;
     }
-    std::vector<std::tuple<int, int, int, int, int>> seen;  // (team, G, threads, b, nwg) of applied plans
+    std::vector<std::tuple<int, int, int, int, int, int>> seen;  // (team, G, threads, b, nwg, K) of applied plans
     for (size_t i = 0; ok && i < cands.size(); ++i) {
         Plan Q = P;
         if (apply_tile(c, Q, cands[i], batched)) continue;
-        auto sig = std::make_tuple(Q.team, Q.job.G, Q.threads, Q.job.b, Q.ts.nwg);
+        auto sig = std::make_tuple(Q.team, Q.job.G, Q.threads, Q.job.b, Q.ts.nwg, Q.K);
         if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
         seen.push_back(sig);
         const double us = time_tile(c, P, cands[i], batched, tb, o_src, o_A, o_V, o_cnt, cnt_bytes, o_jobs, o_tj, o_tk,
@@ -603,14 +641,14 @@ int tune_tile(tsvd_ctx* c, const Plan& P, bool batched, Tile* out, double* us_ou
 
 // The tile of a plan: forced by options, cached, autotuned, or the default.
 int pick_tile(tsvd_ctx* c, const Plan& P, bool batched, hipStream_t s, Tile* t) {
-    if (c->team_size > 0 || c->group_lanes > 0) {
-        *t = default_tile(P, c->team_size, c->group_lanes);
+    if (c->team_size > 0 || c->group_lanes > 0 || c->group_cols > 0) {
+        *t = default_tile(P, c->team_size, c->group_lanes, c->group_cols, batched);
         t->source = 2;
         return TSVD_OK;
     }
     const TileKey key(batched ? 1 : 0, P.prec, P.m, P.p, batched ? 0 : (int)P.n3, P.with_v);
     if (tile_cache_get(key, t)) return TSVD_OK;
-    *t = default_tile(P, 0, 0);
+    *t = default_tile(P, 0, 0, 0, batched);
     if (!c->autotune) return TSVD_OK;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
@@ -654,7 +692,7 @@ int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int wit
     P.o_ybar = cv.take(slice * n3 * es);
     P.o_V = with_v ? cv.take((size_t)P.p * P.p * n3 * es) : 0;
     P.o_ctr_begin = cv.off;
-    P.o_rot = cv.take((size_t)n3 * kMaxSweeps * 4);
+    P.o_rot = cv.take((size_t)n3 * kRotStride * 4);
     P.o_sw = cv.take((size_t)n3 * 4);
     P.o_bar = cv.take((size_t)(kTeamCtlInts + std::max(1, P.ts.nwg)) * 4);
     P.o_rank = cv.take((size_t)n3 * 4);
@@ -680,6 +718,10 @@ void bind_plan(Plan& P, char* base) {
     J.refine64 = (P.prec == TSVD_MIXED) ? 1 : 0;
     const double u64 = ldexp(1.0, -53), u32 = ldexp(1.0, -24);
     J.tol = P.prec == TSVD_FP64 ? P.m * u64 : P.prec == TSVD_FP32 ? 2.0 * sqrt((double)P.m) * u32 : P.m * u32;
+    // A sweep whose cosines are all <= sqrt(tol) / 64 leaves the next one rotating by ~tol / 4096
+    // (quadratic convergence), below the rotation threshold: the sweep that would only confirm it
+    // is skipped.
+    J.skip2 = J.tol / 4096.0;
     P.ts.ctl = (int*)(base + P.o_bar);
 }
 
@@ -700,7 +742,7 @@ int run_jacobi(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s) {
                                    ctrl, P.lds, P.threads, P.with_v, s);
     else
         e = launch_jacobi_team(P.prec, P.job, (int)P.n3, P.ts, clamp_sweeps(c->max_sweeps), ctrl, P.lds, P.threads,
-                               P.with_v, c->spin_limit, P.job.R, P.job.G, c->capturing ? 0 : 1, s);
+                               P.with_v, c->spin_limit, P.job.R, P.job.G, P.K, c->capturing ? 0 : 1, s);
     if (e != hipSuccess) return hip_fail(c, e, "jacobi launch");
     return TSVD_OK;
 }
@@ -836,6 +878,10 @@ int tsvd_set_option(tsvd_ctx* c, int opt, double v) {
         case TSVD_OPT_PROFILE: c->prof = v != 0.0; return TSVD_OK;
         case TSVD_OPT_GRAPHS: c->use_graphs = v != 0.0; return TSVD_OK;
         case TSVD_OPT_AUTOTUNE: c->autotune = v != 0.0; return TSVD_OK;
+        case TSVD_OPT_GROUP_COLUMNS:
+            if (v != 0 && v != 1 && v != 2) return fail(c, TSVD_EINVAL, "group columns must be 0, 1 or 2");
+            c->group_cols = (int)v;
+            return TSVD_OK;
         case TSVD_OPT_GROUP_LANES:
             if (v != 0 && v != 16 && v != 32) return fail(c, TSVD_EINVAL, "group lanes must be 0, 16 or 32");
             c->group_lanes = (int)v;
@@ -854,6 +900,7 @@ double tsvd_get_option(const tsvd_ctx* c, int opt) {
         case TSVD_OPT_PROFILE: return c->prof;
         case TSVD_OPT_GRAPHS: return c->use_graphs;
         case TSVD_OPT_AUTOTUNE: return c->autotune;
+        case TSVD_OPT_GROUP_COLUMNS: return c->group_cols;
         case TSVD_OPT_GROUP_LANES: return c->group_lanes;
     }
     return -1.0;
@@ -875,6 +922,7 @@ int tsvd_get_tile(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int
     out[2] = P.team ? P.ts.W : 0;
     out[3] = P.threads;
     out[4] = P.tile_source;
+    out[5] = P.team ? P.K : 0;
     return TSVD_OK;
 }
 
@@ -1331,7 +1379,7 @@ size_t tsvd_batched_workspace_bytes(int prec, int64_t n1, int64_t n2, int64_t n3
     // mirrors make_plan's regions (upper bound: counters and alignment)
     const size_t es = prec == TSVD_FP64 ? 8 : 4;
     const size_t m = (size_t)std::max(n1, n2), p = (size_t)std::min(n1, n2), N = (size_t)n1 * n2;
-    return es * (2 * N * n3 + 2 * m * p * n3 + p * p * n3) + 16 * p * n3 + 4 * n3 * (kMaxSweeps + 3) + 16 * 256 +
+    return es * (2 * N * n3 + 2 * m * p * n3 + p * p * n3) + 16 * p * n3 + 4 * n3 * (kRotStride + 3) + 16 * 256 +
            sizeof(JacobiJob) + 8 * n3;
 }
 

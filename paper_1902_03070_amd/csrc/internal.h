@@ -10,6 +10,7 @@
 namespace tsvd {
 
 constexpr int kMaxSweeps = 64;       // hard cap on Jacobi sweeps (per-sweep counters are sized by it)
+constexpr int kRotStride = 2 * kMaxSweeps;  // per slice: rotations per sweep, then large-angle pairs per sweep
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kMaxEpl = 8;           // rows per lane in the Jacobi kernels: m <= 512
 constexpr int kMaxRows = kWave * kMaxEpl;
@@ -37,7 +38,8 @@ struct JacobiJob {
     const void* src;   // transformed tensor Zbar (n1 x n2 x n3)
     void* A;           // work/output: m x p per slice, ld = m, slice stride m*p
     void* V;           // p x p per slice (ld = p) or nullptr
-    int* rot;          // [n3 * kMaxSweeps] rotation counters (zeroed before launch)
+    int* rot;          // [n3 * kRotStride] per-sweep counters (zeroed before launch): rotations, then
+                       // pairs whose cosine exceeded sqrt(skip2)
     int* sweeps;       // [n3] sweeps used per slice (-1 = not converged)
     int64_t src_ss, src_rs, src_cs;
     int m, p, n3;
@@ -48,6 +50,8 @@ struct JacobiJob {
     int nb;            // number of column blocks (even) = ceil(p / b) rounded up to even
     int refine64;      // 1: after convergence run one sweep with FP64 arithmetic (FP32 data)
     double tol;        // rotate a pair iff |x.y| > tol |x| |y| (precision dependent, set on the host)
+    double skip2;      // a sweep whose pairs all have (x.y)^2 <= skip2 |x|^2 |y|^2 ends the iteration
+                       // (the next sweep would rotate by angles far below tol: no check sweep)
 };
 
 struct TeamSched {
@@ -102,9 +106,11 @@ hipError_t launch_tube_mfma(int eng, const TubeArgs& a, const void* frag, hipStr
 hipError_t launch_jacobi_resident(int prec, const JacobiJob& job1, const JacobiJob* jobs_dev, const int* task_job,
                                   const int* task_slice, int ntasks, int max_sweeps, Ctrl* ctrl, int lds_bytes,
                                   int threads, int with_v, hipStream_t s);
+// K: lane-group columns (1, or 2 with two I columns per group and no V; the
+// block width job.b is then 2 * threads / G).
 hipError_t launch_jacobi_team(int prec, const JacobiJob& job, int ntasks, const TeamSched& ts, int max_sweeps,
-                              Ctrl* ctrl, int lds_bytes, int threads, int with_v, int spin_limit, int R, int G, int coop,
-                              hipStream_t s);
+                              Ctrl* ctrl, int lds_bytes, int threads, int with_v, int spin_limit, int R, int G, int K,
+                              int coop, hipStream_t s);
 // One persistent launch over (tensor, slice) tasks drawn from *queue (zeroed).
 // One persistent launch per row geometry (R, G) present in the batch.
 hipError_t launch_jacobi_batched(int prec, int R, int G, const JacobiJob* jobs_dev, const int* task_job,
@@ -118,7 +124,7 @@ void jacobi_geometry(int m, int p, int* G, int* R, int* ldv);
 int jacobi_geometry_g(int m, int p, int G, int* R, int* ldv);
 int jacobi_resident_lds_bytes(int prec, int m, int p, int G, int with_v);
 int jacobi_team_lds_bytes(int prec, int m, int p, int G, int b, int with_v);
-int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v, int R, int G);
+int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v, int R, int G, int K);
 
 // Batched strided GEMM with optional per-batch K (ranks) and column scale.
 //   C_b(i,j) = cscale_b(j) * sum_{t < K_b} A_b(i,t) B_b(t,j)

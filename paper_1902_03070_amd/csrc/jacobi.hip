@@ -126,14 +126,14 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // s = sgn |2g| z, and t = s / c = sgn |2g| 2 r z^2.  Two reciprocal square
 // roots and no reciprocal; c^2 + s^2 = 1 to working precision, so the rotation
 // is orthogonal.  After it, |x'|^2 = a - t g and |y'|^2 = b + t g.
-__device__ __forceinline__ bool rotation(double a, double b, double g, double tol, double& c, double& s,
-                                         double& t) {
-    const double g2 = g * g;
-    if (g == 0.0 || g2 <= (tol * tol) * (a * b)) return false;
+__device__ __forceinline__ bool needs_rotation(double a, double b, double g, double tol) {
+    return !(g == 0.0 || g * g <= (tol * tol) * (a * b));
+}
+__device__ __forceinline__ void rotation_angle(double a, double b, double g, double& c, double& s, double& t) {
     const double d = b - a;
-    const double w = fma(d, d, 4.0 * g2);    // r^2, r = sqrt(d^2 + 4 g^2)
+    const double w = fma(d, d, 4.0 * (g * g));  // r^2, r = sqrt(d^2 + 4 g^2)
     const double r = w * rsq_nr(w);
-    const double den = fabs(d) + r;          // t = sgn 2|g| / den
+    const double den = fabs(d) + r;              // t = sgn 2|g| / den
     // 1 + t^2 = 2 r / den, so with z = 1/sqrt(2 r den):  c = den z,  |s| = 2|g| z,
     // and 1/den = 2 r z^2 gives t without a reciprocal
     const double z = rsq_nr(2.0 * r * den);
@@ -143,6 +143,11 @@ __device__ __forceinline__ bool rotation(double a, double b, double g, double to
     c = den * z;
     s = sg * z;
     t = sg * (2.0 * r * z * z);
+}
+__device__ __forceinline__ bool rotation(double a, double b, double g, double tol, double& c, double& s,
+                                         double& t) {
+    if (!needs_rotation(a, b, g, tol)) return false;
+    rotation_angle(a, b, g, c, s, t);
     return true;
 }
 
@@ -225,7 +230,7 @@ __device__ __forceinline__ void rotate_lds_col(T* vx, T* vy, int n, int gl, int 
 template <typename T, int R, int G>
 __device__ __forceinline__ int gpair_lds(T* __restrict__ x, T* __restrict__ y, double* na, double* nb,
                                          T* __restrict__ vx, T* __restrict__ vy, int vrows, int gl, double tol,
-                                         bool f64) {
+                                         bool f64, double th2, int& big) {
     T xr[R], yr[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -234,6 +239,7 @@ __device__ __forceinline__ int gpair_lds(T* __restrict__ x, T* __restrict__ y, d
     }
     const double a = *na, b = *nb;
     const double g = group_sum<G>(partial_dot<T, R>(xr, yr, f64));
+    big += g * g > th2 * (a * b);
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
     rotate_regs<T, R>(xr, yr, c, s, f64);
@@ -255,13 +261,14 @@ __device__ __forceinline__ int gpair_lds(T* __restrict__ x, T* __restrict__ y, d
 template <typename T, int R, int G>
 __device__ __forceinline__ int gpair_reg(T (&xr)[R], double& na, T* __restrict__ y, double* nb,
                                          T* __restrict__ vx, T* __restrict__ vy, int vrows, int gl, double tol,
-                                         bool f64) {
+                                         bool f64, double th2, int& big) {
     const double b = *nb;
     T yr[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) yr[q] = y[gl + G * q];
     const double a = na;
     const double g = group_sum<G>(partial_dot<T, R>(xr, yr, f64));
+    big += g * g > th2 * (a * b);
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
     rotate_regs<T, R>(xr, yr, c, s, f64);
@@ -271,6 +278,35 @@ __device__ __forceinline__ int gpair_reg(T (&xr)[R], double& na, T* __restrict__
     na = a - t * g;
     if (gl == 0) *nb = b + t * g;
     return 1;
+}
+
+// Two independent pairs (x1, y1) and (x2, y2), all in registers, with squared
+// norms n1, m1, n2, m2 (uniform in the group); v1, v2 say whether each pair is
+// real (padding columns are skipped).  The two dot products, reductions and
+// angles are independent chains, which the wavefront interleaves.  A pair
+// that needs no rotation gets c = 1, s = 0 (exact identity).
+template <typename T, int R, int G>
+__device__ __forceinline__ int gpair2(T (&x1)[R], double& n1, T (&y1)[R], double& m1, T (&x2)[R], double& n2,
+                                      T (&y2)[R], double& m2, bool v1, bool v2, double tol, bool f64, double th2,
+                                      int& big) {
+    const double g1 = group_sum<G>(partial_dot<T, R>(x1, y1, f64));
+    const double g2 = group_sum<G>(partial_dot<T, R>(x2, y2, f64));
+    big += (v1 && g1 * g1 > th2 * (n1 * m1)) + (v2 && g2 * g2 > th2 * (n2 * m2));
+    const bool r1 = v1 && needs_rotation(n1, m1, g1, tol);
+    const bool r2 = v2 && needs_rotation(n2, m2, g2, tol);
+    if (r1 || r2) {
+        double c1, s1, t1, c2, s2, t2;
+        // benign arguments for a pair that does not rotate; its results are replaced below
+        rotation_angle(r1 ? n1 : 1.0, r1 ? m1 : 2.0, r1 ? g1 : 1.0, c1, s1, t1);
+        rotation_angle(r2 ? n2 : 1.0, r2 ? m2 : 2.0, r2 ? g2 : 1.0, c2, s2, t2);
+        c1 = r1 ? c1 : 1.0; s1 = r1 ? s1 : 0.0; t1 = r1 ? t1 : 0.0;
+        c2 = r2 ? c2 : 1.0; s2 = r2 ? s2 : 0.0; t2 = r2 ? t2 : 0.0;
+        rotate_regs<T, R>(x1, y1, c1, s1, f64);
+        rotate_regs<T, R>(x2, y2, c2, s2, f64);
+        n1 -= t1 * g1; m1 += t1 * g1;
+        n2 -= t2 * g2; m2 += t2 * g2;
+    }
+    return (int)r1 + (int)r2;
 }
 
 // Squared norm of an LDS column (rows gl + G q), reduced over the group.
@@ -345,7 +381,7 @@ __device__ void resident_task(const JacobiJob& J, int k, int max_sweeps, Ctrl* c
     for (int sw = 0; sw < max_sweeps + (refine ? 1 : 0); ++sw) {
         const bool f64 = refine && sw == max_sweeps;  // reached only through the refinement path
         const double tl = f64 ? (double)m * Unit<double>::v : tol;
-        int rot = 0;
+        int rot = 0, big = 0;
         ++executed;
         // exact squared column norms at the start of each sweep, tracked after
         for (int c = grp; c < p; c += ngrp) {
@@ -360,13 +396,14 @@ __device__ void resident_task(const JacobiJob& J, int k, int max_sweeps, Ctrl* c
                 if (j < p)
                     rot += gpair_lds<T, R, G>(As + i * ldl, As + j * ldl, s_nrm + i, s_nrm + j,
                                               WV ? Vs + i * ldv : nullptr, WV ? Vs + j * ldv : nullptr, WV ? p : 0,
-                                              gl, tl, f64);
+                                              gl, tl, f64, J.skip2, big);
             }
             __syncthreads();
         }
         const int tot = block_sum_groups(rot, gl, s_scratch);
+        const int btot = block_sum_groups(big, gl, s_scratch);
         if (f64) break;
-        if (tot == 0) {
+        if (tot == 0 || btot == 0) {
             sweeps = sw + 1;
             if (!refine) break;
             sw = max_sweeps - 1;  // one more sweep, in FP64 arithmetic
@@ -515,6 +552,63 @@ __device__ __forceinline__ void team_load_block(const JacobiJob& J, int k, int b
     }
 }
 
+// Load a block of B = 2 ng columns into LDS: group g takes columns 2g, 2g + 1.
+template <typename T, int R, int G>
+__device__ __forceinline__ void team_load_block2(const JacobiJob& J, int k, int blk, bool first, T* As) {
+    constexpr int ldl = R * G + kLdsPad;
+    const int m = J.m, p = J.p, B = J.b;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const T* Ag = (const T*)J.A + (int64_t)k * m * p;
+    if (first && J.src_rs != 1) {
+        // transposed source: consecutive lanes take consecutive columns (contiguous in memory)
+        for (int e = tid; e < B * ldl; e += nth) {
+            const int r = e / B, cl = e - r * B, c = blk * B + cl;
+            As[cl * ldl + r] = (c < p && r < m) ? src_at<T>(J, k, r, c) : (T)0;
+        }
+        return;
+    }
+    const int grp = tid / G, gl = tid % G, ca = blk * B + 2 * grp, cb = ca + 1;
+    T va[R], vb[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = gl + G * q;
+        va[q] = (T)0;
+        vb[q] = (T)0;
+        if (r < m) {
+            if (ca < p) va[q] = first ? src_at<T>(J, k, r, ca) : ld_team(Ag + (int64_t)ca * m + r);
+            if (cb < p) vb[q] = first ? src_at<T>(J, k, r, cb) : ld_team(Ag + (int64_t)cb * m + r);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        As[(2 * grp) * ldl + gl + G * q] = va[q];
+        As[(2 * grp + 1) * ldl + gl + G * q] = vb[q];
+    }
+}
+
+// Store a block of B = 2 ng columns: group g writes columns 2g, 2g + 1.
+template <typename T, int R, int G>
+__device__ __forceinline__ void team_store_block2(const JacobiJob& J, int k, int blk, const T* As) {
+    constexpr int ldl = R * G + kLdsPad;
+    const int m = J.m, p = J.p, B = J.b;
+    const int grp = threadIdx.x / G, gl = threadIdx.x % G, ca = blk * B + 2 * grp, cb = ca + 1;
+    T* Ag = (T*)J.A + (int64_t)k * m * p;
+    T va[R], vb[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        va[q] = As[(2 * grp) * ldl + gl + G * q];
+        vb[q] = As[(2 * grp + 1) * ldl + gl + G * q];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = gl + G * q;
+        if (r < m) {
+            if (ca < p) Ag[(int64_t)ca * m + r] = va[q];
+            if (cb < p) Ag[(int64_t)cb * m + r] = vb[q];
+        }
+    }
+}
+
 // Write a block back to the work array (group g stores column g).
 template <typename T, int R, int G, bool WV>
 __device__ __forceinline__ void team_store_block(const JacobiJob& J, int k, int blk, const T* As, const T* Vs) {
@@ -556,12 +650,12 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
     const double tol = J.tol;
     const bool refine = J.refine64 != 0;
     int sweeps = -1, executed = 0;
-    int* rot_g = J.rot + (int64_t)k * kMaxSweeps;
+    int* rot_g = J.rot + (int64_t)k * kRotStride;
     T* Ag = (T*)J.A + (int64_t)k * m * p;
     for (int sw = 0; sw < max_sweeps + (refine ? 1 : 0); ++sw) {
         const bool f64 = refine && sw == max_sweeps;
         const double tl = f64 ? (double)m * Unit<double>::v : tol;
-        int rot = 0;
+        int rot = 0, big = 0;
         ++executed;
         for (int s = 0; s < nb - 1; ++s) {
             for (int q = rank; q < nb / 2; q += ts.W) {
@@ -608,7 +702,7 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                         if (blk * b + j < p)
                             rot += gpair_lds<T, R, G>(base + i * ldl, base + j * ldl, nb_ + i, nb_ + j,
                                                       WV ? vb + i * ldv : nullptr, WV ? vb + j * ldv : nullptr,
-                                                      WV ? p : 0, gl, tl, f64);
+                                                      WV ? p : 0, gl, tl, f64, J.skip2, big);
                         __syncthreads();
                     }
 #pragma unroll
@@ -622,7 +716,7 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                 for (int r = 0; r < b; ++r, j = (j + 1 == b) ? 0 : j + 1) {
                     if (ci < p && BJ * b + j < p)
                         rot += gpair_reg<T, R, G>(xr, na, Js + j * ldl, nJ + j, WV ? Vi + grp * ldv : nullptr,
-                                                  WV ? Vj + j * ldv : nullptr, WV ? p : 0, gl, tl, f64);
+                                                  WV ? Vj + j * ldv : nullptr, WV ? p : 0, gl, tl, f64, J.skip2, big);
                     __syncthreads();
                 }
                 if (ci < p) {
@@ -644,13 +738,179 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
             }
             if (s == nb - 2) {
                 const int tot = block_sum_groups(rot, gl, s_scratch);
+                const int btot = block_sum_groups(big, gl, s_scratch);
                 if (tid == 0 && tot) atomicAdd(rot_g + sw, tot);
+                if (tid == 0 && btot) atomicAdd(rot_g + kMaxSweeps + sw, btot);
             }
             if (!team_barrier(ts, s_flag)) return false;
         }
         if (f64) break;
         const int total = __hip_atomic_load(rot_g + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (total == 0) {
+        const int large = __hip_atomic_load(rot_g + kMaxSweeps + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (total == 0 || large == 0) {
+            sweeps = sw + 1;
+            if (!refine) break;
+            sw = max_sweeps - 1;
+        }
+    }
+    if (tid == 0 && rank == 0) record_slice(J, k, sweeps, executed, ts.ctrl);
+    return true;
+}
+
+// Team task with two columns per lane group (no V).  Blocks are B = J.b
+// columns wide and a workgroup has ng = B / 2 groups.  The I block lives in
+// registers, columns 2g and 2g + 1 in group g; the J block in LDS.  A cross
+// round gives group g the J columns 2j, 2j + 1 (j = (g + r) mod ng) and does
+// the pairs (x1, y1), (x2, y2) together, then (x1, y2), (x2, y1): two
+// independent rotations at a time, and each J column read from LDS serves two
+// pairs (half the LDS traffic of one column per group).  The first step of a
+// sweep also pairs the columns inside each block: B - 1 rounds, group g takes
+// pair g of the I block and pair g of the J block.
+template <typename T, int R, int G>
+__device__ bool team_task_k2(const JacobiJob& J, int k, int rank, TeamState& ts, int max_sweeps, T* lds,
+                             int* s_scratch, int* s_flag, double* nI, double* nJ) {
+    constexpr int ldl = R * G + kLdsPad;
+    const int m = J.m, p = J.p, B = J.b, nb = J.nb, ng = J.b / 2;
+    const int tid = threadIdx.x, grp = tid / G, gl = tid % G;
+    T* Is = lds;                        // B columns x ldl (first step of a sweep)
+    T* Js = lds + (int64_t)B * ldl;     // B columns x ldl
+    const double tol = J.tol;
+    const bool refine = J.refine64 != 0;
+    int sweeps = -1, executed = 0;
+    int* rot_g = J.rot + (int64_t)k * kRotStride;
+    T* Ag = (T*)J.A + (int64_t)k * m * p;
+    for (int sw = 0; sw < max_sweeps + (refine ? 1 : 0); ++sw) {
+        const bool f64 = refine && sw == max_sweeps;
+        const double tl = f64 ? (double)m * Unit<double>::v : tol;
+        int rot = 0, big = 0;
+        ++executed;
+        for (int s = 0; s < nb - 1; ++s) {
+            for (int q = rank; q < nb / 2; q += ts.W) {
+                int BI, BJ;
+                rr_pair(s, q, nb, BI, BJ);
+                const bool first = (sw == 0 && s == 0);
+                const int c1 = BI * B + 2 * grp, c2 = c1 + 1;  // this group's I columns
+                T x1[R], x2[R];
+                double n1 = 0.0, n2 = 0.0;
+                if (s != 0) {
+                    // the I columns come from the work array; their loads are issued first
+                    const T* xs1 = Ag + (int64_t)(c1 < p ? c1 : 0) * m;
+                    const T* xs2 = Ag + (int64_t)(c2 < p ? c2 : 0) * m;
+#pragma unroll
+                    for (int q2 = 0; q2 < R; ++q2) {
+                        const int r = gl + G * q2;
+                        x1[q2] = (T)0;
+                        x2[q2] = (T)0;
+                        if (r < m) {
+                            x1[q2] = ld_team(xs1 + r);
+                            x2[q2] = ld_team(xs2 + r);
+                        }
+                    }
+                }
+                team_load_block2<T, R, G>(J, k, BJ, first, Js);
+                if (s == 0) team_load_block2<T, R, G>(J, k, BI, first, Is);
+                __syncthreads();
+                {
+                    const double a0 = lds_col_norm<T, R, G>(Js + (2 * grp) * ldl, gl);
+                    const double a1 = lds_col_norm<T, R, G>(Js + (2 * grp + 1) * ldl, gl);
+                    if (gl == 0) { nJ[2 * grp] = a0; nJ[2 * grp + 1] = a1; }
+                    if (s == 0) {
+                        const double b0 = lds_col_norm<T, R, G>(Is + (2 * grp) * ldl, gl);
+                        const double b1 = lds_col_norm<T, R, G>(Is + (2 * grp + 1) * ldl, gl);
+                        if (gl == 0) { nI[2 * grp] = b0; nI[2 * grp + 1] = b1; }
+                    }
+                }
+                __syncthreads();
+                if (s == 0) {
+                    // pairs inside each block: B - 1 rounds of ng pairs per block
+                    for (int r = 0; r < B - 1; ++r) {
+                        int i1, j1;
+                        rr_pair(r, grp, B, i1, j1);  // pair grp of this round, in both blocks
+                        const bool vI = BI * B + j1 < p, vJ = BJ * B + j1 < p;
+                        T a[R], b[R], c[R], d[R];
+#pragma unroll
+                        for (int q2 = 0; q2 < R; ++q2) {
+                            const int rr = gl + G * q2;
+                            a[q2] = Is[i1 * ldl + rr];
+                            b[q2] = Is[j1 * ldl + rr];
+                            c[q2] = Js[i1 * ldl + rr];
+                            d[q2] = Js[j1 * ldl + rr];
+                        }
+                        double na = nI[i1], nbb = nI[j1], nc = nJ[i1], nd = nJ[j1];
+                        rot += gpair2<T, R, G>(a, na, b, nbb, c, nc, d, nd, vI, vJ, tl, f64, J.skip2, big);
+#pragma unroll
+                        for (int q2 = 0; q2 < R; ++q2) {
+                            const int rr = gl + G * q2;
+                            Is[i1 * ldl + rr] = a[q2];
+                            Is[j1 * ldl + rr] = b[q2];
+                            Js[i1 * ldl + rr] = c[q2];
+                            Js[j1 * ldl + rr] = d[q2];
+                        }
+                        if (gl == 0) {
+                            nI[i1] = na; nI[j1] = nbb;
+                            nJ[i1] = nc; nJ[j1] = nd;
+                        }
+                        __syncthreads();
+                    }
+#pragma unroll
+                    for (int q2 = 0; q2 < R; ++q2) {
+                        x1[q2] = Is[(2 * grp) * ldl + gl + G * q2];
+                        x2[q2] = Is[(2 * grp + 1) * ldl + gl + G * q2];
+                    }
+                    n1 = nI[2 * grp];
+                    n2 = nI[2 * grp + 1];
+                } else {
+                    n1 = group_sum<G>(partial_norm<T, R>(x1));
+                    n2 = group_sum<G>(partial_norm<T, R>(x2));
+                }
+                // cross pairs: ng rounds; group g meets J columns 2j, 2j + 1, j = (g + r) mod ng
+                const bool u1 = c1 < p, u2 = c2 < p;
+                int j = grp;
+                for (int r = 0; r < ng; ++r, j = (j + 1 == ng) ? 0 : j + 1) {
+                    T y1[R], y2[R];
+#pragma unroll
+                    for (int q2 = 0; q2 < R; ++q2) {
+                        y1[q2] = Js[(2 * j) * ldl + gl + G * q2];
+                        y2[q2] = Js[(2 * j + 1) * ldl + gl + G * q2];
+                    }
+                    double m1 = nJ[2 * j], m2 = nJ[2 * j + 1];
+                    const bool w1 = BJ * B + 2 * j < p, w2 = BJ * B + 2 * j + 1 < p;
+                    rot += gpair2<T, R, G>(x1, n1, y1, m1, x2, n2, y2, m2, u1 && w1, u2 && w2, tl, f64, J.skip2, big);
+                    rot += gpair2<T, R, G>(x1, n1, y2, m2, x2, n2, y1, m1, u1 && w2, u2 && w1, tl, f64, J.skip2, big);
+#pragma unroll
+                    for (int q2 = 0; q2 < R; ++q2) {
+                        Js[(2 * j) * ldl + gl + G * q2] = y1[q2];
+                        Js[(2 * j + 1) * ldl + gl + G * q2] = y2[q2];
+                    }
+                    if (gl == 0) {
+                        nJ[2 * j] = m1;
+                        nJ[2 * j + 1] = m2;
+                    }
+                    __syncthreads();
+                }
+#pragma unroll
+                for (int q2 = 0; q2 < R; ++q2) {
+                    const int r = gl + G * q2;
+                    if (r < m) {
+                        if (u1) Ag[(int64_t)c1 * m + r] = x1[q2];
+                        if (u2) Ag[(int64_t)c2 * m + r] = x2[q2];
+                    }
+                }
+                team_store_block2<T, R, G>(J, k, BJ, Js);
+                __syncthreads();
+            }
+            if (s == nb - 2) {
+                const int tot = block_sum_groups(rot, gl, s_scratch);
+                const int btot = block_sum_groups(big, gl, s_scratch);
+                if (tid == 0 && tot) atomicAdd(rot_g + sw, tot);
+                if (tid == 0 && btot) atomicAdd(rot_g + kMaxSweeps + sw, btot);
+            }
+            if (!team_barrier(ts, s_flag)) return false;
+        }
+        if (f64) break;
+        const int total = __hip_atomic_load(rot_g + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int large = __hip_atomic_load(rot_g + kMaxSweeps + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (total == 0 || large == 0) {
             sweeps = sw + 1;
             if (!refine) break;
             sw = max_sweeps - 1;
@@ -666,12 +926,12 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
 // XCDs and take slices t, t + nteams, ...  ctl layout (ints, zeroed before the
 // launch): [0, 16) slot counter per XCD, [16] arrivals, [32 + i] barrier of
 // team i.
-template <typename T, bool WV, int R, int G>
+template <typename T, bool WV, int R, int G, int K>
 __global__ __launch_bounds__(512) void k_jacobi_team(JacobiJob J1, int ntasks, TeamSched sched, int max_sweeps,
                                                      Ctrl* ctrl, int spin_limit) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_scratch, s_flag, s_team, s_rank, s_nteams;
-    __shared__ double s_nI[kTeamMaxThreads / 16], s_nJ[kTeamMaxThreads / 16];
+    __shared__ double s_nI[kTeamMaxThreads / 8], s_nJ[kTeamMaxThreads / 8];
     T* lds = (T*)smem_raw;
     const int W = sched.W;
     int* ctl = sched.ctl;
@@ -706,8 +966,14 @@ __global__ __launch_bounds__(512) void k_jacobi_team(JacobiJob J1, int ntasks, T
     const int team = s_team, rank = s_rank, nteams = s_nteams;
     if (team < 0) return;
     TeamState ts{ctl + 32 + team, 0, W, spin_limit, ctrl};
-    for (int t = team; t < ntasks; t += nteams)
-        if (!team_task<T, R, G, WV>(J1, t, rank, ts, max_sweeps, lds, &s_scratch, &s_flag, s_nI, s_nJ)) return;
+    for (int t = team; t < ntasks; t += nteams) {
+        if constexpr (K == 2) {
+            static_assert(!WV, "two columns per group: no V");
+            if (!team_task_k2<T, R, G>(J1, t, rank, ts, max_sweeps, lds, &s_scratch, &s_flag, s_nI, s_nJ)) return;
+        } else {
+            if (!team_task<T, R, G, WV>(J1, t, rank, ts, max_sweeps, lds, &s_scratch, &s_flag, s_nI, s_nJ)) return;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -784,26 +1050,29 @@ int jacobi_team_lds_bytes(int prec, int m, int p, int G, int b, int with_v) {
     return (int)(elems * elem_size(prec));
 }
 
-template <typename T, bool WV>
+template <typename T, bool WV, int K>
 static const void* team_fn_rg(int R, int G) {
     if (G == 16) {
         switch (R) {
-            case 4: return (const void*)k_jacobi_team<T, WV, 4, 16>;
-            case 8: return (const void*)k_jacobi_team<T, WV, 8, 16>;
-            case 12: return (const void*)k_jacobi_team<T, WV, 12, 16>;
-            default: return (const void*)k_jacobi_team<T, WV, 16, 16>;
+            case 4: return (const void*)k_jacobi_team<T, WV, 4, 16, K>;
+            case 8: return (const void*)k_jacobi_team<T, WV, 8, 16, K>;
+            case 12: return (const void*)k_jacobi_team<T, WV, 12, 16, K>;
+            default: return (const void*)k_jacobi_team<T, WV, 16, 16, K>;
         }
     }
     switch (R) {
-        case 4: return (const void*)k_jacobi_team<T, WV, 4, 32>;
-        case 8: return (const void*)k_jacobi_team<T, WV, 8, 32>;
-        case 12: return (const void*)k_jacobi_team<T, WV, 12, 32>;
-        default: return (const void*)k_jacobi_team<T, WV, 16, 32>;
+        case 4: return (const void*)k_jacobi_team<T, WV, 4, 32, K>;
+        case 8: return (const void*)k_jacobi_team<T, WV, 8, 32, K>;
+        case 12: return (const void*)k_jacobi_team<T, WV, 12, 32, K>;
+        default: return (const void*)k_jacobi_team<T, WV, 16, 32, K>;
     }
 }
-static const void* team_fn(int prec, int with_v, int R, int G) {
-    return prec == 0 ? (with_v ? team_fn_rg<double, true>(R, G) : team_fn_rg<double, false>(R, G))
-                     : (with_v ? team_fn_rg<float, true>(R, G) : team_fn_rg<float, false>(R, G));
+// K = 2 (two columns per lane group) exists without V only
+static const void* team_fn(int prec, int with_v, int R, int G, int K) {
+    if (K == 2)
+        return prec == 0 ? team_fn_rg<double, false, 2>(R, G) : team_fn_rg<float, false, 2>(R, G);
+    return prec == 0 ? (with_v ? team_fn_rg<double, true, 1>(R, G) : team_fn_rg<double, false, 1>(R, G))
+                     : (with_v ? team_fn_rg<float, true, 1>(R, G) : team_fn_rg<float, false, 1>(R, G));
 }
 template <typename T, bool WV>
 static const void* res_fn() { return (const void*)k_jacobi_resident<T, WV>; }
@@ -823,10 +1092,11 @@ hipError_t launch_jacobi_resident(int prec, const JacobiJob& job1, const JacobiJ
 }
 
 hipError_t launch_jacobi_team(int prec, const JacobiJob& job, int ntasks, const TeamSched& ts_in, int max_sweeps,
-                              Ctrl* ctrl, int lds_bytes, int threads, int with_v, int spin_limit, int R, int G, int coop,
-                              hipStream_t s) {
+                              Ctrl* ctrl, int lds_bytes, int threads, int with_v, int spin_limit, int R, int G, int K,
+                              int coop, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
-    const void* f = team_fn(prec, with_v, R, G);
+    if (K == 2 && with_v) return hipErrorInvalidValue;
+    const void* f = team_fn(prec, with_v, R, G, K);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
     TeamSched ts = ts_in;
@@ -875,9 +1145,10 @@ hipError_t launch_jacobi_batched(int prec, int R, int G, const JacobiJob* jobs_d
     return hipLaunchKernel(f, dim3(grid), dim3(kTeamMaxThreads), args, (size_t)lds_bytes, s);
 }
 
-int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v, int R, int G) {
+int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v, int R, int G, int K) {
     int nb = 0;
-    const void* f = team_fn(prec, with_v, R, G);
+    if (K == 2 && with_v) return 0;
+    const void* f = team_fn(prec, with_v, R, G, K);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();  // do not leave a sticky error for the caller's runtime

@@ -24,33 +24,41 @@ def case(shape, seed):
                            0.1 * (np.sqrt(n1) + np.sqrt(n2)), seed)
 
 
-# (shape, group widths, team sizes): resident slices, team slices with both
-# group widths, and a wide tensor whose 300-row slices need 32-lane groups
+# (shape, group widths, team sizes, group columns): resident slices, team
+# slices with both group widths and one or two columns per group, and a wide
+# tensor whose 300-row slices need 32-lane groups
 FORCED = [
-    ((64, 48, 9), (16, 32), (0,)),
-    ((256, 200, 3), (16, 32), (1, 2, 3, 4)),
-    ((130, 300, 2), (32,), (1, 2, 4)),
+    ((64, 48, 9), (16, 32), (0,), (1,)),
+    ((256, 200, 3), (16, 32), (1, 2, 3, 4), (1, 2)),
+    ((130, 300, 2), (32,), (1, 2, 4), (1, 2)),
+    ((257, 190, 2), (32,), (1, 3, 8), (2,)),
 ]
 
 
-@pytest.mark.parametrize("shape,widths,teams", FORCED)
-def test_forced_tiles_match_oracle(tm, shape, widths, teams):
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape,widths,teams,cols", FORCED)
+def test_forced_tiles_match_oracle(tm, shape, widths, teams, cols, prec):
     c = case(shape, 700 + shape[0])
-    want = oracle.tsvt_dct(c.Z, c.tau)
-    Z = to_dev(c.Z)
+    dt = torch.float64 if prec == 0 else torch.float32
+    Zh = c.Z if prec == 0 else c.Z.astype(np.float32).astype(np.float64)
+    want = oracle.tsvt_dct(Zh, c.tau)
+    Z = to_dev(Zh, dt)
     for G in widths:
         for W in teams:
-            announce("forced_tile", shape=shape, G=G, W=W)
-            ctx = tm.Context(0)
-            ctx.set_option(tm.OPT_GROUP_LANES, G)
-            ctx.set_option(tm.OPT_TEAM_SIZE, W)
-            t = ctx.tile(tm.FP64, *shape)
-            assert t["source"] == 2 and t["G"] == G
-            Y = tm.tsvt_dct(Z, c.tau, ctx=ctx)
-            err = rel(to_np(Y), want)
-            print("shape %s G %d W %d tile %s rel err %.2e" % (shape, G, W, t, err))
-            assert err <= 1e-10
-            ctx.close()
+            for K in cols:
+                announce("forced_tile", shape=shape, G=G, W=W, K=K, prec=prec)
+                ctx = tm.Context(0)
+                ctx.set_option(tm.OPT_GROUP_LANES, G)
+                ctx.set_option(tm.OPT_TEAM_SIZE, W)
+                ctx.set_option(tm.OPT_GROUP_COLUMNS, K)
+                t = ctx.tile(prec, *shape)
+                assert t["source"] == 2 and t["G"] == G
+                assert t["K"] == (K if t["team"] else 0)
+                Y = tm.tsvt_dct(Z, c.tau, prec=prec, ctx=ctx)
+                err = rel(to_np(Y), want)
+                print("shape %s prec %d G %d W %d K %d tile %s rel err %.2e" % (shape, prec, G, W, K, t, err))
+                assert err <= (1e-10 if prec == 0 else 1e-4)
+                ctx.close()
 
 
 @pytest.mark.parametrize("shape", [(64, 48, 9), (256, 200, 3), (200, 256, 5)])
