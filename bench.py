@@ -82,7 +82,7 @@ def run_completion(tm, torch, case, prec, steps, warmup, profile):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = ctx.stats(reset=True)
-    tile = ctx.tile(prec, N1, N2, N3)
+    tile = ctx.tile(prec, N1, N2, N3, with_v=ctx.get_option(tm.OPT_WARM_START) != 0)
     Xn = X.detach().cpu().to(torch.float64).numpy()
     # the next iteration's t-SVT input, Z = X - M / beta (Algorithm 1, first step)
     beta = 1.0 / taus[steps]

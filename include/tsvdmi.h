@@ -85,9 +85,13 @@ enum {
                                   built-in heuristic.  See tsvd_get_tile. */
     TSVD_OPT_GROUP_LANES = 7,  /* 0: automatic; 16 or 32: lanes per column-pair group in the Jacobi
                                   kernels (a forced setting, like TEAM_SIZE, disables tuning) */
-    TSVD_OPT_GROUP_COLUMNS = 8 /* 0: automatic; 1 or 2: columns each lane group of the multi-workgroup
+    TSVD_OPT_GROUP_COLUMNS = 8, /* 0: automatic; 1 or 2: columns each lane group of the multi-workgroup
                                   Jacobi kernel holds (2: two independent rotations at a time; not
                                   with V).  A forced setting disables tuning. */
+    TSVD_OPT_WARM_START = 9    /* complete_tensor: -1 (default) warm-start each iteration's Jacobi SVDs
+                                  from the previous iteration's right singular vectors, resetting
+                                  them every 64 (FP64) or 16 (FP32, MIXED) iterations; N >= 1: reset
+                                  every N iterations; 0: cold starts */
 };
 int tsvd_set_option(tsvd_ctx* ctx, int option, double value);
 double tsvd_get_option(const tsvd_ctx* ctx, int option);
@@ -120,14 +124,15 @@ int tsvd_get_tile(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, i
 
 /* Counters since the last reset.  Phases: 0 forward transform (with the
  * completion prologue), 1 Jacobi SVD, 2 thresholding and rebuild, 3 inverse
- * transform (with the completion epilogue).  ms/launches are filled only
+ * transform (with the completion epilogue), 4 warm start of the completion's
+ * Jacobi (reset of V and the product Zbar V).  ms/launches are filled only
  * while TSVD_OPT_PROFILE is 1 (event pairs on the launch stream).
  * slice_sweeps counts Jacobi sweeps summed over all slices processed, always.
  * Synchronizes `stream`. */
 typedef struct {
     int64_t slice_sweeps;
-    double ms[4];
-    int64_t launches[4];
+    double ms[5];
+    int64_t launches[5];
 } tsvd_stats;
 int tsvd_get_stats(tsvd_ctx* ctx, void* stream, tsvd_stats* out, int reset);
 

@@ -20,8 +20,8 @@ LIB_PATH = os.path.join(HERE, "libtsvdmi.so")
 FP64, FP32, MIXED = 0, 1, 2
 OK, WARN_NOCONV, EINVAL, ENOMEM, EHIP, ENONFINITE, EBUSY, ETIMEOUT = 0, 1, -1, -2, -3, -4, -5, -6
 OPT_MAX_SWEEPS, OPT_SYNC_STATUS, OPT_TEAM_SIZE, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_GRAPHS = 0, 1, 2, 3, 4, 5
-OPT_AUTOTUNE, OPT_GROUP_LANES, OPT_GROUP_COLUMNS = 6, 7, 8
-PHASES = ("forward_transform", "jacobi", "threshold_rebuild", "inverse_transform")
+OPT_AUTOTUNE, OPT_GROUP_LANES, OPT_GROUP_COLUMNS, OPT_WARM_START = 6, 7, 8, 9
+PHASES = ("forward_transform", "jacobi", "threshold_rebuild", "inverse_transform", "warm_start")
 TRANSFORM_DOMAIN = 1
 REQ_TSVT, REQ_COMPLETE = 0, 1
 
@@ -51,7 +51,7 @@ class CompleteInfo(C.Structure):
 
 
 class Stats(C.Structure):
-    _fields_ = [("slice_sweeps", C.c_int64), ("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
+    _fields_ = [("slice_sweeps", C.c_int64), ("ms", C.c_double * 5), ("launches", C.c_int64 * 5)]
 
 
 class Request(C.Structure):
@@ -132,8 +132,8 @@ class Context:
         st = Stats()
         self.check(lib.tsvd_get_stats(self.h, _stream(stream, self.device), C.byref(st), int(reset)))
         return {"slice_sweeps": st.slice_sweeps,
-                "ms": {PHASES[i]: st.ms[i] for i in range(4)},
-                "launches": {PHASES[i]: st.launches[i] for i in range(4)}}
+                "ms": {PHASES[i]: st.ms[i] for i in range(5)},
+                "launches": {PHASES[i]: st.launches[i] for i in range(5)}}
 
     def tile(self, prec: int, n1: int, n2: int, n3: int, batched: bool = False, with_v: bool = False) -> dict:
         """Jacobi tile this context uses for the shape (tunes it if needed)."""

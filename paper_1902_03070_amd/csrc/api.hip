@@ -30,6 +30,7 @@ struct tsvd_ctx {
     int group_lanes = 0;
     int group_cols = 0;
     int autotune = 1;
+    int warm_start = -1;  // complete_tensor: -1 automatic period, 0 off, N: reset V every N iterations
     int spin_limit = 1 << 24;
     std::string err = "";
     // transform matrices: (n3, prec) -> {C, C^T} rows, element type by prec
@@ -272,6 +273,8 @@ struct Plan {
     int threads = 256;
     int tile_source = 0, tile_W = 0;
     int K = 1;           // team kernel lane-group columns
+    int warm = 0, warm_period = 0;  // completion warm start: A0 = Zbar V before Jacobi (V kept across iterations)
+    size_t o_A0 = 0;
     int lds = 0;
     TeamSched ts{};
     JacobiJob job{};
@@ -720,8 +723,9 @@ void bind_plan(Plan& P, char* base) {
     J.tol = P.prec == TSVD_FP64 ? P.m * u64 : P.prec == TSVD_FP32 ? 2.0 * sqrt((double)P.m) * u32 : P.m * u32;
     // A sweep whose cosines are all <= sqrt(tol) / 64 leaves the next one rotating by ~tol / 4096
     // (quadratic convergence), below the rotation threshold: the sweep that would only confirm it
-    // is skipped.
-    J.skip2 = J.tol / 4096.0;
+    // is skipped.  MIXED hands over to its FP64 sweep once the FP32 sweeps are at cosines <= 3e-3:
+    // that sweep starts from ~1e-5 and ends far below the FP32 rounding of the stored columns.
+    J.skip2 = P.prec == TSVD_MIXED ? 9e-6 : J.tol / 4096.0;
     P.ts.ctl = (int*)(base + P.o_bar);
 }
 
@@ -752,14 +756,44 @@ int run_jacobi(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s) {
 int enqueue_after_jacobi(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau_val, const double* tau_sched,
                          hipStream_t s);
 
+int enqueue_warm_start(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s);
+
 int enqueue_svt_core(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau_val, const double* tau_sched,
                      hipStream_t s) {
+    if (P.warm) {
+        PhaseMark pm(c, 4, s);
+        int rc = enqueue_warm_start(c, P, base, ctrl, s);
+        if (rc) return rc;
+    }
     {
         PhaseMark pm(c, 1, s);
         int rc = run_jacobi(c, P, base, ctrl, s);
         if (rc) return rc;
     }
     return enqueue_after_jacobi(c, P, base, ctrl, tau_val, tau_sched, s);
+}
+
+// Warm start (completion only): V of every slice is kept from the previous
+// iteration (reset to the identity every warm_period iterations) and the
+// Jacobi input is A0 = Zbar_k V_k, whose one-sided Jacobi ends at Zbar_k V_k J
+// with V_k J the new V: the singular vectors change little between
+// iterations, so A0 is nearly orthogonal already and few sweeps are needed.
+int enqueue_warm_start(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s) {
+    const int prec = P.prec == TSVD_FP64 ? 0 : 1;
+    hipError_t e = launch_warm_reset(prec, base + P.o_V, P.p, (int)P.n3, ctrl, P.warm_period, s);
+    if (e != hipSuccess) return hip_fail(c, e, "warm reset");
+    GemmArgs g{};
+    g.A = base + P.o_zbar;  // tall view of the slice
+    if (!P.trans) { g.a_rs = 1; g.a_cs = P.n1; } else { g.a_rs = P.n1; g.a_cs = 1; }
+    g.a_bs = P.N;
+    g.B = base + P.o_V; g.b_rs = 1; g.b_cs = P.p; g.b_bs = (int64_t)P.p * P.p;
+    g.C = base + P.o_A0; g.c_rs = 1; g.c_cs = P.m; g.c_bs = (int64_t)P.m * P.p;
+    g.cscale = nullptr;
+    g.M = P.m; g.Nn = P.p; g.K = P.p; g.Kdev = nullptr; g.Ndev = nullptr;
+    g.batch = (int)P.n3;
+    e = launch_gemm(prec, g, s);
+    if (e != hipSuccess) return hip_fail(c, e, "warm start gemm");
+    return TSVD_OK;
 }
 
 // Thresholding and rebuild (Ybar in the workspace) once A' is ready.
@@ -882,6 +916,10 @@ int tsvd_set_option(tsvd_ctx* c, int opt, double v) {
             if (v != 0 && v != 1 && v != 2) return fail(c, TSVD_EINVAL, "group columns must be 0, 1 or 2");
             c->group_cols = (int)v;
             return TSVD_OK;
+        case TSVD_OPT_WARM_START:
+            if (v < -1 || v > 1e6) return fail(c, TSVD_EINVAL, "warm start must be -1, 0 or a period >= 1");
+            c->warm_start = (int)v;
+            return TSVD_OK;
         case TSVD_OPT_GROUP_LANES:
             if (v != 0 && v != 16 && v != 32) return fail(c, TSVD_EINVAL, "group lanes must be 0, 16 or 32");
             c->group_lanes = (int)v;
@@ -901,6 +939,7 @@ double tsvd_get_option(const tsvd_ctx* c, int opt) {
         case TSVD_OPT_GRAPHS: return c->use_graphs;
         case TSVD_OPT_AUTOTUNE: return c->autotune;
         case TSVD_OPT_GROUP_COLUMNS: return c->group_cols;
+        case TSVD_OPT_WARM_START: return c->warm_start;
         case TSVD_OPT_GROUP_LANES: return c->group_lanes;
     }
     return -1.0;
@@ -1131,14 +1170,28 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
     hipStream_t s = (hipStream_t)stream;
     Plan P;
     Carve cv;
-    int rc = make_plan(c, prec, n1, n2, n3, 0, P, cv, s);
+    const int warm_period = c->warm_start < 0 ? (prec == TSVD_FP64 ? 64 : 16) : c->warm_start;
+    int rc = make_plan(c, prec, n1, n2, n3, warm_period > 0 ? 1 : 0, P, cv, s);
     if (rc) return rc;
     const size_t es = esize(prec);
     const size_t oM = cv.take((size_t)P.N * n3 * es);
+    if (warm_period > 0) {
+        P.warm = 1;
+        P.warm_period = warm_period;
+        P.o_A0 = cv.take((size_t)P.m * P.p * n3 * es);
+    }
     const size_t oBeta = cv.take((size_t)L * 8), oTau = cv.take((size_t)L * 8);
     if ((rc = ensure_ws(c, cv.off))) return rc;
     char* base = (char*)c->ws.p;
     if ((rc = upload_plan(c, P, base))) return rc;
+    if (P.warm) {
+        // Jacobi reads A0 = Zbar V (tall, column-major) and starts V from the kept V
+        P.job.src = base + P.o_A0;
+        P.job.src_ss = (int64_t)P.m * P.p;
+        P.job.src_rs = 1;
+        P.job.src_cs = P.m;
+        P.job.vinit = 1;
+    }
     CtrlRegion cr;
     if ((rc = ensure_ctrl(c, &cr))) return rc;
     const void *C, *Ct;

@@ -49,6 +49,7 @@ struct JacobiJob {
     int b;             // block width for the team kernel (even)
     int nb;            // number of column blocks (even) = ceil(p / b) rounded up to even
     int refine64;      // 1: after convergence run one sweep with FP64 arithmetic (FP32 data)
+    int vinit;         // with V: 1 starts V from the contents of V (a warm start), 0 from the identity
     double tol;        // rotate a pair iff |x.y| > tol |x| |y| (precision dependent, set on the host)
     double skip2;      // a sweep whose pairs all have (x.y)^2 <= skip2 |x|^2 |y|^2 ends the iteration
                        // (the next sweep would rotate by angles far below tol: no check sweep)
@@ -174,6 +175,8 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
 // n values of a deterministic pseudo-random pattern in [-1, 1) (prec 0: double, else float).
 hipError_t launch_fill_pattern(void* p, int64_t n, int prec, uint32_t seed, hipStream_t s);
 hipError_t launch_iter_advance(Ctrl* ctrl, double* norms, double* relchg_hist, int hist_len, hipStream_t s);
+// V (p x p per slice, n3 slices) := identity when ctrl->iter % period == 0.
+hipError_t launch_warm_reset(int prec, void* V, int p, int n3, const Ctrl* ctrl, int period, hipStream_t s);
 // Sort singular values descending per slice and build U = A'(:,perm)/sigma, with the
 // sign convention, and permute V; used by tsvd_dct.
 struct TsvdFinishArgs {

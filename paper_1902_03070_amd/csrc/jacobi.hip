@@ -155,7 +155,7 @@ __device__ __forceinline__ bool rotation(double a, double b, double g, double to
 // set, the partial squared norms).  FP32 data accumulate their R products in
 // FP32 unless f64 (refinement sweep) asks for FP64.
 template <typename T, int R>
-__device__ __forceinline__ double partial_dot(const T (&x)[R], const T (&y)[R], bool f64) {
+__device__ __forceinline__ double partial_dot(const T* x, const T* y, bool f64) {
     // four independent accumulators shorten the dependency chain
     if (sizeof(T) == 8 || f64) {
         double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
@@ -180,7 +180,7 @@ __device__ __forceinline__ double partial_dot(const T (&x)[R], const T (&y)[R], 
 }
 
 template <typename T, int R>
-__device__ __forceinline__ double partial_norm(const T (&x)[R]) {
+__device__ __forceinline__ double partial_norm(const T* x) {
     double pa = 0.0;
 #pragma unroll
     for (int q = 0; q < R; ++q) pa = fma((double)x[q], (double)x[q], pa);
@@ -256,25 +256,54 @@ __device__ __forceinline__ int gpair_lds(T* __restrict__ x, T* __restrict__ y, d
     return 1;
 }
 
-// Pair with x in registers (squared norm na, uniform in the group) and y in
-// LDS (squared norm *nb).
-template <typename T, int R, int G>
-__device__ __forceinline__ int gpair_reg(T (&xr)[R], double& na, T* __restrict__ y, double* nb,
-                                         T* __restrict__ vx, T* __restrict__ vy, int vrows, int gl, double tol,
-                                         bool f64, double th2, int& big) {
-    const double b = *nb;
-    T yr[R];
+
+// Team-kernel columns carry RT values per lane: the first R are the rows of A
+// (row gl + G q), the others (RT > R when V is accumulated) the rows of V
+// (row gl + G (q - R)).  Inner products and norms use the A rows; rotations
+// act on the whole column, so V follows every rotation of A.
+template <typename T, int R, int RT, int G>
+__device__ __forceinline__ int tpair_lds(T* __restrict__ x, T* __restrict__ y, double* na, double* nb, int gl,
+                                         double tol, bool f64, double th2, int& big) {
+    T xr[RT], yr[RT];
 #pragma unroll
-    for (int q = 0; q < R; ++q) yr[q] = y[gl + G * q];
+    for (int q = 0; q < RT; ++q) {
+        xr[q] = x[gl + G * q];
+        yr[q] = y[gl + G * q];
+    }
+    const double a = *na, b = *nb;
+    const double g = group_sum<G>(partial_dot<T, R>(xr, yr, f64));
+    big += g * g > th2 * (a * b);
+    double c, s, t;
+    if (!rotation(a, b, g, tol, c, s, t)) return 0;
+    rotate_regs<T, RT>(xr, yr, c, s, f64);
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        x[gl + G * q] = xr[q];
+        y[gl + G * q] = yr[q];
+    }
+    if (gl == 0) {
+        *na = a - t * g;
+        *nb = b + t * g;
+    }
+    return 1;
+}
+
+// Pair with x in registers (squared norm na, uniform in the group) and y in LDS.
+template <typename T, int R, int RT, int G>
+__device__ __forceinline__ int tpair_reg(T (&xr)[RT], double& na, T* __restrict__ y, double* nb, int gl,
+                                         double tol, bool f64, double th2, int& big) {
+    const double b = *nb;
+    T yr[RT];
+#pragma unroll
+    for (int q = 0; q < RT; ++q) yr[q] = y[gl + G * q];
     const double a = na;
     const double g = group_sum<G>(partial_dot<T, R>(xr, yr, f64));
     big += g * g > th2 * (a * b);
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
-    rotate_regs<T, R>(xr, yr, c, s, f64);
+    rotate_regs<T, RT>(xr, yr, c, s, f64);
 #pragma unroll
-    for (int q = 0; q < R; ++q) y[gl + G * q] = yr[q];
-    if (vrows) rotate_lds_col<T>(vx, vy, vrows, gl, G, c, s, f64);
+    for (int q = 0; q < RT; ++q) y[gl + G * q] = yr[q];
     na = a - t * g;
     if (gl == 0) *nb = b + t * g;
     return 1;
@@ -368,11 +397,15 @@ __device__ void resident_task(const JacobiJob& J, int k, int max_sweeps, Ctrl* c
             As[c * ldl + r] = (c < p && r < m) ? src_at<T>(J, k, r, c) : (T)0;
         }
     }
-    if (WV)
+    if (WV) {
+        const T* Vg0 = (const T*)J.V + (int64_t)k * p * p;
         for (int e = tid; e < pp * ldv; e += nth) {
             const int c = e / ldv, r = e - c * ldv;
-            Vs[e] = (r == c) ? (T)1 : (T)0;
+            T v = (r == c) ? (T)1 : (T)0;
+            if (J.vinit) v = (c < p && r < p) ? Vg0[(int64_t)c * p + r] : (T)0;  // warm start
+            Vs[e] = v;
         }
+    }
     __syncthreads();
 
     const double tol = J.tol;
@@ -517,20 +550,21 @@ __device__ bool team_barrier(TeamState& ts, int* s_flag) {
 // Load b columns of block `blk` into LDS (ld ldl); from the source tensor on
 // the first step of the first sweep, else from A.  Zero padding beyond m / p.
 template <typename T, int R, int G, bool WV>
-__device__ __forceinline__ void team_load_block(const JacobiJob& J, int k, int blk, bool first, T* As, T* Vs) {
-    constexpr int ldl = R * G + kLdsPad;
-    const int m = J.m, p = J.p, b = J.b, ldv = J.ldv;
+__device__ __forceinline__ void team_load_block(const JacobiJob& J, int k, int blk, bool first, T* As) {
+    constexpr int RT = WV ? 2 * R : R;
+    constexpr int ldl = RT * G + kLdsPad;
+    const int m = J.m, p = J.p, b = J.b;
     const int tid = threadIdx.x, nth = blockDim.x;
+    const int grp = tid / G, gl = tid % G, c = blk * b + grp;
     const T* Ag = (const T*)J.A + (int64_t)k * m * p;
     if (first && J.src_rs != 1) {
         // transposed source: consecutive lanes take consecutive columns (contiguous in memory)
-        for (int e = tid; e < b * ldl; e += nth) {
-            const int r = e / b, cl = e - r * b, c = blk * b + cl;
-            As[cl * ldl + r] = (c < p && r < m) ? src_at<T>(J, k, r, c) : (T)0;
+        for (int e = tid; e < b * (R * G); e += nth) {
+            const int r = e / b, cl = e - r * b, cc = blk * b + cl;
+            As[cl * ldl + r] = (cc < p && r < m) ? src_at<T>(J, k, r, cc) : (T)0;
         }
     } else {
         // group g (G lanes) takes column g of the block, rows gl + G q: R loads in flight per lane
-        const int grp = tid / G, gl = tid % G, c = blk * b + grp;
         T v[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -542,12 +576,47 @@ __device__ __forceinline__ void team_load_block(const JacobiJob& J, int k, int b
         for (int q = 0; q < R; ++q) As[grp * ldl + gl + G * q] = v[q];
     }
     if (WV) {
+        // V rows below the A rows: the identity, the caller's V (warm start) or the work array
         const T* Vg = (const T*)J.V + (int64_t)k * p * p;
-        for (int e = tid; e < b * ldv; e += nth) {
-            const int cl = e / ldv, r = e - cl * ldv, c = blk * b + cl;
-            T v = (T)0;
-            if (c < p && r < p) v = first ? (T)(r == c ? 1 : 0) : ld_team(Vg + (int64_t)c * p + r);
-            Vs[e] = v;
+        T v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = gl + G * q;
+            v[q] = (T)0;
+            if (c < p && r < p) {
+                if (!first) v[q] = ld_team(Vg + (int64_t)c * p + r);
+                else v[q] = J.vinit ? Vg[(int64_t)c * p + r] : (T)(r == c ? 1 : 0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) As[grp * ldl + gl + G * (R + q)] = v[q];
+    }
+}
+
+// Write a block back to the work arrays (group g stores column g).
+template <typename T, int R, int G, bool WV>
+__device__ __forceinline__ void team_store_block(const JacobiJob& J, int k, int blk, const T* As) {
+    constexpr int RT = WV ? 2 * R : R;
+    constexpr int ldl = RT * G + kLdsPad;
+    const int m = J.m, p = J.p, b = J.b;
+    const int grp = threadIdx.x / G, gl = threadIdx.x % G, c = blk * b + grp;
+    T* Ag = (T*)J.A + (int64_t)k * m * p;
+    T v[RT];
+#pragma unroll
+    for (int q = 0; q < RT; ++q) v[q] = As[grp * ldl + gl + G * q];
+    if (c < p) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = gl + G * q;
+            if (r < m) Ag[(int64_t)c * m + r] = v[q];
+        }
+        if (WV) {
+            T* Vg = (T*)J.V + (int64_t)k * p * p;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int r = gl + G * q;
+                if (r < p) Vg[(int64_t)c * p + r] = v[R + q];
+            }
         }
     }
 }
@@ -640,18 +709,18 @@ __device__ __forceinline__ void team_store_block(const JacobiJob& J, int k, int 
 template <typename T, int R, int G, bool WV>
 __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, int max_sweeps, T* lds,
                           int* s_scratch, int* s_flag, double* nI, double* nJ) {
-    constexpr int ldl = R * G + kLdsPad;
-    const int m = J.m, p = J.p, b = J.b, nb = J.nb, ldv = J.ldv;
+    constexpr int RT = WV ? 2 * R : R;     // A rows, then V rows, per lane
+    constexpr int ldl = RT * G + kLdsPad;
+    const int m = J.m, p = J.p, b = J.b, nb = J.nb;
     const int tid = threadIdx.x, grp = tid / G, gl = tid % G;  // one lane group per I column (b groups)
     T* Is = lds;                           // b columns x ldl (first step of a sweep)
     T* Js = lds + (int64_t)b * ldl;        // b columns x ldl
-    T* Vi = lds + (int64_t)2 * b * ldl;    // b columns x ldv
-    T* Vj = Vi + (int64_t)b * ldv;         // b columns x ldv
     const double tol = J.tol;
     const bool refine = J.refine64 != 0;
     int sweeps = -1, executed = 0;
     int* rot_g = J.rot + (int64_t)k * kRotStride;
     T* Ag = (T*)J.A + (int64_t)k * m * p;
+    T* Vg = WV ? (T*)J.V + (int64_t)k * p * p : nullptr;
     for (int sw = 0; sw < max_sweeps + (refine ? 1 : 0); ++sw) {
         const bool f64 = refine && sw == max_sweeps;
         const double tl = f64 ? (double)m * Unit<double>::v : tol;
@@ -663,22 +732,26 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                 rr_pair(s, q, nb, BI, BJ);
                 const bool first = (sw == 0 && s == 0);
                 const int ci = BI * b + grp;  // this group's I column
-                T xr[R];
+                const int cs = ci < p ? ci : 0;
+                T xr[RT];
                 double na = 0.0;
                 if (s != 0) {
-                    // this group's I column comes from the work array; its loads are issued
+                    // this group's I column comes from the work arrays; its loads are issued
                     // first so that they overlap with the J block's (the clamped column keeps
-                    // every load in bounds; rows beyond m read as zero)
-                    const T* xs = Ag + (int64_t)(ci < p ? ci : 0) * m;
+                    // every load in bounds; rows beyond m, or p for V, read as zero)
 #pragma unroll
                     for (int q2 = 0; q2 < R; ++q2) {
                         const int r = gl + G * q2;
                         xr[q2] = (T)0;
-                        if (r < m) xr[q2] = ld_team(xs + r);
+                        if (r < m) xr[q2] = ld_team(Ag + (int64_t)cs * m + r);
+                        if (WV) {
+                            xr[R + q2] = (T)0;
+                            if (r < p) xr[R + q2] = ld_team(Vg + (int64_t)cs * p + r);
+                        }
                     }
                 }
-                team_load_block<T, R, G, WV>(J, k, BJ, first, Js, Vj);
-                if (s == 0 || WV) team_load_block<T, R, G, WV>(J, k, BI, first, Is, Vi);
+                team_load_block<T, R, G, WV>(J, k, BJ, first, Js);
+                if (s == 0) team_load_block<T, R, G, WV>(J, k, BI, first, Is);
                 __syncthreads();
                 {
                     const double nn = lds_col_norm<T, R, G>(Js + grp * ldl, gl);
@@ -697,16 +770,14 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                         rr_pair(r, grp - half * (b / 2), b, i, j);
                         const int blk = half ? BJ : BI;
                         T* base = half ? Js : Is;
-                        T* vb = half ? Vj : Vi;
                         double* nb_ = half ? nJ : nI;
                         if (blk * b + j < p)
-                            rot += gpair_lds<T, R, G>(base + i * ldl, base + j * ldl, nb_ + i, nb_ + j,
-                                                      WV ? vb + i * ldv : nullptr, WV ? vb + j * ldv : nullptr,
-                                                      WV ? p : 0, gl, tl, f64, J.skip2, big);
+                            rot += tpair_lds<T, R, RT, G>(base + i * ldl, base + j * ldl, nb_ + i, nb_ + j, gl, tl,
+                                                          f64, J.skip2, big);
                         __syncthreads();
                     }
 #pragma unroll
-                    for (int q2 = 0; q2 < R; ++q2) xr[q2] = Is[grp * ldl + gl + G * q2];
+                    for (int q2 = 0; q2 < RT; ++q2) xr[q2] = Is[grp * ldl + gl + G * q2];
                     na = nI[grp];
                 } else {
                     na = group_sum<G>(partial_norm<T, R>(xr));
@@ -715,8 +786,7 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                 int j = grp;
                 for (int r = 0; r < b; ++r, j = (j + 1 == b) ? 0 : j + 1) {
                     if (ci < p && BJ * b + j < p)
-                        rot += gpair_reg<T, R, G>(xr, na, Js + j * ldl, nJ + j, WV ? Vi + grp * ldv : nullptr,
-                                                  WV ? Vj + j * ldv : nullptr, WV ? p : 0, gl, tl, f64, J.skip2, big);
+                        rot += tpair_reg<T, R, RT, G>(xr, na, Js + j * ldl, nJ + j, gl, tl, f64, J.skip2, big);
                     __syncthreads();
                 }
                 if (ci < p) {
@@ -724,16 +794,10 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                     for (int q2 = 0; q2 < R; ++q2) {
                         const int r = gl + G * q2;
                         if (r < m) Ag[(int64_t)ci * m + r] = xr[q2];
+                        if (WV && r < p) Vg[(int64_t)ci * p + r] = xr[R + q2];
                     }
                 }
-                team_store_block<T, R, G, WV>(J, k, BJ, Js, Vj);
-                if (WV) {
-                    T* Vg = (T*)J.V + (int64_t)k * p * p;
-                    for (int e = tid; e < b * p; e += blockDim.x) {
-                        const int cl = e / p, rr = e - cl * p, c = BI * b + cl;
-                        if (c < p) Vg[(int64_t)c * p + rr] = Vi[cl * ldv + rr];
-                    }
-                }
+                team_store_block<T, R, G, WV>(J, k, BJ, Js);
                 __syncthreads();
             }
             if (s == nb - 2) {
@@ -1046,7 +1110,8 @@ int jacobi_resident_lds_bytes(int prec, int m, int p, int G, int with_v) {
 int jacobi_team_lds_bytes(int prec, int m, int p, int G, int b, int with_v) {
     int R, ldv;
     if (jacobi_geometry_g(m, p, G, &R, &ldv)) return 1 << 30;
-    const int64_t elems = (int64_t)2 * b * (R * G + kLdsPad) + (with_v ? (int64_t)2 * b * ldv : 0);
+    // two blocks of b columns; with V each column holds R G rows of V below its R G rows of A
+    const int64_t elems = (int64_t)2 * b * ((with_v ? 2 : 1) * R * G + kLdsPad);
     return (int)(elems * elem_size(prec));
 }
 

@@ -375,6 +375,33 @@ hipError_t launch_fill_pattern(void* p, int64_t n, int prec, uint32_t seed, hipS
     return hipGetLastError();
 }
 
+// Warm start of the completion's Jacobi SVDs: at iterations whose index (the
+// device iteration counter) is a multiple of `period`, V of every slice is
+// reset to the identity, which bounds the drift of V from orthogonality.
+template <typename T>
+__global__ void k_warm_reset(T* V, int p, int64_t total, const Ctrl* ctrl, int period) {
+    if (ctrl->iter % period != 0) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t rc = e % ((int64_t)p * p);
+        const int r = (int)(rc % p), c = (int)(rc / p);
+        V[e] = (T)(r == c ? 1 : 0);
+    }
+}
+
+hipError_t launch_warm_reset(int prec, void* V, int p, int n3, const Ctrl* ctrl, int period, hipStream_t s) {
+    const int64_t total = (int64_t)p * p * n3;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (prec == 0)
+        hipLaunchKernelGGL(k_warm_reset<double>, dim3((unsigned)blocks), dim3(256), 0, s, (double*)V, p, total, ctrl,
+                           period);
+    else
+        hipLaunchKernelGGL(k_warm_reset<float>, dim3((unsigned)blocks), dim3(256), 0, s, (float*)V, p, total, ctrl,
+                           period);
+    return hipGetLastError();
+}
+
 // End of one completion iteration: record the relative change, clear the
 // norm accumulators, advance the iteration counter.
 __global__ void k_iter_advance(Ctrl* ctrl, double* norms, double* hist, int hist_len) {
