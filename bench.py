@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip cold t-SVT, batch and serving measurements")
     ap.add_argument("--serving-requests", type=int, default=60)
     ap.add_argument("--serving-loads", default="0.5,0.8", help="fractions of the measured saturation throughput")
+    ap.add_argument("--warm-period", type=int, default=-1,
+                    help="completion warm start: -1 automatic, 0 cold starts, N: reset every N iterations")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (hardware-counter scale for profiling runs)")
     return ap.parse_args()
@@ -64,9 +66,10 @@ def gpu_tprod_factory(tm, torch):
     return gpu_tprod
 
 
-def run_completion(tm, torch, case, prec, steps, warmup, profile):
+def run_completion(tm, torch, case, prec, steps, warmup, profile, warm_period=-1):
     dt = torch.float64 if prec == tm.FP64 else torch.float32
     ctx = tm.Context(0)
+    ctx.set_option(tm.OPT_WARM_START, warm_period)
     B = torch.from_numpy(case.B).to(dt).to("cuda:0")
     mask = torch.from_numpy(case.mask).to("cuda:0")
     taus = list(case.taus) + [case.taus[-1]] * max(0, steps + warmup + 1 - len(case.taus))
@@ -287,7 +290,8 @@ def main():
     precs = {"fp64": tm.FP64, "fp32": tm.FP32, "mixed": tm.MIXED}
     results = {}
     for name in paths:
-        r = run_completion(tm, torch, case, precs[name], args.steps, args.warmup, profile=True)
+        r = run_completion(tm, torch, case, precs[name], args.steps, args.warmup, profile=True,
+                           warm_period=args.warm_period)
         results[name] = r
         log("%s: %.3f s for %d steps (%.3f ms/step), jacobi %.3f ms/launch, slice-sweeps %d" % (
             name, r["seconds"], args.steps, 1e3 * r["seconds"] / args.steps,
@@ -295,7 +299,7 @@ def main():
     head = paths[0]
     r = results[head]
     # the same run replayed as a captured HIP graph (no per-kernel events)
-    g = run_completion(tm, torch, case, precs[head], args.steps, 0, profile=False)
+    g = run_completion(tm, torch, case, precs[head], args.steps, 0, profile=False, warm_period=args.warm_period)
     log("%s graph replay: %.3f ms/step" % (head, 1e3 * g["seconds"] / args.steps))
     out = {
         "metric": "t-SVT/s at 256x256x31 (mixed vs plain FP64) + p50/p99 latency at fixed QPS",

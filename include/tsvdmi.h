@@ -90,8 +90,8 @@ enum {
                                   with V).  A forced setting disables tuning. */
     TSVD_OPT_WARM_START = 9    /* complete_tensor: -1 (default) warm-start each iteration's Jacobi SVDs
                                   from the previous iteration's right singular vectors, resetting
-                                  them every 64 (FP64) or 16 (FP32, MIXED) iterations; N >= 1: reset
-                                  every N iterations; 0: cold starts */
+                                  them to the identity every 64 iterations; N >= 1: reset every N
+                                  iterations; 0: cold starts */
 };
 int tsvd_set_option(tsvd_ctx* ctx, int option, double value);
 double tsvd_get_option(const tsvd_ctx* ctx, int option);

@@ -774,7 +774,8 @@ int enqueue_svt_core(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau_va
 }
 
 // Warm start (completion only): V of every slice is kept from the previous
-// iteration (reset to the identity every warm_period iterations) and the
+// iteration (reset to the identity every warm_period iterations, 64 by
+// default, which bounds the drift of V from orthogonality) and the
 // Jacobi input is A0 = Zbar_k V_k, whose one-sided Jacobi ends at Zbar_k V_k J
 // with V_k J the new V: the singular vectors change little between
 // iterations, so A0 is nearly orthogonal already and few sweeps are needed.
@@ -1170,7 +1171,7 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
     hipStream_t s = (hipStream_t)stream;
     Plan P;
     Carve cv;
-    const int warm_period = c->warm_start < 0 ? (prec == TSVD_FP64 ? 64 : 16) : c->warm_start;
+    const int warm_period = c->warm_start < 0 ? 64 : c->warm_start;
     int rc = make_plan(c, prec, n1, n2, n3, warm_period > 0 ? 1 : 0, P, cv, s);
     if (rc) return rc;
     const size_t es = esize(prec);

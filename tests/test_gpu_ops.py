@@ -67,12 +67,21 @@ def small_case(L=30, shape=(20, 18, 6), r=2, sr=0.6, seed=80):
     return synth.completion_case(oracle.tprod_dct, *shape, r, sr, L, seed, tau0=1.0, tau1=0.01)
 
 
-def test_complete_fp64_matches_oracle(tm):
-    announce("complete_fp64")
+# warm start of the Jacobi SVDs: automatic period, cold starts, and a reset every
+# other iteration (exercises the reset inside the captured iteration)
+WARM = [-1, 0, 2]
+
+
+@pytest.mark.parametrize("warm", WARM)
+def test_complete_fp64_matches_oracle(tm, warm):
+    announce("complete_fp64", warm=warm)
     cc = small_case()
     Xo, Mo, it, _ = oracle.complete(cc.B, cc.mask, cc.betas, cc.taus)
+    ctx = tm.Context(0)
+    ctx.set_option(tm.OPT_WARM_START, warm)
     X, info, M = tm.complete_tensor(to_dev(cc.B), to_dev(cc.mask, torch.uint8), max_iter=len(cc.taus), tol=0.0,
-                                    tau_schedule=cc.taus, return_M=True)
+                                    tau_schedule=cc.taus, return_M=True, ctx=ctx)
+    ctx.close()
     assert info["iters"] == it
     assert rel(to_np(X), Xo) <= 1e-10
     assert rel(to_np(M), Mo) <= 1e-10
@@ -80,13 +89,36 @@ def test_complete_fp64_matches_oracle(tm):
     assert np.array_equal(to_np(X)[obs], cc.B[obs])
 
 
-def test_complete_fp64_team_shape_matches_oracle(tm):
-    announce("complete_fp64_team")
-    cc = small_case(L=4, shape=(180, 160, 3), r=4, sr=0.5)
+@pytest.mark.parametrize("warm", WARM)
+@pytest.mark.parametrize("shape", [(180, 160, 3), (150, 280, 2)])
+def test_complete_fp64_team_shape_matches_oracle(tm, warm, shape):
+    announce("complete_fp64_team", warm=warm, shape=shape)
+    cc = small_case(L=6, shape=shape, r=4, sr=0.5)
     Xo, _, _, _ = oracle.complete(cc.B, cc.mask, cc.betas, cc.taus)
-    X, info = tm.complete_tensor(to_dev(cc.B), to_dev(cc.mask, torch.uint8), max_iter=4, tol=0.0,
-                                 tau_schedule=cc.taus)
+    ctx = tm.Context(0)
+    ctx.set_option(tm.OPT_WARM_START, warm)
+    X, info = tm.complete_tensor(to_dev(cc.B), to_dev(cc.mask, torch.uint8), max_iter=6, tol=0.0,
+                                 tau_schedule=cc.taus, ctx=ctx)
+    ctx.close()
     assert rel(to_np(X), Xo) <= 1e-10
+
+
+def test_complete_warm_start_needs_fewer_sweeps(tm):
+    # same iterates to rounding; the warm-started SVDs take fewer sweeps
+    announce("complete_warm_sweeps")
+    cc = small_case(L=12, shape=(120, 100, 4), r=3, sr=0.5)
+    out = {}
+    for warm in (0, -1):
+        ctx = tm.Context(0)
+        ctx.set_option(tm.OPT_WARM_START, warm)
+        ctx.stats(reset=True)
+        X, _ = tm.complete_tensor(to_dev(cc.B), to_dev(cc.mask, torch.uint8), max_iter=12, tol=0.0,
+                                  tau_schedule=cc.taus, ctx=ctx)
+        out[warm] = (to_np(X), ctx.stats(reset=True)["slice_sweeps"])
+        ctx.close()
+    print("slice sweeps cold %d warm %d" % (out[0][1], out[-1][1]))
+    assert rel(out[-1][0], out[0][0]) <= 1e-12
+    assert out[-1][1] < 0.8 * out[0][1]
 
 
 def test_complete_resume(tm):
