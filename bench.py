@@ -85,7 +85,8 @@ def run_completion(tm, torch, case, prec, steps, warmup, profile, warm_period=-1
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = ctx.stats(reset=True)
-    tile = ctx.tile(prec, N1, N2, N3, with_v=ctx.get_option(tm.OPT_WARM_START) != 0)
+    with_v = ctx.get_option(tm.OPT_WARM_START) != 0
+    tile = dict(ctx.tile(prec, N1, N2, N3, with_v=with_v), with_v=with_v)
     Xn = X.detach().cpu().to(torch.float64).numpy()
     # the next iteration's t-SVT input, Z = X - M / beta (Algorithm 1, first step)
     beta = 1.0 / taus[steps]
@@ -97,10 +98,12 @@ def run_completion(tm, torch, case, prec, steps, warmup, profile, warm_period=-1
 def jacobi_roofline(res, prec_name):
     st = res["stats"]
     m, p = max(N1, N2), min(N1, N2)
-    # one-sided Jacobi without V, norms tracked: per column pair one inner
-    # product (2m flops) and the rotation of two length-m columns (6m flops);
-    # p(p-1)/2 pairs per sweep.  Units: slice-sweeps (counted on the device).
-    flops_per_slice_sweep = 8.0 * m * p * (p - 1) / 2.0
+    # one-sided Jacobi, norms tracked: per column pair one inner product (2m
+    # flops) and the rotation of two length-m columns (6m flops), plus the
+    # rotation of the two length-p columns of V when the warm start carries V
+    # (6p); p(p-1)/2 pairs per sweep.  Units: slice-sweeps (counted on the device).
+    with_v = res["tile"].get("with_v", False)
+    flops_per_slice_sweep = (8.0 * m + (6.0 * p if with_v else 0.0)) * p * (p - 1) / 2.0
     launches = max(1, st["launches"]["jacobi"])
     avg_ms = st["ms"]["jacobi"] / launches
     flops_per_launch = flops_per_slice_sweep * st["slice_sweeps"] / launches
