@@ -304,6 +304,9 @@ def main():
     # the same run replayed as a captured HIP graph (no per-kernel events)
     g = run_completion(tm, torch, case, precs[head], args.steps, 0, profile=False, warm_period=args.warm_period)
     log("%s graph replay: %.3f ms/step" % (head, 1e3 * g["seconds"] / args.steps))
+    # the same completion with every Jacobi SVD started cold, for comparison
+    cold = run_completion(tm, torch, case, precs[head], args.steps, 1, profile=False, warm_period=0)
+    log("%s cold-start SVDs: %.3f ms/step" % (head, 1e3 * cold["seconds"] / args.steps))
     out = {
         "metric": "t-SVT/s at 256x256x31 (mixed vs plain FP64) + p50/p99 latency at fixed QPS",
         "value": round(args.steps / r["seconds"], 3),
@@ -324,6 +327,9 @@ def main():
         "dct_roofline": dct_roofline(r, head),
         "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in r["stats"]["ms"].items()},
         "graph_replay_ms_per_step": round(1e3 * g["seconds"] / args.steps, 4),
+        "jacobi_start": ("warm: V of the previous iteration, reset every %d iterations" % (
+            64 if args.warm_period < 0 else args.warm_period)) if args.warm_period != 0 else "cold",
+        "cold_start_t_svt_per_s": round(args.steps / cold["seconds"], 3),
     }
     T = case.T
     for name, rr in results.items():
