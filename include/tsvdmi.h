@@ -230,7 +230,10 @@ typedef struct {
     double tau0, tau1;
 } tsvd_request;
 /* budget_bytes: device memory the server may hold for admitted requests;
- * max_active: most requests advanced per tick. */
+ * max_active: most requests advanced per tick.  With FP32 or MIXED data a
+ * completion request warm-starts its Jacobi SVDs from its previous
+ * iteration's right singular vectors, kept on the device, following the
+ * context's TSVD_OPT_WARM_START (read at creation). */
 int tsvd_server_create(tsvd_server** srv, tsvd_ctx* ctx, int prec, int64_t budget_bytes, int max_active);
 /* Copies the request; returns a request id > 0, or TSVD_EBUSY when it can never
  * fit the budget, or another negative error. */

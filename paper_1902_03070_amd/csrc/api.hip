@@ -553,7 +553,7 @@ double time_tile(tsvd_ctx* c, const Plan& P0, const Tile& t, bool batched, char*
         if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
         hipError_t e;
         if (batched)
-            e = launch_jacobi_batched(P.prec == TSVD_FP64 ? 0 : 1, J.R, J.G, (const JacobiJob*)(tb + o_jobs),
+            e = launch_jacobi_batched(P.prec == TSVD_FP64 ? 0 : 1, J.R, J.G, P.with_v, (const JacobiJob*)(tb + o_jobs),
                                       (const int*)(tb + o_tj), (const int*)(tb + o_tk), ntasks, queue, kTuneSweeps,
                                       ctrl, P.lds, s);
         else if (!P.team)
@@ -779,22 +779,27 @@ int enqueue_svt_core(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau_va
 // Jacobi input is A0 = Zbar_k V_k, whose one-sided Jacobi ends at Zbar_k V_k J
 // with V_k J the new V: the singular vectors change little between
 // iterations, so A0 is nearly orthogonal already and few sweeps are needed.
-int enqueue_warm_start(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s) {
+int enqueue_warm_gemm(tsvd_ctx* c, Plan& P, char* base, const void* V, hipStream_t s) {
     const int prec = P.prec == TSVD_FP64 ? 0 : 1;
-    hipError_t e = launch_warm_reset(prec, base + P.o_V, P.p, (int)P.n3, ctrl, P.warm_period, s);
-    if (e != hipSuccess) return hip_fail(c, e, "warm reset");
     GemmArgs g{};
     g.A = base + P.o_zbar;  // tall view of the slice
     if (!P.trans) { g.a_rs = 1; g.a_cs = P.n1; } else { g.a_rs = P.n1; g.a_cs = 1; }
     g.a_bs = P.N;
-    g.B = base + P.o_V; g.b_rs = 1; g.b_cs = P.p; g.b_bs = (int64_t)P.p * P.p;
+    g.B = V; g.b_rs = 1; g.b_cs = P.p; g.b_bs = (int64_t)P.p * P.p;
     g.C = base + P.o_A0; g.c_rs = 1; g.c_cs = P.m; g.c_bs = (int64_t)P.m * P.p;
     g.cscale = nullptr;
     g.M = P.m; g.Nn = P.p; g.K = P.p; g.Kdev = nullptr; g.Ndev = nullptr;
     g.batch = (int)P.n3;
-    e = launch_gemm(prec, g, s);
+    const hipError_t e = launch_gemm(prec, g, s);
     if (e != hipSuccess) return hip_fail(c, e, "warm start gemm");
     return TSVD_OK;
+}
+
+int enqueue_warm_start(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s) {
+    const int prec = P.prec == TSVD_FP64 ? 0 : 1;
+    const hipError_t e = launch_warm_reset(prec, base + P.o_V, P.p, (int)P.n3, ctrl, P.warm_period, s);
+    if (e != hipSuccess) return hip_fail(c, e, "warm reset");
+    return enqueue_warm_gemm(c, P, base, base + P.o_V, s);
 }
 
 // Thresholding and rebuild (Ybar in the workspace) once A' is ready.
@@ -1340,25 +1345,43 @@ int batched_step_locked(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb
     int rc;
     int64_t ntasks = 0;
     for (int j = 0; j < count; ++j) {
-        if ((rc = make_plan(c, prec, jb[j].n1, jb[j].n2, jb[j].n3, 0, plans[j], cv, s, true))) return rc;
+        Plan& P = plans[j];
+        const int wv = jb[j].V ? 1 : 0;
+        if ((rc = make_plan(c, prec, jb[j].n1, jb[j].n2, jb[j].n3, wv, P, cv, s, true))) return rc;
+        if (wv && jb[j].vinit) {
+            P.warm = 1;
+            P.o_A0 = cv.take((size_t)P.m * P.p * P.n3 * esize(prec));
+        }
         ntasks += jb[j].n3;
     }
     const size_t o_jobs = cv.take(sizeof(JacobiJob) * count);
     const size_t o_tj = cv.take(sizeof(int) * ntasks), o_tk = cv.take(sizeof(int) * ntasks);
-    const size_t o_queue = cv.take(256);  // one work counter per row geometry (8 x 32 bytes)
+    const size_t o_queue = cv.take(512);  // one work counter per (V, row geometry) (16 x 32 bytes)
     if ((rc = ensure_ws(c, cv.off))) return rc;
     char* base = (char*)c->ws.p;
     CtrlRegion cr;
     if ((rc = ensure_ctrl(c, &cr))) return rc;
     // job table; task lists grouped by row geometry (R, G), each sorted by
     // estimated cost (m p^2 per slice), largest first
-    auto geo = [](const Plan& P) { return (P.job.G == 32 ? 4 : 0) + P.job.R / 4 - 1; };  // 0..7
+    auto geo = [](const Plan& P) { return (P.with_v ? 8 : 0) + (P.job.G == 32 ? 4 : 0) + P.job.R / 4 - 1; };  // 0..15
     std::vector<JacobiJob> jobs(count);
     std::vector<std::pair<double, std::pair<int, int>>> order;
     order.reserve(ntasks);
     for (int j = 0; j < count; ++j) {
-        bind_plan(plans[j], base);
-        jobs[j] = plans[j].job;
+        Plan& P = plans[j];
+        bind_plan(P, base);
+        if (P.with_v) {
+            // the job's own V, kept across steps; a warm start reads A0 = Zbar V
+            P.job.V = jb[j].V;
+            P.job.vinit = jb[j].vinit ? 1 : 0;
+            if (P.warm) {
+                P.job.src = base + P.o_A0;
+                P.job.src_ss = (int64_t)P.m * P.p;
+                P.job.src_rs = 1;
+                P.job.src_cs = P.m;
+            }
+        }
+        jobs[j] = P.job;
         const double cost = (double)plans[j].m * plans[j].p * plans[j].p;
         for (int k = 0; k < plans[j].n3; ++k) order.push_back({geo(plans[j]) * 1e30 - cost, {j, k}});
     }
@@ -1367,20 +1390,20 @@ int batched_step_locked(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb
                          return a.first < b.first;
                      });
     std::vector<int> tj(ntasks), tk(ntasks);
-    int gbeg[9] = {0}, gcnt[8] = {0};
+    int gbeg[17] = {0}, gcnt[16] = {0};
     for (int64_t t = 0; t < ntasks; ++t) {
         tj[t] = order[t].second.first;
         tk[t] = order[t].second.second;
         gcnt[geo(plans[tj[t]])]++;
     }
-    for (int g = 0; g < 8; ++g) gbeg[g + 1] = gbeg[g] + gcnt[g];
-    int glds[8] = {0};
+    for (int g = 0; g < 16; ++g) gbeg[g + 1] = gbeg[g] + gcnt[g];
+    int glds[16] = {0};
     for (int j = 0; j < count; ++j) glds[geo(plans[j])] = std::max(glds[geo(plans[j])], plans[j].lds);
     HIPCHK(c, hipStreamSynchronize(s));  // tables live in the shared workspace
     HIPCHK(c, hipMemcpy(base + o_jobs, jobs.data(), sizeof(JacobiJob) * count, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(base + o_tj, tj.data(), sizeof(int) * ntasks, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(base + o_tk, tk.data(), sizeof(int) * ntasks, hipMemcpyHostToDevice));
-    hipError_t e = launch_fill_zero(base + o_queue, 256, s);
+    hipError_t e = launch_fill_zero(base + o_queue, 512, s);
     if (e != hipSuccess) return hip_fail(c, e, "fill");
     for (int j = 0; j < count; ++j) {
         Plan& P = plans[j];
@@ -1393,12 +1416,17 @@ int batched_step_locked(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb
         PhaseMark pm(c, 0, s);
         if ((rc = run_tube(c, prec, f, 0, s))) return rc;
     }
+    for (int j = 0; j < count; ++j) {
+        if (!plans[j].warm) continue;
+        PhaseMark pm(c, 4, s);
+        if ((rc = enqueue_warm_gemm(c, plans[j], base, jb[j].V, s))) return rc;
+    }
     {
         PhaseMark pm(c, 1, s);
-        for (int g = 0; g < 8; ++g) {
+        for (int g = 0; g < 16; ++g) {
             if (!gcnt[g]) continue;
-            const int G = g >= 4 ? 32 : 16, R = 4 * (g % 4 + 1);
-            e = launch_jacobi_batched(prec == TSVD_FP64 ? 0 : 1, R, G, (const JacobiJob*)(base + o_jobs),
+            const int G = (g % 8) >= 4 ? 32 : 16, R = 4 * (g % 4 + 1), wv = g >= 8;
+            e = launch_jacobi_batched(prec == TSVD_FP64 ? 0 : 1, R, G, wv, (const JacobiJob*)(base + o_jobs),
                                       (const int*)(base + o_tj) + gbeg[g], (const int*)(base + o_tk) + gbeg[g],
                                       gcnt[g], (int*)(base + o_queue) + 8 * g, clamp_sweeps(c->max_sweeps), cr.ctrl,
                                       glds[g], s);
@@ -1433,7 +1461,8 @@ size_t tsvd_batched_workspace_bytes(int prec, int64_t n1, int64_t n2, int64_t n3
     // mirrors make_plan's regions (upper bound: counters and alignment)
     const size_t es = prec == TSVD_FP64 ? 8 : 4;
     const size_t m = (size_t)std::max(n1, n2), p = (size_t)std::min(n1, n2), N = (size_t)n1 * n2;
-    return es * (2 * N * n3 + 2 * m * p * n3 + p * p * n3) + 16 * p * n3 + 4 * n3 * (kRotStride + 3) + 16 * 256 +
+    // Zbar, Ybar; A', F, A0 (warm start); G, V (workspace copy); counters
+    return es * (2 * N * n3 + 3 * m * p * n3 + 2 * p * p * n3) + 16 * p * n3 + 4 * n3 * (kRotStride + 3) + 32 * 256 +
            sizeof(JacobiJob) + 8 * n3;
 }
 

@@ -114,7 +114,7 @@ hipError_t launch_jacobi_team(int prec, const JacobiJob& job, int ntasks, const 
                               int coop, hipStream_t s);
 // One persistent launch over (tensor, slice) tasks drawn from *queue (zeroed).
 // One persistent launch per row geometry (R, G) present in the batch.
-hipError_t launch_jacobi_batched(int prec, int R, int G, const JacobiJob* jobs_dev, const int* task_job,
+hipError_t launch_jacobi_batched(int prec, int R, int G, int with_v, const JacobiJob* jobs_dev, const int* task_job,
                                  const int* task_slice, int ntasks, int* queue, int max_sweeps, Ctrl* ctrl,
                                  int lds_bytes, hipStream_t s);
 // Row geometry of a tall m x p slice: G lanes per column pair (16 or 32), R
@@ -168,6 +168,8 @@ struct BatchJobSpec {
     const void* B;        // observed data
     const uint8_t* mask;  // observed set
     double beta, tau;
+    void* V;              // completion warm start: the job's V (p x p per slice) kept across steps, or nullptr
+    int vinit;            // with V: 1 warm-starts from V (Jacobi input Zbar V), 0 starts V from the identity
 };
 
 // Small utility kernels.

@@ -1051,7 +1051,7 @@ __global__ __launch_bounds__(512) void k_jacobi_team(JacobiJob J1, int ntasks, T
 // does not depend on what else is in the batch.  512 threads; a streamed task
 // needs b * G == 512.
 // ---------------------------------------------------------------------------
-template <typename T, int R, int G>
+template <typename T, int R, int G, bool WV>
 __global__ __launch_bounds__(512) void k_jacobi_batched(const JacobiJob* __restrict__ jobs,
                                                         const int* __restrict__ task_job,
                                                         const int* __restrict__ task_slice, int ntasks, int* queue,
@@ -1069,10 +1069,10 @@ __global__ __launch_bounds__(512) void k_jacobi_batched(const JacobiJob* __restr
         const JacobiJob J = jobs[task_job[t]];
         const int k = task_slice[t];
         if (J.nb == 0) {
-            resident_task<T, R, G, false>(J, k, max_sweeps, ctrl, lds, &s_scratch, s_nrm);
+            resident_task<T, R, G, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch, s_nrm);
         } else {
             TeamState ts{nullptr, 0, 1, 0, ctrl};
-            (void)team_task<T, R, G, false>(J, k, 0, ts, max_sweeps, lds, &s_scratch, &s_flag, s_nrm, s_nrm + 64);
+            (void)team_task<T, R, G, WV>(J, k, 0, ts, max_sweeps, lds, &s_scratch, &s_flag, s_nrm, s_nrm + 64);
         }
         __syncthreads();
     }
@@ -1174,29 +1174,30 @@ hipError_t launch_jacobi_team(int prec, const JacobiJob& job, int ntasks, const 
     return hipLaunchKernel(f, grid, block, args, (size_t)lds_bytes, s);
 }
 
-template <typename T>
+template <typename T, bool WV>
 static const void* batched_fn_t(int R, int G) {
     if (G == 16) {
         switch (R) {
-            case 4: return (const void*)k_jacobi_batched<T, 4, 16>;
-            case 8: return (const void*)k_jacobi_batched<T, 8, 16>;
-            case 12: return (const void*)k_jacobi_batched<T, 12, 16>;
-            default: return (const void*)k_jacobi_batched<T, 16, 16>;
+            case 4: return (const void*)k_jacobi_batched<T, 4, 16, WV>;
+            case 8: return (const void*)k_jacobi_batched<T, 8, 16, WV>;
+            case 12: return (const void*)k_jacobi_batched<T, 12, 16, WV>;
+            default: return (const void*)k_jacobi_batched<T, 16, 16, WV>;
         }
     }
     switch (R) {
-        case 4: return (const void*)k_jacobi_batched<T, 4, 32>;
-        case 8: return (const void*)k_jacobi_batched<T, 8, 32>;
-        case 12: return (const void*)k_jacobi_batched<T, 12, 32>;
-        default: return (const void*)k_jacobi_batched<T, 16, 32>;
+        case 4: return (const void*)k_jacobi_batched<T, 4, 32, WV>;
+        case 8: return (const void*)k_jacobi_batched<T, 8, 32, WV>;
+        case 12: return (const void*)k_jacobi_batched<T, 12, 32, WV>;
+        default: return (const void*)k_jacobi_batched<T, 16, 32, WV>;
     }
 }
 
-hipError_t launch_jacobi_batched(int prec, int R, int G, const JacobiJob* jobs_dev, const int* task_job,
+hipError_t launch_jacobi_batched(int prec, int R, int G, int with_v, const JacobiJob* jobs_dev, const int* task_job,
                                  const int* task_slice, int ntasks, int* queue, int max_sweeps, Ctrl* ctrl,
                                  int lds_bytes, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
-    const void* f = prec == 0 ? batched_fn_t<double>(R, G) : batched_fn_t<float>(R, G);
+    const void* f = prec == 0 ? (with_v ? batched_fn_t<double, true>(R, G) : batched_fn_t<double, false>(R, G))
+                              : (with_v ? batched_fn_t<float, true>(R, G) : batched_fn_t<float, false>(R, G));
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
     int per_cu = 0, dev = 0, cus = 0;

@@ -5,8 +5,9 @@
 // their device-memory footprint fits the budget and fewer than max_active are
 // running.  Each tick advances every admitted request by one step in a single
 // batched call: a t-SVT request finishes in one tick; a completion request
-// runs one iteration of Algorithm 1 per tick with its iterates X, M kept on
-// the device between ticks.  A request that arrives while a tick runs joins
+// runs one iteration of Algorithm 1 per tick with its iterates X, M (and, for
+// FP32 data, the right singular vectors that warm-start its next Jacobi SVDs)
+// kept on the device between ticks.  A request that arrives while a tick runs joins
 // at the next tick; a finished one releases its memory at once.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -39,7 +40,7 @@ struct Req {
     double t_submit = 0.0, t_admit = -1.0, t_done = -1.0;
     bool admitted = false, done = false;
     int status = TSVD_OK;
-    void *dIn = nullptr, *dOut = nullptr, *dM = nullptr;
+    void *dIn = nullptr, *dOut = nullptr, *dM = nullptr, *dV = nullptr;
     uint8_t* dMask = nullptr;
     std::vector<unsigned char> result;
 };
@@ -57,6 +58,7 @@ struct tsvd_server {
     size_t es = 4;
     int64_t budget = 0;
     int max_active = 1;
+    int warm_period = 0;  // completion requests: Jacobi warm start, V reset every warm_period iterations (0: off)
     std::mutex mu;
     std::condition_variable cv;
     std::deque<std::shared_ptr<Req>> pending;
@@ -76,9 +78,15 @@ struct tsvd_server {
         if (r.dIn) (void)hipFree(r.dIn);
         if (r.dOut) (void)hipFree(r.dOut);
         if (r.dM) (void)hipFree(r.dM);
+        if (r.dV) (void)hipFree(r.dV);
         if (r.dMask) (void)hipFree(r.dMask);
-        r.dIn = r.dOut = r.dM = nullptr;
+        r.dIn = r.dOut = r.dM = r.dV = nullptr;
         r.dMask = nullptr;
+    }
+
+    size_t vbytes(const Req& r) const {
+        const int64_t p = r.n1 < r.n2 ? r.n1 : r.n2;
+        return (size_t)p * p * r.n3 * es;
     }
 
     // Allocate and fill the request's device state (server thread, no lock held).
@@ -93,6 +101,9 @@ struct tsvd_server {
                 hipMemsetAsync(r.dM, 0, bytes, stream) != hipSuccess ||
                 hipMemcpyAsync(r.dMask, r.mask.data(), (size_t)r.N, hipMemcpyHostToDevice, stream) != hipSuccess)
                 return TSVD_EHIP;
+            // the request's right singular vectors, kept across its iterations (the first
+            // step starts them from the identity)
+            if (warm_period > 0 && hipMalloc(&r.dV, vbytes(r)) != hipSuccess) return TSVD_ENOMEM;
         }
         return TSVD_OK;
     }
@@ -162,6 +173,10 @@ struct tsvd_server {
                     s.mask = r->dMask;
                     s.tau = t;
                     s.beta = 1.0 / t;
+                    if (r->dV) {
+                        s.V = r->dV;
+                        s.vinit = (r->done_iters % warm_period) != 0;
+                    }
                 }
                 jb.push_back(s);
                 in_step.push_back(r);
@@ -209,6 +224,10 @@ int tsvd_server_create(tsvd_server** out, tsvd_ctx* ctx, int prec, int64_t budge
     s->es = prec == TSVD_FP64 ? 8 : 4;
     s->budget = budget_bytes;
     s->max_active = max_active;
+    // the context's warm-start setting (FP32 data only: the batched kernel's one-workgroup
+    // blocks of FP64 columns with V do not fit in LDS for the largest slices)
+    const int ws = (int)tsvd_get_option(ctx, TSVD_OPT_WARM_START);
+    s->warm_period = prec == TSVD_FP64 ? 0 : (ws < 0 ? 64 : ws);
     s->t0 = std::chrono::steady_clock::now();
     (void)hipSetDevice(tsvd_ctx_device(ctx));
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
@@ -259,6 +278,7 @@ int64_t tsvd_server_submit(tsvd_server* s, const tsvd_request* q) {
     }
     const size_t tensors = q->kind == TSVD_REQ_TSVT ? 2 : 3;
     r->footprint = tensors * N * s->es + (q->kind == TSVD_REQ_COMPLETE ? N : 0) +
+                   (q->kind == TSVD_REQ_COMPLETE && s->warm_period > 0 ? s->vbytes(*r) : 0) +
                    tsvd_batched_workspace_bytes(s->prec, q->n1, q->n2, q->n3);
     std::lock_guard<std::mutex> lk(s->mu);
     if ((int64_t)r->footprint > s->budget) return TSVD_EBUSY;
