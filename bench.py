@@ -263,6 +263,24 @@ def serving(tm, torch, tprod, nreq, loads):
     return out
 
 
+def video_shaped(tm, torch, tprod, steps):
+    """Mixed-precision completion at 144x176x100 (rank 15, 20% observed), with
+    its relative difference from the FP64 GPU path on the same input."""
+    import synth
+
+    cc = synth.completion_case(tprod, 144, 176, 100, 15, 0.2, 100, synth.SEED_BASE + 3)
+    out = {}
+    for name, prec in (("mixed", tm.MIXED), ("fp64", tm.FP64)):
+        r = run_completion(tm, torch, cc, prec, steps, 2, profile=False)
+        out[name] = r
+    X64, Xm = out["fp64"]["X"], out["mixed"]["X"]
+    return {"shape": [144, 176, 100], "rank": 15, "observed": 0.2, "iterations": steps,
+            "t_svt_per_s_mixed": round(steps / out["mixed"]["seconds"], 2),
+            "t_svt_per_s_fp64": round(steps / out["fp64"]["seconds"], 2),
+            "mixed_rel_err_vs_fp64_gpu": float(np.linalg.norm(Xm - X64) / np.linalg.norm(X64)),
+            "recovery_rel_err_mixed": float(np.linalg.norm(Xm - cc.T) / np.linalg.norm(cc.T))}
+
+
 def cpu_baseline(case):
     import oracle
 
@@ -354,6 +372,8 @@ def main():
                                                        precs[name])}
         out["isolated_tsvt"] = iso
         log("isolated t-SVT:", iso)
+        out["video_shaped"] = video_shaped(tm, torch, tprod, 100)
+        log("video-shaped:", out["video_shaped"])
         out["batched"] = batched(tm, torch, tprod)
         log("batched:", out["batched"])
         out["serving"] = serving(tm, torch, tprod, args.serving_requests,

@@ -79,3 +79,31 @@ def test_complete_mixed_tracks_fp64(tm):
         print("completion prec %d rel err vs FP64 oracle %.3e" % (prec, err))
         # 20 iterations, each within the single-t-SVT bound: at most linear growth
         assert err <= 20 * C_BOUND * U_EFF[prec] * np.linalg.norm(Bf) / np.linalg.norm(Xo)
+
+
+def test_video_shaped_mixed_sampled_slices(tm):
+    # 144 x 176 x 100 (rank 15, observed 20%), MIXED, at full size: sampled
+    # transformed slices of the result against the oracle's matrix SVT of the
+    # same slice of the (float-rounded) input, within the stated bound
+    import scipy.fft
+
+    announce("video_shaped_mixed")
+
+    def lib_tprod(A, B):
+        Ab = scipy.fft.dct(A, type=2, norm="ortho", axis=2)
+        Bb = scipy.fft.dct(B, type=2, norm="ortho", axis=2)
+        Zb = np.matmul(Ab.transpose(2, 0, 1), Bb.transpose(2, 0, 1)).transpose(1, 2, 0)
+        return np.asfortranarray(scipy.fft.idct(Zb, type=2, norm="ortho", axis=2))
+
+    cc = synth.completion_case(lib_tprod, 144, 176, 100, 15, 0.2, 100, synth.SEED_BASE + 3)
+    Zf = cc.B.astype(np.float32).astype(np.float64)
+    tau = float(cc.taus[0])
+    Y = to_np(tm.tsvt_dct(to_dev(Zf, torch.float32), tau, prec=2))
+    Yb = scipy.fft.dct(Y, type=2, norm="ortho", axis=2)
+    Zb = oracle.dct_tubes(Zf)
+    zn = np.linalg.norm(Zf)
+    for k in (0, 1, 37, 99):
+        want = oracle.tsvt_dct(np.asfortranarray(Zb[:, :, k:k + 1]), tau)[:, :, 0]
+        err = np.linalg.norm(Yb[:, :, k] - want)
+        print("slice %d: |Y - Y*| / (u_eff |Z|) = %.2f" % (k, err / (U_EFF[2] * zn)))
+        assert err <= C_BOUND * U_EFF[2] * zn
