@@ -279,7 +279,7 @@ struct Plan {
     TeamSched ts{};
     JacobiJob job{};
     // workspace offsets
-    size_t o_zbar, o_A, o_F, o_G, o_w, o_sig, o_ybar, o_V, o_rot, o_sw, o_bar, o_rank, o_end;
+    size_t o_zbar, o_A, o_F, o_G, o_w, o_sig, o_ybar, o_V, o_rot, o_sw, o_bar, o_rank, o_pos, o_end;
     size_t o_ctr_begin, o_ctr_end;  // region zeroed per call (counters)
 };
 
@@ -699,6 +699,7 @@ int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int wit
     P.o_sw = cv.take((size_t)n3 * 4);
     P.o_bar = cv.take((size_t)(kTeamCtlInts + std::max(1, P.ts.nwg)) * 4);
     P.o_rank = cv.take((size_t)n3 * 4);
+    P.o_pos = cv.take((size_t)n3 * P.p * 4);
     P.o_ctr_end = cv.off;
     P.o_end = cv.off;
     return TSVD_OK;
@@ -813,6 +814,7 @@ int enqueue_after_jacobi(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double ta
     sp.w = (double*)(base + P.o_w); sp.w_ss = P.p;
     sp.sig = (double*)(base + P.o_sig); sp.sig_ss = P.p;
     sp.ranks = (int*)(base + P.o_rank);
+    sp.pos = (int*)(base + P.o_pos);
     sp.n3 = (int)P.n3;
     sp.tau_val = tau_val; sp.tau_sched = tau_sched; sp.ctrl = ctrl;
     hipError_t e = launch_svt_prep(prec, sp, s);
@@ -1128,7 +1130,8 @@ int tsvd_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
     sp.F = base + P.o_F; sp.f_ss = (int64_t)P.m * P.p;
     sp.w = (double*)(base + P.o_w); sp.w_ss = P.p;
     sp.sig = (double*)(base + P.o_sig); sp.sig_ss = P.p;
-    sp.ranks = (int*)(base + P.o_rank); sp.n3 = (int)n3; sp.tau_val = 0.0; sp.ctrl = cr.ctrl;
+    sp.ranks = (int*)(base + P.o_rank); sp.pos = (int*)(base + P.o_pos); sp.n3 = (int)n3; sp.tau_val = 0.0;
+    sp.ctrl = cr.ctrl;
     if ((e = launch_svt_prep(dp, sp, s)) != hipSuccess) return hip_fail(c, e, "sigma");
     void* Uo = U ? U : (void*)(base + oU);
     void* Vo = V ? V : (void*)(base + oV);
@@ -1462,7 +1465,7 @@ size_t tsvd_batched_workspace_bytes(int prec, int64_t n1, int64_t n2, int64_t n3
     const size_t es = prec == TSVD_FP64 ? 8 : 4;
     const size_t m = (size_t)std::max(n1, n2), p = (size_t)std::min(n1, n2), N = (size_t)n1 * n2;
     // Zbar, Ybar; A', F, A0 (warm start); G, V (workspace copy); counters
-    return es * (2 * N * n3 + 3 * m * p * n3 + 2 * p * p * n3) + 16 * p * n3 + 4 * n3 * (kRotStride + 3) + 32 * 256 +
+    return es * (2 * N * n3 + 3 * m * p * n3 + 2 * p * p * n3) + 20 * p * n3 + 4 * n3 * (kRotStride + 3) + 32 * 256 +
            sizeof(JacobiJob) + 8 * n3;
 }
 

@@ -151,6 +151,7 @@ struct SvtPrepArgs {
     double* w; int64_t w_ss;                  // scales
     double* sig; int64_t sig_ss;              // singular values (unsorted, per column)
     int* ranks;
+    int* pos;                                 // scratch: p per slice (position of each kept column, or -1)
     int n3;
     double tau_val; const double* tau_sched; Ctrl* ctrl;
 };

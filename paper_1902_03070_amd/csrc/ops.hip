@@ -208,61 +208,69 @@ hipError_t launch_gemm(int prec, const GemmArgs& g, hipStream_t s) {
 // so (sigma_c - tau) u_c v_c^T = w_c a_c a_c^T T.
 // One workgroup (256 threads) per slice.
 // ---------------------------------------------------------------------------
+// Three launches, each spread over (column groups, slices):
+//   norms:  sigma_c = |A'(:,c)| for every column (one wavefront per column);
+//   select: per slice, keep = sigma > tau, positions of the kept columns in
+//           order (a wavefront ballot), rank, w_q = (sigma - tau) / sigma^3;
+//   gather: copy each kept column of A' to its position in F.
 template <typename T>
-__global__ __launch_bounds__(256) void k_svt_prep(SvtPrepArgs a) {
-    __shared__ double s_sig[kMaxRows];
-    __shared__ int s_pos[kMaxRows];
-    __shared__ int s_rank;
-    const int k = blockIdx.x;
-    const int m = a.m, p = a.p;
-    const T* A = (const T*)a.A + (int64_t)k * a.a_ss;
-    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    const double tau = a.tau_sched ? a.tau_sched[a.ctrl->iter] : a.tau_val;
-    for (int c = wave; c < p; c += 4) {
-        double acc = 0.0;
-        for (int r = lane; r < m; r += kWave) {
-            const double v = (double)A[(int64_t)c * m + r];
-            acc = fma(v, v, acc);
-        }
+__global__ __launch_bounds__(256) void k_svt_norms(SvtPrepArgs a) {
+    const int k = blockIdx.y, lane = threadIdx.x % kWave;
+    const int c = blockIdx.x * 4 + threadIdx.x / kWave;
+    if (c >= a.p) return;
+    const T* col = (const T*)a.A + (int64_t)k * a.a_ss + (int64_t)c * a.m;
+    double acc = 0.0;
+    for (int r = lane; r < a.m; r += kWave) {
+        const double v = (double)col[r];
+        acc = fma(v, v, acc);
+    }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-        if (lane == 0) s_sig[c] = sqrt(acc);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+    if (lane == 0) a.sig[(int64_t)k * a.sig_ss + c] = sqrt(acc);
+}
+
+__global__ __launch_bounds__(64) void k_svt_select(SvtPrepArgs a) {
+    const int k = blockIdx.x, lane = threadIdx.x;
+    const double tau = a.tau_sched ? a.tau_sched[a.ctrl->iter] : a.tau_val;
+    const double* sig = a.sig + (int64_t)k * a.sig_ss;
+    int* pos = a.pos + (int64_t)k * a.p;
+    int base = 0;
+    for (int c0 = 0; c0 < a.p; c0 += kWave) {
+        const int c = c0 + lane;
+        const double sg = c < a.p ? sig[c] : 0.0;
+        const bool keep = c < a.p && sg > tau;
+        const unsigned long long mask = __ballot(keep);
+        const int q = base + __popcll(mask & ((1ull << lane) - 1ull));
+        if (c < a.p) pos[c] = keep ? q : -1;
+        if (keep) a.w[(int64_t)k * a.w_ss + q] = ((sg - tau) / sg) / sg / sg;
+        base += __popcll(mask);
     }
-    __syncthreads();
-    if (wave == 0) {
-        int base = 0;
-        for (int c0 = 0; c0 < p; c0 += kWave) {
-            const int c = c0 + lane;
-            const bool keep = c < p && s_sig[c] > tau;
-            const unsigned long long mask = __ballot(keep);
-            const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
-            if (c < p) s_pos[c] = keep ? pos : -1;
-            base += __popcll(mask);
-        }
-        if (lane == 0) s_rank = base;
-    }
-    __syncthreads();
-    if (tid == 0) a.ranks[k] = s_rank;
-    for (int c = tid; c < p; c += blockDim.x) {
-        a.sig[(int64_t)k * a.sig_ss + c] = s_sig[c];
-        const int q = s_pos[c];
-        if (q >= 0) {
-            const double sg = s_sig[c];
-            a.w[(int64_t)k * a.w_ss + q] = ((sg - tau) / sg) / sg / sg;
-        }
-    }
-    T* F = (T*)a.F + (int64_t)k * a.f_ss;
-    for (int c = wave; c < p; c += 4) {
-        const int q = s_pos[c];
-        if (q < 0) continue;
-        for (int r = lane; r < m; r += kWave) F[(int64_t)q * m + r] = A[(int64_t)c * m + r];
-    }
+    if (lane == 0) a.ranks[k] = base;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_svt_gather(SvtPrepArgs a) {
+    const int k = blockIdx.y, lane = threadIdx.x % kWave;
+    const int c = blockIdx.x * 4 + threadIdx.x / kWave;
+    if (c >= a.p) return;
+    const int q = a.pos[(int64_t)k * a.p + c];
+    if (q < 0) return;
+    const T* src = (const T*)a.A + (int64_t)k * a.a_ss + (int64_t)c * a.m;
+    T* dst = (T*)a.F + (int64_t)k * a.f_ss + (int64_t)q * a.m;
+    for (int r = lane; r < a.m; r += kWave) dst[r] = src[r];
 }
 
 hipError_t launch_svt_prep(int prec, const SvtPrepArgs& a, hipStream_t s) {
-    if (a.n3 <= 0) return hipSuccess;
-    if (prec == 0) hipLaunchKernelGGL(k_svt_prep<double>, dim3(a.n3), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_svt_prep<float>, dim3(a.n3), dim3(256), 0, s, a);
+    if (a.n3 <= 0 || a.p <= 0) return hipSuccess;
+    const dim3 grid((a.p + 3) / 4, a.n3);
+    if (prec == 0) hipLaunchKernelGGL(k_svt_norms<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_svt_norms<float>, grid, dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_svt_select, dim3(a.n3), dim3(kWave), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (prec == 0) hipLaunchKernelGGL(k_svt_gather<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_svt_gather<float>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
