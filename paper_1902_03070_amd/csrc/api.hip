@@ -726,7 +726,7 @@ void bind_plan(Plan& P, char* base) {
     // (quadratic convergence), below the rotation threshold: the sweep that would only confirm it
     // is skipped.  MIXED hands over to its FP64 sweep once the FP32 sweeps are at cosines <= 3e-3:
     // that sweep starts from ~1e-5 and ends far below the FP32 rounding of the stored columns.
-    J.skip2 = P.prec == TSVD_MIXED ? 9e-6 : J.tol / 4096.0;
+    J.skip2 = P.prec == TSVD_MIXED ? 1e-4 : J.tol / 4096.0;
     P.ts.ctl = (int*)(base + P.o_bar);
 }
 
