@@ -77,6 +77,27 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
+// The same sum for an FP32 value: one DPP add per step instead of two moves
+// and an FP64 add.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    const int i = __float_as_int(v);
+    return __int_as_float(__builtin_amdgcn_update_dpp(i, i, CTRL, 0xF, 0xF, true));
+}
+template <int G>
+__device__ __forceinline__ float group_sum_f(float v) {
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x141>(v);
+    v += dpp_f<0x140>(v);
+    if (G == 32) {
+        const unsigned u = __float_as_uint(v);
+        const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    }
+    return v;
+}
+
 // Circle-method round robin on n (even) players: round s (0..n-2), pair q
 // (0..n/2-1) -> players (i < j).  Every pair meets exactly once in n-1 rounds.
 // (s + q and s - q stay within one period of n - 1, so a conditional add or
@@ -179,6 +200,26 @@ __device__ __forceinline__ double partial_dot(const T* x, const T* y, bool f64) 
     return (double)((p0 + p1) + (p2 + p3));
 }
 
+// Group-reduced inner product of the first R values of x and y.  FP32 data
+// outside an FP64 sweep are summed in FP32 throughout (lane partials and the
+// reduction): the error, a few units of 2^-24 times |x||y|, stays far below
+// every rotation threshold used with FP32 data.
+template <typename T, int R, int G>
+__device__ __forceinline__ double group_dot(const T* x, const T* y, bool f64) {
+    if (sizeof(T) == 4 && !f64) {
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll
+        for (int q = 0; q < R; q += 4) {
+            p0 = fmaf((float)x[q], (float)y[q], p0);
+            p1 = fmaf((float)x[q + 1], (float)y[q + 1], p1);
+            p2 = fmaf((float)x[q + 2], (float)y[q + 2], p2);
+            p3 = fmaf((float)x[q + 3], (float)y[q + 3], p3);
+        }
+        return (double)group_sum_f<G>((p0 + p1) + (p2 + p3));
+    }
+    return group_sum<G>(partial_dot<T, R>(x, y, f64));
+}
+
 template <typename T, int R>
 __device__ __forceinline__ double partial_norm(const T* x) {
     double pa = 0.0;
@@ -271,7 +312,7 @@ __device__ __forceinline__ int tpair_lds(T* __restrict__ x, T* __restrict__ y, d
         yr[q] = y[gl + G * q];
     }
     const double a = *na, b = *nb;
-    const double g = group_sum<G>(partial_dot<T, R>(xr, yr, f64));
+    const double g = group_dot<T, R, G>(xr, yr, f64);
     big += g * g > th2 * (a * b);
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
@@ -297,7 +338,7 @@ __device__ __forceinline__ int tpair_reg(T (&xr)[RT], double& na, T* __restrict_
 #pragma unroll
     for (int q = 0; q < RT; ++q) yr[q] = y[gl + G * q];
     const double a = na;
-    const double g = group_sum<G>(partial_dot<T, R>(xr, yr, f64));
+    const double g = group_dot<T, R, G>(xr, yr, f64);
     big += g * g > th2 * (a * b);
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
@@ -782,12 +823,29 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                 } else {
                     na = group_sum<G>(partial_norm<T, R>(xr));
                 }
-                // cross pairs: b rounds, group g pairs I[g] with J[(g + r) mod b]
-                int j = grp;
-                for (int r = 0; r < b; ++r, j = (j + 1 == b) ? 0 : j + 1) {
-                    if (ci < p && BJ * b + j < p)
-                        rot += tpair_reg<T, R, RT, G>(xr, na, Js + j * ldl, nJ + j, gl, tl, f64, J.skip2, big);
-                    __syncthreads();
+                // cross pairs.  The J block is cut into sub-blocks of gw = 64 / G columns, one
+                // per wavefront of gw lane groups.  In super-round r wavefront w owns sub-block
+                // (w + r) mod nw, and its group u pairs with column (u + v) mod gw of it in
+                // sub-round v.  Between sub-rounds a J column passes between groups of one
+                // wavefront, whose LDS accesses complete in program order, so only the
+                // super-rounds end at a workgroup barrier.
+                {
+                    constexpr int gw = kWave / G;
+                    const int nw = b / gw, w = grp / gw, u = grp - w * gw;
+                    int sb = w;
+                    for (int r = 0; r < nw; ++r, sb = (sb + 1 == nw) ? 0 : sb + 1) {
+#pragma unroll
+                        for (int v = 0; v < gw; ++v) {
+                            const int j = sb * gw + ((u + v) & (gw - 1));
+                            if (ci < p && BJ * b + j < p)
+                                rot += tpair_reg<T, R, RT, G>(xr, na, Js + j * ldl, nJ + j, gl, tl, f64, J.skip2,
+                                                              big);
+                            // keeps the compiler from moving the next sub-round's LDS reads
+                            // above this one's writes (no instruction is emitted)
+                            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        }
+                        __syncthreads();
+                    }
                 }
                 if (ci < p) {
 #pragma unroll
