@@ -724,8 +724,8 @@ void bind_plan(Plan& P, char* base) {
     J.tol = P.prec == TSVD_FP64 ? P.m * u64 : P.prec == TSVD_FP32 ? 2.0 * sqrt((double)P.m) * u32 : P.m * u32;
     // A sweep whose cosines are all <= sqrt(tol) / 64 leaves the next one rotating by ~tol / 4096
     // (quadratic convergence), below the rotation threshold: the sweep that would only confirm it
-    // is skipped.  MIXED hands over to its FP64 sweep once the FP32 sweeps are at cosines <= 3e-3:
-    // that sweep starts from ~1e-5 and ends far below the FP32 rounding of the stored columns.
+    // is skipped.  MIXED hands over to its FP64 sweep once the FP32 sweeps are at cosines <= 1e-2:
+    // that sweep starts from ~1e-4 and ends near 1e-8, below the FP32 rounding of the stored columns.
     J.skip2 = P.prec == TSVD_MIXED ? 1e-4 : J.tol / 4096.0;
     P.ts.ctl = (int*)(base + P.o_bar);
 }

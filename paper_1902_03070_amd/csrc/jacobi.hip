@@ -6,9 +6,10 @@
 // Columns of T are rotated in pairs until every pair is orthogonal to a
 // tolerance tol (m u for FP64, u = 2^-53; 2 sqrt(m) u32 for FP32 sweeps, since
 // FP32 rounding of the stored columns bounds the attainable orthogonality;
-// m u32 for the FP32 sweeps of the mixed path, which ends with one sweep in
-// FP64 arithmetic at m u):
-//     alpha = |x|^2, beta = |y|^2, gamma = x.y        (FP64 sums)
+// m u32 for the FP32 sweeps of the mixed path, which ends with one sweep at
+// m u whose inner products and angles are FP64):
+//     alpha = |x|^2, beta = |y|^2 (FP64 sums), gamma = x.y (FP64 sums; FP32
+//     for FP32 sweeps of the team kernel)
 //     rotate iff gamma^2 > tol^2 alpha beta
 //     zeta = (beta - alpha) / (2 gamma),  t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2))
 //     c = 1 / sqrt(1 + t^2),  s = c t,  x' = c x - s y,  y' = s x + c y.
@@ -228,41 +229,28 @@ __device__ __forceinline__ double partial_norm(const T* x) {
     return pa;
 }
 
+// Rotations run in the data's precision: the cosine and sine are rounded to
+// T once and each rotated value takes a product and an FMA.  In the mixed
+// path's FP64 sweep the inner products and angles are FP64 while the
+// rotation arithmetic stays FP32, the precision the values are stored in.
 template <typename T, int R>
-__device__ __forceinline__ void rotate_regs(T (&x)[R], T (&y)[R], double c, double s, bool f64) {
-    if (sizeof(T) == 8 || f64) {
+__device__ __forceinline__ void rotate_regs(T (&x)[R], T (&y)[R], double c, double s) {
+    const T cc = (T)c, ss = (T)s;
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const double xd = (double)x[q], yd = (double)y[q];
-            x[q] = (T)(c * xd - s * yd);
-            y[q] = (T)(s * xd + c * yd);
-        }
-    } else {
-        const T cc = (T)c, ss = (T)s;
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const T xd = x[q], yd = y[q];
-            x[q] = cc * xd - ss * yd;
-            y[q] = ss * xd + cc * yd;
-        }
+    for (int q = 0; q < R; ++q) {
+        const T xd = x[q], yd = y[q];
+        x[q] = cc * xd - ss * yd;
+        y[q] = ss * xd + cc * yd;
     }
 }
 
 template <typename T>
-__device__ __forceinline__ void rotate_lds_col(T* vx, T* vy, int n, int gl, int G, double c, double s, bool f64) {
-    if (sizeof(T) == 8 || f64) {
-        for (int r = gl; r < n; r += G) {
-            const double xd = (double)vx[r], yd = (double)vy[r];
-            vx[r] = (T)(c * xd - s * yd);
-            vy[r] = (T)(s * xd + c * yd);
-        }
-    } else {
-        const T cc = (T)c, ss = (T)s;
-        for (int r = gl; r < n; r += G) {
-            const T xd = vx[r], yd = vy[r];
-            vx[r] = cc * xd - ss * yd;
-            vy[r] = ss * xd + cc * yd;
-        }
+__device__ __forceinline__ void rotate_lds_col(T* vx, T* vy, int n, int gl, int G, double c, double s) {
+    const T cc = (T)c, ss = (T)s;
+    for (int r = gl; r < n; r += G) {
+        const T xd = vx[r], yd = vy[r];
+        vx[r] = cc * xd - ss * yd;
+        vy[r] = ss * xd + cc * yd;
     }
 }
 
@@ -283,13 +271,13 @@ __device__ __forceinline__ int gpair_lds(T* __restrict__ x, T* __restrict__ y, d
     big += g * g > th2 * (a * b);
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
-    rotate_regs<T, R>(xr, yr, c, s, f64);
+    rotate_regs<T, R>(xr, yr, c, s);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         x[gl + G * q] = xr[q];
         y[gl + G * q] = yr[q];
     }
-    if (vrows) rotate_lds_col<T>(vx, vy, vrows, gl, G, c, s, f64);
+    if (vrows) rotate_lds_col<T>(vx, vy, vrows, gl, G, c, s);
     if (gl == 0) {
         *na = a - t * g;
         *nb = b + t * g;
@@ -316,7 +304,7 @@ __device__ __forceinline__ int tpair_lds(T* __restrict__ x, T* __restrict__ y, d
     big += g * g > th2 * (a * b);
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
-    rotate_regs<T, RT>(xr, yr, c, s, f64);
+    rotate_regs<T, RT>(xr, yr, c, s);
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
         x[gl + G * q] = xr[q];
@@ -342,7 +330,7 @@ __device__ __forceinline__ int tpair_reg(T (&xr)[RT], double& na, T* __restrict_
     big += g * g > th2 * (a * b);
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
-    rotate_regs<T, RT>(xr, yr, c, s, f64);
+    rotate_regs<T, RT>(xr, yr, c, s);
 #pragma unroll
     for (int q = 0; q < RT; ++q) y[gl + G * q] = yr[q];
     na = a - t * g;
@@ -371,8 +359,8 @@ __device__ __forceinline__ int gpair2(T (&x1)[R], double& n1, T (&y1)[R], double
         rotation_angle(r2 ? n2 : 1.0, r2 ? m2 : 2.0, r2 ? g2 : 1.0, c2, s2, t2);
         c1 = r1 ? c1 : 1.0; s1 = r1 ? s1 : 0.0; t1 = r1 ? t1 : 0.0;
         c2 = r2 ? c2 : 1.0; s2 = r2 ? s2 : 0.0; t2 = r2 ? t2 : 0.0;
-        rotate_regs<T, R>(x1, y1, c1, s1, f64);
-        rotate_regs<T, R>(x2, y2, c2, s2, f64);
+        rotate_regs<T, R>(x1, y1, c1, s1);
+        rotate_regs<T, R>(x2, y2, c2, s2);
         n1 -= t1 * g1; m1 += t1 * g1;
         n2 -= t2 * g2; m2 += t2 * g2;
     }
@@ -480,7 +468,7 @@ __device__ void resident_task(const JacobiJob& J, int k, int max_sweeps, Ctrl* c
         if (tot == 0 || btot == 0) {
             sweeps = sw + 1;
             if (!refine) break;
-            sw = max_sweeps - 1;  // one more sweep, in FP64 arithmetic
+            sw = max_sweeps - 1;  // one more sweep, with FP64 inner products and angles
         }
     }
     T* Ag = (T*)J.A + (int64_t)k * m * p;
