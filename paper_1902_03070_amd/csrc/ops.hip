@@ -124,69 +124,121 @@ hipError_t launch_tube_transform(int prec, const TubeArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Batched strided GEMM  C_b = (A_b B_b) diag(cscale_b), K_b from Kdev or K.
-// 64 x 64 output tile per workgroup, 256 threads, 4 x 4 outputs per thread
-// (rows tx + 16u, columns ty + 16v), K staged through LDS in chunks of 16.
+// Batched strided GEMM  C_b = (A_b B_b) diag(cscale_b), K_b from Kdev or K,
+// on the matrix cores (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64).
+// A workgroup of 256 threads computes a 64 x 64 tile of C; wavefront w takes
+// the 32 x 32 quarter (w & 1, w >> 1) as 2 x 2 blocks of 16 x 16.  K goes
+// through LDS in chunks of 32, and the next chunk's global loads are issued
+// before the current chunk's products.  Each block is formed as
+// C^T = B^T A^T, so the 16 lanes of a result row run down a column of C
+// (contiguous stores for column-major C).
+//
+// Lane layouts (gfx950): A 16xK operand, lane l holds row l%16 and K slice
+// l/16; B Kx16 operand, lane l holds column l%16 and K slice l/16; result:
+// FP64 element v of lane l is row l/16 + 4v, FP32 element v is row
+// 4(l/16) + v, column l%16 in both.
 // ---------------------------------------------------------------------------
+typedef double gd4_t __attribute__((ext_vector_type(4)));
+typedef float gf4_t __attribute__((ext_vector_type(4)));
+template <typename T> struct GemmAcc;
+template <> struct GemmAcc<double> { typedef gd4_t V; };
+template <> struct GemmAcc<float> { typedef gf4_t V; };
+
+constexpr int kGemmKT = 32;  // K chunk staged in LDS
+
+template <typename T>
+__device__ __forceinline__ typename GemmAcc<T>::V mfma16x16x4(T a, T b, typename GemmAcc<T>::V c) {
+    if constexpr (sizeof(T) == 8) return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Element q (< 8) of thread tid in a 64 x 32 (A) or 32 x 64 (B) chunk: the
+// index pairs run along the operand's unit-stride dimension for coalescing.
+__device__ __forceinline__ void gemm_chunk_index(int e, bool along64, int& x64, int& x32) {
+    if (along64) { x64 = e & 63; x32 = e >> 6; }
+    else { x32 = e & 31; x64 = e >> 5; }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-    __shared__ T As[16][64 + 1];
-    __shared__ T Bs[16][64 + 1];
+    constexpr int LD = 64 + (sizeof(T) == 4 ? 16 : 8);  // row pitch: 16-lane runs of adjacent rows fall in different banks
+    __shared__ T As[kGemmKT][LD];  // As[k][i]
+    __shared__ T Bs[kGemmKT][LD];  // Bs[k][j]
+    typedef typename GemmAcc<T>::V Acc;
     const int b = blockIdx.z;
     const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
     const int K = g.Kdev ? g.Kdev[b] : g.K;
     const int Nb = g.Ndev ? g.Ndev[b] : g.Nn;
     if (j0 >= Nb) return;
-    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
     const T* A = (const T*)g.A + (int64_t)b * g.a_bs;
     const T* B = (const T*)g.B + (int64_t)b * g.b_bs;
-    T acc[4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = (T)0;
     const bool a_rowfast = g.a_rs == 1;
-    const bool b_rowfast = g.b_rs == 1;
-    for (int t0 = 0; t0 < K; t0 += 16) {
+    const bool b_kfast = g.b_rs == 1;
+    T ra[8], rb[8];
+    auto fetch = [&](int t0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 8; ++q) {
             const int e = tid + 256 * q;
-            int ii, tt;
-            if (a_rowfast) { ii = e % 64; tt = e / 64; }
-            else { tt = e % 16; ii = e / 16; }
-            const int gi = i0 + ii, gt = t0 + tt;
-            As[tt][ii] = (gi < g.M && gt < K) ? A[(int64_t)gi * g.a_rs + (int64_t)gt * g.a_cs] : (T)0;
-            int jj;
-            if (b_rowfast) { tt = e % 16; jj = e / 16; }
-            else { jj = e % 64; tt = e / 64; }
-            const int gj = j0 + jj, gt2 = t0 + tt;
-            Bs[tt][jj] = (gj < Nb && gt2 < K) ? B[(int64_t)gt2 * g.b_rs + (int64_t)gj * g.b_cs] : (T)0;
+            int ii, tt, jj, tb;
+            gemm_chunk_index(e, a_rowfast, ii, tt);
+            gemm_chunk_index(e, !b_kfast, jj, tb);
+            const int gi = i0 + ii, gt = t0 + tt, gj = j0 + jj, gtb = t0 + tb;
+            ra[q] = (gi < g.M && gt < K) ? A[(int64_t)gi * g.a_rs + (int64_t)gt * g.a_cs] : (T)0;
+            rb[q] = (gj < Nb && gtb < K) ? B[(int64_t)gtb * g.b_rs + (int64_t)gj * g.b_cs] : (T)0;
+        }
+    };
+    Acc acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[u][v][e] = (T)0;
+    if (K > 0) fetch(0);
+    for (int t0 = 0; t0 < K; t0 += kGemmKT) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + 256 * q;
+            int ii, tt, jj, tb;
+            gemm_chunk_index(e, a_rowfast, ii, tt);
+            gemm_chunk_index(e, !b_kfast, jj, tb);
+            As[tt][ii] = ra[q];
+            Bs[tb][jj] = rb[q];
         }
         __syncthreads();
+        if (t0 + kGemmKT < K) fetch(t0 + kGemmKT);
 #pragma unroll
-        for (int tt = 0; tt < 16; ++tt) {
-            T av[4], bv[4];
+        for (int ks = 0; ks < kGemmKT; ks += 4) {
+            const int kk = ks + (lane >> 4);
+            T af[2], bf[2];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) av[u] = As[tt][tx + 16 * u];
+            for (int u = 0; u < 2; ++u) af[u] = As[kk][wi + 16 * u + (lane & 15)];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) bv[v] = Bs[tt][ty + 16 * v];
+            for (int v = 0; v < 2; ++v) bf[v] = Bs[kk][wj + 16 * v + (lane & 15)];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+                for (int v = 0; v < 2; ++v) acc[u][v] = mfma16x16x4<T>(bf[v], af[u], acc[u][v]);
         }
         __syncthreads();
     }
     T* C = (T*)g.C + (int64_t)b * g.c_bs;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int j = j0 + ty + 16 * v;
-        if (j >= Nb) continue;
-        const double sc = g.cscale ? g.cscale[(int64_t)b * g.s_bs + j] : 1.0;
+    for (int u = 0; u < 2; ++u) {
+        const int i = i0 + wi + 16 * u + (lane & 15);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = i0 + tx + 16 * u;
-            if (i < g.M) C[(int64_t)i * g.c_rs + (int64_t)j * g.c_cs] = g.cscale ? (T)((double)acc[u][v] * sc) : acc[u][v];
+        for (int v = 0; v < 2; ++v) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int jr = sizeof(T) == 8 ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e;
+                const int j = j0 + wj + 16 * v + jr;
+                if (i >= g.M || j >= Nb) continue;
+                const T val = acc[u][v][e];
+                C[(int64_t)i * g.c_rs + (int64_t)j * g.c_cs] =
+                    g.cscale ? (T)((double)val * g.cscale[(int64_t)b * g.s_bs + j]) : val;
+            }
         }
     }
 }
