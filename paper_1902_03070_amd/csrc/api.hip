@@ -198,7 +198,7 @@ constexpr int kHist = 4096;  // relative-change history slots in the control reg
 
 struct CtrlRegion {
     Ctrl* ctrl;
-    double* norms;  // [2]
+    double* norms;  // [2 kNormSlots]
     double* hist;   // [kHist]
 };
 

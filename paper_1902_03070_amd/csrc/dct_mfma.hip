@@ -157,8 +157,10 @@ __global__ __launch_bounds__(256) void k_tube_mfma(TubeArgs a, const void* __res
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            atomicAdd(&a.norms[0], s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3]);
-            atomicAdd(&a.norms[1], s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3]);
+            // kNormSlots slot pairs spread the atomics of the workgroups over addresses
+            double* slot = a.norms + 2 * (blockIdx.x % kNormSlots);
+            atomicAdd(slot, s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3]);
+            atomicAdd(slot + 1, s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3]);
         }
     }
 }

@@ -16,6 +16,7 @@ constexpr int kMaxEpl = 8;           // rows per lane in the Jacobi kernels: m <
 constexpr int kMaxRows = kWave * kMaxEpl;
 constexpr int kTeamMaxThreads = 512;  // launch bound of the Jacobi team kernel
 constexpr int kLdsPad = 16;            // extra elements per LDS column (spreads lane groups over banks)
+constexpr int kNormSlots = 16;       // slot pairs of the completion's change norms (256 bytes)
 constexpr int kLdsBudget = 160 * 1024 - 8 * 1024;  // dynamic LDS per workgroup (gfx950: 160 KB, minus static use)
 
 // Device status bits (accumulated with atomicOr in ctrl->status).
@@ -83,7 +84,7 @@ struct TubeArgs {
     const uint8_t* emask;
     void* eX;
     void* eM;
-    double* norms;         // [2] += (||Xn - X||^2, ||X||^2) (FP64 atomics)
+    double* norms;         // [2 kNormSlots]: slot pairs += (||Xn - X||^2, ||X||^2) (FP64 atomics)
     // beta: beta_val, or beta_sched[ctrl->iter] when beta_sched != nullptr
     double beta_val;
     const double* beta_sched;

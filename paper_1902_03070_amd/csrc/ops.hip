@@ -104,8 +104,9 @@ __global__ __launch_bounds__(256) void k_tube(TubeArgs a) {
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            atomicAdd(&a.norms[0], s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3]);
-            atomicAdd(&a.norms[1], s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3]);
+            double* slot = a.norms + 2 * (blockIdx.x % kNormSlots);
+            atomicAdd(slot, s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3]);
+            atomicAdd(slot + 1, s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3]);
         }
     }
 }
@@ -466,12 +467,16 @@ hipError_t launch_warm_reset(int prec, void* V, int p, int n3, const Ctrl* ctrl,
 // norm accumulators, advance the iteration counter.
 __global__ void k_iter_advance(Ctrl* ctrl, double* norms, double* hist, int hist_len) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const double dn = norms[0], xn = norms[1];
+        double dn = 0.0, xn = 0.0;
+        for (int i = 0; i < kNormSlots; ++i) {
+            dn += norms[2 * i];
+            xn += norms[2 * i + 1];
+            norms[2 * i] = 0.0;
+            norms[2 * i + 1] = 0.0;
+        }
         const double rc = xn > 0.0 ? sqrt(dn / xn) : sqrt(dn);
         const int it = ctrl->iter;
         if (it < hist_len) hist[it] = rc;
-        norms[0] = 0.0;
-        norms[1] = 0.0;
         ctrl->iter = it + 1;
     }
 }
