@@ -120,6 +120,34 @@ __global__ __launch_bounds__(256) void k_tube_mfma(TubeArgs a, const void* __res
                 }
             }
             if (!live) continue;
+            if (!a.eX) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int ko = mb * 16 + out_row<ENG>(lane, v);
+                    if (a.out && ko < n3) ((T*)a.out)[r + N * ko] = (T)acc[v];
+                }
+                continue;
+            }
+            // completion epilogue: every input of the block's four rows is loaded before
+            // the first store (one memory round trip per block; B is read whether or not
+            // the entry is observed, so no load waits on the mask)
+            T* X = (T*)a.eX;
+            T* Ml = (T*)a.eM;
+            T xo[4], mo[4], bo[4];
+            unsigned char mk[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ko = mb * 16 + out_row<ENG>(lane, v);
+                xo[v] = mo[v] = bo[v] = (T)0;
+                mk[v] = 0;
+                if (ko < n3) {
+                    const int64_t e = r + N * ko;
+                    xo[v] = X[e];
+                    mo[v] = Ml[e];
+                    bo[v] = ((const T*)a.eB)[e];
+                    mk[v] = a.emask[e];
+                }
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int ko = mb * 16 + out_row<ENG>(lane, v);
@@ -127,20 +155,14 @@ __global__ __launch_bounds__(256) void k_tube_mfma(TubeArgs a, const void* __res
                 const int64_t e = r + N * ko;
                 const T y = (T)acc[v];
                 if (a.out) ((T*)a.out)[e] = y;
-                if (a.eX) {
-                    T* X = (T*)a.eX;
-                    T* Ml = (T*)a.eM;
-                    const T xold = X[e];
-                    const T mold = Ml[e];
-                    T xnew;
-                    if (a.emask[e]) xnew = ((const T*)a.eB)[e];
-                    else xnew = (T)((double)y + (double)mold / beta);
-                    Ml[e] = (T)((double)mold + beta * ((double)y - (double)xnew));
-                    X[e] = xnew;
-                    const double d = (double)xnew - (double)xold;
-                    dn += d * d;
-                    xn += (double)xold * (double)xold;
-                }
+                const T xold = xo[v];
+                const T mold = mo[v];
+                const T xnew = mk[v] ? bo[v] : (T)((double)y + (double)mold / beta);
+                Ml[e] = (T)((double)mold + beta * ((double)y - (double)xnew));
+                X[e] = xnew;
+                const double d = (double)xnew - (double)xold;
+                dn += d * d;
+                xn += (double)xold * (double)xold;
             }
         }
     }
