@@ -30,9 +30,12 @@ def test_tprod_fp64(tm, shape):
     assert rel(to_np(Z), oracle.tprod_dct(X, Y)) <= 1e-12
 
 
-def test_tprod_fp32(tm):
-    announce("tprod_fp32")
-    X, Y = rnd(3, 20, 10, 8), rnd(4, 10, 12, 8)
+# (130, 75, 90, 7): several 64-wide output tiles and 32-deep K chunks, each with a ragged tail
+@pytest.mark.parametrize("shape", [(20, 10, 12, 8), (130, 75, 90, 7)])
+def test_tprod_fp32(tm, shape):
+    n1, n2, n4, n3 = shape
+    announce("tprod_fp32", shape=shape)
+    X, Y = rnd(3, n1, n2, n3), rnd(4, n2, n4, n3)
     Z = tm.tprod_dct(to_dev(X, torch.float32), to_dev(Y, torch.float32))
     assert rel(to_np(Z), oracle.tprod_dct(X, Y)) <= 1e-5
 
