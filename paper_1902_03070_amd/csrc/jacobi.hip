@@ -571,15 +571,18 @@ __device__ bool team_barrier(TeamState& ts, int* s_flag) {
         }
     }
     __syncthreads();
-    const bool ok = (*s_flag == 0);
-    __syncthreads();
-    return ok;
+    // s_flag is next written by thread 0 after the workgroup barrier that opens the
+    // next team barrier, so every thread has read it by then
+    return *s_flag == 0;
 }
 
 // Load b columns of block `blk` into LDS (ld ldl); from the source tensor on
 // the first step of the first sweep, else from A.  Zero padding beyond m / p.
+// Column squared norms go to nrm[] (LDS), except from a transposed source,
+// whose loads do not follow the lane groups (the caller takes those from LDS).
 template <typename T, int R, int G, bool WV>
-__device__ __forceinline__ void team_load_block(const JacobiJob& J, int k, int blk, bool first, T* As) {
+__device__ __forceinline__ void team_load_block(const JacobiJob& J, int k, int blk, bool first, T* As,
+                                                double* nrm) {
     constexpr int RT = WV ? 2 * R : R;
     constexpr int ldl = RT * G + kLdsPad;
     const int m = J.m, p = J.p, b = J.b;
@@ -603,6 +606,9 @@ __device__ __forceinline__ void team_load_block(const JacobiJob& J, int k, int b
         }
 #pragma unroll
         for (int q = 0; q < R; ++q) As[grp * ldl + gl + G * q] = v[q];
+        // the column's squared norm from the loaded values (same order as lds_col_norm)
+        const double nn = group_sum<G>(partial_norm<T, R>(v));
+        if (gl == 0) nrm[grp] = nn;
     }
     if (WV) {
         // V rows below the A rows: the identity, the caller's V (warm start) or the work array
@@ -779,18 +785,18 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                         }
                     }
                 }
-                team_load_block<T, R, G, WV>(J, k, BJ, first, Js);
-                if (s == 0) team_load_block<T, R, G, WV>(J, k, BI, first, Is);
+                team_load_block<T, R, G, WV>(J, k, BJ, first, Js, nJ);
+                if (s == 0) team_load_block<T, R, G, WV>(J, k, BI, first, Is, nI);
                 __syncthreads();
-                {
+                if (first && J.src_rs != 1) {
                     const double nn = lds_col_norm<T, R, G>(Js + grp * ldl, gl);
-                    if (gl == 0) nJ[grp] = nn;
-                    if (s == 0) {
-                        const double ni = lds_col_norm<T, R, G>(Is + grp * ldl, gl);
-                        if (gl == 0) nI[grp] = ni;
+                    const double ni = lds_col_norm<T, R, G>(Is + grp * ldl, gl);
+                    if (gl == 0) {
+                        nJ[grp] = nn;
+                        nI[grp] = ni;
                     }
+                    __syncthreads();
                 }
-                __syncthreads();
                 if (s == 0) {
                     // pairs inside each block: b-1 rounds, b/2 pairs per block per round
                     for (int r = 0; r < b - 1; ++r) {
@@ -844,7 +850,9 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                     }
                 }
                 team_store_block<T, R, G, WV>(J, k, BJ, Js);
-                __syncthreads();
+                // the LDS blocks are reloaded next by this loop or after the team barrier,
+                // which begins with a workgroup barrier
+                if (q + ts.W < nb / 2) __syncthreads();
             }
             if (s == nb - 2) {
                 const int tot = block_sum_groups(rot, gl, s_scratch);
