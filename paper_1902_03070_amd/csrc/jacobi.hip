@@ -529,11 +529,12 @@ __global__ __launch_bounds__(1024) void k_jacobi_resident(JacobiJob job1, const 
 // Team kernel.
 // ---------------------------------------------------------------------------
 struct TeamState {
-    int* bar;       // this team's barrier counter
+    int* bar;       // this team's W barrier flags (one per workgroup)
     int passed;     // barriers passed so far by this workgroup
     int W;
     int spin_limit;
     Ctrl* ctrl;
+    int rank;       // this workgroup's flag
 };
 
 // XCD (accelerator complex die) of the executing workgroup: hardware register
@@ -541,29 +542,36 @@ struct TeamState {
 __device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg((15 << 11) | 20) & 0xF; }
 
 // Team barrier.  Each wavefront first waits for its own global stores to be
-// acknowledged by the L2 (vmcnt(0)); then one lane per workgroup arrives on
-// the team counter (a device-scope atomic) and waits for the team with a
-// bounded spin.  All workgroups of a team run on one XCD and so share one L2:
-// the exchanged blocks are there as soon as the stores are acknowledged, so
-// the release needs no L2 write-back (a device-scope release would write the
-// XCD's dirty L2 lines back to memory at every barrier), and the readers load
-// them with ld_team, which bypasses the L1, so no acquire invalidation is
-// needed either.  Returns false when the wait gave up.
+// acknowledged by the L2 (vmcnt(0)); then thread 0 writes the number of
+// barriers this workgroup has passed to its own flag with an ordinary store
+// (through to the L2), and lanes 0..W-1 of wavefront 0 poll the W flags of the
+// team together, with a bounded spin, until every one has reached that count.
+// All workgroups of a team run on one XCD and so share one L2: the flags and
+// the exchanged blocks are there as soon as the stores are acknowledged, and
+// the polls and block loads bypass the L1 (ld_team), so neither a release
+// write-back of the L2 nor an acquire invalidation is needed, and no
+// device-scope atomic either.  Returns false when the wait gave up.
 __device__ bool team_barrier(TeamState& ts, int* s_flag) {
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's stores are complete
     __syncthreads();
     ts.passed += 1;
-    if (threadIdx.x == 0) {
-        *s_flag = 0;
+    if (threadIdx.x < kWave) {
+        if (threadIdx.x == 0) *s_flag = 0;
         if (ts.W > 1) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // XCD-local team: see above
-            __hip_atomic_fetch_add(ts.bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int target = ts.passed * ts.W;
+            if (threadIdx.x == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __hip_atomic_store(ts.bar + ts.rank, ts.passed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            const int lane = threadIdx.x;
             int it = 0;
-            while (__hip_atomic_load(ts.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            for (;;) {
+                const int f = lane < ts.W ? ld_team(ts.bar + lane) : ts.passed;
+                if (__all(f >= ts.passed)) break;
                 if (++it > ts.spin_limit) {
-                    atomicOr(&ts.ctrl->status, kStTimeout);
-                    *s_flag = 1;
+                    if (lane == 0) {
+                        atomicOr(&ts.ctrl->status, kStTimeout);
+                        *s_flag = 1;
+                    }
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
@@ -1042,8 +1050,8 @@ __device__ bool team_task_k2(const JacobiJob& J, int k, int rank, TeamState& ts,
 // arrived, slots [W t, W t + W) of an XCD form team t there, and a workgroup
 // left over on an XCD without a full team exits.  Teams are numbered across
 // XCDs and take slices t, t + nteams, ...  ctl layout (ints, zeroed before the
-// launch): [0, 16) slot counter per XCD, [16] arrivals, [32 + i] barrier of
-// team i.
+// launch): [0, 16) slot counter per XCD, [16] arrivals, [32 + W i + r] barrier
+// flag of rank r in team i.
 template <typename T, bool WV, int R, int G, int K>
 __global__ __launch_bounds__(512) void k_jacobi_team(JacobiJob J1, int ntasks, TeamSched sched, int max_sweeps,
                                                      Ctrl* ctrl, int spin_limit) {
@@ -1083,7 +1091,7 @@ __global__ __launch_bounds__(512) void k_jacobi_team(JacobiJob J1, int ntasks, T
     __syncthreads();
     const int team = s_team, rank = s_rank, nteams = s_nteams;
     if (team < 0) return;
-    TeamState ts{ctl + 32 + team, 0, W, spin_limit, ctrl};
+    TeamState ts{ctl + 32 + team * W, 0, W, spin_limit, ctrl, rank};
     for (int t = team; t < ntasks; t += nteams) {
         if constexpr (K == 2) {
             static_assert(!WV, "two columns per group: no V");
@@ -1125,7 +1133,7 @@ __global__ __launch_bounds__(512) void k_jacobi_batched(const JacobiJob* __restr
         if (J.nb == 0) {
             resident_task<T, R, G, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch, s_nrm);
         } else {
-            TeamState ts{nullptr, 0, 1, 0, ctrl};
+            TeamState ts{nullptr, 0, 1, 0, ctrl, 0};
             (void)team_task<T, R, G, WV>(J, k, 0, ts, max_sweeps, lds, &s_scratch, &s_flag, s_nrm, s_nrm + 64);
         }
         __syncthreads();
