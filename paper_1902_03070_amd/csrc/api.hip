@@ -697,7 +697,7 @@ int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int wit
     P.o_ctr_begin = cv.off;
     P.o_rot = cv.take((size_t)n3 * kRotStride * 4);
     P.o_sw = cv.take((size_t)n3 * 4);
-    P.o_bar = cv.take((size_t)(kTeamCtlInts + std::max(1, P.ts.nwg)) * 4);
+    P.o_bar = cv.take((size_t)(kTeamCtlInts + (size_t)std::max(1, P.ts.nwg) * (1 + std::max(1, P.job.nb))) * 4);
     P.o_rank = cv.take((size_t)n3 * 4);
     P.o_pos = cv.take((size_t)n3 * P.p * 4);
     P.o_ctr_end = cv.off;

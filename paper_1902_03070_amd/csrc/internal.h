@@ -59,7 +59,7 @@ struct JacobiJob {
 struct TeamSched {
     int W;             // workgroups per team
     int nwg;           // workgroups in the grid (a multiple of 8 W: whole teams on each XCD)
-    int* ctl;          // team formation and barrier counters, kTeamCtlInts + nwg ints, zeroed
+    int* ctl;          // team formation and barrier counters, kTeamCtlInts + nwg (1 + nb) ints, zeroed
 };
 constexpr int kTeamCtlInts = 32;
 

@@ -535,6 +535,8 @@ struct TeamState {
     int spin_limit;
     Ctrl* ctrl;
     int rank;       // this workgroup's flag
+    int* blk;       // this team's block flags (nb): the step at which each block was last released
+    int steps;      // block-pair steps finished so far by this workgroup
 };
 
 // XCD (accelerator complex die) of the executing workgroup: hardware register
@@ -581,6 +583,48 @@ __device__ bool team_barrier(TeamState& ts, int* s_flag) {
     __syncthreads();
     // s_flag is next written by thread 0 after the workgroup barrier that opens the
     // next team barrier, so every thread has read it by then
+    return *s_flag == 0;
+}
+
+// Point-to-point hand-over of blocks between the steps of a sweep.  A block
+// goes from the workgroup that held it in one step to the one that holds it
+// in the next, so a workgroup waits only for the two previous holders of its
+// blocks instead of the whole team.  Release: every wavefront's stores are
+// acknowledged by the L2 (vmcnt(0)), then thread 0 writes the step number to
+// both block flags with ordinary stores.  Wait: lanes 0 and 1 of wavefront 0
+// poll the two flags (L1-bypassing loads, bounded spin).  The last step of a
+// sweep still ends at the full team barrier, which also publishes the
+// rotation counts that decide convergence.
+__device__ void team_release_blocks(TeamState& ts, int BI, int BJ, int step) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's stores are complete
+    __syncthreads();
+    if (ts.W > 1 && threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __hip_atomic_store(ts.blk + BI, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(ts.blk + BJ, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+__device__ bool team_wait_blocks(TeamState& ts, int BI, int BJ, int step, int* s_flag) {
+    if (ts.W == 1) return true;  // this workgroup stored them itself (release waited for the stores)
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        if (lane == 0) *s_flag = 0;
+        int it = 0;
+        for (;;) {
+            const int f = lane == 0 ? ld_team(ts.blk + BI) : lane == 1 ? ld_team(ts.blk + BJ) : step;
+            if (__all(f >= step)) break;
+            if (++it > ts.spin_limit) {
+                if (lane == 0) {
+                    atomicOr(&ts.ctrl->status, kStTimeout);
+                    *s_flag = 1;
+                }
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
     return *s_flag == 0;
 }
 
@@ -770,9 +814,12 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
         int rot = 0, big = 0;
         ++executed;
         for (int s = 0; s < nb - 1; ++s) {
+            const bool last = (s == nb - 2);
             for (int q = rank; q < nb / 2; q += ts.W) {
                 int BI, BJ;
                 rr_pair(s, q, nb, BI, BJ);
+                // the first step of a sweep follows a full team barrier (or reads the source)
+                if (s > 0 && !team_wait_blocks(ts, BI, BJ, ts.steps, s_flag)) return false;
                 const bool first = (sw == 0 && s == 0);
                 const int ci = BI * b + grp;  // this group's I column
                 const int cs = ci < p ? ci : 0;
@@ -859,16 +906,18 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                 }
                 team_store_block<T, R, G, WV>(J, k, BJ, Js);
                 // the LDS blocks are reloaded next by this loop or after the team barrier,
-                // which begins with a workgroup barrier
-                if (q + ts.W < nb / 2) __syncthreads();
+                // and both the release and the team barrier begin with a workgroup barrier
+                if (!last) team_release_blocks(ts, BI, BJ, ts.steps + 1);
+                else if (q + ts.W < nb / 2) __syncthreads();
             }
-            if (s == nb - 2) {
+            ts.steps += 1;
+            if (last) {
                 const int tot = block_sum_groups(rot, gl, s_scratch);
                 const int btot = block_sum_groups(big, gl, s_scratch);
                 if (tid == 0 && tot) atomicAdd(rot_g + sw, tot);
                 if (tid == 0 && btot) atomicAdd(rot_g + kMaxSweeps + sw, btot);
+                if (!team_barrier(ts, s_flag)) return false;
             }
-            if (!team_barrier(ts, s_flag)) return false;
         }
         if (f64) break;
         const int total = __hip_atomic_load(rot_g + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1051,7 +1100,7 @@ __device__ bool team_task_k2(const JacobiJob& J, int k, int rank, TeamState& ts,
 // left over on an XCD without a full team exits.  Teams are numbered across
 // XCDs and take slices t, t + nteams, ...  ctl layout (ints, zeroed before the
 // launch): [0, 16) slot counter per XCD, [16] arrivals, [32 + W i + r] barrier
-// flag of rank r in team i.
+// flag of rank r in team i, [32 + nwg + nb i + x] flag of block x in team i.
 template <typename T, bool WV, int R, int G, int K>
 __global__ __launch_bounds__(512) void k_jacobi_team(JacobiJob J1, int ntasks, TeamSched sched, int max_sweeps,
                                                      Ctrl* ctrl, int spin_limit) {
@@ -1091,7 +1140,7 @@ __global__ __launch_bounds__(512) void k_jacobi_team(JacobiJob J1, int ntasks, T
     __syncthreads();
     const int team = s_team, rank = s_rank, nteams = s_nteams;
     if (team < 0) return;
-    TeamState ts{ctl + 32 + team * W, 0, W, spin_limit, ctrl, rank};
+    TeamState ts{ctl + 32 + team * W, 0, W, spin_limit, ctrl, rank, ctl + 32 + gridDim.x + team * J1.nb, 0};
     for (int t = team; t < ntasks; t += nteams) {
         if constexpr (K == 2) {
             static_assert(!WV, "two columns per group: no V");
@@ -1133,7 +1182,7 @@ __global__ __launch_bounds__(512) void k_jacobi_batched(const JacobiJob* __restr
         if (J.nb == 0) {
             resident_task<T, R, G, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch, s_nrm);
         } else {
-            TeamState ts{nullptr, 0, 1, 0, ctrl, 0};
+            TeamState ts{nullptr, 0, 1, 0, ctrl, 0, nullptr, 0};
             (void)team_task<T, R, G, WV>(J, k, 0, ts, max_sweeps, lds, &s_scratch, &s_flag, s_nrm, s_nrm + 64);
         }
         __syncthreads();
