@@ -444,7 +444,7 @@ std::vector<Tile> tile_candidates(const Plan& P, bool batched) {
             for (int K : {1, 2}) {
                 if (K == 2 && P.with_v) continue;
                 t.K = K;
-                for (int W : {1, 2, 3, 4, 6, 8}) {
+                for (int W : {1, 2, 3, 4, 6, 8, 12, 16}) {
                     t.W = W;
                     out.push_back(t);
                 }
