@@ -25,13 +25,15 @@ def case(shape, seed):
 
 
 # (shape, group widths, team sizes, group columns): resident slices, team
-# slices with both group widths and one or two columns per group, and a wide
-# tensor whose 300-row slices need 32-lane groups
+# slices with both group widths and one or two columns per group, a wide
+# tensor whose 300-row slices need 32-lane groups, and large teams
 FORCED = [
     ((64, 48, 9), (16, 32), (0,), (1,)),
     ((256, 200, 3), (16, 32), (1, 2, 3, 4), (1, 2)),
     ((130, 300, 2), (32,), (1, 2, 4), (1, 2)),
     ((257, 190, 2), (32,), (1, 3, 8), (2,)),
+    # teams of 12 and 16 workgroups: 4-column blocks, 32 of them, handed over point to point
+    ((300, 128, 2), (32,), (12, 16), (1,)),
 ]
 
 
