@@ -136,3 +136,42 @@ def test_tsvt_full_size_sampled_slices(tm):
     for k in (0, 7, 30):
         want = oracle.tsvt_dct(Zb[:, :, k:k + 1], tau)[:, :, 0]
         assert rel(Yb[:, :, k], want) <= TOL64, k
+
+
+def degenerate_tensor(kind, shape, seed):
+    """Frontal slices all equal to one matrix M, so the transformed tensor has
+    sqrt(n3) M as slice 0 and exact zeros elsewhere.  kind: 'zero' (M = 0),
+    'repeated' (singular values 3, 3, 3, 1, 1, 1) or 'equal_columns' (every
+    column of M the same vector: pairs of equal norm and cosine 1)."""
+    n1, n2, n3 = shape
+    g = synth.rng(seed)
+    if kind == "zero":
+        M = np.zeros((n1, n2))
+    elif kind == "repeated":
+        q1, _ = np.linalg.qr(synth.gaussian(g, (n1, 6)))
+        q2, _ = np.linalg.qr(synth.gaussian(g, (n2, 6)))
+        M = q1 @ np.diag([3.0, 3.0, 3.0, 1.0, 1.0, 1.0]) @ q2.T
+    else:
+        M = np.outer(synth.gaussian(g, (n1,)), np.ones(n2)) / np.sqrt(n2)
+    return np.asfortranarray(np.repeat(M[:, :, None], n3, axis=2))
+
+
+# resident slices and team slices; tau between the two repeated groups (scaled
+# by sqrt(n3)), and below the single singular value of the equal-columns case
+@pytest.mark.parametrize("shape", [(24, 16, 3), (260, 200, 2)])
+@pytest.mark.parametrize("kind", ["zero", "repeated", "equal_columns"])
+@pytest.mark.parametrize("prec", [0, 2])
+def test_tsvt_degenerate_spectra(tm, shape, kind, prec):
+    announce("tsvt_degenerate", shape=shape, kind=kind, prec=prec)
+    Z = degenerate_tensor(kind, shape, 31 + shape[0])
+    tau = 2.0 * np.sqrt(shape[2])
+    Yo, ro, _ = oracle.tsvt_dct(Z, tau, return_ranks=True)
+    dt = torch.float64 if prec == 0 else torch.float32
+    Y, ranks = tm.tsvt_dct(to_dev(Z, dt), tau, prec=prec, return_ranks=True)
+    Yg = to_np(Y)
+    assert np.isfinite(Yg).all()
+    assert list(ranks) == [int(x) for x in ro]
+    if kind == "zero":
+        assert float(np.abs(Yg).max()) == 0.0
+    else:
+        assert rel(Yg, Yo) <= (TOL64 if prec == 0 else 1e-4)
