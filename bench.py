@@ -76,7 +76,7 @@ def run_completion(tm, torch, case, prec, steps, warmup, profile, warm_period=-1
     if warmup > 0:
         tm.complete_tensor(B, mask, max_iter=warmup, tol=0.0, tau_schedule=taus, prec=prec, ctx=ctx)
     torch.cuda.synchronize()
-    ctx.set_option(tm.OPT_PROFILE, 1 if profile else 0)
+    ctx.set_option(tm.OPT_PROFILE, int(profile))  # 0 off, 1 every phase, 2 Jacobi launches only
     ctx.stats(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -311,7 +311,8 @@ def main():
     precs = {"fp64": tm.FP64, "fp32": tm.FP32, "mixed": tm.MIXED}
     results = {}
     for name in paths:
-        r = run_completion(tm, torch, case, precs[name], args.steps, args.warmup, profile=True,
+        # events around the Jacobi launches only (each event pair costs a few us of GPU time)
+        r = run_completion(tm, torch, case, precs[name], args.steps, args.warmup, profile=2,
                            warm_period=args.warm_period)
         results[name] = r
         log("%s: %.3f s for %d steps (%.3f ms/step), jacobi %.3f ms/launch, slice-sweeps %d" % (
@@ -319,6 +320,10 @@ def main():
             r["stats"]["ms"]["jacobi"] / max(1, r["stats"]["launches"]["jacobi"]), r["stats"]["slice_sweeps"]))
     head = paths[0]
     r = results[head]
+    # the phase split comes from a second run of the same workload with events around every phase
+    ph = run_completion(tm, torch, case, precs[head], args.steps, args.warmup, profile=1,
+                        warm_period=args.warm_period)
+    log("%s with events around every phase: %.3f ms/step" % (head, 1e3 * ph["seconds"] / args.steps))
     # the same run replayed as a captured HIP graph (no per-kernel events)
     g = run_completion(tm, torch, case, precs[head], args.steps, 0, profile=False, warm_period=args.warm_period)
     log("%s graph replay: %.3f ms/step" % (head, 1e3 * g["seconds"] / args.steps))
@@ -342,8 +347,9 @@ def main():
                                "tau 10->0.1 over 100 iterations, path=%s" % head,
                    "n1": N1, "n2": N2, "n3": N3, "rank": RANK, "observed": SR, "iterations": args.steps},
         "roofline": jacobi_roofline(r, head),
-        "dct_roofline": dct_roofline(r, head),
-        "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in r["stats"]["ms"].items()},
+        "dct_roofline": dct_roofline(ph, head),
+        "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in ph["stats"]["ms"].items()},
+        "phase_run_ms_per_step": round(1e3 * ph["seconds"] / args.steps, 4),
         "graph_replay_ms_per_step": round(1e3 * g["seconds"] / args.steps, 4),
         "jacobi_start": ("warm: V of the previous iteration, reset every %d iterations" % (
             64 if args.warm_period < 0 else args.warm_period)) if args.warm_period != 0 else "cold",

@@ -78,7 +78,9 @@ enum {
                                   kernel for slices too large for one workgroup's LDS */
     TSVD_OPT_SPIN_LIMIT = 3,   /* polls before a device wait gives up (test hook; default 2^24) */
     TSVD_OPT_PROFILE = 4,      /* 1: record HIP events around every kernel phase on the launch
-                                  stream (read with tsvd_get_stats); 0: off (default) */
+                                  stream (read with tsvd_get_stats); 2: only around the Jacobi
+                                  launches (phase 1; each event pair costs a few microseconds
+                                  of GPU time); 0: off (default) */
     TSVD_OPT_GRAPHS = 5,       /* 1: complete_tensor replays one captured iteration as a HIP graph
                                   (default; not while profiling); 0: direct launches */
     TSVD_OPT_AUTOTUNE = 6,     /* 1: choose Jacobi tiles by timing the candidates (default); 0: the

@@ -236,12 +236,14 @@ int read_status(tsvd_ctx* c, hipStream_t s, int* max_sweeps) {
     return TSVD_OK;
 }
 
-// Records an event pair around the launches of one phase when profiling.
+// Records an event pair around the launches of one phase when profiling: every
+// phase at level 1, only the Jacobi phase (1) at level 2.
 struct PhaseMark {
     tsvd_ctx* c;
     int ph;
     hipStream_t s;
     hipEvent_t a = nullptr;
+    bool on() const { return c->prof == 1 || (c->prof == 2 && ph == 1); }
     static hipEvent_t take(tsvd_ctx* c) {
         if (c->ev_used == c->ev_pool.size()) {
             hipEvent_t e;
@@ -251,10 +253,10 @@ struct PhaseMark {
         return c->ev_pool[c->ev_used++];
     }
     PhaseMark(tsvd_ctx* c_, int ph_, hipStream_t s_) : c(c_), ph(ph_), s(s_) {
-        if (c->prof && (a = take(c))) (void)hipEventRecord(a, s);
+        if (on() && (a = take(c))) (void)hipEventRecord(a, s);
     }
     ~PhaseMark() {
-        if (!c->prof || !a) return;
+        if (!on() || !a) return;
         hipEvent_t b = take(c);
         if (!b) return;
         (void)hipEventRecord(b, s);
@@ -917,7 +919,10 @@ int tsvd_set_option(tsvd_ctx* c, int opt, double v) {
             if (v < 1 || v > 1e9) return fail(c, TSVD_EINVAL, "spin limit out of range");
             c->spin_limit = (int)v;
             return TSVD_OK;
-        case TSVD_OPT_PROFILE: c->prof = v != 0.0; return TSVD_OK;
+        case TSVD_OPT_PROFILE:
+            if (v != 0.0 && v != 1.0 && v != 2.0) return fail(c, TSVD_EINVAL, "profile level is 0, 1 or 2");
+            c->prof = (int)v;
+            return TSVD_OK;
         case TSVD_OPT_GRAPHS: c->use_graphs = v != 0.0; return TSVD_OK;
         case TSVD_OPT_AUTOTUNE: c->autotune = v != 0.0; return TSVD_OK;
         case TSVD_OPT_GROUP_COLUMNS:
