@@ -165,3 +165,31 @@ def test_complete_graph_replays_match_direct_launches(tm, shape):
             ctx.close()
         assert outs[0][2] == outs[1][2] == L
         assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_profile_levels(tm):
+    # level 1 times every phase, level 2 the Jacobi launches only; results are unchanged
+    announce("profile_levels")
+    cc = small_case(L=4)
+    B, mk = to_dev(cc.B), to_dev(cc.mask, torch.uint8)
+    out = {}
+    for level in (0, 1, 2):
+        ctx = tm.Context(0)
+        ctx.set_option(tm.OPT_PROFILE, level)
+        ctx.stats(reset=True)
+        X, _ = tm.complete_tensor(B, mk, max_iter=4, tol=0.0, tau_schedule=cc.taus, ctx=ctx)
+        st = ctx.stats(reset=True)
+        out[level] = to_np(X)
+        if level == 0:
+            assert all(v == 0 for v in st["launches"].values())
+        elif level == 1:
+            assert st["launches"]["jacobi"] == 4 and st["launches"]["forward_transform"] == 4
+        else:
+            assert st["launches"]["jacobi"] == 4 and st["launches"]["forward_transform"] == 0
+            assert st["ms"]["jacobi"] > 0.0
+        ctx.close()
+    assert rel(out[1], out[0]) <= 1e-13 and rel(out[2], out[0]) <= 1e-13
+    ctx = tm.Context(0)
+    with pytest.raises(tm.TsvdError):
+        ctx.set_option(tm.OPT_PROFILE, 3)
+    ctx.close()
