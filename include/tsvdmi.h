@@ -85,8 +85,9 @@ enum {
                                   (default; not while profiling); 0: direct launches */
     TSVD_OPT_AUTOTUNE = 6,     /* 1: choose Jacobi tiles by timing the candidates (default); 0: the
                                   built-in heuristic.  See tsvd_get_tile. */
-    TSVD_OPT_GROUP_LANES = 7,  /* 0: automatic; 16 or 32: lanes per column-pair group in the Jacobi
-                                  kernels (a forced setting, like TEAM_SIZE, disables tuning) */
+    TSVD_OPT_GROUP_LANES = 7,  /* 0: automatic; 16, 32 or 64: lanes per column-pair group in the
+                                  Jacobi kernels (64: multi-workgroup kernel only, one column pair
+                                  per wavefront; a forced setting, like TEAM_SIZE, disables tuning) */
     TSVD_OPT_GROUP_COLUMNS = 8, /* 0: automatic; 1 or 2: columns each lane group of the multi-workgroup
                                   Jacobi kernel holds (2: two independent rotations at a time; not
                                   with V).  A forced setting disables tuning. */

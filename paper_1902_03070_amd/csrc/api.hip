@@ -319,6 +319,8 @@ int apply_tile(tsvd_ctx* c, Plan& P, const Tile& t, bool batched) {
     P.job.G = t.G;
     P.job.R = R;
     P.job.ldv = ldv;
+    if (t.G == 64 && (!t.team || batched || t.K == 2))
+        return fail(c, TSVD_EINVAL, "64-lane groups exist for the multi-workgroup Jacobi kernel only");
     if (!t.team) {
         const int rl = jacobi_resident_lds_bytes(P.prec, P.m, P.p, t.G, P.with_v);
         if (rl > kLdsBudget) return fail(c, TSVD_EINVAL, "slice does not fit in LDS");
@@ -376,7 +378,7 @@ int apply_tile(tsvd_ctx* c, Plan& P, const Tile& t, bool batched) {
     }
     P.K = 1;
     const int bstep = std::max(2, kWave / t.G);  // b G must fill whole wavefronts
-    const int bmax = kTeamMaxThreads / t.G;
+    const int bmax = (t.G == 64 ? kTeamMaxThreads64 : kTeamMaxThreads) / t.G;
     int W = std::max(1, t.W);
     int b = (P.p + 2 * W - 1) / (2 * W);
     b = (b + bstep - 1) / bstep * bstep;
@@ -451,6 +453,20 @@ std::vector<Tile> tile_candidates(const Plan& P, bool batched) {
                     out.push_back(t);
                 }
             }
+        }
+    }
+    // multi-workgroup slices also try one column pair per wavefront (64-lane
+    // groups, up to 1024 threads): twice the wavefronts per CU to hide the
+    // latency of each pair's chain, at up to 8 rows per lane
+    int R64, ldv64;
+    if (!batched && !out.empty() && out.back().team && !jacobi_geometry_g(P.m, P.p, 64, &R64, &ldv64) && R64 <= 8) {
+        Tile t;
+        t.G = 64;
+        t.team = 1;
+        t.K = 1;
+        for (int W : {2, 4, 8, 12, 16}) {
+            t.W = W;
+            out.push_back(t);
         }
     }
     return out;
@@ -934,7 +950,7 @@ int tsvd_set_option(tsvd_ctx* c, int opt, double v) {
             c->warm_start = (int)v;
             return TSVD_OK;
         case TSVD_OPT_GROUP_LANES:
-            if (v != 0 && v != 16 && v != 32) return fail(c, TSVD_EINVAL, "group lanes must be 0, 16 or 32");
+            if (v != 0 && v != 16 && v != 32 && v != 64) return fail(c, TSVD_EINVAL, "group lanes must be 0, 16, 32 or 64");
             c->group_lanes = (int)v;
             return TSVD_OK;
     }

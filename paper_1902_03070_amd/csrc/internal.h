@@ -15,6 +15,7 @@ constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kMaxEpl = 8;           // rows per lane in the Jacobi kernels: m <= 512
 constexpr int kMaxRows = kWave * kMaxEpl;
 constexpr int kTeamMaxThreads = 512;  // launch bound of the Jacobi team kernel
+constexpr int kTeamMaxThreads64 = 1024;  // ... with 64-lane groups (one column pair per wavefront)
 constexpr int kLdsPad = 16;            // extra elements per LDS column (spreads lane groups over banks)
 constexpr int kNormSlots = 16;       // slot pairs of the completion's change norms (256 bytes)
 constexpr int kLdsBudget = 160 * 1024 - 8 * 1024;  // dynamic LDS per workgroup (gfx950: 160 KB, minus static use)

@@ -65,16 +65,27 @@ __device__ __forceinline__ double pair_rows_sum(double v) {
     return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
 }
 
-// Sum over a group of G lanes (G = 16: one DPP row; G = 32: two rows).  Each
-// step adds a value to its mirror image, so every lane of the group ends with
-// the same bits.
+// Sum of the two 32-lane halves of the wavefront: v_permlane32_swap of a value
+// with itself leaves the lower half's value in one result and the upper
+// half's in the other, in every lane, so every lane adds them in one order.
+__device__ __forceinline__ double halves_sum(double v) {
+    const unsigned l = (unsigned)__double2loint(v), h = (unsigned)__double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane32_swap(l, l, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(h, h, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+
+// Sum over a group of G lanes (G = 16: one DPP row; G = 32: two rows; G = 64:
+// the wavefront).  Each step adds a value to its mirror image, so every lane
+// of the group ends with the same bits.
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
     v += dpp_d<0xB1>(v);
     v += dpp_d<0x4E>(v);
     v += dpp_d<0x141>(v);
     v += dpp_d<0x140>(v);
-    if (G == 32) v = pair_rows_sum(v);
+    if (G >= 32) v = pair_rows_sum(v);
+    if (G == 64) v = halves_sum(v);
     return v;
 }
 
@@ -91,9 +102,14 @@ __device__ __forceinline__ float group_sum_f(float v) {
     v += dpp_f<0x4E>(v);
     v += dpp_f<0x141>(v);
     v += dpp_f<0x140>(v);
-    if (G == 32) {
+    if (G >= 32) {
         const unsigned u = __float_as_uint(v);
         const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    }
+    if (G == 64) {
+        const unsigned u = __float_as_uint(v);
+        const auto a = __builtin_amdgcn_permlane32_swap(u, u, false, false);
         v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
     }
     return v;
@@ -1102,7 +1118,7 @@ __device__ bool team_task_k2(const JacobiJob& J, int k, int rank, TeamState& ts,
 // launch): [0, 16) slot counter per XCD, [16] arrivals, [32 + W i + r] barrier
 // flag of rank r in team i, [32 + nwg + nb i + x] flag of block x in team i.
 template <typename T, bool WV, int R, int G, int K>
-__global__ __launch_bounds__(512) void k_jacobi_team(JacobiJob J1, int ntasks, TeamSched sched, int max_sweeps,
+__global__ __launch_bounds__(G == 64 ? kTeamMaxThreads64 : kTeamMaxThreads) void k_jacobi_team(JacobiJob J1, int ntasks, TeamSched sched, int max_sweeps,
                                                      Ctrl* ctrl, int spin_limit) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_scratch, s_flag, s_team, s_rank, s_nteams;
@@ -1195,7 +1211,7 @@ __global__ __launch_bounds__(512) void k_jacobi_batched(const JacobiJob* __restr
 static int elem_size(int prec) { return prec == 0 ? 8 : 4; }
 
 int jacobi_geometry_g(int m, int p, int G, int* R, int* ldv) {
-    if (G != 16 && G != 32) return -1;
+    if (G != 16 && G != 32 && G != 64) return -1;
     int r = (m + G - 1) / G;
     r = (r + 3) / 4 * 4;
     if (r < 4) r = 4;
@@ -1236,6 +1252,17 @@ static const void* team_fn_rg(int R, int G) {
             default: return (const void*)k_jacobi_team<T, WV, 16, 16, K>;
         }
     }
+    if (G == 64) {
+        if constexpr (K == 1) {
+            switch (R) {
+                case 4: return (const void*)k_jacobi_team<T, WV, 4, 64, 1>;
+                case 8: return (const void*)k_jacobi_team<T, WV, 8, 64, 1>;
+                case 12: return (const void*)k_jacobi_team<T, WV, 12, 64, 1>;
+                default: return (const void*)k_jacobi_team<T, WV, 16, 64, 1>;
+            }
+        }
+        return nullptr;  // two columns per group: 16- and 32-lane groups only
+    }
     switch (R) {
         case 4: return (const void*)k_jacobi_team<T, WV, 4, 32, K>;
         case 8: return (const void*)k_jacobi_team<T, WV, 8, 32, K>;
@@ -1273,6 +1300,7 @@ hipError_t launch_jacobi_team(int prec, const JacobiJob& job, int ntasks, const 
     if (ntasks <= 0) return hipSuccess;
     if (K == 2 && with_v) return hipErrorInvalidValue;
     const void* f = team_fn(prec, with_v, R, G, K);
+    if (!f) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
     TeamSched ts = ts_in;
@@ -1326,6 +1354,7 @@ int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v, i
     int nb = 0;
     if (K == 2 && with_v) return 0;
     const void* f = team_fn(prec, with_v, R, G, K);
+    if (!f) return 0;
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();  // do not leave a sticky error for the caller's runtime

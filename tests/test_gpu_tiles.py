@@ -34,6 +34,9 @@ FORCED = [
     ((257, 190, 2), (32,), (1, 3, 8), (2,)),
     # teams of 12 and 16 workgroups: 4-column blocks, 32 of them, handed over point to point
     ((300, 128, 2), (32,), (12, 16), (1,)),
+    # one column pair per wavefront (64-lane groups, up to 1024 threads)
+    ((256, 200, 3), (64,), (2, 4, 8), (1,)),
+    ((300, 128, 2), (64,), (3, 16), (1,)),
 ]
 
 
