@@ -640,6 +640,10 @@ int tune_tile(tsvd_ctx* c, const Plan& P, bool batched, Tile* out, double* us_ou
         seen.push_back(sig);
         const double us = time_tile(c, P, cands[i], batched, tb, o_src, o_A, o_V, o_cnt, cnt_bytes, o_jobs, o_tj, o_tk,
                                     ntasks, e0, e1);
+        if (getenv("TSVDMI_TUNE_LOG"))
+            fprintf(stderr, "tsvdmi tune prec %d m %d p %d n3 %lld v %d: team %d G %d W %d threads %d K %d: %.1f us\n",
+                    P.prec, P.m, P.p, (long long)P.n3, P.with_v, cands[i].team, cands[i].G, cands[i].W, Q.threads,
+                    cands[i].K, us);
         // a later candidate must be 2% faster to replace an earlier one, so that
         // near-ties resolve the same way from run to run
         if (us > 0.0 && (best_us < 0.0 || us < 0.98 * best_us)) {

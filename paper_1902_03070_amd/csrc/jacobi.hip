@@ -1365,6 +1365,22 @@ int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v, i
         (void)hipGetLastError();
         return 0;
     }
+    // Workgroups per CU by registers counted per SIMD: a workgroup of w
+    // wavefronts puts up to ceil(w/4) of them on one of the CU's 4 SIMDs, and a
+    // SIMD holds 512 / (VGPRs rounded to 8) wavefronts.  With 6 wavefronts of
+    // 149 VGPRs the occupancy query allows 2 workgroups per CU (12 of 12
+    // wavefronts), but only one fits the SIMDs, and a team whose members cannot
+    // all be resident would wait until its bounded spin gives up.
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, f) == hipSuccess && fa.numRegs > 0) {
+        const int vg = (fa.numRegs + 7) / 8 * 8;
+        const int per_simd = std::min(8, 512 / vg);
+        const int waves = (threads + kWave - 1) / kWave;
+        nb = std::min(nb, per_simd / ((waves + 3) / 4));
+    } else {
+        (void)hipGetLastError();
+        nb = std::min(nb, 1);
+    }
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

@@ -97,3 +97,24 @@ def test_batched_tiles_are_per_shape(tm):
         assert t["threads"] == 512
     ctx.close()
     ctx2.close()
+
+
+def test_team_residency_with_six_wavefront_workgroups(tm):
+    # 200 x 144 x 48 FP32 completion (V carried), forced 32-lane groups and teams
+    # of 6: 12-column blocks give 384-thread workgroups (6 wavefronts) whose
+    # registers allow one workgroup per CU, although the occupancy query allows
+    # two.  The launch must size the grid so that every team member is resident
+    # (otherwise a team waits until its bounded spin gives up).
+    announce("team_residency", shape=(200, 144, 48))
+    cc = synth.completion_case(oracle.tprod_dct, 200, 144, 48, 4, 0.5, 2, 812, tau0=1.0, tau1=0.5)
+    Xo, _, _, _ = oracle.complete(cc.B, cc.mask, cc.betas, cc.taus)
+    ctx = tm.Context(0)
+    ctx.set_option(tm.OPT_GROUP_LANES, 32)
+    ctx.set_option(tm.OPT_TEAM_SIZE, 6)
+    t = ctx.tile(1, 200, 144, 48, with_v=True)
+    assert t["threads"] == 384 and t["W"] == 6
+    X, info = tm.complete_tensor(to_dev(cc.B, torch.float32), to_dev(cc.mask, torch.uint8), max_iter=2, tol=0.0,
+                                 tau_schedule=cc.taus, prec=1, ctx=ctx)
+    ctx.close()
+    assert info["status"] == 0
+    assert rel(to_np(X), Xo) <= 1e-4
