@@ -116,7 +116,8 @@ int tsvd_sync_status(tsvd_ctx* ctx, void* stream, int* max_sweeps_out);
  * temporary buffer) and caches the fastest for the process; the class is
  * (precision, m, p, n3, with_v), or (precision, m, p, with_v) for batched
  * calls (batched != 0).  If the environment variable TSVDMI_TILE_CACHE names
- * a file, tuned tiles are read from and appended to it.  No tuning happens
+ * a file, tuned tiles are read from and appended to it; if TSVDMI_TUNE_LOG is
+ * set, every candidate's time (or -1 when it failed) goes to stderr.  No tuning happens
  * while `stream` of a call is being captured.  Results of different tiles
  * agree to the precision's tolerance, not bitwise.
  * out[6]: team (0 resident, 1 team), G, W (0 when resident), workgroup size,
