@@ -411,7 +411,11 @@ std::vector<int> group_widths(int m, int p) {
         int R, ldv;
         if (!jacobi_geometry_g(m, p, G, &R, &ldv)) best = std::min(best, R * G);
     }
-    for (int G : {16, 32}) {
+    // 32-lane groups first: the tuner keeps the first of two candidates within 2%
+    // of each other, and for the completion at 256 x 256 x 31 (FP64) the tuner's
+    // synthetic sweeps put 32-lane groups only 2.3% ahead where the real ones
+    // gain 4.6%
+    for (int G : {32, 16}) {
         int R, ldv;
         if (!jacobi_geometry_g(m, p, G, &R, &ldv) && R * G == best) out.push_back(G);
     }
