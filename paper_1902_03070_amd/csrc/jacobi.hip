@@ -16,10 +16,11 @@
 // On exit A holds T V (columns = sigma_j u_j); V is accumulated only when asked.
 //
 // Work decomposition.  A column pair is handled by a group of G lanes (G = 16
-// for m <= 256, 32 above), each lane holding R rows (rows l, l+G, ..., so LDS
-// accesses of a group are contiguous).  The three dot products are reduced
-// inside the group with DPP row operations (plus one lane swizzle for G = 32);
-// a wavefront therefore works on 64/G pairs at once.
+// or 32, chosen by the tuner; 64 in the team kernel), each lane holding R rows
+// (rows l, l+G, ..., so LDS accesses of a group are contiguous).  The dot
+// products are reduced inside the group with DPP row operations (plus one or
+// two lane swaps for G = 32, 64); a wavefront therefore works on 64/G pairs
+// at once.
 //
 //  * resident kernel: one workgroup per slice, the whole slice (and V) in LDS,
 //    circle-method round robin over all columns (p/2 disjoint pairs per round).
@@ -29,10 +30,12 @@
 //    block in LDS and, during the b cross rounds, each I column in the
 //    registers of its own lane group (only J columns move through LDS).  The
 //    first step of a sweep also orthogonalizes the pairs inside each block.
-//    Blocks go back to global memory after each step and the team meets at a
-//    barrier.  The grid is launched cooperatively, so every workgroup of a team
-//    is resident; the barrier's wait is bounded and reports a timeout instead
-//    of hanging.
+//    Blocks go back to global memory (the XCD's L2) after each step; within a
+//    sweep each block passes from its holder to the next one through a flag,
+//    and the sweep ends at a team barrier.  The grid is sized so that every
+//    workgroup of a team is resident (and launched cooperatively outside graph
+//    capture); every wait is bounded and reports a timeout instead of
+//    hanging.
 #include <algorithm>
 
 #include "internal.h"
