@@ -1,21 +1,26 @@
 #!/usr/bin/env python3
-"""Benchmark: t-SVT/s of TNN-C completion at 256 x 256 x 31 on one MI355X.
+"""Benchmark: t-SVT/s at 256 x 256 x 31 on one MI355X.
 
-One step = one iteration of Algorithm 1 (ADMM) on the multispectral-shaped
-workload: Z = X - M/beta, forward DCT along tubes, one-sided Jacobi SVD of all
-31 transformed slices, soft-threshold, rebuild, inverse DCT, X- and M-updates.
-Each step performs exactly one t-SVT, so steps/s = t-SVT/s.
-
-Workload (synthetic, seeded): tubal-rank-10 DCT t-product of N(0,1) factors
-256x10x31 and 10x256x31, min-max scaled to [0,1]; 30% of entries observed
-(Bernoulli mask); tau decays geometrically from 10 to 0.1 over the 100
-iterations of the run, beta_l = 1/tau_l.  Inputs are resident in HBM before
-timing starts; the library's own t-product builds the tensor on the GPU.
+One step = one t-SVT (Theorem 5: forward DCT along tubes, one-sided Jacobi SVD
+of all 31 transformed slices, soft threshold, rebuild, inverse DCT) of an
+iterate of the multispectral-shaped completion workload.  The steps alternate
+between two fixed inputs, so the work per step does not depend on --steps:
+  * Z_0  = B (Algorithm 1's first iterate), tau = 10 (start of the schedule);
+  * Z_99 = X_99 - M_99 / beta_99, the input of the schedule's last iteration
+    (tau = 0.1), captured once, untimed, from a 99-iteration FP64 completion
+    on the GPU.
+Every SVD starts cold (no warm start).  Workload (synthetic, seeded):
+tubal-rank-10 DCT t-product of N(0,1) factors 256x10x31 and 10x256x31,
+min-max scaled to [0,1]; 30% of entries observed (Bernoulli mask); tau decays
+geometrically from 10 to 0.1 over 100 iterations, beta_l = 1/tau_l.  Inputs
+are resident in HBM before timing starts.
 
 `value` is the mixed-precision path (BF16 hi+lo transforms, FP32 Jacobi
-sweeps with FP64 angles, one FP64 sweep); the plain FP64 path is reported
-beside it.  Also reported: cold single t-SVT rates, the uneven 64-tensor batch
-and the serving stream (p50/p99 latency at a fixed request rate).
+sweeps with FP64 angles, one FP64 sweep); the plain FP64 path is timed the
+same way beside it.  Also reported: the whole 100-iteration completion in
+situ (warm-started SVDs), the video-shaped completion, the uneven 64-tensor
+batch, the serving stream (p50/p99 latency at fixed request rates), and the
+FP64 oracle on the host's threads (cpu_baseline).
 
 Prints one JSON line (progress goes to stderr).
 """
@@ -33,6 +38,9 @@ sys.path.insert(0, ROOT)
 
 N1, N2, N3, RANK, SR, L_FULL = 256, 256, 31, 10, 0.3, 100
 PEAK = {"fp64_alu": 78.6, "fp32_alu": 157.3, "hbm_GBs": 8000.0}
+WORKLOAD = ("isolated t-SVT (Theorem 5), 256x256x31, cold Jacobi SVDs, steps alternating between the first "
+            "(Z_0 = B, tau 10) and last (Z_99, tau 0.1) iterates of the tubal-rank-10, 30%-observed completion "
+            "workload (tau 10->0.1 over 100 iterations)")
 
 
 def log(*a):
@@ -42,15 +50,13 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="mixed,fp64")
-    ap.add_argument("--no-extras", action="store_true", help="skip cold t-SVT, batch and serving measurements")
+    ap.add_argument("--no-extras", action="store_true", help="skip completion, batch and serving measurements")
     ap.add_argument("--serving-requests", type=int, default=60)
     ap.add_argument("--serving-loads", default="0.5,0.8", help="fractions of the measured saturation throughput")
-    ap.add_argument("--warm-period", type=int, default=-1,
-                    help="completion warm start: -1 automatic, 0 cold starts, N: reset every N iterations")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (hardware-counter scale for profiling runs)")
     return ap.parse_args()
@@ -58,51 +64,38 @@ def parse():
 
 def gpu_tprod_factory(tm, torch):
     def gpu_tprod(F1, F2):
+        ctx = tm.Context(0)
         a = torch.from_numpy(np.asfortranarray(F1)).to("cuda:0")
         b = torch.from_numpy(np.asfortranarray(F2)).to("cuda:0")
-        z = tm.tprod_dct(a, b)
+        z = tm.tprod_dct(a, b, ctx=ctx)
         torch.cuda.synchronize()
-        return np.asfortranarray(z.cpu().numpy())
+        out = np.asfortranarray(z.cpu().numpy())
+        ctx.close()
+        return out
     return gpu_tprod
 
 
-def run_completion(tm, torch, case, prec, steps, warmup, profile, warm_period=-1):
-    dt = torch.float64 if prec == tm.FP64 else torch.float32
+def capture_last_iterate(tm, torch, case):
+    """Z_99 = X_99 - M_99 / beta_99: the t-SVT input of the schedule's last
+    iteration, from 99 FP64 iterations of Algorithm 1 on the GPU (untimed)."""
     ctx = tm.Context(0)
-    ctx.set_option(tm.OPT_WARM_START, warm_period)
-    B = torch.from_numpy(case.B).to(dt).to("cuda:0")
+    B = torch.from_numpy(case.B).to("cuda:0")
     mask = torch.from_numpy(case.mask).to("cuda:0")
-    taus = list(case.taus) + [case.taus[-1]] * max(0, steps + warmup + 1 - len(case.taus))
-    if warmup > 0:
-        tm.complete_tensor(B, mask, max_iter=warmup, tol=0.0, tau_schedule=taus, prec=prec, ctx=ctx)
-    torch.cuda.synchronize()
-    ctx.set_option(tm.OPT_PROFILE, int(profile))  # 0 off, 1 every phase, 2 Jacobi launches only
-    ctx.stats(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    X, info, M = tm.complete_tensor(B, mask, max_iter=steps, tol=0.0, tau_schedule=taus, prec=prec, ctx=ctx,
+    X, info, M = tm.complete_tensor(B, mask, max_iter=L_FULL - 1, tol=0.0, tau_schedule=list(case.taus), ctx=ctx,
                                     return_M=True)
+    Z = (X - M * float(case.taus[L_FULL - 1])).contiguous()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = ctx.stats(reset=True)
-    with_v = ctx.get_option(tm.OPT_WARM_START) != 0
-    tile = dict(ctx.tile(prec, N1, N2, N3, with_v=with_v), with_v=with_v)
-    Xn = X.detach().cpu().to(torch.float64).numpy()
-    # the next iteration's t-SVT input, Z = X - M / beta (Algorithm 1, first step)
-    beta = 1.0 / taus[steps]
-    Zn = (X - M / beta).detach().cpu().to(torch.float64).numpy()
     ctx.close()
-    return {"seconds": t1 - t0, "info": info, "stats": st, "X": Xn, "Z_next": Zn, "tau_next": taus[steps], "tile": tile}
+    return tm.fortran(Z.permute(2, 1, 0).contiguous().permute(2, 1, 0)), info
 
 
-def jacobi_roofline(res, prec_name):
-    st = res["stats"]
+def jacobi_roofline(st, prec_name, with_v, n3_total):
+    """Roofline of the Jacobi kernel from the device's slice-sweep count and the
+    HIP events around its launches.  One-sided Jacobi with tracked norms: per
+    column pair an inner product (2m flops) and the rotation of two length-m
+    columns (6m), plus the rotation of two length-p columns of V when V is
+    carried (6p); p(p-1)/2 pairs per sweep."""
     m, p = max(N1, N2), min(N1, N2)
-    # one-sided Jacobi, norms tracked: per column pair one inner product (2m
-    # flops) and the rotation of two length-m columns (6m flops), plus the
-    # rotation of the two length-p columns of V when the warm start carries V
-    # (6p); p(p-1)/2 pairs per sweep.  Units: slice-sweeps (counted on the device).
-    with_v = res["tile"].get("with_v", False)
     flops_per_slice_sweep = (8.0 * m + (6.0 * p if with_v else 0.0)) * p * (p - 1) / 2.0
     launches = max(1, st["launches"]["jacobi"])
     avg_ms = st["ms"]["jacobi"] / launches
@@ -110,15 +103,16 @@ def jacobi_roofline(res, prec_name):
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     peak = PEAK["fp64_alu"] if prec_name == "fp64" else PEAK["fp32_alu"]
     return {"kernel": "k_jacobi_team", "bound": "alu", "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic_for("jacobi", prec_name),
-            "avg_launch_ms": round(avg_ms, 4), "sweeps_per_slice": round(st["slice_sweeps"] / (launches * N3), 2),
-            "flops_per_launch": flops_per_launch}
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "traffic": traffic_for("jacobi_tsvt" if not with_v else "jacobi", prec_name),
+            "avg_launch_ms": round(avg_ms, 4), "launches": launches,
+            "slice_sweeps": st["slice_sweeps"], "sweeps_per_slice": round(st["slice_sweeps"] / (launches * n3_total), 3),
+            "flops_per_slice_sweep": flops_per_slice_sweep, "flops_per_launch": flops_per_launch}
 
 
-def dct_roofline(res, prec_name):
-    # forward transform with the completion prologue: reads X and M, writes
-    # Zbar (3 N n3 elements); algorithmic bytes per launch
-    st = res["stats"]
+def dct_roofline(st, prec_name, launches_per_step=1):
+    """Forward transform with the completion prologue: reads X and M, writes
+    Zbar (3 N n3 elements per launch, the algorithmic bytes)."""
     es = 8 if prec_name == "fp64" else 4
     launches = max(1, st["launches"]["forward_transform"])
     avg_ms = st["ms"]["forward_transform"] / launches
@@ -141,7 +135,7 @@ def kernel_source_md5():
 def traffic_for(kernel, prec_name):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken with the kernel sources that are built now; else None."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_completion_256x256x31.json")
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_bench_256x256x31.json")
     try:
         with open(path) as f:
             t = json.load(f)
@@ -153,20 +147,128 @@ def traffic_for(kernel, prec_name):
     return None
 
 
-def isolated_tsvt(tm, torch, Zh, tau, prec, reps=5):
-    """tsvt_dct calls one after another on one resident input."""
+def timed_tsvt(tm, torch, inputs, prec, steps, warmup):
+    """The timed loop: `steps` cold t-SVTs, step i on inputs[i % len(inputs)],
+    asynchronous calls on one stream with HIP events around the Jacobi
+    launches (the device status is checked after the loop)."""
     dt = torch.float64 if prec == tm.FP64 else torch.float32
-    Z = torch.from_numpy(np.asfortranarray(Zh)).to(dt).to("cuda:0")
+    Zs = [(Z.to(dt), float(tau)) for Z, tau in inputs]
+    Zs = [(tm.fortran(Z.permute(2, 1, 0).contiguous().permute(2, 1, 0)), tau) for Z, tau in Zs]
+    Ys = [tm.empty_f(N1, N2, N3, dt, "cuda:0") for _ in Zs]
     ctx = tm.Context(0)
-    tm.tsvt_dct(Z, float(tau), prec=prec, ctx=ctx)
+    for i in range(max(warmup, len(Zs))):  # the first calls tune the Jacobi tile
+        Z, tau = Zs[i % len(Zs)]
+        tm.tsvt_dct(Z, tau, Y=Ys[i % len(Zs)], prec=prec, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.set_option(tm.OPT_SYNC_STATUS, 0)
+    ctx.set_option(tm.OPT_PROFILE, 2)
+    ctx.stats(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(reps):
-        tm.tsvt_dct(Z, float(tau), prec=prec, ctx=ctx)
+    for i in range(steps):
+        Z, tau = Zs[i % len(Zs)]
+        tm.tsvt_dct(Z, tau, Y=Ys[i % len(Zs)], prec=prec, ctx=ctx)
     torch.cuda.synchronize()
-    dt_s = (time.perf_counter() - t0) / reps
+    t1 = time.perf_counter()
+    status, max_sweeps = ctx.sync_status()
+    st = ctx.stats(reset=True)
+    tile = ctx.tile(prec, N1, N2, N3)
+    # each input alone (per-input time, same context and tile)
+    ctx.set_option(tm.OPT_PROFILE, 0)
+    per = []
+    for Z, tau in Zs:
+        reps = 5
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            tm.tsvt_dct(Z, tau, Y=Ys[0], prec=prec, ctx=ctx)
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - a) / reps)
+    ctx.sync_status()
     ctx.close()
-    return {"t_svt_per_s": round(1.0 / dt_s, 2), "ms": round(1e3 * dt_s, 3)}
+    return {"seconds": t1 - t0, "stats": st, "status": status, "max_sweeps": max_sweeps, "tile": tile,
+            "per_input_ms": [round(1e3 * x, 4) for x in per]}
+
+
+def run_completion(tm, torch, case, prec, steps, warmup, profile, warm_period=-1):
+    """Algorithm 1 in situ: `steps` iterations of the schedule (after an untimed
+    warm-up run that tunes the tile), warm-started SVDs by default."""
+    dt = torch.float64 if prec == tm.FP64 else torch.float32
+    ctx = tm.Context(0)
+    ctx.set_option(tm.OPT_WARM_START, warm_period)
+    B = torch.from_numpy(case.B).to(dt).to("cuda:0")
+    mask = torch.from_numpy(case.mask).to("cuda:0")
+    taus = list(case.taus)
+    if warmup > 0:
+        tm.complete_tensor(B, mask, max_iter=warmup, tol=0.0, tau_schedule=taus, prec=prec, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.set_option(tm.OPT_PROFILE, int(profile))  # 0 off, 1 every phase, 2 Jacobi launches only
+    ctx.stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, info = tm.complete_tensor(B, mask, max_iter=steps, tol=0.0, tau_schedule=taus, prec=prec, ctx=ctx)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = ctx.stats(reset=True)
+    with_v = ctx.get_option(tm.OPT_WARM_START) != 0
+    tile = dict(ctx.tile(prec, N1, N2, N3, with_v=with_v), with_v=with_v)
+    Xn = X.detach().cpu().to(torch.float64).numpy()
+    ctx.close()
+    return {"seconds": t1 - t0, "info": info, "stats": st, "X": Xn, "tile": tile}
+
+
+def psnr(X, T):
+    """Peak signal-to-noise ratio in dB of X against the ground truth T in [0, 1]."""
+    mse = float(np.mean((np.clip(X, 0.0, 1.0) - T) ** 2))
+    return float("inf") if mse == 0.0 else 10.0 * np.log10(1.0 / mse)
+
+
+def completion_in_situ(tm, torch, case):
+    out = {}
+    for name, prec in (("mixed", tm.MIXED), ("fp64", tm.FP64)):
+        r = run_completion(tm, torch, case, prec, L_FULL, 3, profile=2)
+        ph = run_completion(tm, torch, case, prec, L_FULL, 0, profile=1) if name == "mixed" else None
+        X = r["X"]
+        out[name] = {
+            "t_svt_per_s": round(L_FULL / r["seconds"], 2), "ms_per_iteration": round(1e3 * r["seconds"] / L_FULL, 4),
+            "jacobi_roofline": jacobi_roofline(r["stats"], name, True, N3),
+            "recovery_rel_err": float(np.linalg.norm(X - case.T) / np.linalg.norm(case.T)),
+            "psnr_db": round(psnr(X, case.T), 3), "status": r["info"]["status"],
+            "max_sweeps": r["info"]["max_sweeps"], "jacobi_tile": r["tile"], "X": X}
+        if ph is not None:
+            out[name]["phase_ms_per_iteration"] = {k: round(v / L_FULL, 4) for k, v in ph["stats"]["ms"].items()}
+            out[name]["dct_roofline"] = dct_roofline(ph["stats"], name)
+        log("completion %s: %.3f ms/iteration" % (name, 1e3 * r["seconds"] / L_FULL))
+    out["mixed"]["rel_err_vs_fp64_gpu"] = float(np.linalg.norm(out["mixed"]["X"] - out["fp64"]["X"]) /
+                                                 np.linalg.norm(out["fp64"]["X"]))
+    for v in out.values():
+        v.pop("X")
+    out["iterations"] = L_FULL
+    out["warm_start"] = "V of the previous iteration, reset every 64 iterations"
+    return out
+
+
+def beta_sweep(tm, torch, case):
+    """Parameter study of Algorithm 1's fixed penalty beta (tau = 1/beta), at
+    the paper's experimental settings otherwise (at most 500 iterations,
+    tolerance 1e-8): recovery error and PSNR against beta, MIXED path."""
+    rows = []
+    B = torch.from_numpy(case.B).float().to("cuda:0")
+    mask = torch.from_numpy(case.mask).to("cuda:0")
+    ctx = tm.Context(0)
+    for beta in (1e-3, 3e-3, 1e-2, 3e-2, 1e-1, 3e-1):
+        t0 = time.perf_counter()
+        X, info = tm.complete_tensor(B, mask, max_iter=500, tol=1e-8, beta=beta, check_every=10, prec=tm.MIXED,
+                                     ctx=ctx)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        Xh = X.detach().cpu().double().numpy()
+        rows.append({"beta": beta, "iters": info["iters"], "seconds": round(sec, 3),
+                     "recovery_rel_err": float(np.linalg.norm(Xh - case.T) / np.linalg.norm(case.T)),
+                     "psnr_db": round(psnr(Xh, case.T), 3)})
+        log("beta sweep:", rows[-1])
+    ctx.close()
+    return rows
 
 
 def batched(tm, torch, tprod):
@@ -179,16 +281,34 @@ def batched(tm, torch, tprod):
                   .float().to("cuda:0"))
         taus.append(s.tau)
     ctx = tm.Context(0)
-    tm.tsvt_dct_batched(Zs, taus, prec=tm.FP32, ctx=ctx)  # warm
+    tm.tsvt_dct_batched(Zs, taus, prec=tm.FP32, ctx=ctx)  # warm (tunes the batched tiles)
     torch.cuda.synchronize()
+    ctx.set_option(tm.OPT_PROFILE, 1)
+    ctx.stats(reset=True)
     t0 = time.perf_counter()
-    tm.tsvt_dct_batched(Zs, taus, prec=tm.FP32, ctx=ctx)
+    _, status = tm.tsvt_dct_batched(Zs, taus, prec=tm.FP32, ctx=ctx, return_status=True)
     torch.cuda.synchronize()
     dt_s = time.perf_counter() - t0
+    st = ctx.stats(reset=True)
     ctx.close()
+    # algorithmic Jacobi flops of the batch: per slice-sweep 8 m p(p-1)/2, summed
+    # over the batch with each tensor's executed sweeps unknown individually;
+    # the device counts slice-sweeps in total, so use the mean per slice-sweep
     slices = sum(s.n3 for s in shapes)
+    f_mean = sum(8.0 * max(s.n1, s.n2) * min(s.n1, s.n2) * (min(s.n1, s.n2) - 1) / 2.0 * s.n3
+                 for s in shapes) / slices
+    jac_ms = st["ms"]["jacobi"]
+    flops = f_mean * st["slice_sweeps"]
     return {"tensors": len(shapes), "slices": slices, "makespan_ms": round(1e3 * dt_s, 2),
-            "t_svt_per_s": round(len(shapes) / dt_s, 2), "dtype": "f32",
+            "t_svt_per_s": round(len(shapes) / dt_s, 2), "dtype": "f32", "statuses_ok": all(v == 0 for v in status),
+            "phase_ms": {k: round(v, 3) for k, v in st["ms"].items()},
+            "jacobi_roofline": {"bound": "alu", "slice_sweeps": st["slice_sweeps"],
+                                "sweeps_per_slice": round(st["slice_sweeps"] / slices, 3),
+                                "achieved": round(flops / (jac_ms * 1e-3) / 1e12, 3) if jac_ms > 0 else None,
+                                "peak": PEAK["fp32_alu"], "unit": "TFLOP/s",
+                                "frac": round(flops / (jac_ms * 1e-3) / 1e12 / PEAK["fp32_alu"], 4) if jac_ms > 0
+                                else None,
+                                "note": "flops from the slice-weighted mean per slice-sweep"},
             "recipe": "n1,n2 ~ U{32..512}, n3 ~ U{8..128}, rank min(n1,n2)/10, t-product + N(0,0.01)"}
 
 
@@ -271,7 +391,7 @@ def video_shaped(tm, torch, tprod, steps):
     cc = synth.completion_case(tprod, 144, 176, 100, 15, 0.2, 100, synth.SEED_BASE + 3)
     out = {}
     for name, prec in (("mixed", tm.MIXED), ("fp64", tm.FP64)):
-        r = run_completion(tm, torch, cc, prec, steps, 2, profile=False)
+        r = run_completion(tm, torch, cc, prec, steps, 2, profile=0)
         out[name] = r
     X64, Xm = out["fp64"]["X"], out["mixed"]["X"]
     return {"shape": [144, 176, 100], "rank": 15, "observed": 0.2, "iterations": steps,
@@ -281,16 +401,33 @@ def video_shaped(tm, torch, tprod, steps):
             "recovery_rel_err_mixed": float(np.linalg.norm(Xm - cc.T) / np.linalg.norm(cc.T))}
 
 
-def cpu_baseline(case):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(inputs):
+    """The FP64 oracle, as it stands, on the host's threads (frontal slices split
+    over threads; per-slice arithmetic unchanged): one t-SVT of each input."""
     import oracle
 
     oracle.build(force=False)
+    T = min(16, oracle.host_threads())
+    oracle.set_threads(T)
     t0 = time.perf_counter()
-    oracle.tsvt_dct(case.B, float(case.taus[0]))
+    for Zh, tau in inputs:
+        oracle.tsvt_dct(Zh, float(tau))
     dt = time.perf_counter() - t0
-    return {"value": round(1.0 / dt, 5), "unit": "t-SVT/s", "cores": 1, "kind": "oracle",
-            "sample": "one FP64 oracle t-SVT of the first completion iterate (Z = B, tau = 10) at 256x256x31, "
-                      "single thread, %.1f s" % dt}
+    return {"value": round(len(inputs) / dt, 5), "unit": "t-SVT/s", "cores": T, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": "one FP64 oracle t-SVT of each of Z_0 (tau 10) and Z_99 (tau 0.1) at 256x256x31 on %d host "
+                      "threads, %.1f s" % (T, dt)}
 
 
 def main():
@@ -307,29 +444,22 @@ def main():
     assert torch.cuda.is_available(), "needs a ROCm GPU"
     tprod = gpu_tprod_factory(tm, torch)
     case = synth.completion_case(tprod, N1, N2, N3, RANK, SR, L_FULL, synth.SEED_BASE + 2)
+    Z0 = tm.fortran(torch.from_numpy(case.B).to("cuda:0"))
+    Z99, cap = capture_last_iterate(tm, torch, case)
+    inputs = [(Z0, case.taus[0]), (Z99, case.taus[L_FULL - 1])]
+    log("captured Z_99 (FP64, %d iterations, status %d)" % (cap["iters"], cap["status"]))
     paths = args.paths.split(",")
     precs = {"fp64": tm.FP64, "fp32": tm.FP32, "mixed": tm.MIXED}
     results = {}
     for name in paths:
-        # events around the Jacobi launches only (each event pair costs a few us of GPU time)
-        r = run_completion(tm, torch, case, precs[name], args.steps, args.warmup, profile=2,
-                           warm_period=args.warm_period)
+        r = timed_tsvt(tm, torch, inputs, precs[name], args.steps, args.warmup)
         results[name] = r
-        log("%s: %.3f s for %d steps (%.3f ms/step), jacobi %.3f ms/launch, slice-sweeps %d" % (
+        log("%s: %.4f s for %d steps (%.4f ms/step), jacobi %.4f ms/launch, slice-sweeps %d, status %d" % (
             name, r["seconds"], args.steps, 1e3 * r["seconds"] / args.steps,
-            r["stats"]["ms"]["jacobi"] / max(1, r["stats"]["launches"]["jacobi"]), r["stats"]["slice_sweeps"]))
+            r["stats"]["ms"]["jacobi"] / max(1, r["stats"]["launches"]["jacobi"]), r["stats"]["slice_sweeps"],
+            r["status"]))
     head = paths[0]
     r = results[head]
-    # the phase split comes from a second run of the same workload with events around every phase
-    ph = run_completion(tm, torch, case, precs[head], args.steps, args.warmup, profile=1,
-                        warm_period=args.warm_period)
-    log("%s with events around every phase: %.3f ms/step" % (head, 1e3 * ph["seconds"] / args.steps))
-    # the same run replayed as a captured HIP graph (no per-kernel events)
-    g = run_completion(tm, torch, case, precs[head], args.steps, 0, profile=False, warm_period=args.warm_period)
-    log("%s graph replay: %.3f ms/step" % (head, 1e3 * g["seconds"] / args.steps))
-    # the same completion with every Jacobi SVD started cold, for comparison
-    cold = run_completion(tm, torch, case, precs[head], args.steps, 1, profile=False, warm_period=0)
-    log("%s cold-start SVDs: %.3f ms/step" % (head, 1e3 * cold["seconds"] / args.steps))
     out = {
         "metric": "t-SVT/s at 256x256x31 (mixed vs plain FP64) + p50/p99 latency at fixed QPS",
         "value": round(args.steps / r["seconds"], 3),
@@ -343,45 +473,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if head != "fp64" else "f64",
         "data": "synthetic",
-        "config": {"workload": "TNN-C completion (Algorithm 1), 256x256x31, tubal rank 10, 30%% observed, "
-                               "tau 10->0.1 over 100 iterations, path=%s" % head,
-                   "n1": N1, "n2": N2, "n3": N3, "rank": RANK, "observed": SR, "iterations": args.steps},
-        "roofline": jacobi_roofline(r, head),
-        "dct_roofline": dct_roofline(ph, head),
-        "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in ph["stats"]["ms"].items()},
-        "phase_run_ms_per_step": round(1e3 * ph["seconds"] / args.steps, 4),
-        "graph_replay_ms_per_step": round(1e3 * g["seconds"] / args.steps, 4),
-        "jacobi_start": ("warm: V of the previous iteration, reset every %d iterations" % (
-            64 if args.warm_period < 0 else args.warm_period)) if args.warm_period != 0 else "cold",
-        "cold_start_t_svt_per_s": round(args.steps / cold["seconds"], 3),
+        "config": {"workload": WORKLOAD + ", path=%s" % head, "n1": N1, "n2": N2, "n3": N3, "rank": RANK,
+                   "observed": SR, "taus": [float(case.taus[0]), float(case.taus[L_FULL - 1])]},
+        "roofline": jacobi_roofline(r["stats"], head, False, N3),
     }
-    T = case.T
     for name, rr in results.items():
         out.setdefault("paths", {})[name] = {
             "t_svt_per_s": round(args.steps / rr["seconds"], 3),
             "ms_per_step": round(1e3 * rr["seconds"] / args.steps, 4),
-            "jacobi_roofline": jacobi_roofline(rr, name),
-            "recovery_rel_err": float(np.linalg.norm(rr["X"] - T) / np.linalg.norm(T)),
-            "status": rr["info"]["status"], "max_sweeps": rr["info"]["max_sweeps"], "jacobi_tile": rr["tile"],
-        }
+            "per_input_ms": {"Z_0": rr["per_input_ms"][0], "Z_99": rr["per_input_ms"][1]},
+            "jacobi_roofline": jacobi_roofline(rr["stats"], name, False, N3),
+            "status": rr["status"], "max_sweeps": rr["max_sweeps"], "jacobi_tile": rr["tile"]}
     if "fp64" in results and head != "fp64":
-        X64 = results["fp64"]["X"]
-        out["paths"][head]["rel_err_vs_fp64_gpu"] = float(np.linalg.norm(r["X"] - X64) / np.linalg.norm(X64))
         out["speedup_vs_fp64"] = round(results["fp64"]["seconds"] / r["seconds"], 3)
     if not args.no_extras:
-        # isolated t-SVTs on the first iterate (Z = B, tau = 10) and on the
-        # iterate after the timed run (tau at its end), each path on its own iterate
-        iso = {}
-        for name in paths:
-            iso[name] = {"first_iterate": isolated_tsvt(tm, torch, case.B, case.taus[0], precs[name]),
-                         "last_iterate": isolated_tsvt(tm, torch, results[name]["Z_next"], results[name]["tau_next"],
-                                                       precs[name])}
-        out["isolated_tsvt"] = iso
-        log("isolated t-SVT:", iso)
+        out["completion_in_situ"] = completion_in_situ(tm, torch, case)
         out["video_shaped"] = video_shaped(tm, torch, tprod, 100)
         log("video-shaped:", out["video_shaped"])
         out["batched"] = batched(tm, torch, tprod)
         log("batched:", out["batched"])
+        out["beta_sweep"] = beta_sweep(tm, torch, case)
         out["serving"] = serving(tm, torch, tprod, args.serving_requests,
                                  [float(x) for x in args.serving_loads.split(",")])
         log("serving:", out["serving"])
@@ -391,7 +502,9 @@ def main():
         torch.cuda.synchronize()
         del a, b
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case)
+        host = [(np.asfortranarray(Z.detach().cpu().numpy()), tau) for Z, tau in inputs]
+        out["cpu_baseline"] = cpu_baseline(host)
+    tm.close_all()
     print(json.dumps(out), flush=True)
 
 

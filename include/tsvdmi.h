@@ -60,7 +60,8 @@ enum {
     TSVD_EHIP = -3,        /* a HIP runtime call failed (see tsvd_last_error) */
     TSVD_ENONFINITE = -4,  /* the input holds a NaN or an infinity */
     TSVD_EBUSY = -5,       /* admission refused: request exceeds the memory budget */
-    TSVD_ETIMEOUT = -6     /* a bounded device wait or a host deadline expired */
+    TSVD_ETIMEOUT = -6,    /* a bounded device wait or a host deadline expired */
+    TSVD_ECANCELED = -7    /* a serving request was cancelled */
 };
 
 /* Context.  `device` is a HIP device ordinal.  Returns TSVD_OK and sets *ctx. */
@@ -171,8 +172,10 @@ int tsvt_dct(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const 
 /* Algorithm 1 (ADMM for TNN-C completion).
  *   B    : observed data (only entries with mask != 0 are read).
  *   mask : DEVICE uint8 array, N = n1*n2*n3 entries, nonzero = observed.
- *   X    : in = initial iterate (normally B on the observed set, 0 elsewhere),
- *          out = the recovered tensor.
+ *   X    : in = initial iterate, out = the recovered tensor.  With
+ *          opts->init_observed = 1 the input contents are ignored and the
+ *          library starts from Algorithm 1's initial iterate, B on the
+ *          observed set and 0 elsewhere (formed on the device).
  * Iteration l of the call uses beta_l = opts->beta, or
  * 1/opts->tau_schedule[start_iter + l] when a schedule is given, in Z = X - M/beta_l, in
  * the X-update and in the multiplier update, and thresholds at
@@ -181,7 +184,10 @@ int tsvt_dct(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const 
  * iterations; tol <= 0 disables the test).  M_init (DEVICE, may be NULL for
  * zero) and M_out (DEVICE, may be NULL) carry the multiplier for warm starts.
  * The whole iteration runs on the device and is replayed as a captured HIP
- * graph; the call synchronizes. */
+ * graph; the call synchronizes.  Every iteration checks its input
+ * Z = X - M/beta_l for NaN and infinity: the call then returns
+ * TSVD_ENONFINITE.  Any max_iter > 0 is accepted (the device keeps the last
+ * 4096 relative changes in a ring). */
 typedef struct {
     int max_iter;               /* L (> 0) */
     double tol;                 /* stopping tolerance on the relative change */
@@ -192,6 +198,7 @@ typedef struct {
     int start_iter;             /* schedule offset for warm starts; 0 normally */
     const void* M_init;
     void* M_out;
+    int init_observed;          /* 1: start from X = B on the observed set, 0 elsewhere */
 } tsvd_complete_opts;
 typedef struct {
     int iters;         /* iterations run */
@@ -211,9 +218,15 @@ int complete_tensor(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3,
  * HOST array of thresholds.  A tensor's tile depends only on its own shape
  * and each task is done by one workgroup, so its result is bitwise the same
  * as in a batched call holding it alone; it agrees with tsvt_dct on it to the
- * precision's tolerance (tsvt_dct may use a multi-workgroup team). */
+ * precision's tolerance (tsvt_dct may use a multi-workgroup team).
+ * status_out: NULL, or a HOST array of `count` codes.  When given, the call
+ * synchronizes and writes every tensor's own status (TSVD_OK,
+ * TSVD_WARN_NOCONV, TSVD_ENONFINITE or TSVD_ETIMEOUT), so that one bad
+ * tensor does not mark the others; the return value then reports only
+ * argument and launch errors.  When NULL, the statuses of all tensors are
+ * accumulated as for any asynchronous call. */
 int tsvt_dct_batched(tsvd_ctx* ctx, int prec, int count, const int64_t* dims, const void* const* Z,
-                     void* const* Y, const double* tau, void* stream);
+                     void* const* Y, const double* tau, int32_t* status_out, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Serving: a host thread that admits t-SVT and completion requests by device
@@ -232,6 +245,8 @@ typedef struct {
     double tau;            /* t-SVT threshold */
     int iters;             /* completion: iterations, tau decays geometrically tau0 -> tau1 */
     double tau0, tau1;
+    double deadline_s;     /* > 0: the request ends with TSVD_ETIMEOUT unless done this many seconds
+                              after submit (checked between ticks); <= 0: no deadline */
 } tsvd_request;
 /* budget_bytes: device memory the server may hold for admitted requests;
  * max_active: most requests advanced per tick.  With FP32 or MIXED data a
@@ -239,12 +254,21 @@ typedef struct {
  * iteration's right singular vectors, kept on the device, following the
  * context's TSVD_OPT_WARM_START (read at creation). */
 int tsvd_server_create(tsvd_server** srv, tsvd_ctx* ctx, int prec, int64_t budget_bytes, int max_active);
-/* Copies the request; returns a request id > 0, or TSVD_EBUSY when it can never
- * fit the budget, or another negative error. */
+/* Copies the request; returns a request id > 0, TSVD_EBUSY when it can never
+ * fit the budget, or TSVD_EINVAL for bad sizes or parameters or a shape the
+ * batched kernels cannot hold (frontal slices above 512 rows or columns).
+ * Admission is first in, first out: a queued request is never overtaken. */
 int64_t tsvd_server_submit(tsvd_server* srv, const tsvd_request* req);
-/* Non-blocking poll. Returns 1 and fills `out` (HOST, n1*n2*n3 floats) and the
- * times (seconds on the server's steady clock) when request `id` is done, 0 if
- * not yet, negative on error or unknown id. */
+/* Cancels request `id`: a queued one ends at once, a running one before its
+ * next step; either then polls as TSVD_ECANCELED.  Returns 0, 1 if it had
+ * already ended, or TSVD_EINVAL for an unknown id. */
+int tsvd_server_cancel(tsvd_server* srv, int64_t id);
+/* Non-blocking poll.  When request `id` is done, fills `out` (HOST, n1*n2*n3
+ * floats) and the times (seconds on the server's steady clock) and returns 1
+ * (2 when one of its Jacobi SVDs hit the sweep limit); 0 if not done yet; its
+ * negative status if it failed (only that request: TSVD_ENONFINITE,
+ * TSVD_ETIMEOUT, TSVD_ECANCELED, ...), or TSVD_EINVAL for an unknown id.  A
+ * done request is forgotten after it is polled. */
 int tsvd_server_poll(tsvd_server* srv, int64_t id, float* out, double* t_submit, double* t_admit, double* t_done);
 /* Server clock now (seconds). */
 double tsvd_server_now(tsvd_server* srv);

@@ -6,6 +6,8 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 """
 from .oracle import (  # noqa: F401
     build,
+    set_threads,
+    host_threads,
     dct_matrix,
     dct_tubes,
     idct_tubes,

@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
     os.makedirs(_OUT_DIR, exist_ok=True)
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fPIC", "-shared", "-pthread", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -40,6 +40,8 @@ def _load():
     build(force=False)
     lib = C.CDLL(_LIB)
     lib.or_dct_matrix.argtypes = [C.c_int, _dp]
+    lib.or_set_threads.argtypes = [C.c_int]
+    lib.or_get_threads.restype = C.c_int
     for name in ("or_dct_tubes", "or_idct_tubes", "or_split_shift", "or_bt", "or_bh", "or_btph",
                  "or_unfold", "or_fold"):
         getattr(lib, name).argtypes = [_i64, _i64, _i64, _dp, _dp]
@@ -77,6 +79,23 @@ def _as3(a) -> np.ndarray:
 
 
 MAX_SWEEPS = 100
+
+
+def set_threads(n: int) -> int:
+    """Split independent work (slices, tubes) over n host threads; results
+    are bitwise the same for every n.  Returns the previous count."""
+    lib = _load()
+    old = lib.or_get_threads()
+    lib.or_set_threads(int(n))
+    return old
+
+
+def host_threads() -> int:
+    """Threads this process may run on (its CPU affinity)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
 
 
 def dct_matrix(n: int) -> np.ndarray:

@@ -19,11 +19,46 @@
  *     reordering beyond the textbook definitions cited at each function.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define X3(i, j, k, n1, n2) ((int64_t)(i) + (int64_t)(n1) * ((int64_t)(j) + (int64_t)(n2) * (int64_t)(k)))
+
+/* ------------------------------------------------------------------------- */
+/* Host threads.  Work that is independent by construction (the frontal      */
+/* slices of the transform domain, the lateral index of the tube transforms) */
+/* may be split over or_set_threads(T) POSIX threads in contiguous chunks.   */
+/* Each item's arithmetic is exactly the single-threaded one, so results are */
+/* bitwise identical for every T.  Default: 1 thread.                         */
+/* ------------------------------------------------------------------------- */
+static int g_threads = 1;
+void or_set_threads(int t) { g_threads = t < 1 ? 1 : (t > 256 ? 256 : t); }
+int or_get_threads(void) { return g_threads; }
+
+typedef void (*range_fn)(void* ctx, int64_t begin, int64_t end);
+struct range_job { range_fn fn; void* ctx; int64_t begin, end; };
+static void* range_run(void* a) {
+    struct range_job* j = (struct range_job*)a;
+    j->fn(j->ctx, j->begin, j->end);
+    return NULL;
+}
+/* fn(ctx, b, e) over [0, n) split into min(T, n) contiguous chunks. */
+static void parallel_for(int64_t n, range_fn fn, void* ctx) {
+    int T = g_threads;
+    if (T > n) T = (int)n;
+    if (T <= 1) { if (n > 0) fn(ctx, 0, n); return; }
+    pthread_t th[256];
+    struct range_job jobs[256];
+    for (int t = 0; t < T; ++t) {
+        jobs[t].fn = fn; jobs[t].ctx = ctx;
+        jobs[t].begin = n * t / T; jobs[t].end = n * (t + 1) / T;
+    }
+    for (int t = 1; t < T; ++t) pthread_create(&th[t], NULL, range_run, &jobs[t]);
+    range_run(&jobs[0]);
+    for (int t = 1; t < T; ++t) pthread_join(th[t], NULL);
+}
 
 /* ------------------------------------------------------------------------- */
 /* Section 3: the cosine transform along tubes.                              */
@@ -39,17 +74,32 @@ void or_dct_matrix(int n, double* C) {
     }
 }
 
+/* Tube transform with a given n3 x n3 matrix M (row-major):
+ *   out(i,j,k) = sum_t M[k][t] in(i,j,t)   (trans = 0), or
+ *   out(i,j,t) = sum_k M[k][t] in(i,j,k)   (trans = 1, the product with M^T). */
+struct tube_ctx { int64_t n1, n2, n3; const double* M; const double* in; double* out; int trans; };
+static void tube_range(void* a, int64_t j0, int64_t j1) {
+    const struct tube_ctx* c = (const struct tube_ctx*)a;
+    const int64_t n1 = c->n1, n2 = c->n2, n3 = c->n3;
+    for (int64_t j = j0; j < j1; ++j)
+        for (int64_t i = 0; i < n1; ++i)
+            for (int64_t k = 0; k < n3; ++k) {
+                double acc = 0.0;
+                for (int64_t t = 0; t < n3; ++t)
+                    acc += (c->trans ? c->M[t * n3 + k] : c->M[k * n3 + t]) * c->in[X3(i, j, t, n1, n2)];
+                c->out[X3(i, j, k, n1, n2)] = acc;
+            }
+}
+static void tube_apply(int64_t n1, int64_t n2, int64_t n3, const double* M, int trans, const double* in, double* out) {
+    struct tube_ctx c = {n1, n2, n3, M, in, out, trans};
+    parallel_for(n2, tube_range, &c);
+}
+
 /* Xbar(:,:,k) = sum_t C[k][t] X(:,:,t)   (Section 3, Xbar = dct(X,[],3)). */
 void or_dct_tubes(int64_t n1, int64_t n2, int64_t n3, const double* X, double* Xbar) {
     double* C = (double*)malloc(sizeof(double) * n3 * n3);
     or_dct_matrix((int)n3, C);
-    for (int64_t j = 0; j < n2; ++j)
-        for (int64_t i = 0; i < n1; ++i)
-            for (int64_t k = 0; k < n3; ++k) {
-                double acc = 0.0;
-                for (int64_t t = 0; t < n3; ++t) acc += C[k * n3 + t] * X[X3(i, j, t, n1, n2)];
-                Xbar[X3(i, j, k, n1, n2)] = acc;
-            }
+    tube_apply(n1, n2, n3, C, 0, X, Xbar);
     free(C);
 }
 
@@ -57,13 +107,7 @@ void or_dct_tubes(int64_t n1, int64_t n2, int64_t n3, const double* X, double* X
 void or_idct_tubes(int64_t n1, int64_t n2, int64_t n3, const double* Xbar, double* X) {
     double* C = (double*)malloc(sizeof(double) * n3 * n3);
     or_dct_matrix((int)n3, C);
-    for (int64_t j = 0; j < n2; ++j)
-        for (int64_t i = 0; i < n1; ++i)
-            for (int64_t t = 0; t < n3; ++t) {
-                double acc = 0.0;
-                for (int64_t k = 0; k < n3; ++k) acc += C[k * n3 + t] * Xbar[X3(i, j, k, n1, n2)];
-                X[X3(i, j, t, n1, n2)] = acc;
-            }
+    tube_apply(n1, n2, n3, C, 1, Xbar, X);
     free(C);
 }
 
@@ -312,19 +356,34 @@ int or_jacobi_svd(int64_t m, int64_t n, const double* A, int64_t lda, double* U,
 /*   Ubar n1 x p x n3, Sbar p x n3 (column k = singular values of slice k),  */
 /*   Vbar n2 x p x n3.  Returns the largest sweep count, or -1.              */
 /* ------------------------------------------------------------------------- */
+/* The slice SVDs are independent: slices are split over the host threads. */
+struct svd_ctx { int64_t n1, n2, p; const double* Xb; double *U, *S, *V; int max_sweeps; int* sweeps; };
+static void svd_range(void* a, int64_t k0, int64_t k1) {
+    const struct svd_ctx* c = (const struct svd_ctx*)a;
+    for (int64_t k = k0; k < k1; ++k)
+        c->sweeps[k] = or_jacobi_svd(c->n1, c->n2, c->Xb + k * c->n1 * c->n2, c->n1, c->U ? c->U + k * c->n1 * c->p : NULL,
+                                     c->S + k * c->p, c->V ? c->V + k * c->n2 * c->p : NULL, c->max_sweeps);
+}
+static int worst_sweeps(const int* sw, int64_t n) {
+    int worst = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        if (sw[k] < 0) worst = -1;
+        else if (worst >= 0 && sw[k] > worst) worst = sw[k];
+    }
+    return worst;
+}
+
 int or_tsvd_dct(int64_t n1, int64_t n2, int64_t n3, const double* X, double* Ubar, double* Sbar, double* Vbar,
                 int max_sweeps) {
     int64_t p = n1 < n2 ? n1 : n2;
     double* Xb = (double*)malloc(sizeof(double) * n1 * n2 * n3);
+    int* sw = (int*)malloc(sizeof(int) * n3);
     or_dct_tubes(n1, n2, n3, X, Xb);
-    int worst = 0;
-    for (int64_t k = 0; k < n3; ++k) {
-        int sw = or_jacobi_svd(n1, n2, Xb + k * n1 * n2, n1, Ubar ? Ubar + k * n1 * p : NULL, Sbar + k * p,
-                               Vbar ? Vbar + k * n2 * p : NULL, max_sweeps);
-        if (sw < 0) worst = -1;
-        else if (worst >= 0 && sw > worst) worst = sw;
-    }
+    struct svd_ctx c = {n1, n2, p, Xb, Ubar, Sbar, Vbar, max_sweeps, sw};
+    parallel_for(n3, svd_range, &c);
+    int worst = worst_sweeps(sw, n3);
     free(Xb);
+    free(sw);
     return worst;
 }
 
@@ -334,36 +393,49 @@ int or_tsvd_dct(int64_t n1, int64_t n2, int64_t n3, const double* X, double* Uba
 /* Ubar Dbar Vbar^T; Y = idct.  ranks[k] = #{sigma > tau} (may be NULL).      */
 /* Returns the largest sweep count, or -1.                                    */
 /* ------------------------------------------------------------------------- */
-int or_tsvt_dct(int64_t n1, int64_t n2, int64_t n3, const double* Z, double tau, double* Y, int32_t* ranks,
-                int max_sweeps) {
-    int64_t p = n1 < n2 ? n1 : n2, s = n1 * n2;
-    double* Zb = (double*)malloc(sizeof(double) * s * n3);
-    double* Yb = (double*)malloc(sizeof(double) * s * n3);
+/* One transform-domain slice of the t-SVT: SVD, (sigma - tau)_+, rebuild. */
+static int svt_slice(int64_t n1, int64_t n2, const double* Zk, double tau, double* Yk, int32_t* rank, int max_sweeps) {
+    int64_t p = n1 < n2 ? n1 : n2;
     double* U = (double*)malloc(sizeof(double) * n1 * p);
     double* V = (double*)malloc(sizeof(double) * n2 * p);
     double* sv = (double*)malloc(sizeof(double) * p);
-    or_dct_tubes(n1, n2, n3, Z, Zb);
-    int worst = 0;
-    for (int64_t k = 0; k < n3; ++k) {
-        int sw = or_jacobi_svd(n1, n2, Zb + k * s, n1, U, sv, V, max_sweeps);
-        if (sw < 0) worst = -1;
-        else if (worst >= 0 && sw > worst) worst = sw;
-        int32_t r = 0;
-        for (int64_t c = 0; c < p; ++c) if (sv[c] > tau) ++r;
-        if (ranks) ranks[k] = r;
-        double* Ybk = Yb + k * s;
-        for (int64_t j = 0; j < n2; ++j)
-            for (int64_t i = 0; i < n1; ++i) {
-                double acc = 0.0;
-                for (int64_t c = 0; c < p; ++c) {
-                    double d = sv[c] - tau;
-                    if (d > 0.0) acc += U[i + n1 * c] * d * V[j + n2 * c];
-                }
-                Ybk[i + n1 * j] = acc;
+    int sw = or_jacobi_svd(n1, n2, Zk, n1, U, sv, V, max_sweeps);
+    int32_t r = 0;
+    for (int64_t c = 0; c < p; ++c) if (sv[c] > tau) ++r;
+    if (rank) *rank = r;
+    for (int64_t j = 0; j < n2; ++j)
+        for (int64_t i = 0; i < n1; ++i) {
+            double acc = 0.0;
+            for (int64_t c = 0; c < p; ++c) {
+                double d = sv[c] - tau;
+                if (d > 0.0) acc += U[i + n1 * c] * d * V[j + n2 * c];
             }
-    }
+            Yk[i + n1 * j] = acc;
+        }
+    free(U); free(V); free(sv);
+    return sw;
+}
+struct svt_ctx { int64_t n1, n2; const double* Zb; double* Yb; double tau; int32_t* ranks; int max_sweeps; int* sweeps; };
+static void svt_range(void* a, int64_t k0, int64_t k1) {
+    const struct svt_ctx* c = (const struct svt_ctx*)a;
+    const int64_t s = c->n1 * c->n2;
+    for (int64_t k = k0; k < k1; ++k)
+        c->sweeps[k] = svt_slice(c->n1, c->n2, c->Zb + k * s, c->tau, c->Yb + k * s, c->ranks ? c->ranks + k : NULL,
+                                 c->max_sweeps);
+}
+
+int or_tsvt_dct(int64_t n1, int64_t n2, int64_t n3, const double* Z, double tau, double* Y, int32_t* ranks,
+                int max_sweeps) {
+    int64_t s = n1 * n2;
+    double* Zb = (double*)malloc(sizeof(double) * s * n3);
+    double* Yb = (double*)malloc(sizeof(double) * s * n3);
+    int* sw = (int*)malloc(sizeof(int) * n3);
+    or_dct_tubes(n1, n2, n3, Z, Zb);
+    struct svt_ctx c = {n1, n2, Zb, Yb, tau, ranks, max_sweeps, sw};
+    parallel_for(n3, svt_range, &c);
+    int worst = worst_sweeps(sw, n3);
     or_idct_tubes(n1, n2, n3, Yb, Y);
-    free(Zb); free(Yb); free(U); free(V); free(sv);
+    free(Zb); free(Yb); free(sw);
     return worst;
 }
 

@@ -8,8 +8,10 @@ module raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
 from typing import Optional, Sequence
 
 import torch
@@ -18,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtsvdmi.so")
 
 FP64, FP32, MIXED = 0, 1, 2
-OK, WARN_NOCONV, EINVAL, ENOMEM, EHIP, ENONFINITE, EBUSY, ETIMEOUT = 0, 1, -1, -2, -3, -4, -5, -6
+OK, WARN_NOCONV, EINVAL, ENOMEM, EHIP, ENONFINITE, EBUSY, ETIMEOUT, ECANCELED = 0, 1, -1, -2, -3, -4, -5, -6, -7
 OPT_MAX_SWEEPS, OPT_SYNC_STATUS, OPT_TEAM_SIZE, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_GRAPHS = 0, 1, 2, 3, 4, 5
 OPT_AUTOTUNE, OPT_GROUP_LANES, OPT_GROUP_COLUMNS, OPT_WARM_START = 6, 7, 8, 9
 PHASES = ("forward_transform", "jacobi", "threshold_rebuild", "inverse_transform", "warm_start")
@@ -29,7 +31,8 @@ EXPORTED = [
     "tsvd_create", "tsvd_destroy", "tsvd_last_error", "tsvd_set_option", "tsvd_get_option", "tsvd_sync_status",
     "tsvd_get_stats", "tsvd_get_tile",
     "tprod_dct", "tsvd_dct", "tsvt_dct", "complete_tensor", "tsvt_dct_batched", "tsvd_server_create",
-    "tsvd_server_submit", "tsvd_server_poll", "tsvd_server_now", "tsvd_server_stats", "tsvd_server_destroy",
+    "tsvd_server_submit", "tsvd_server_cancel", "tsvd_server_poll", "tsvd_server_now", "tsvd_server_stats",
+    "tsvd_server_destroy",
 ]
 
 if not os.path.exists(LIB_PATH):
@@ -43,7 +46,7 @@ _vp, _i64, _i32, _d = C.c_void_p, C.c_int64, C.c_int, C.c_double
 class CompleteOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("tol", C.c_double), ("beta", C.c_double),
                 ("tau_schedule", C.POINTER(C.c_double)), ("check_every", C.c_int), ("start_iter", C.c_int),
-                ("M_init", C.c_void_p), ("M_out", C.c_void_p)]
+                ("M_init", C.c_void_p), ("M_out", C.c_void_p), ("init_observed", C.c_int)]
 
 
 class CompleteInfo(C.Structure):
@@ -57,7 +60,7 @@ class Stats(C.Structure):
 class Request(C.Structure):
     _fields_ = [("kind", C.c_int), ("n1", C.c_int64), ("n2", C.c_int64), ("n3", C.c_int64),
                 ("input", C.POINTER(C.c_float)), ("mask", C.POINTER(C.c_uint8)), ("tau", C.c_double),
-                ("iters", C.c_int), ("tau0", C.c_double), ("tau1", C.c_double)]
+                ("iters", C.c_int), ("tau0", C.c_double), ("tau1", C.c_double), ("deadline_s", C.c_double)]
 
 
 lib.tsvd_create.argtypes = [C.POINTER(_vp), _i32]
@@ -77,10 +80,11 @@ lib.tsvt_dct.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _d, C.POINTER(C.
 lib.complete_tensor.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _vp, C.POINTER(CompleteOpts),
                                 C.POINTER(CompleteInfo), _vp]
 lib.tsvt_dct_batched.argtypes = [_vp, _i32, _i32, C.POINTER(C.c_int64), C.POINTER(_vp), C.POINTER(_vp),
-                                 C.POINTER(C.c_double), _vp]
+                                 C.POINTER(C.c_double), C.POINTER(C.c_int32), _vp]
 lib.tsvd_server_create.argtypes = [C.POINTER(_vp), _vp, _i32, _i64, _i32]
 lib.tsvd_server_submit.argtypes = [_vp, C.POINTER(Request)]
 lib.tsvd_server_submit.restype = _i64
+lib.tsvd_server_cancel.argtypes = [_vp, _i64]
 lib.tsvd_server_poll.argtypes = [_vp, _i64, C.POINTER(C.c_float), C.POINTER(_d), C.POINTER(_d), C.POINTER(_d)]
 lib.tsvd_server_now.argtypes = [_vp]
 lib.tsvd_server_now.restype = _d
@@ -105,6 +109,7 @@ class Context:
             raise TsvdError(rc, "tsvd_create(%d) failed" % device)
         self.h = h
         self.device = device
+        _register(self)
 
     def close(self):
         if self.h:
@@ -112,6 +117,11 @@ class Context:
             self.h = None
 
     def __del__(self):
+        # no HIP call while the interpreter shuts down: contexts still open
+        # then were closed by the exit hook below, before the runtime's own
+        # teardown; anything left is reclaimed by the process exit
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -148,12 +158,39 @@ class Context:
 
 
 _contexts = {}
+_open = []  # weak references to every context and server, closed at exit
 
 
 def default_context(device: int = 0) -> Context:
     if device not in _contexts:
         _contexts[device] = Context(device)
     return _contexts[device]
+
+
+def _register(obj):
+    import weakref
+
+    _open[:] = [r for r in _open if r() is not None]
+    _open.append(weakref.ref(obj))
+
+
+def close_all():
+    """Close every server and context this process opened (servers first).
+
+    Runs at interpreter exit, before module teardown, so that no device object
+    of the library outlives the HIP runtime or a profiler attached to it."""
+    objs = [r() for r in _open]
+    for o in objs:
+        if isinstance(o, Server):
+            o.close()
+    for o in objs:
+        if isinstance(o, Context):
+            o.close()
+    _open.clear()
+    _contexts.clear()
+
+
+atexit.register(close_all)
 
 
 def _stream(stream, device):
@@ -258,8 +295,9 @@ def complete_tensor(B: torch.Tensor, mask: torch.Tensor, X: Optional[torch.Tenso
     ctx = ctx or default_context(d)
     n1, n2, n3 = B.shape
     mask = fortran(mask.to(torch.uint8))
+    init_observed = X is None  # the library forms Algorithm 1's initial iterate B on the observed set
     if X is None:
-        X = fortran(torch.where(mask != 0, B, torch.zeros_like(B)))
+        X = empty_f(n1, n2, n3, B.dtype, B.device)
     else:
         X = fortran(X.clone())
     M_out = empty_f(n1, n2, n3, B.dtype, B.device) if return_M else None
@@ -271,7 +309,7 @@ def complete_tensor(B: torch.Tensor, mask: torch.Tensor, X: Optional[torch.Tenso
     opts = CompleteOpts(max_iter, float(tol), float(beta),
                         C.cast(sched, C.POINTER(C.c_double)) if sched is not None else None, check_every,
                         start_iter, fortran(M_init).data_ptr() if M_init is not None else None,
-                        M_out.data_ptr() if M_out is not None else None)
+                        M_out.data_ptr() if M_out is not None else None, int(init_observed))
     info = CompleteInfo()
     rc = lib.complete_tensor(ctx.h, prec, n1, n2, n3, B.data_ptr(), mask.data_ptr(), X.data_ptr(),
                              C.byref(opts), C.byref(info), _stream(stream, d))
@@ -284,8 +322,10 @@ def complete_tensor(B: torch.Tensor, mask: torch.Tensor, X: Optional[torch.Tenso
 
 
 def tsvt_dct_batched(Zs: Sequence[torch.Tensor], taus: Sequence[float], Ys: Optional[Sequence[torch.Tensor]] = None,
-                     prec: Optional[int] = None, ctx: Optional[Context] = None, stream=None):
-    """Batched t-SVT of tensors of independent shapes.  Returns the list of Y."""
+                     prec: Optional[int] = None, ctx: Optional[Context] = None, stream=None,
+                     return_status: bool = False):
+    """Batched t-SVT of tensors of independent shapes.  Returns the list of Y
+    (and, with return_status, each tensor's own status code)."""
     Zs = [fortran(z) for z in Zs]
     d = _dev(Zs[0])
     prec = _prec_of(Zs[0], prec)
@@ -297,7 +337,10 @@ def tsvt_dct_batched(Zs: Sequence[torch.Tensor], taus: Sequence[float], Ys: Opti
     zp = (_vp * count)(*[z.data_ptr() for z in Zs])
     yp = (_vp * count)(*[y.data_ptr() for y in Ys])
     tp = (C.c_double * count)(*[float(t) for t in taus])
-    ctx.check(lib.tsvt_dct_batched(ctx.h, prec, count, dims, zp, yp, tp, _stream(stream, d)))
+    st = (C.c_int32 * count)() if return_status else None
+    ctx.check(lib.tsvt_dct_batched(ctx.h, prec, count, dims, zp, yp, tp, st, _stream(stream, d)))
+    if return_status:
+        return list(Ys), [int(v) for v in st]
     return list(Ys)
 
 
@@ -319,6 +362,7 @@ class Server:
             raise TsvdError(rc, "tsvd_server_create failed")
         self.h = h
         self.shapes = {}
+        _register(self)
 
     @staticmethod
     def _host(a):
@@ -333,24 +377,34 @@ class Server:
         self.shapes[rid] = shape
         return rid
 
-    def submit_tsvt(self, Z, tau: float) -> int:
+    def submit_tsvt(self, Z, tau: float, deadline_s: float = 0.0) -> int:
         Z = self._host(Z)
         n1, n2, n3 = Z.shape
-        req = Request(REQ_TSVT, n1, n2, n3, Z.ctypes.data_as(C.POINTER(C.c_float)), None, float(tau), 0, 0.0, 0.0)
+        req = Request(REQ_TSVT, n1, n2, n3, Z.ctypes.data_as(C.POINTER(C.c_float)), None, float(tau), 0, 0.0, 0.0,
+                      float(deadline_s))
         return self._submit(req, Z.shape)
 
-    def submit_complete(self, B, mask, iters: int, tau0: float, tau1: float) -> int:
+    def submit_complete(self, B, mask, iters: int, tau0: float, tau1: float, deadline_s: float = 0.0) -> int:
         import numpy as np
 
         B = self._host(B)
         mk = np.asfortranarray(np.asarray(mask, dtype=np.uint8))
         n1, n2, n3 = B.shape
         req = Request(REQ_COMPLETE, n1, n2, n3, B.ctypes.data_as(C.POINTER(C.c_float)),
-                      mk.ctypes.data_as(C.POINTER(C.c_uint8)), 0.0, int(iters), float(tau0), float(tau1))
+                      mk.ctypes.data_as(C.POINTER(C.c_uint8)), 0.0, int(iters), float(tau0), float(tau1),
+                      float(deadline_s))
         return self._submit(req, B.shape)
 
+    def cancel(self, rid: int) -> int:
+        """0 if cancelled (polls as ECANCELED), 1 if it had already ended."""
+        rc = lib.tsvd_server_cancel(self.h, rid)
+        if rc < 0:
+            raise TsvdError(rc, "cancel of request %d failed" % rid)
+        return rc
+
     def poll(self, rid: int):
-        """None while running; else (result array, (t_submit, t_admit, t_done))."""
+        """None while running; else (result array, (t_submit, t_admit, t_done)).
+        A failed request raises TsvdError with its own code."""
         import numpy as np
 
         shape = self.shapes[rid]
@@ -382,6 +436,8 @@ class Server:
             self.ctx = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

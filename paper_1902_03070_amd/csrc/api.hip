@@ -194,7 +194,7 @@ struct Carve {
     }
 };
 
-constexpr int kHist = 4096;  // relative-change history slots in the control region
+constexpr int kHist = 4096;  // relative-change history ring (slot = iteration mod kHist) in the control region
 
 struct CtrlRegion {
     Ctrl* ctrl;
@@ -214,6 +214,15 @@ int ensure_ctrl(tsvd_ctx* c, CtrlRegion* r) {
     r->ctrl = (Ctrl*)b;
     r->norms = (double*)(b + 256);
     r->hist = (double*)(b + 512);
+    return TSVD_OK;
+}
+
+// Status code of a set of device status bits (non-finite input first, then a
+// timed-out wait, then a Jacobi SVD that hit the sweep limit).
+int status_code(int bits) {
+    if (bits & kStNonFinite) return TSVD_ENONFINITE;
+    if (bits & kStTimeout) return TSVD_ETIMEOUT;
+    if (bits & kStNoConv) return TSVD_WARN_NOCONV;
     return TSVD_OK;
 }
 
@@ -1237,6 +1246,10 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
     HIPCHK(c, hipStreamSynchronize(s));
     HIPCHK(c, hipMemcpy(base + oBeta, betas.data(), L * 8, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(base + oTau, taus.data(), L * 8, hipMemcpyHostToDevice));
+    if (o->init_observed) {
+        const hipError_t ei = launch_observed_init(prec == TSVD_FP64 ? 0 : 1, X, B, mask, P.N * n3, s);
+        if (ei != hipSuccess) return hip_fail(c, ei, "initial iterate");
+    }
     if (o->M_init) HIPCHK(c, hipMemcpyAsync(base + oM, o->M_init, P.N * n3 * es, hipMemcpyDeviceToDevice, s));
     else if (launch_fill_zero(base + oM, P.N * n3 * es, s) != hipSuccess) return fail(c, TSVD_EHIP, "fill M");
     // iteration counter, norms and history start at zero (status and statistics are kept)
@@ -1253,7 +1266,7 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
         hipError_t e = launch_fill_zero(base + P.o_ctr_begin, P.o_ctr_end - P.o_ctr_begin, st);
         if (e != hipSuccess) return hip_fail(c, e, "fill");
         TubeArgs f{};
-        f.out = base + P.o_zbar; f.M = C; f.N = P.N; f.n3 = (int)n3; f.ctrl = cr.ctrl;
+        f.out = base + P.o_zbar; f.M = C; f.N = P.N; f.n3 = (int)n3; f.ctrl = cr.ctrl; f.check_finite = 1;
         f.pX = X; f.pM = base + oM; f.beta_sched = (const double*)(base + oBeta);
         {
             PhaseMark pm(c, 0, st);
@@ -1320,7 +1333,7 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
         if (check && (iters % o->check_every == 0 || iters == L)) {
             if (hipStreamSynchronize(run) != hipSuccess) { rc = fail(c, TSVD_EHIP, "sync"); break; }
             double h = 0.0;
-            if (hipMemcpy(&h, cr.hist + (iters - 1), 8, hipMemcpyDeviceToHost) != hipSuccess) {
+            if (hipMemcpy(&h, cr.hist + (iters - 1) % kHist, 8, hipMemcpyDeviceToHost) != hipSuccess) {
                 rc = fail(c, TSVD_EHIP, "history read");
                 break;
             }
@@ -1332,7 +1345,7 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
     if (exec) (void)hipGraphExecDestroy(exec);
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(s));
-    if (iters >= 1 && iters <= kHist) HIPCHK(c, hipMemcpy(&last, cr.hist + (iters - 1), 8, hipMemcpyDeviceToHost));
+    if (iters >= 1) HIPCHK(c, hipMemcpy(&last, cr.hist + (iters - 1) % kHist, 8, hipMemcpyDeviceToHost));
     if (o->M_out) HIPCHK(c, hipMemcpyAsync(o->M_out, base + oM, P.N * n3 * es, hipMemcpyDeviceToDevice, s));
     int msw = 0;
     rc = read_status(c, s, &msw);
@@ -1346,7 +1359,7 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
 }
 
 int tsvt_dct_batched(tsvd_ctx* c, int prec, int count, const int64_t* dims, const void* const* Z, void* const* Y,
-                     const double* tau, void* stream) {
+                     const double* tau, int32_t* status_out, void* stream) {
     if (!c) return TSVD_EINVAL;
     std::lock_guard<std::mutex> lk(c->mu);
     if (bad_prec(prec)) return fail(c, TSVD_EINVAL, "unknown precision");
@@ -1362,7 +1375,14 @@ int tsvt_dct_batched(tsvd_ctx* c, int prec, int count, const int64_t* dims, cons
     }
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
-    int rc = batched_step_locked(c, prec, count, jb.data(), s);
+    if (status_out) {
+        // every tensor gets its own code; the call waits for the step
+        int rc = batched_step_locked(c, prec, count, jb.data(), status_out, s);
+        if (rc) return rc;
+        (void)read_status(c, s, nullptr);
+        return TSVD_OK;
+    }
+    int rc = batched_step_locked(c, prec, count, jb.data(), nullptr, s);
     if (rc) return rc;
     return finish_call(c, s);
 }
@@ -1371,7 +1391,7 @@ int tsvt_dct_batched(tsvd_ctx* c, int prec, int count, const int64_t* dims, cons
 
 // Batched step shared by tsvt_dct_batched and the serving loop.  Called with
 // the context lock held.
-int batched_step_locked(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb, hipStream_t s) {
+int batched_step_locked(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb, int* job_status, hipStream_t s) {
     std::vector<Plan> plans(count);
     Carve cv;
     int rc;
@@ -1389,10 +1409,12 @@ int batched_step_locked(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb
     const size_t o_jobs = cv.take(sizeof(JacobiJob) * count);
     const size_t o_tj = cv.take(sizeof(int) * ntasks), o_tk = cv.take(sizeof(int) * ntasks);
     const size_t o_queue = cv.take(512);  // one work counter per (V, row geometry) (16 x 32 bytes)
+    const size_t o_jctrl = cv.take((size_t)kJobCtrlBytes * count);  // each job's own status and counters
     if ((rc = ensure_ws(c, cv.off))) return rc;
     char* base = (char*)c->ws.p;
     CtrlRegion cr;
     if ((rc = ensure_ctrl(c, &cr))) return rc;
+    auto jctrl = [&](int j) { return (Ctrl*)(base + o_jctrl + (size_t)kJobCtrlBytes * j); };
     // job table; task lists grouped by row geometry (R, G), each sorted by
     // estimated cost (m p^2 per slice), largest first
     auto geo = [](const Plan& P) { return (P.with_v ? 8 : 0) + (P.job.G == 32 ? 4 : 0) + P.job.R / 4 - 1; };  // 0..15
@@ -1402,6 +1424,7 @@ int batched_step_locked(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb
     for (int j = 0; j < count; ++j) {
         Plan& P = plans[j];
         bind_plan(P, base);
+        P.job.ctrl = jctrl(j);
         if (P.with_v) {
             // the job's own V, kept across steps; a warm start reads A0 = Zbar V
             P.job.V = jb[j].V;
@@ -1437,12 +1460,14 @@ int batched_step_locked(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb
     HIPCHK(c, hipMemcpy(base + o_tk, tk.data(), sizeof(int) * ntasks, hipMemcpyHostToDevice));
     hipError_t e = launch_fill_zero(base + o_queue, 512, s);
     if (e != hipSuccess) return hip_fail(c, e, "fill");
+    if ((e = launch_fill_zero(base + o_jctrl, (int64_t)kJobCtrlBytes * count, s)) != hipSuccess)
+        return hip_fail(c, e, "fill");
     for (int j = 0; j < count; ++j) {
         Plan& P = plans[j];
         if ((e = launch_fill_zero(base + P.o_ctr_begin, P.o_ctr_end - P.o_ctr_begin, s)) != hipSuccess)
             return hip_fail(c, e, "fill");
         TubeArgs f{};
-        f.out = base + P.o_zbar; f.N = P.N; f.n3 = (int)P.n3; f.ctrl = cr.ctrl; f.check_finite = 1;
+        f.out = base + P.o_zbar; f.N = P.N; f.n3 = (int)P.n3; f.ctrl = jctrl(j); f.check_finite = 1;
         f.beta_val = jb[j].X ? jb[j].beta : 1.0;
         if (jb[j].X) { f.pX = jb[j].X; f.pM = jb[j].M; } else { f.in = jb[j].Z; }
         PhaseMark pm(c, 0, s);
@@ -1467,9 +1492,9 @@ int batched_step_locked(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb
     }
     for (int j = 0; j < count; ++j) {
         Plan& P = plans[j];
-        if ((rc = enqueue_after_jacobi(c, P, base, cr.ctrl, jb[j].tau, nullptr, s))) return rc;
+        if ((rc = enqueue_after_jacobi(c, P, base, jctrl(j), jb[j].tau, nullptr, s))) return rc;
         TubeArgs iv{};
-        iv.in = base + P.o_ybar; iv.N = P.N; iv.n3 = (int)P.n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
+        iv.in = base + P.o_ybar; iv.N = P.N; iv.n3 = (int)P.n3; iv.ctrl = jctrl(j); iv.beta_val = 1.0;
         if (jb[j].X) {
             iv.eB = jb[j].B; iv.emask = jb[j].mask; iv.eX = jb[j].X; iv.eM = jb[j].M; iv.beta_val = jb[j].beta;
         } else {
@@ -1478,15 +1503,44 @@ int batched_step_locked(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb
         PhaseMark pm(c, 3, s);
         if ((rc = run_tube(c, prec, iv, 1, s))) return rc;
     }
+    // the jobs' statuses and counters join the context's block (tsvd_sync_status, statistics)
+    if ((e = launch_fold_ctrl(cr.ctrl, jctrl(0), count, kJobCtrlBytes, s)) != hipSuccess) return hip_fail(c, e, "fold");
+    if (job_status) {
+        std::vector<Ctrl> h(count);
+        HIPCHK(c, hipStreamSynchronize(s));
+        HIPCHK(c, hipMemcpy2D(h.data(), sizeof(Ctrl), jctrl(0), kJobCtrlBytes, sizeof(Ctrl), count,
+                              hipMemcpyDeviceToHost));
+        for (int j = 0; j < count; ++j) job_status[j] = status_code(h[j].status);
+    }
     return TSVD_OK;
 }
 
-int tsvd_batched_step_sync(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb, hipStream_t s) {
+int tsvd_batched_step_sync(tsvd_ctx* c, int prec, int count, const BatchJobSpec* jb, int* job_status,
+                           hipStream_t s) {
     std::lock_guard<std::mutex> lk(c->mu);
     HIPCHK(c, hipSetDevice(c->device));
-    int rc = batched_step_locked(c, prec, count, jb, s);
+    int rc = batched_step_locked(c, prec, count, jb, job_status, s);
     if (rc) return rc;
-    return read_status(c, s, nullptr);
+    // per-job codes are in job_status; the context's accumulated status is cleared
+    rc = read_status(c, s, nullptr);
+    return rc < 0 && rc != TSVD_ENONFINITE && rc != TSVD_ETIMEOUT ? rc : TSVD_OK;
+}
+
+int tsvd_batched_shape_check(int prec, int64_t n1, int64_t n2, int with_v) {
+    if (n1 <= 0 || n2 <= 0 || std::max(n1, n2) > kMaxRows) return TSVD_EINVAL;
+    Plan P;
+    P.prec = prec;
+    P.n1 = n1; P.n2 = n2; P.n3 = 1; P.N = n1 * n2;
+    P.m = (int)std::max(n1, n2);
+    P.p = (int)std::min(n1, n2);
+    P.with_v = with_v ? 1 : 0;
+    // every candidate tile of a batched plan: one of them must hold the slice
+    for (const Tile& t : tile_candidates(P, true)) {
+        Plan Q = P;
+        if (apply_tile(nullptr, Q, t, true) == TSVD_OK) return TSVD_OK;
+    }
+    Plan Q = P;
+    return apply_tile(nullptr, Q, default_tile(P, 0, 0, 0, true), true) == TSVD_OK ? TSVD_OK : TSVD_EINVAL;
 }
 
 size_t tsvd_batched_workspace_bytes(int prec, int64_t n1, int64_t n2, int64_t n3) {
@@ -1495,7 +1549,7 @@ size_t tsvd_batched_workspace_bytes(int prec, int64_t n1, int64_t n2, int64_t n3
     const size_t m = (size_t)std::max(n1, n2), p = (size_t)std::min(n1, n2), N = (size_t)n1 * n2;
     // Zbar, Ybar; A', F, A0 (warm start); G, V (workspace copy); counters
     return es * (2 * N * n3 + 3 * m * p * n3 + 2 * p * p * n3) + 20 * p * n3 + 4 * n3 * (kRotStride + 3) + 32 * 256 +
-           sizeof(JacobiJob) + 8 * n3;
+           sizeof(JacobiJob) + 8 * n3 + kJobCtrlBytes;
 }
 
 int tsvd_ctx_device(const tsvd_ctx* c) { return c->device; }

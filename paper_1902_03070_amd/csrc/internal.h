@@ -55,6 +55,7 @@ struct JacobiJob {
     double tol;        // rotate a pair iff |x.y| > tol |x| |y| (precision dependent, set on the host)
     double skip2;      // a sweep whose pairs all have (x.y)^2 <= skip2 |x|^2 |y|^2 ends the iteration
                        // (the next sweep would rotate by angles far below tol: no check sweep)
+    Ctrl* ctrl;        // per-job status and counters (batched steps), or nullptr: the launch's block
 };
 
 struct TeamSched {
@@ -63,6 +64,7 @@ struct TeamSched {
     int* ctl;          // team formation and barrier counters, kTeamCtlInts + nwg (1 + nb) ints, zeroed
 };
 constexpr int kTeamCtlInts = 32;
+constexpr int kJobCtrlBytes = 256;  // per-job control block of a batched step (a Ctrl, padded)
 
 // ---- launch helpers (defined in the .hip files) -----------------------------
 // All return hipSuccess or the first HIP error.
@@ -180,6 +182,10 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
 // n values of a deterministic pseudo-random pattern in [-1, 1) (prec 0: double, else float).
 hipError_t launch_fill_pattern(void* p, int64_t n, int prec, uint32_t seed, hipStream_t s);
 hipError_t launch_iter_advance(Ctrl* ctrl, double* norms, double* relchg_hist, int hist_len, hipStream_t s);
+// X = mask ? B : 0 (n elements; prec 0: double, else float).
+hipError_t launch_observed_init(int prec, void* X, const void* B, const uint8_t* mask, int64_t n, hipStream_t s);
+// dst: status |= OR of the count per-job blocks (stride_bytes apart), max_sweeps = max, slice_sweeps += sum.
+hipError_t launch_fold_ctrl(Ctrl* dst, const Ctrl* jobs, int count, int stride_bytes, hipStream_t s);
 // V (p x p per slice, n3 slices) := identity when ctrl->iter % period == 0.
 hipError_t launch_warm_reset(int prec, void* V, int p, int n3, const Ctrl* ctrl, int period, hipStream_t s);
 // Sort singular values descending per slice and build U = A'(:,perm)/sigma, with the
@@ -200,10 +206,23 @@ hipError_t launch_tsvd_finish(int prec, const TsvdFinishArgs& a, hipStream_t s);
 
 // Internal entry points of the library used by the serving loop (C++ linkage).
 struct tsvd_ctx;
-int batched_step_locked(tsvd_ctx* c, int prec, int count, const tsvd::BatchJobSpec* jb, hipStream_t s);
-// Takes the context lock, runs one batched step on `s`, waits for it and
-// returns the device status (as tsvd_sync_status).
-int tsvd_batched_step_sync(tsvd_ctx* c, int prec, int count, const tsvd::BatchJobSpec* jb, hipStream_t s);
+// One batched step of `count` jobs, each with its own device status word.
+// job_status (HOST, count entries, may be NULL): when given, the call waits
+// for the step and writes each job's code (TSVD_OK, TSVD_WARN_NOCONV,
+// TSVD_ENONFINITE, TSVD_ETIMEOUT).  The jobs' statuses are also folded into
+// the context's accumulated status.
+int batched_step_locked(tsvd_ctx* c, int prec, int count, const tsvd::BatchJobSpec* jb, int* job_status,
+                        hipStream_t s);
+// Takes the context lock, runs one batched step on `s`, waits for it, writes
+// every job's own status to job_status and clears the context's accumulated
+// status.  Returns TSVD_OK, or a negative code when the step itself could not
+// run (its jobs then have no result).
+int tsvd_batched_step_sync(tsvd_ctx* c, int prec, int count, const tsvd::BatchJobSpec* jb, int* job_status,
+                           hipStream_t s);
+// 0 when a tensor of this shape can run in a batched step (frontal slices of
+// at most 512 rows and columns whose Jacobi block fits one workgroup's LDS),
+// else TSVD_EINVAL.  No device call.
+int tsvd_batched_shape_check(int prec, int64_t n1, int64_t n2, int with_v);
 // Bytes of workspace one batched step needs for a tensor of this shape.
 size_t tsvd_batched_workspace_bytes(int prec, int64_t n1, int64_t n2, int64_t n3);
 int tsvd_ctx_device(const tsvd_ctx* c);

@@ -287,7 +287,7 @@ __device__ __forceinline__ int gpair_lds(T* __restrict__ x, T* __restrict__ y, d
     }
     const double a = *na, b = *nb;
     const double g = group_sum<G>(partial_dot<T, R>(xr, yr, f64));
-    big += g * g > th2 * (a * b);
+    big += !(g * g <= th2 * (a * b));  // a NaN counts as large: never converged
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
     rotate_regs<T, R>(xr, yr, c, s);
@@ -320,7 +320,7 @@ __device__ __forceinline__ int tpair_lds(T* __restrict__ x, T* __restrict__ y, d
     }
     const double a = *na, b = *nb;
     const double g = group_dot<T, R, G>(xr, yr, f64);
-    big += g * g > th2 * (a * b);
+    big += !(g * g <= th2 * (a * b));  // a NaN counts as large: never converged
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
     rotate_regs<T, RT>(xr, yr, c, s);
@@ -346,7 +346,7 @@ __device__ __forceinline__ int tpair_reg(T (&xr)[RT], double& na, T* __restrict_
     for (int q = 0; q < RT; ++q) yr[q] = y[gl + G * q];
     const double a = na;
     const double g = group_dot<T, R, G>(xr, yr, f64);
-    big += g * g > th2 * (a * b);
+    big += !(g * g <= th2 * (a * b));  // a NaN counts as large: never converged
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
     rotate_regs<T, RT>(xr, yr, c, s);
@@ -368,7 +368,7 @@ __device__ __forceinline__ int gpair2(T (&x1)[R], double& n1, T (&y1)[R], double
                                       int& big) {
     const double g1 = group_sum<G>(partial_dot<T, R>(x1, y1, f64));
     const double g2 = group_sum<G>(partial_dot<T, R>(x2, y2, f64));
-    big += (v1 && g1 * g1 > th2 * (n1 * m1)) + (v2 && g2 * g2 > th2 * (n2 * m2));
+    big += (v1 && !(g1 * g1 <= th2 * (n1 * m1))) + (v2 && !(g2 * g2 <= th2 * (n2 * m2)));
     const bool r1 = v1 && needs_rotation(n1, m1, g1, tol);
     const bool r2 = v2 && needs_rotation(n2, m2, g2, tol);
     if (r1 || r2) {
@@ -537,7 +537,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_resident(JacobiJob job1, const 
         // one tensor: the job travels by value and task t is slice t
         const JacobiJob J = jobs ? jobs[task_job[t]] : job1;
         const int k = jobs ? task_slice[t] : t;
-#define TSVD_RES_CALL(RR, GG) resident_task<T, RR, GG, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch, s_nrm)
+        Ctrl* jc = J.ctrl ? J.ctrl : ctrl;
+#define TSVD_RES_CALL(RR, GG) resident_task<T, RR, GG, WV>(J, k, max_sweeps, jc, lds, &s_scratch, s_nrm)
         TSVD_DISPATCH_RG(J, TSVD_RES_CALL);
 #undef TSVD_RES_CALL
         __syncthreads();
@@ -1198,10 +1199,11 @@ __global__ __launch_bounds__(512) void k_jacobi_batched(const JacobiJob* __restr
         if (t >= ntasks) break;
         const JacobiJob J = jobs[task_job[t]];
         const int k = task_slice[t];
+        Ctrl* jc = J.ctrl ? J.ctrl : ctrl;  // the job's own status and counters when it has them
         if (J.nb == 0) {
-            resident_task<T, R, G, WV>(J, k, max_sweeps, ctrl, lds, &s_scratch, s_nrm);
+            resident_task<T, R, G, WV>(J, k, max_sweeps, jc, lds, &s_scratch, s_nrm);
         } else {
-            TeamState ts{nullptr, 0, 1, 0, ctrl, 0, nullptr, 0};
+            TeamState ts{nullptr, 0, 1, 0, jc, 0, nullptr, 0};
             (void)team_task<T, R, G, WV>(J, k, 0, ts, max_sweeps, lds, &s_scratch, &s_flag, s_nrm, s_nrm + 64);
         }
         __syncthreads();

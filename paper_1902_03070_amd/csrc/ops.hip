@@ -463,8 +463,9 @@ hipError_t launch_warm_reset(int prec, void* V, int p, int n3, const Ctrl* ctrl,
     return hipGetLastError();
 }
 
-// End of one completion iteration: record the relative change, clear the
-// norm accumulators, advance the iteration counter.
+// End of one completion iteration: record the relative change in the history
+// ring (slot iter mod hist_len), clear the norm accumulators, advance the
+// iteration counter.
 __global__ void k_iter_advance(Ctrl* ctrl, double* norms, double* hist, int hist_len) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         double dn = 0.0, xn = 0.0;
@@ -476,13 +477,57 @@ __global__ void k_iter_advance(Ctrl* ctrl, double* norms, double* hist, int hist
         }
         const double rc = xn > 0.0 ? sqrt(dn / xn) : sqrt(dn);
         const int it = ctrl->iter;
-        if (it < hist_len) hist[it] = rc;
+        hist[it % hist_len] = rc;
         ctrl->iter = it + 1;
     }
 }
 
 hipError_t launch_iter_advance(Ctrl* ctrl, double* norms, double* relchg_hist, int hist_len, hipStream_t s) {
     hipLaunchKernelGGL(k_iter_advance, dim3(1), dim3(64), 0, s, ctrl, norms, relchg_hist, hist_len);
+    return hipGetLastError();
+}
+
+// Algorithm 1's initial iterate: X = B on the observed set, 0 elsewhere.
+template <typename T>
+__global__ void k_observed_init(T* X, const T* B, const uint8_t* mask, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+        X[e] = mask[e] ? B[e] : (T)0;
+}
+
+hipError_t launch_observed_init(int prec, void* X, const void* B, const uint8_t* mask, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (prec == 0)
+        hipLaunchKernelGGL(k_observed_init<double>, dim3((unsigned)blocks), dim3(256), 0, s, (double*)X,
+                           (const double*)B, mask, n);
+    else
+        hipLaunchKernelGGL(k_observed_init<float>, dim3((unsigned)blocks), dim3(256), 0, s, (float*)X,
+                           (const float*)B, mask, n);
+    return hipGetLastError();
+}
+
+// Per-job control blocks of a batched step folded into the launch's block:
+// status bits ORed, largest sweep count and summed slice-sweeps.
+__global__ void k_fold_ctrl(Ctrl* dst, const Ctrl* jobs, int count, int stride_bytes) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int st = 0, ms = 0;
+    unsigned long long sw = 0;
+    for (int j = 0; j < count; ++j) {
+        const Ctrl* c = (const Ctrl*)((const char*)jobs + (int64_t)j * stride_bytes);
+        st |= c->status;
+        ms = c->max_sweeps > ms ? c->max_sweeps : ms;
+        sw += c->slice_sweeps;
+    }
+    dst->status |= st;
+    if (ms > dst->max_sweeps) dst->max_sweeps = ms;
+    dst->slice_sweeps += sw;
+}
+
+hipError_t launch_fold_ctrl(Ctrl* dst, const Ctrl* jobs, int count, int stride_bytes, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fold_ctrl, dim3(1), dim3(64), 0, s, dst, jobs, count, stride_bytes);
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 import synth
+from bounds import within
 from gpu_util import announce, need_gpu, rel, to_dev, to_np, torch
 
 pytestmark = pytest.mark.gpu
@@ -124,20 +125,6 @@ def test_tsvt_invalid_arguments(tm):
     assert tm.lib.tsvt_dct(ctx.h, 0, 4, 4, 2, None, Z.data_ptr(), 1.0, None, None) == tm.EINVAL
 
 
-def test_tsvt_full_size_sampled_slices(tm):
-    # 256 x 256 x 31, FP64, checked on sampled transformed slices: the DCT of
-    # the GPU output must equal the oracle's matrix SVT of those slices.
-    announce("tsvt_fp64_256x256x31_sampled")
-    cc = synth.completion_case(oracle.tprod_dct, 256, 256, 31, 10, 0.3, 100, synth.SEED_BASE + 2)
-    tau = float(cc.taus[0])
-    Y = tm.tsvt_dct(to_dev(cc.B), tau)
-    Yb = oracle.dct_tubes(to_np(Y))
-    Zb = oracle.dct_tubes(cc.B)
-    for k in (0, 7, 30):
-        want = oracle.tsvt_dct(Zb[:, :, k:k + 1], tau)[:, :, 0]
-        assert rel(Yb[:, :, k], want) <= TOL64, k
-
-
 def degenerate_tensor(kind, shape, seed):
     """Frontal slices all equal to one matrix M, so the transformed tensor has
     sqrt(n3) M as slice 0 and exact zeros elsewhere.  kind: 'zero' (M = 0),
@@ -174,4 +161,8 @@ def test_tsvt_degenerate_spectra(tm, shape, kind, prec):
     if kind == "zero":
         assert float(np.abs(Yg).max()) == 0.0
     else:
-        assert rel(Yg, Yo) <= (TOL64 if prec == 0 else 1e-4)
+        if prec == 0:
+            assert rel(Yg, Yo) <= TOL64
+        else:
+            assert within(Yg, oracle.tsvt_dct(Z.astype(np.float32).astype(np.float64), tau),
+                          Z.astype(np.float32).astype(np.float64), prec)
