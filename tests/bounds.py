@@ -15,8 +15,11 @@ up to a power of two (observed maxima recorded next to each constant).
 import numpy as np
 
 U_EFF = {1: 2.0 ** -24, 2: 2.0 ** -16}
-# largest observed c: FP32 ~60 (256 x 256 slices); MIXED ~0.3
-C_PATH = {1: 128.0, 2: 1.0}
+# largest observed c: FP32 170.5 (one slice of the 256 x 256 x 31 t-SVT at
+# tau = 0.1, whole tensor 149.5); MIXED ~0.3.  The FP32 floor is set by the
+# rotation threshold 2 sqrt(m) u of the FP32 sweeps (pairs whose cosine is
+# below it stay unrotated): 32 u at m = 256, times a small factor.
+C_PATH = {1: 512.0, 2: 1.0}
 FP64_TOL = 1e-10
 
 
