@@ -33,6 +33,7 @@
 #ifndef TSVDMI_H
 #define TSVDMI_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -49,7 +50,8 @@ typedef struct tsvd_ctx tsvd_ctx;
  *   TSVD_MIXED : float data; transforms on BF16 matrix cores with a hi+lo
  *                split (three products, FP32 accumulation); Jacobi sweeps in
  *                FP32 with FP64 angles and test, then one final sweep whose
- *                dot products and rotations are computed in FP64. */
+ *                dot products and angles are computed in FP64 (its
+ *                rotations act on the FP32 values in FP32). */
 enum { TSVD_FP64 = 0, TSVD_FP32 = 1, TSVD_MIXED = 2 };
 
 enum {
@@ -92,7 +94,7 @@ enum {
     TSVD_OPT_GROUP_COLUMNS = 8, /* 0: automatic; 1 or 2: columns each lane group of the multi-workgroup
                                   Jacobi kernel holds (2: two independent rotations at a time; not
                                   with V).  A forced setting disables tuning. */
-    TSVD_OPT_WARM_START = 9    /* complete_tensor: -1 (default) warm-start each iteration's Jacobi SVDs
+    TSVD_OPT_WARM_START = 9,   /* complete_tensor: -1 (default) warm-start each iteration's Jacobi SVDs
                                   from the previous iteration's right singular vectors, resetting
                                   them to the identity every 64 iterations; N >= 1: reset every N
                                   iterations; 0: cold starts */
@@ -168,6 +170,25 @@ int tsvd_dct(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const 
  * per slice; when given, the call synchronizes.  Y may alias Z. */
 int tsvt_dct(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const void* Z, void* Y, double tau,
              int32_t* ranks_out, void* stream);
+
+/* tsvt_dct for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, result and status as tsvt_dct (to the precision's tolerance:
+ * the Jacobi tile is the one tsvt_dct has tuned for this shape in this
+ * process, else the default one, since tuning needs memory).  Every device
+ * buffer of the call - workspace, transform matrices (built on the device) -
+ * lives in one fixed array of TSVD_NOALLOC_MAX_BYTES compiled into the
+ * library, one per GPU, held until the process ends; the control block is the
+ * one tsvd_create allocated.  The call makes no device allocation and no
+ * profiling events.
+ *   - A tensor whose workspace does not fit returns TSVD_EINVAL (the message
+ *     gives the bytes needed); 256 x 256 x 31 fits in every precision.
+ *   - All calls on one GPU share that GPU's array, which keeps the last call's
+ *     contents: calls that overlap on one GPU (two streams, two threads, two
+ *     contexts) race and give undefined results.  Order them. */
+#define TSVD_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+int tsvt_dct_noalloc(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const void* Z, void* Y,
+                     double tau, int32_t* ranks_out, void* stream);
 
 /* Algorithm 1 (ADMM for TNN-C completion).
  *   B    : observed data (only entries with mask != 0 are read).

@@ -30,7 +30,7 @@ REQ_TSVT, REQ_COMPLETE = 0, 1
 EXPORTED = [
     "tsvd_create", "tsvd_destroy", "tsvd_last_error", "tsvd_set_option", "tsvd_get_option", "tsvd_sync_status",
     "tsvd_get_stats", "tsvd_get_tile",
-    "tprod_dct", "tsvd_dct", "tsvt_dct", "complete_tensor", "tsvt_dct_batched", "tsvd_server_create",
+    "tprod_dct", "tsvd_dct", "tsvt_dct", "tsvt_dct_noalloc", "complete_tensor", "tsvt_dct_batched", "tsvd_server_create",
     "tsvd_server_submit", "tsvd_server_cancel", "tsvd_server_poll", "tsvd_server_now", "tsvd_server_stats",
     "tsvd_server_destroy",
 ]
@@ -77,6 +77,7 @@ lib.tsvd_get_tile.argtypes = [_vp, _i32, _i64, _i64, _i64, _i32, _i32, C.POINTER
 lib.tprod_dct.argtypes = [_vp, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp]
 lib.tsvd_dct.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _i32, _vp]
 lib.tsvt_dct.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _d, C.POINTER(C.c_int32), _vp]
+lib.tsvt_dct_noalloc.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _d, C.POINTER(C.c_int32), _vp]
 lib.complete_tensor.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _vp, C.POINTER(CompleteOpts),
                                 C.POINTER(CompleteInfo), _vp]
 lib.tsvt_dct_batched.argtypes = [_vp, _i32, _i32, C.POINTER(C.c_int64), C.POINTER(_vp), C.POINTER(_vp),
@@ -243,6 +244,30 @@ def tsvt_dct(Z: torch.Tensor, tau: float, Y: Optional[torch.Tensor] = None, prec
     ranks = (C.c_int32 * n3)() if return_ranks else None
     rc = lib.tsvt_dct(ctx.h, prec, n1, n2, n3, Z.data_ptr(), Y.data_ptr(), float(tau), ranks,
                       _stream(stream, d))
+    ctx.check(rc)
+    if return_ranks:
+        return Y, [int(r) for r in ranks]
+    return Y
+
+
+NOALLOC_MAX_BYTES = 128 << 20
+
+
+def tsvt_dct_noalloc(Z: torch.Tensor, tau: float, Y: torch.Tensor, prec: Optional[int] = None,
+                     return_ranks: bool = False, ctx: Optional[Context] = None, stream=None):
+    """t-SVT (Theorem 5) through the entry point that makes no device
+    allocation: the caller passes the output Y (column-major, Z's shape and
+    type) and the library works in its fixed per-GPU scratch."""
+    Z, Y = fortran(Z), fortran(Y)
+    d = _dev(Z)
+    prec = _prec_of(Z, prec)
+    ctx = ctx or default_context(d)
+    n1, n2, n3 = Z.shape
+    if tuple(Y.shape) != (n1, n2, n3) or Y.dtype != Z.dtype:
+        raise ValueError("Y must have Z's shape and type")
+    ranks = (C.c_int32 * n3)() if return_ranks else None
+    rc = lib.tsvt_dct_noalloc(ctx.h, prec, n1, n2, n3, Z.data_ptr(), Y.data_ptr(), float(tau), ranks,
+                              _stream(stream, d))
     ctx.check(rc)
     if return_ranks:
         return Y, [int(r) for r in ranks]

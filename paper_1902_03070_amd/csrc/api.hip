@@ -51,7 +51,16 @@ struct tsvd_ctx {
     int use_graphs = 1;
     int capturing = 0;
     hipStream_t own = nullptr;  // context stream (capture cannot use the legacy default stream)
+    int noalloc = 0;            // inside tsvt_dct_noalloc: no tuning, no profiling events
 };
+
+// Fixed scratch of tsvt_dct_noalloc (TSVD_NOALLOC_MAX_BYTES).  Every GPU the
+// library runs on holds one copy of this array for the life of the process.
+// Its device address on each device is looked up once (tsvd_create, with that
+// device current) and kept; host code passes that address to kernels and
+// copies, never the array's name, which on the host is only a stand-in.
+constexpr size_t kScratchBytes = TSVD_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -141,22 +150,32 @@ int get_frag(tsvd_ctx* c, int n3, int prec, int inverse, const void** out) {
 
 // Tube transform along n3 (forward or inverse) on the matrix cores; tubes
 // longer than kMaxTube use the vector-ALU kernel with the dense matrix.
-int run_tube(tsvd_ctx* c, int prec, TubeArgs a, int inverse, hipStream_t s) {
+// `mat` is the transform operand: fragments for n3 <= kMaxTube, else the
+// dense matrix (see launch_tube_matrix).
+int run_tube_mat(tsvd_ctx* c, int prec, TubeArgs a, int inverse, const void* mat, hipStream_t s) {
     hipError_t e;
     if (a.n3 <= kMaxTube) {
-        const void* fr;
-        int rc = get_frag(c, a.n3, prec, inverse, &fr);
-        if (rc) return rc;
-        e = launch_tube_mfma(tube_engine(prec), a, fr, s);
+        e = launch_tube_mfma(tube_engine(prec), a, mat, s);
     } else {
-        const void *C, *Ct;
-        int rc = get_dct(c, a.n3, prec, &C, &Ct);
-        if (rc) return rc;
-        a.M = inverse ? Ct : C;
+        a.M = mat;
         e = launch_tube_transform(prec == TSVD_FP64 ? 0 : 1, a, s);
     }
     if (e != hipSuccess) return hip_fail(c, e, inverse ? "inverse tube transform" : "tube transform");
     return TSVD_OK;
+}
+
+int run_tube(tsvd_ctx* c, int prec, TubeArgs a, int inverse, hipStream_t s) {
+    const void* mat;
+    if (a.n3 <= kMaxTube) {
+        int rc = get_frag(c, a.n3, prec, inverse, &mat);
+        if (rc) return rc;
+    } else {
+        const void *C, *Ct;
+        int rc = get_dct(c, a.n3, prec, &C, &Ct);
+        if (rc) return rc;
+        mat = inverse ? Ct : C;
+    }
+    return run_tube_mat(c, prec, a, inverse, mat, s);
 }
 
 // Grow-only workspace.  Growing frees the old buffer (hipFree waits for the device).
@@ -252,7 +271,7 @@ struct PhaseMark {
     int ph;
     hipStream_t s;
     hipEvent_t a = nullptr;
-    bool on() const { return c->prof == 1 || (c->prof == 2 && ph == 1); }
+    bool on() const { return !c->noalloc && (c->prof == 1 || (c->prof == 2 && ph == 1)); }
     static hipEvent_t take(tsvd_ctx* c) {
         if (c->ev_used == c->ev_pool.size()) {
             hipEvent_t e;
@@ -687,7 +706,7 @@ int pick_tile(tsvd_ctx* c, const Plan& P, bool batched, hipStream_t s, Tile* t) 
     const TileKey key(batched ? 1 : 0, P.prec, P.m, P.p, batched ? 0 : (int)P.n3, P.with_v);
     if (tile_cache_get(key, t)) return TSVD_OK;
     *t = default_tile(P, 0, 0, 0, batched);
-    if (!c->autotune) return TSVD_OK;
+    if (!c->autotune || c->noalloc) return TSVD_OK;  // tuning allocates its test data
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
         (void)hipGetLastError();
@@ -891,6 +910,77 @@ int finish_call(tsvd_ctx* c, hipStream_t s) {
     return read_status(c, s, nullptr);
 }
 
+int tsvt_check(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const void* Z, const void* Y,
+               double tau) {
+    if (bad_prec(prec)) return fail(c, TSVD_EINVAL, "unknown precision");
+    if (n1 <= 0 || n2 <= 0 || n3 <= 0) return fail(c, TSVD_EINVAL, "sizes must be positive");
+    if (!Z || !Y) return fail(c, TSVD_EINVAL, "null tensor pointer");
+    if (!(tau >= 0.0) || !isfinite(tau)) return fail(c, TSVD_EINVAL, "tau must be finite and >= 0");
+    return TSVD_OK;
+}
+
+// One t-SVT (Theorem 5) of a planned tensor on the workspace at `base`.  The
+// transform operands are fwd / inv, or (nullptr) the context's cached copies.
+int tsvt_enqueue(tsvd_ctx* c, Plan& P, char* base, const void* fwd, const void* inv, const void* Z, void* Y,
+                 double tau, int32_t* ranks_out, hipStream_t s) {
+    int rc;
+    if ((rc = upload_plan(c, P, base))) return rc;
+    CtrlRegion cr;
+    if ((rc = ensure_ctrl(c, &cr))) return rc;
+    hipError_t e = launch_fill_zero(base + P.o_ctr_begin, P.o_ctr_end - P.o_ctr_begin, s);
+    if (e != hipSuccess) return hip_fail(c, e, "fill");
+    TubeArgs f{};
+    f.in = Z; f.out = base + P.o_zbar; f.N = P.N; f.n3 = (int)P.n3; f.ctrl = cr.ctrl; f.check_finite = 1;
+    f.beta_val = 1.0;
+    {
+        PhaseMark pm(c, 0, s);
+        rc = fwd ? run_tube_mat(c, P.prec, f, 0, fwd, s) : run_tube(c, P.prec, f, 0, s);
+        if (rc) return rc;
+    }
+    if ((rc = enqueue_svt_core(c, P, base, cr.ctrl, tau, nullptr, s))) return rc;
+    TubeArgs iv{};
+    iv.in = base + P.o_ybar; iv.out = Y; iv.N = P.N; iv.n3 = (int)P.n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
+    {
+        PhaseMark pm(c, 3, s);
+        rc = inv ? run_tube_mat(c, P.prec, iv, 1, inv, s) : run_tube(c, P.prec, iv, 1, s);
+        if (rc) return rc;
+    }
+    if (ranks_out) {
+        HIPCHK(c, hipMemcpyAsync(ranks_out, base + P.o_rank, P.n3 * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        return read_status(c, s, nullptr);
+    }
+    return finish_call(c, s);
+}
+
+// Device addresses of the scratch array (see its definition above).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices];
+
+// With `device` current: look up the device address of the scratch array.
+int scratch_lookup(int device) {
+    if (device < 0 || device >= kMaxDevices) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return TSVD_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return TSVD_EHIP;
+    }
+    g_scratch_ptr[device] = (char*)p;
+    return TSVD_OK;
+}
+
+int scratch_of(tsvd_ctx* c, char** out) {
+    if (scratch_lookup(c->device) != TSVD_OK)
+        return fail(c, TSVD_EHIP, "address of the fixed scratch array unavailable on this device");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    *out = g_scratch_ptr[c->device];
+    return TSVD_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -912,6 +1002,9 @@ int tsvd_create(tsvd_ctx** out, int device) {
         delete c;
         return TSVD_EHIP;
     }
+    // device address of the no-allocation scratch on this device (a failure
+    // here only disables tsvt_dct_noalloc, which reports it)
+    (void)scratch_lookup(device);
     *out = c;
     return TSVD_OK;
 }
@@ -1050,45 +1143,57 @@ int tsvt_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
              int32_t* ranks_out, void* stream) {
     if (!c) return TSVD_EINVAL;
     std::lock_guard<std::mutex> lk(c->mu);
-    if (bad_prec(prec)) return fail(c, TSVD_EINVAL, "unknown precision");
-    if (n1 <= 0 || n2 <= 0 || n3 <= 0) return fail(c, TSVD_EINVAL, "sizes must be positive");
-    if (!Z || !Y) return fail(c, TSVD_EINVAL, "null tensor pointer");
-    if (!(tau >= 0.0) || !isfinite(tau)) return fail(c, TSVD_EINVAL, "tau must be finite and >= 0");
+    int rc = tsvt_check(c, prec, n1, n2, n3, Z, Y, tau);
+    if (rc) return rc;
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     Plan P;
     Carve cv;
-    int rc = make_plan(c, prec, n1, n2, n3, 0, P, cv, s);
-    if (rc) return rc;
+    if ((rc = make_plan(c, prec, n1, n2, n3, 0, P, cv, s))) return rc;
     if ((rc = ensure_ws(c, P.o_end))) return rc;
-    char* base = (char*)c->ws.p;
-    if ((rc = upload_plan(c, P, base))) return rc;
-    CtrlRegion cr;
-    if ((rc = ensure_ctrl(c, &cr))) return rc;
-    const void *C, *Ct;
-    if ((rc = get_dct(c, (int)n3, prec, &C, &Ct))) return rc;
-    hipError_t e = launch_fill_zero(base + P.o_ctr_begin, P.o_ctr_end - P.o_ctr_begin, s);
-    if (e != hipSuccess) return hip_fail(c, e, "fill");
-    TubeArgs f{};
-    f.in = Z; f.out = base + P.o_zbar; f.M = C; f.N = P.N; f.n3 = (int)n3; f.ctrl = cr.ctrl; f.check_finite = 1;
-    f.beta_val = 1.0;
-    {
-        PhaseMark pm(c, 0, s);
-        if ((rc = run_tube(c, prec, f, 0, s))) return rc;
+    return tsvt_enqueue(c, P, (char*)c->ws.p, nullptr, nullptr, Z, Y, tau, ranks_out, s);
+}
+
+int tsvt_dct_noalloc(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const void* Z, void* Y,
+                     double tau, int32_t* ranks_out, void* stream) {
+    if (!c) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    int rc = tsvt_check(c, prec, n1, n2, n3, Z, Y, tau);
+    if (rc) return rc;
+    HIPCHK(c, hipSetDevice(c->device));
+    char* sp = nullptr;
+    if ((rc = scratch_of(c, &sp))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    // the call's layout in the scratch array: forward and inverse transform
+    // operands, then the workspace of the plan
+    const int eng = tube_engine(prec);
+    Carve cv;
+    const size_t o_fwd = cv.take(tube_matrix_bytes(eng, (int)n3));
+    const size_t o_inv = cv.take(tube_matrix_bytes(eng, (int)n3));
+    const size_t o_ws = cv.off;
+    Plan P;
+    Carve wv;
+    c->noalloc = 1;  // make_plan: the cached or default tile, no tuning
+    rc = make_plan(c, prec, n1, n2, n3, 0, P, wv, s);
+    if (rc) {
+        c->noalloc = 0;
+        return rc;
     }
-    if ((rc = enqueue_svt_core(c, P, base, cr.ctrl, tau, nullptr, s))) return rc;
-    TubeArgs iv{};
-    iv.in = base + P.o_ybar; iv.out = Y; iv.M = Ct; iv.N = P.N; iv.n3 = (int)n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
-    {
-        PhaseMark pm(c, 3, s);
-        if ((rc = run_tube(c, prec, iv, 1, s))) return rc;
+    if (o_ws + P.o_end > kScratchBytes) {
+        c->noalloc = 0;
+        return fail(c, TSVD_EINVAL, "tsvt_dct_noalloc: the tensor needs " + std::to_string(o_ws + P.o_end) +
+                                        " bytes of scratch; the fixed scratch holds " +
+                                        std::to_string(kScratchBytes));
     }
-    if (ranks_out) {
-        HIPCHK(c, hipMemcpyAsync(ranks_out, base + P.o_rank, n3 * 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipStreamSynchronize(s));
-        return read_status(c, s, nullptr);
+    hipError_t e = launch_tube_matrix(eng, (int)n3, 0, sp + o_fwd, s);
+    if (e == hipSuccess) e = launch_tube_matrix(eng, (int)n3, 1, sp + o_inv, s);
+    if (e != hipSuccess) {
+        c->noalloc = 0;
+        return hip_fail(c, e, "transform matrix");
     }
-    return finish_call(c, s);
+    rc = tsvt_enqueue(c, P, sp + o_ws, sp + o_fwd, sp + o_inv, Z, Y, tau, ranks_out, s);
+    c->noalloc = 0;
+    return rc;
 }
 
 int tprod_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n4, int64_t n3, const void* X, const void* Yp,

@@ -282,6 +282,75 @@ static hipError_t launch_eng(const TubeArgs& a, const void* frag, hipStream_t s)
     return hipGetLastError();
 }
 
+// The transform matrix built on the device, for callers that keep it in
+// memory the library did not allocate.  Entry (row, col) of M is C[row][col]
+// forward and C[col][row] inverse, with the orthonormal DCT-II
+// C[k][t] = s_k cos(pi (2t + 1) k / (2 n3)), s_0 = sqrt(1/n3), s_k = sqrt(2/n3)
+// (Section 3, dct(., [], 3)), evaluated in FP64 with the same expression as
+// the host copy.  dense = 1: row-major n3 x n3 in FP64 (eng 0) or FP32
+// (otherwise), the vector-ALU kernel's operand; dense = 0: the fragment order
+// of make_tube_fragments for engine eng, KS = tube_ks(eng, n3).
+__device__ __forceinline__ double dct_entry(int n3, int k, int t) {
+    const double sk = k == 0 ? sqrt(1.0 / n3) : sqrt(2.0 / n3);
+    return sk * cos(3.141592653589793 * (2.0 * t + 1.0) * k / (2.0 * n3));
+}
+
+__device__ __forceinline__ unsigned short bf16_rne_dev(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__global__ void k_tube_matrix(int eng, int n3, int inverse, int KS, int dense, void* out, int64_t total) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    if (dense) {
+        const int row = (int)(idx / n3), col = (int)(idx % n3);
+        const double v = inverse ? dct_entry(n3, col, row) : dct_entry(n3, row, col);
+        if (eng == 0) ((double*)out)[idx] = v;
+        else ((float*)out)[idx] = (float)v;
+        return;
+    }
+    const int64_t nfr = (int64_t)((n3 + 15) / 16) * KS * 64;
+    if (eng != 2) {
+        const int lane = (int)(idx % 64), ks = (int)((idx / 64) % KS), mb = (int)(idx / 64 / KS);
+        const int row = mb * 16 + lane % 16, k = ks * 4 + lane / 16;
+        double v = 0.0;
+        if (row < n3 && k < n3) v = inverse ? dct_entry(n3, k, row) : dct_entry(n3, row, k);
+        if (eng == 0) ((double*)out)[idx] = v;
+        else ((float*)out)[idx] = (float)v;
+        return;
+    }
+    const int e = (int)(idx % 8);
+    const int64_t fi = idx / 8;
+    const int lane = (int)(fi % 64), ks = (int)((fi / 64) % KS), mb = (int)(fi / 64 / KS);
+    const int row = mb * 16 + lane % 16, k = ks * 32 + 8 * (lane / 16) + e;
+    float v = 0.0f;
+    if (row < n3 && k < n3) v = (float)(inverse ? dct_entry(n3, k, row) : dct_entry(n3, row, k));
+    const unsigned short hi = bf16_rne_dev(v);
+    const unsigned short lo = bf16_rne_dev(v - __uint_as_float((uint32_t)hi << 16));
+    ((unsigned short*)out)[fi * 8 + e] = hi;
+    ((unsigned short*)out)[(nfr + fi) * 8 + e] = lo;
+}
+
+size_t tube_matrix_bytes(int eng, int n3) {
+    if (n3 <= kMaxTube) return tube_fragment_bytes(eng, n3);
+    return (size_t)n3 * n3 * (eng == 0 ? 8 : 4);
+}
+
+hipError_t launch_tube_matrix(int eng, int n3, int inverse, void* out, hipStream_t s) {
+    if (n3 <= 0) return hipErrorInvalidValue;
+    const int dense = n3 > kMaxTube ? 1 : 0;
+    const int KS = dense ? 0 : tube_ks(eng, n3);
+    int64_t total;
+    if (dense) total = (int64_t)n3 * n3;
+    else total = (int64_t)((n3 + 15) / 16) * KS * 64 * (eng == 2 ? 8 : 1);
+    const int threads = 256;
+    hipLaunchKernelGGL(k_tube_matrix, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, s, eng,
+                       n3, inverse, KS, dense, out, total);
+    return hipGetLastError();
+}
+
 hipError_t launch_tube_mfma(int eng, const TubeArgs& a, const void* frag, hipStream_t s) {
     if (a.N <= 0) return hipSuccess;
     if (a.n3 > kMaxTube) return hipErrorInvalidValue;

@@ -104,6 +104,11 @@ int tube_ks(int eng, int n3);
 size_t tube_fragment_bytes(int eng, int n3);
 void make_tube_fragments(int eng, int n3, const double* M, void* out);
 hipError_t launch_tube_mfma(int eng, const TubeArgs& a, const void* frag, hipStream_t s);
+// The operand of the tube transform built on the device (no host copy): the
+// fragments of engine eng for n3 <= kMaxTube, else the dense row-major matrix
+// (FP64 for eng 0, FP32 otherwise).  tube_matrix_bytes gives its size.
+size_t tube_matrix_bytes(int eng, int n3);
+hipError_t launch_tube_matrix(int eng, int n3, int inverse, void* out, hipStream_t s);
 
 // Jacobi one-sided SVD of every slice.  Single tensor: `job1` by value, task
 // t = slice t (jobs_dev == nullptr).  Batched: job table and task list in
