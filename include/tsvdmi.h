@@ -98,6 +98,15 @@ enum {
                                   from the previous iteration's right singular vectors, resetting
                                   them to the identity every 64 iterations; N >= 1: reset every N
                                   iterations; 0: cold starts */
+    TSVD_OPT_COOPERATIVE = 10  /* 0 (default): ordinary launches of the multi-workgroup Jacobi kernel
+                                  (its grid is sized so that every team is resident, and a team
+                                  wait that exceeds the spin limit returns TSVD_ETIMEOUT); 1:
+                                  cooperative launches outside graph capture (the runtime then
+                                  refuses a grid that cannot be resident).  Both run at the same
+                                  speed; a process that made cooperative launches ended in a
+                                  segmentation fault at exit under rocprofv3, one that made only
+                                  ordinary launches did not.  The environment variable
+                                  TSVDMI_COOPERATIVE=1 sets 1 at context creation. */
 };
 int tsvd_set_option(tsvd_ctx* ctx, int option, double value);
 double tsvd_get_option(const tsvd_ctx* ctx, int option);

@@ -52,6 +52,7 @@ struct tsvd_ctx {
     int capturing = 0;
     hipStream_t own = nullptr;  // context stream (capture cannot use the legacy default stream)
     int noalloc = 0;            // inside tsvt_dct_noalloc: no tuning, no profiling events
+    int coop = 0;               // 1: cooperative launches of the team kernel outside capture
 };
 
 // Fixed scratch of tsvt_dct_noalloc (TSVD_NOALLOC_MAX_BYTES).  Every GPU the
@@ -611,7 +612,7 @@ double time_tile(tsvd_ctx* c, const Plan& P0, const Tile& t, bool batched, char*
                                        P.threads, P.with_v, s);
         else
             e = launch_jacobi_team(P.prec, J, ntasks, P.ts, kTuneSweeps, ctrl, P.lds, P.threads, P.with_v,
-                                   c->spin_limit, J.R, J.G, P.K, 1, s);
+                                   c->spin_limit, J.R, J.G, P.K, c->coop, s);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return -1.0;
@@ -801,7 +802,7 @@ int run_jacobi(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s) {
                                    ctrl, P.lds, P.threads, P.with_v, s);
     else
         e = launch_jacobi_team(P.prec, P.job, (int)P.n3, P.ts, clamp_sweeps(c->max_sweeps), ctrl, P.lds, P.threads,
-                               P.with_v, c->spin_limit, P.job.R, P.job.G, P.K, c->capturing ? 0 : 1, s);
+                               P.with_v, c->spin_limit, P.job.R, P.job.G, P.K, (c->capturing || !c->coop) ? 0 : 1, s);
     if (e != hipSuccess) return hip_fail(c, e, "jacobi launch");
     return TSVD_OK;
 }
@@ -997,6 +998,7 @@ int tsvd_create(tsvd_ctx** out, int device) {
     auto* c = new tsvd_ctx();
     c->device = device;
     (void)hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (const char* v = getenv("TSVDMI_COOPERATIVE")) c->coop = strcmp(v, "1") == 0;
     CtrlRegion cr;
     if (ensure_ctrl(c, &cr) != TSVD_OK) {
         delete c;
@@ -1063,6 +1065,7 @@ int tsvd_set_option(tsvd_ctx* c, int opt, double v) {
             if (v != 0 && v != 16 && v != 32 && v != 64) return fail(c, TSVD_EINVAL, "group lanes must be 0, 16, 32 or 64");
             c->group_lanes = (int)v;
             return TSVD_OK;
+        case TSVD_OPT_COOPERATIVE: c->coop = v != 0.0; return TSVD_OK;
     }
     return fail(c, TSVD_EINVAL, "unknown option");
 }
@@ -1080,6 +1083,7 @@ double tsvd_get_option(const tsvd_ctx* c, int opt) {
         case TSVD_OPT_GROUP_COLUMNS: return c->group_cols;
         case TSVD_OPT_WARM_START: return c->warm_start;
         case TSVD_OPT_GROUP_LANES: return c->group_lanes;
+        case TSVD_OPT_COOPERATIVE: return c->coop;
     }
     return -1.0;
 }

@@ -33,9 +33,9 @@
 //    Blocks go back to global memory (the XCD's L2) after each step; within a
 //    sweep each block passes from its holder to the next one through a flag,
 //    and the sweep ends at a team barrier.  The grid is sized so that every
-//    workgroup of a team is resident (and launched cooperatively outside graph
-//    capture); every wait is bounded and reports a timeout instead of
-//    hanging.
+//    workgroup of a team is resident (ordinary launches by default, cooperative
+//    ones on request outside graph capture); every wait is bounded and reports
+//    a timeout instead of hanging.
 #include <algorithm>
 
 #include "internal.h"

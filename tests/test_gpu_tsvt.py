@@ -166,3 +166,25 @@ def test_tsvt_degenerate_spectra(tm, shape, kind, prec):
         else:
             assert within(Yg, oracle.tsvt_dct(Z.astype(np.float32).astype(np.float64), tau),
                           Z.astype(np.float32).astype(np.float64), prec)
+
+
+def test_team_kernel_ordinary_and_cooperative_launches_agree(tm):
+    # the multi-workgroup Jacobi kernel: ordinary launches (default) and
+    # cooperative ones give bitwise the same result
+    announce("tsvt_launch_kinds")
+    c = case((256, 256, 3), r=8, seed=5)
+    Z = to_dev(c.Z)
+    a = tm.Context(0)
+    b = tm.Context(0)
+    try:
+        assert a.get_option(tm.OPT_COOPERATIVE) == 0
+        b.set_option(tm.OPT_COOPERATIVE, 1)
+        assert a.tile(tm.FP64, 256, 256, 3)["team"] == 1
+        Ya = tm.tsvt_dct(Z, c.tau, ctx=a)
+        Yb = tm.tsvt_dct(Z, c.tau, ctx=b)
+        torch.cuda.synchronize()
+        assert torch.equal(Ya, Yb)
+        assert rel(to_np(Ya), oracle.tsvt_dct(c.Z, c.tau)) <= TOL64
+    finally:
+        a.close()
+        b.close()
