@@ -24,4 +24,11 @@ from .oracle import (  # noqa: F401
     tsvt_dct,
     tnn_c,
     complete,
+    tsvt_transform,
+    dft_tubes,
+    idft_tubes,
+    bcirc,
+    svt_complex,
+    tsvt_dft,
+    tnn_f,
 )

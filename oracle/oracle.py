@@ -58,6 +58,18 @@ def _load():
     lib.or_complete.argtypes = [_i64, _i64, _i64, _dp, C.POINTER(C.c_uint8), C.c_int, _dp, _dp, C.c_double,
                                 C.c_int, _dp, _dp, _dp]
     lib.or_complete.restype = C.c_int
+    lib.or_tsvt_transform.argtypes = [_i64, _i64, _i64, _dp, _dp, _dp, C.c_double, _dp, C.POINTER(C.c_int32),
+                                      C.c_int]
+    lib.or_tsvt_transform.restype = C.c_int
+    lib.or_dft_tubes.argtypes = [_i64, _i64, _i64, _dp, _dp, _dp]
+    lib.or_idft_tubes.argtypes = [_i64, _i64, _i64, _dp, _dp, _dp, _dp]
+    lib.or_bcirc.argtypes = [_i64, _i64, _i64, _dp, _dp]
+    lib.or_jacobi_svt_c.argtypes = [_i64, _i64, _dp, _dp, C.c_double, _dp, _dp, _dp, C.POINTER(C.c_int32), C.c_int]
+    lib.or_jacobi_svt_c.restype = C.c_int
+    lib.or_tsvt_dft.argtypes = [_i64, _i64, _i64, _dp, C.c_double, _dp, C.POINTER(C.c_int32), _dp, C.c_int]
+    lib.or_tsvt_dft.restype = C.c_int
+    lib.or_tnn_f.argtypes = [_i64, _i64, _i64, _dp, C.c_int]
+    lib.or_tnn_f.restype = C.c_double
     _lib = lib
     return lib
 
@@ -252,3 +264,84 @@ def complete(B, mask, betas, taus=None, tol: float = 0.0, X0=None, M0=None, max_
     it = _load().or_complete(n1, n2, n3, _p(B), mask.ctypes.data_as(C.POINTER(C.c_uint8)), L, _p(betas), _p(taus),
                              float(tol), max_sweeps, _p(X), _p(M), C.byref(rc))
     return X, M, it, rc.value
+
+
+def tsvt_transform(Z, tau: float, L, Linv=None, max_sweeps: int = MAX_SWEEPS, return_ranks: bool = False):
+    """t-SVT under an invertible transform L along the tubes (Section 6: other
+    transforms in place of the DCT): slices of L applied along the tubes are
+    thresholded, then Linv (default: numpy's inverse of L) maps back."""
+    Z = _as3(Z)
+    n1, n2, n3 = Z.shape
+    L = np.ascontiguousarray(L, dtype=np.float64).reshape(n3, n3)
+    Linv = np.ascontiguousarray(np.linalg.inv(L) if Linv is None else Linv, dtype=np.float64).reshape(n3, n3)
+    Y = np.empty_like(Z, order="F")
+    ranks = np.empty(n3, dtype=np.int32)
+    sw = _load().or_tsvt_transform(n1, n2, n3, _p(L), _p(Linv), _p(Z), float(tau), _p(Y),
+                                   ranks.ctypes.data_as(C.POINTER(C.c_int32)), max_sweeps)
+    if return_ranks:
+        return Y, ranks, sw
+    return Y
+
+
+def dft_tubes(X):
+    """fft(X,[],3) from the definition (unnormalized), as a complex array."""
+    X = _as3(X)
+    Xr = np.empty_like(X, order="F")
+    Xi = np.empty_like(X, order="F")
+    _load().or_dft_tubes(*X.shape, _p(X), _p(Xr), _p(Xi))
+    return Xr + 1j * Xi
+
+
+def idft_tubes(Xt):
+    """ifft(Xt,[],3) from the definition, as a complex array."""
+    Xt = np.asarray(Xt)
+    if Xt.ndim == 2:
+        Xt = Xt.reshape(Xt.shape[0], Xt.shape[1], 1)
+    Xr, Xi = _f64(Xt.real), _f64(Xt.imag)
+    Yr = np.empty_like(Xr, order="F")
+    Yi = np.empty_like(Xr, order="F")
+    _load().or_idft_tubes(*Xr.shape, _p(Xr), _p(Xi), _p(Yr), _p(Yi))
+    return Yr + 1j * Yi
+
+
+def bcirc(X):
+    """Block circulant matrix of the slices of X (equation (bcirc))."""
+    return _block_matrix("or_bcirc", X)
+
+
+def svt_complex(A, tau: float, max_sweeps: int = MAX_SWEEPS):
+    """Matrix SVT of a complex matrix by complex one-sided Jacobi: returns
+    (U (S - tau)_+ V^H, singular values descending, rank, sweeps)."""
+    A = np.asarray(A, dtype=np.complex128)
+    m, n = A.shape
+    Ar, Ai = _f64(A.real), _f64(A.imag)
+    s = np.empty(min(m, n))
+    Yr = np.empty((m, n), order="F")
+    Yi = np.empty((m, n), order="F")
+    rk = C.c_int32(0)
+    sw = _load().or_jacobi_svt_c(m, n, _p(Ar), _p(Ai), float(tau), _p(s), _p(Yr), _p(Yi), C.byref(rk), max_sweeps)
+    return Yr + 1j * Yi, s, int(rk.value), sw
+
+
+def tsvt_dft(Z, tau: float, max_sweeps: int = MAX_SWEEPS, return_ranks: bool = False, return_imag: bool = False):
+    """DFT t-SVT (the TNN-F counterpart of Theorem 5): every slice of the
+    unnormalized fft(Z,[],3) thresholded at tau, then ifft; real output."""
+    Z = _as3(Z)
+    n1, n2, n3 = Z.shape
+    Y = np.empty_like(Z, order="F")
+    ranks = np.empty(n3, dtype=np.int32)
+    mi = C.c_double(0.0)
+    sw = _load().or_tsvt_dft(n1, n2, n3, _p(Z), float(tau), _p(Y), ranks.ctypes.data_as(C.POINTER(C.c_int32)),
+                             C.byref(mi), max_sweeps)
+    out = [Y]
+    if return_ranks:
+        out += [ranks, sw]
+    if return_imag:
+        out.append(mi.value)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def tnn_f(X, max_sweeps: int = MAX_SWEEPS) -> float:
+    """TNN-F: (1/n3) * sum of nuclear norms of the unnormalized DFT slices."""
+    X = _as3(X)
+    return float(_load().or_tnn_f(*X.shape, _p(X), max_sweeps))

@@ -488,3 +488,255 @@ int or_complete(int64_t n1, int64_t n2, int64_t n3, const double* B, const uint8
     free(Z); free(Y);
     return it;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Section 6 (concluding remarks): other invertible transforms along the     */
+/* tubes in place of the DCT.  With a transform matrix L (row-major n3 x n3) */
+/* and its inverse Linv (supplied by the caller):                             */
+/*   Zbar(:,:,k) = sum_t L[k][t] Z(:,:,t),  Ybar^(k) = U (S - tau)_+ V^T of   */
+/*   Zbar^(k),  Y(:,:,t) = sum_k Linv[t][k] Ybar(:,:,k).                      */
+/* With L = C (orthonormal DCT-II) this is or_tsvt_dct.                       */
+/* ------------------------------------------------------------------------- */
+int or_tsvt_transform(int64_t n1, int64_t n2, int64_t n3, const double* L, const double* Linv, const double* Z,
+                      double tau, double* Y, int32_t* ranks, int max_sweeps) {
+    int64_t s = n1 * n2;
+    double* Zb = (double*)malloc(sizeof(double) * s * n3);
+    double* Yb = (double*)malloc(sizeof(double) * s * n3);
+    int* sw = (int*)malloc(sizeof(int) * n3);
+    tube_apply(n1, n2, n3, L, 0, Z, Zb);
+    struct svt_ctx c = {n1, n2, Zb, Yb, tau, ranks, max_sweeps, sw};
+    parallel_for(n3, svt_range, &c);
+    int worst = worst_sweeps(sw, n3);
+    tube_apply(n1, n2, n3, Linv, 0, Yb, Y);
+    free(Zb); free(Yb); free(sw);
+    return worst;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Section 2: the DFT-based t-SVD and TNN-F (complex arithmetic, C99).        */
+/* Xt = fft(X,[],3), the unnormalized DFT along every tube:                   */
+/*   Xt(i,j,k) = sum_t X(i,j,t) exp(-2 pi i k t / n3),                        */
+/* written out from the definition (O(n3^2) per tube).  The angle k t is     */
+/* reduced modulo n3 in integers before the cosine and sine.                  */
+/* ------------------------------------------------------------------------- */
+#include <complex.h>
+
+static void dft_twiddle(int64_t n, int64_t k, int64_t t, double sgn, double* re, double* im) {
+    const double pi = acos(-1.0);
+    const int64_t q = (k * t) % n;
+    const double a = 2.0 * pi * (double)q / (double)n;
+    *re = cos(a);
+    *im = sgn * sin(a);
+}
+
+/* Real input X; output real and imaginary parts (same layout). */
+void or_dft_tubes(int64_t n1, int64_t n2, int64_t n3, const double* X, double* Xr, double* Xi) {
+    for (int64_t j = 0; j < n2; ++j)
+        for (int64_t i = 0; i < n1; ++i)
+            for (int64_t k = 0; k < n3; ++k) {
+                double ar = 0.0, ai = 0.0;
+                for (int64_t t = 0; t < n3; ++t) {
+                    double wr, wi;
+                    dft_twiddle(n3, k, t, -1.0, &wr, &wi);
+                    const double x = X[X3(i, j, t, n1, n2)];
+                    ar += wr * x;
+                    ai += wi * x;
+                }
+                Xr[X3(i, j, k, n1, n2)] = ar;
+                Xi[X3(i, j, k, n1, n2)] = ai;
+            }
+}
+
+/* Inverse DFT along tubes, X(i,j,t) = (1/n3) sum_k Xt(i,j,k) exp(2 pi i k t / n3),
+ * of complex input (Xr, Xi); outputs real and imaginary parts. */
+void or_idft_tubes(int64_t n1, int64_t n2, int64_t n3, const double* Xr, const double* Xi, double* Yr, double* Yi) {
+    for (int64_t j = 0; j < n2; ++j)
+        for (int64_t i = 0; i < n1; ++i)
+            for (int64_t t = 0; t < n3; ++t) {
+                double ar = 0.0, ai = 0.0;
+                for (int64_t k = 0; k < n3; ++k) {
+                    double wr, wi;
+                    dft_twiddle(n3, k, t, 1.0, &wr, &wi);
+                    const double xr = Xr[X3(i, j, k, n1, n2)], xi = Xi[X3(i, j, k, n1, n2)];
+                    ar += wr * xr - wi * xi;
+                    ai += wr * xi + wi * xr;
+                }
+                Yr[X3(i, j, t, n1, n2)] = ar / (double)n3;
+                Yi[X3(i, j, t, n1, n2)] = ai / (double)n3;
+            }
+}
+
+/* Equation (bcirc): the block circulant matrix of X, (n1 n3) x (n2 n3),      */
+/* column-major; block (r, c) is X^(((r - c) mod n3) + 1).                     */
+void or_bcirc(int64_t n1, int64_t n2, int64_t n3, const double* X, double* M) {
+    const int64_t ld = n1 * n3;
+    for (int64_t bc = 0; bc < n3; ++bc)
+        for (int64_t br = 0; br < n3; ++br) {
+            const int64_t k = ((br - bc) % n3 + n3) % n3;
+            for (int64_t j = 0; j < n2; ++j)
+                for (int64_t i = 0; i < n1; ++i) M[(br * n1 + i) + ld * (bc * n2 + j)] = X[X3(i, j, k, n1, n2)];
+        }
+}
+
+/* One-sided Jacobi SVD of a complex m x n matrix (Hestenes; complex columns).
+ * For the pair (x, y) with alpha = |x|^2, beta = |y|^2, gamma = x^H y =
+ * |gamma| e^{i phi}: y is first multiplied by e^{-i phi}, which makes the
+ * pair's inner product real (|gamma|), then the real rotation of the real case
+ * is applied: zeta = (beta - alpha) / (2 |gamma|), t = sgn(zeta) / (|zeta| +
+ * sqrt(1 + zeta^2)), c = 1/sqrt(1 + t^2), s = c t.  The same unitary acts on
+ * the columns of V.  Rotation test |gamma| > tol sqrt(alpha beta), tol = m u.
+ * Works on A (tall form: A itself if m >= n, else A^H); returns the sweeps
+ * (-1 at the limit).  Outputs for the tall form: W (mm x p, columns sigma_j
+ * u_j, unsorted) and Q (p x p) with A_tall Q = W. */
+static int jacobi_tall_c(int64_t m, int64_t n, double complex* W, double complex* V, int max_sweeps, double tol) {
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t r = 0; r < n; ++r) V[r + n * c] = (r == c) ? 1.0 : 0.0;
+    for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
+        int64_t rotations = 0;
+        for (int64_t i = 0; i < n - 1; ++i)
+            for (int64_t j = i + 1; j < n; ++j) {
+                double complex* wi = W + m * i;
+                double complex* wj = W + m * j;
+                double alpha = 0.0, beta = 0.0;
+                double complex gamma = 0.0;
+                for (int64_t r = 0; r < m; ++r) {
+                    alpha += creal(wi[r] * conj(wi[r]));
+                    beta += creal(wj[r] * conj(wj[r]));
+                    gamma += conj(wi[r]) * wj[r];
+                }
+                const double ag = cabs(gamma);
+                if (ag == 0.0 || ag <= tol * sqrt(alpha * beta)) continue;
+                const double complex ph = conj(gamma) / ag; /* e^{-i phi} */
+                double zeta = (beta - alpha) / (2.0 * ag);
+                double sgn = (zeta >= 0.0) ? 1.0 : -1.0;
+                double t = sgn / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                double c = 1.0 / sqrt(1.0 + t * t);
+                double s = c * t;
+                for (int64_t r = 0; r < m; ++r) {
+                    double complex a = wi[r], b = wj[r] * ph;
+                    wi[r] = c * a - s * b;
+                    wj[r] = s * a + c * b;
+                }
+                double complex* vi = V + n * i;
+                double complex* vj = V + n * j;
+                for (int64_t r = 0; r < n; ++r) {
+                    double complex a = vi[r], b = vj[r] * ph;
+                    vi[r] = c * a - s * b;
+                    vj[r] = s * a + c * b;
+                }
+                ++rotations;
+            }
+        if (rotations == 0) return sweep;
+    }
+    return -1;
+}
+
+/* Singular values (descending) of a complex m x n matrix (column-major,
+ * real and imaginary parts); optionally its thresholded rebuild
+ * Y = U (S - tau)_+ V^H (Yr, Yi may be NULL).  Returns the sweeps. */
+int or_jacobi_svt_c(int64_t m, int64_t n, const double* Ar, const double* Ai, double tau, double* s, double* Yr,
+                    double* Yi, int32_t* rank, int max_sweeps) {
+    const int trans = m < n;
+    const int64_t mm = trans ? n : m, p = trans ? m : n;
+    double complex* W = (double complex*)malloc(sizeof(double complex) * mm * p);
+    double complex* Q = (double complex*)malloc(sizeof(double complex) * p * p);
+    for (int64_t c = 0; c < p; ++c)
+        for (int64_t r = 0; r < mm; ++r) {
+            /* tall form: A (m >= n) or A^H */
+            const int64_t e = trans ? c + m * r : r + m * c;
+            const double complex a = Ar[e] + I * Ai[e];
+            W[r + mm * c] = trans ? conj(a) : a;
+        }
+    const int sweeps = jacobi_tall_c(mm, p, W, Q, max_sweeps, (double)mm * ldexp(1.0, -53));
+    double* sv = (double*)malloc(sizeof(double) * p);
+    for (int64_t c = 0; c < p; ++c) {
+        double acc = 0.0;
+        for (int64_t r = 0; r < mm; ++r) acc += creal(W[r + mm * c] * conj(W[r + mm * c]));
+        sv[c] = sqrt(acc);
+    }
+    int32_t rk = 0;
+    for (int64_t c = 0; c < p; ++c) if (sv[c] > tau) ++rk;
+    if (rank) *rank = rk;
+    if (s) { /* descending, by repeated selection */
+        char* used = (char*)calloc((size_t)p, 1);
+        for (int64_t o = 0; o < p; ++o) {
+            int64_t best = -1;
+            for (int64_t c = 0; c < p; ++c)
+                if (!used[c] && (best < 0 || sv[c] > sv[best])) best = c;
+            used[best] = 1;
+            s[o] = sv[best];
+        }
+        free(used);
+    }
+    if (Yr) {
+        /* tall form: A_t = sum_c u_c sigma_c q_c^H with u_c sigma_c = W(:,c);
+         * thresholded: sum_c W(:,c) (sigma_c - tau)/sigma_c q_c^H */
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < m; ++i) {
+                double complex acc = 0.0;
+                for (int64_t c = 0; c < p; ++c) {
+                    const double d = sv[c] - tau;
+                    if (d <= 0.0) continue;
+                    const double f = d / sv[c];
+                    /* element (i, j) of the tall rebuild, or of its conjugate transpose */
+                    acc += trans ? conj(W[j + mm * c] * f * conj(Q[i + p * c])) : W[i + mm * c] * f * conj(Q[j + p * c]);
+                }
+                Yr[i + m * j] = creal(acc);
+                Yi[i + m * j] = cimag(acc);
+            }
+    }
+    free(W); free(Q); free(sv);
+    return sweeps;
+}
+
+/* Slice-wise complex t-SVT in the Fourier domain (Lu et al.'s TNN-F t-SVT,
+ * the DFT counterpart of Theorem 5): Zt = fft(Z,[],3); every slice k gets
+ * Yt^(k) = U (S - tau)_+ V^H; Y = ifft(Yt).  Y is real for real Z (conjugate
+ * slices give conjugate results); the largest |imaginary part| of the
+ * inverse transform is returned in *max_imag.  ranks[k] (may be NULL).
+ * Returns the largest sweep count, or -1. */
+struct svtc_ctx { int64_t n1, n2; const double *Zr, *Zi; double *Yr, *Yi; double tau; int32_t* ranks; int max_sweeps; int* sw; };
+static void svtc_range(void* a, int64_t k0, int64_t k1) {
+    const struct svtc_ctx* c = (const struct svtc_ctx*)a;
+    const int64_t s = c->n1 * c->n2;
+    for (int64_t k = k0; k < k1; ++k)
+        c->sw[k] = or_jacobi_svt_c(c->n1, c->n2, c->Zr + k * s, c->Zi + k * s, c->tau, NULL, c->Yr + k * s,
+                                   c->Yi + k * s, c->ranks ? c->ranks + k : NULL, c->max_sweeps);
+}
+
+int or_tsvt_dft(int64_t n1, int64_t n2, int64_t n3, const double* Z, double tau, double* Y, int32_t* ranks,
+                double* max_imag, int max_sweeps) {
+    const int64_t N = n1 * n2 * n3;
+    double* Zr = (double*)malloc(sizeof(double) * N);
+    double* Zi = (double*)malloc(sizeof(double) * N);
+    double* Yr = (double*)malloc(sizeof(double) * N);
+    double* Yi = (double*)malloc(sizeof(double) * N);
+    double* Ti = (double*)malloc(sizeof(double) * N);
+    int* sw = (int*)malloc(sizeof(int) * n3);
+    or_dft_tubes(n1, n2, n3, Z, Zr, Zi);
+    struct svtc_ctx c = {n1, n2, Zr, Zi, Yr, Yi, tau, ranks, max_sweeps, sw};
+    parallel_for(n3, svtc_range, &c);
+    or_idft_tubes(n1, n2, n3, Yr, Yi, Y, Ti);
+    double mi = 0.0;
+    for (int64_t e = 0; e < N; ++e) if (fabs(Ti[e]) > mi) mi = fabs(Ti[e]);
+    if (max_imag) *max_imag = mi;
+    int worst = worst_sweeps(sw, n3);
+    free(Zr); free(Zi); free(Yr); free(Yi); free(Ti); free(sw);
+    return worst;
+}
+
+/* Section 2, TNN-F: (1/n3) sum_k ||Xt^(k)||_* over the unnormalized DFT slices. */
+double or_tnn_f(int64_t n1, int64_t n2, int64_t n3, const double* X, int max_sweeps) {
+    const int64_t N = n1 * n2 * n3, s = n1 * n2, p = n1 < n2 ? n1 : n2;
+    double* Xr = (double*)malloc(sizeof(double) * N);
+    double* Xi = (double*)malloc(sizeof(double) * N);
+    double* sv = (double*)malloc(sizeof(double) * p);
+    or_dft_tubes(n1, n2, n3, X, Xr, Xi);
+    double acc = 0.0;
+    for (int64_t k = 0; k < n3; ++k) {
+        or_jacobi_svt_c(n1, n2, Xr + k * s, Xi + k * s, 0.0, sv, NULL, NULL, NULL, max_sweeps);
+        for (int64_t c = 0; c < p; ++c) acc += sv[c];
+    }
+    free(Xr); free(Xi); free(sv);
+    return acc / (double)n3;
+}
