@@ -98,7 +98,7 @@ enum {
                                   from the previous iteration's right singular vectors, resetting
                                   them to the identity every 64 iterations; N >= 1: reset every N
                                   iterations; 0: cold starts */
-    TSVD_OPT_COOPERATIVE = 10  /* 0 (default): ordinary launches of the multi-workgroup Jacobi kernel
+    TSVD_OPT_COOPERATIVE = 10, /* 0 (default): ordinary launches of the multi-workgroup Jacobi kernel
                                   (its grid is sized so that every team is resident, and a team
                                   wait that exceeds the spin limit returns TSVD_ETIMEOUT); 1:
                                   cooperative launches outside graph capture (the runtime then
@@ -107,6 +107,11 @@ enum {
                                   segmentation fault at exit under rocprofv3, one that made only
                                   ordinary launches did not.  The environment variable
                                   TSVDMI_COOPERATIVE=1 sets 1 at context creation. */
+    TSVD_OPT_GRAM = 11         /* block-Gram Jacobi kernel for slices that need several workgroups
+                                  (column blocks of 16: Gram matrices and the accumulated rotations
+                                  applied on the matrix cores): 0 a candidate of the tuner, 1
+                                  forced (team size from TSVD_OPT_TEAM_SIZE, else one workgroup
+                                  per 32 columns), -1 (default) never used */
 };
 int tsvd_set_option(tsvd_ctx* ctx, int option, double value);
 double tsvd_get_option(const tsvd_ctx* ctx, int option);
@@ -198,6 +203,42 @@ int tsvt_dct(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const 
 #define TSVD_NOALLOC_MAX_BYTES ((size_t)128 << 20)
 int tsvt_dct_noalloc(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const void* Z, void* Y,
                      double tau, int32_t* ranks_out, void* stream);
+
+/* t-SVT under another invertible transform along the tubes (concluding
+ * remarks: transforms other than the DCT in the t-SVD framework):
+ *   Zbar(:,:,k) = sum_t L[k][t] Z(:,:,t);  Ybar^(k) = Ubar (Sbar - tau)_+ Vbar^T
+ *   of Zbar^(k);  Y(:,:,t) = sum_k Linv[t][k] Ybar(:,:,k).
+ * L: HOST row-major n3 x n3 FP64 matrix, invertible; Linv is computed on the
+ * host in FP64 (Gauss-Jordan with partial pivoting).  With L = the
+ * orthonormal DCT-II matrix this is tsvt_dct.  For an orthogonal L the result
+ * is the proximal map of tau * sum_k ||(L Y)^(k)||_*.  L is copied; its device
+ * form is kept in the context and rebuilt when L changes (which waits for the
+ * stream).  TSVD_EINVAL for a NULL, singular or non-finite L; otherwise as
+ * tsvt_dct. */
+int tsvt_transform(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const double* L, const void* Z,
+                   void* Y, double tau, int32_t* ranks_out, void* stream);
+
+/* t-SVT in the Fourier domain (Section 2: the DFT-based t-SVD, TNN-F): every
+ * frontal slice of the unnormalized Zt = fft(Z,[],3) is thresholded at tau,
+ * Yt^(k) = U (S - tau)_+ V^H, and Y = ifft(Yt,[],3), real for real Z.  This is
+ * the proximal map of tau * TNN-F (the 1/n3 of TNN-F cancels the unnormalized
+ * transform's scale).  Conjugate symmetry leaves floor((n3-1)/2) complex
+ * slices and one or two real ones; a complex slice B + iC is thresholded
+ * through its real form [[B, -C], [C, B]] (same singular values, each twice)
+ * on the DCT path's kernels.  ranks_out (host, n3 entries or NULL) gets the
+ * rank of every Fourier slice k = 0..n3-1.  Slices of at most 256 rows and
+ * columns (their real forms are at most 512).  Otherwise as tsvt_dct. */
+int tsvt_dft(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const void* Z, void* Y, double tau,
+             int32_t* ranks_out, void* stream);
+
+/* TNN-C, equation (equTNN1): (1/n3) sum_k ||Xbar^(k)||_*, with Xbar =
+ * dct(X,[],3).  *out receives the value (host); the call synchronizes. */
+int tnn_c(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const void* X, double* out, void* stream);
+
+/* TNN-F, equation (tnn): (1/n3) sum_k ||Xt^(k)||_* over the slices of the
+ * unnormalized Xt = fft(X,[],3) (same slice limit as tsvt_dft).  *out
+ * receives the value (host); the call synchronizes. */
+int tnn_f(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const void* X, double* out, void* stream);
 
 /* Algorithm 1 (ADMM for TNN-C completion).
  *   B    : observed data (only entries with mask != 0 are read).

@@ -519,7 +519,6 @@ int or_tsvt_transform(int64_t n1, int64_t n2, int64_t n3, const double* L, const
 /* written out from the definition (O(n3^2) per tube).  The angle k t is     */
 /* reduced modulo n3 in integers before the cosine and sine.                  */
 /* ------------------------------------------------------------------------- */
-#include <complex.h>
 
 static void dft_twiddle(int64_t n, int64_t k, int64_t t, double sgn, double* re, double* im) {
     const double pi = acos(-1.0);
@@ -588,41 +587,47 @@ void or_bcirc(int64_t n1, int64_t n2, int64_t n3, const double* X, double* M) {
  * Works on A (tall form: A itself if m >= n, else A^H); returns the sweeps
  * (-1 at the limit).  Outputs for the tall form: W (mm x p, columns sigma_j
  * u_j, unsorted) and Q (p x p) with A_tall Q = W. */
-static int jacobi_tall_c(int64_t m, int64_t n, double complex* W, double complex* V, int max_sweeps, double tol) {
+static int jacobi_tall_c(int64_t m, int64_t n, double* Wr, double* Wi, double* Vr, double* Vi, int max_sweeps,
+                         double tol) {
+    /* complex values as separate real and imaginary arrays, same layout */
     for (int64_t c = 0; c < n; ++c)
-        for (int64_t r = 0; r < n; ++r) V[r + n * c] = (r == c) ? 1.0 : 0.0;
+        for (int64_t r = 0; r < n; ++r) {
+            Vr[r + n * c] = (r == c) ? 1.0 : 0.0;
+            Vi[r + n * c] = 0.0;
+        }
     for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
         int64_t rotations = 0;
         for (int64_t i = 0; i < n - 1; ++i)
             for (int64_t j = i + 1; j < n; ++j) {
-                double complex* wi = W + m * i;
-                double complex* wj = W + m * j;
-                double alpha = 0.0, beta = 0.0;
-                double complex gamma = 0.0;
+                double *xr = Wr + m * i, *xi = Wi + m * i, *yr = Wr + m * j, *yi = Wi + m * j;
+                double alpha = 0.0, beta = 0.0, gr = 0.0, gi = 0.0;
                 for (int64_t r = 0; r < m; ++r) {
-                    alpha += creal(wi[r] * conj(wi[r]));
-                    beta += creal(wj[r] * conj(wj[r]));
-                    gamma += conj(wi[r]) * wj[r];
+                    alpha += xr[r] * xr[r] + xi[r] * xi[r];
+                    beta += yr[r] * yr[r] + yi[r] * yi[r];
+                    /* gamma = conj(x) . y */
+                    gr += xr[r] * yr[r] + xi[r] * yi[r];
+                    gi += xr[r] * yi[r] - xi[r] * yr[r];
                 }
-                const double ag = cabs(gamma);
+                const double ag = sqrt(gr * gr + gi * gi);
                 if (ag == 0.0 || ag <= tol * sqrt(alpha * beta)) continue;
-                const double complex ph = conj(gamma) / ag; /* e^{-i phi} */
+                const double pr = gr / ag, pi = -gi / ag; /* e^{-i phi} = conj(gamma) / |gamma| */
                 double zeta = (beta - alpha) / (2.0 * ag);
                 double sgn = (zeta >= 0.0) ? 1.0 : -1.0;
                 double t = sgn / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                 double c = 1.0 / sqrt(1.0 + t * t);
                 double s = c * t;
                 for (int64_t r = 0; r < m; ++r) {
-                    double complex a = wi[r], b = wj[r] * ph;
-                    wi[r] = c * a - s * b;
-                    wj[r] = s * a + c * b;
+                    const double ar = xr[r], ai = xi[r];
+                    const double br = yr[r] * pr - yi[r] * pi, bi = yr[r] * pi + yi[r] * pr; /* y e^{-i phi} */
+                    xr[r] = c * ar - s * br; xi[r] = c * ai - s * bi;
+                    yr[r] = s * ar + c * br; yi[r] = s * ai + c * bi;
                 }
-                double complex* vi = V + n * i;
-                double complex* vj = V + n * j;
+                double *ur = Vr + n * i, *ui = Vi + n * i, *wr = Vr + n * j, *wi = Vi + n * j;
                 for (int64_t r = 0; r < n; ++r) {
-                    double complex a = vi[r], b = vj[r] * ph;
-                    vi[r] = c * a - s * b;
-                    vj[r] = s * a + c * b;
+                    const double ar = ur[r], ai = ui[r];
+                    const double br = wr[r] * pr - wi[r] * pi, bi = wr[r] * pi + wi[r] * pr;
+                    ur[r] = c * ar - s * br; ui[r] = c * ai - s * bi;
+                    wr[r] = s * ar + c * br; wi[r] = s * ai + c * bi;
                 }
                 ++rotations;
             }
@@ -638,20 +643,22 @@ int or_jacobi_svt_c(int64_t m, int64_t n, const double* Ar, const double* Ai, do
                     double* Yi, int32_t* rank, int max_sweeps) {
     const int trans = m < n;
     const int64_t mm = trans ? n : m, p = trans ? m : n;
-    double complex* W = (double complex*)malloc(sizeof(double complex) * mm * p);
-    double complex* Q = (double complex*)malloc(sizeof(double complex) * p * p);
+    double* Wr = (double*)malloc(sizeof(double) * mm * p);
+    double* Wi = (double*)malloc(sizeof(double) * mm * p);
+    double* Qr = (double*)malloc(sizeof(double) * p * p);
+    double* Qi = (double*)malloc(sizeof(double) * p * p);
     for (int64_t c = 0; c < p; ++c)
         for (int64_t r = 0; r < mm; ++r) {
             /* tall form: A (m >= n) or A^H */
             const int64_t e = trans ? c + m * r : r + m * c;
-            const double complex a = Ar[e] + I * Ai[e];
-            W[r + mm * c] = trans ? conj(a) : a;
+            Wr[r + mm * c] = Ar[e];
+            Wi[r + mm * c] = trans ? -Ai[e] : Ai[e];
         }
-    const int sweeps = jacobi_tall_c(mm, p, W, Q, max_sweeps, (double)mm * ldexp(1.0, -53));
+    const int sweeps = jacobi_tall_c(mm, p, Wr, Wi, Qr, Qi, max_sweeps, (double)mm * ldexp(1.0, -53));
     double* sv = (double*)malloc(sizeof(double) * p);
     for (int64_t c = 0; c < p; ++c) {
         double acc = 0.0;
-        for (int64_t r = 0; r < mm; ++r) acc += creal(W[r + mm * c] * conj(W[r + mm * c]));
+        for (int64_t r = 0; r < mm; ++r) acc += Wr[r + mm * c] * Wr[r + mm * c] + Wi[r + mm * c] * Wi[r + mm * c];
         sv[c] = sqrt(acc);
     }
     int32_t rk = 0;
@@ -669,23 +676,27 @@ int or_jacobi_svt_c(int64_t m, int64_t n, const double* Ar, const double* Ai, do
         free(used);
     }
     if (Yr) {
-        /* tall form: A_t = sum_c u_c sigma_c q_c^H with u_c sigma_c = W(:,c);
-         * thresholded: sum_c W(:,c) (sigma_c - tau)/sigma_c q_c^H */
+        /* tall form A_t = W Q^H with columns W(:,c) = sigma_c u_c; thresholded:
+         * sum_c W(:,c) ((sigma_c - tau)/sigma_c) conj(Q(:,c))^T.  Element (i, j)
+         * of A is element (i, j) of A_t (m >= n) or conj of element (j, i). */
         for (int64_t j = 0; j < n; ++j)
             for (int64_t i = 0; i < m; ++i) {
-                double complex acc = 0.0;
+                double accr = 0.0, acci = 0.0;
                 for (int64_t c = 0; c < p; ++c) {
                     const double d = sv[c] - tau;
                     if (d <= 0.0) continue;
                     const double f = d / sv[c];
-                    /* element (i, j) of the tall rebuild, or of its conjugate transpose */
-                    acc += trans ? conj(W[j + mm * c] * f * conj(Q[i + p * c])) : W[i + mm * c] * f * conj(Q[j + p * c]);
+                    const int64_t a = trans ? j : i, b = trans ? i : j; /* (row of W, row of Q) */
+                    const double wr = Wr[a + mm * c], wi = Wi[a + mm * c];
+                    const double qr = Qr[b + p * c], qi = -Qi[b + p * c]; /* conj(Q) */
+                    accr += f * (wr * qr - wi * qi);
+                    acci += f * (wr * qi + wi * qr);
                 }
-                Yr[i + m * j] = creal(acc);
-                Yi[i + m * j] = cimag(acc);
+                Yr[i + m * j] = accr;
+                Yi[i + m * j] = trans ? -acci : acci;
             }
     }
-    free(W); free(Q); free(sv);
+    free(Wr); free(Wi); free(Qr); free(Qi); free(sv);
     return sweeps;
 }
 

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libtsvdmi.so")
 FP64, FP32, MIXED = 0, 1, 2
 OK, WARN_NOCONV, EINVAL, ENOMEM, EHIP, ENONFINITE, EBUSY, ETIMEOUT, ECANCELED = 0, 1, -1, -2, -3, -4, -5, -6, -7
 OPT_MAX_SWEEPS, OPT_SYNC_STATUS, OPT_TEAM_SIZE, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_GRAPHS = 0, 1, 2, 3, 4, 5
-OPT_AUTOTUNE, OPT_GROUP_LANES, OPT_GROUP_COLUMNS, OPT_WARM_START, OPT_COOPERATIVE = 6, 7, 8, 9, 10
+OPT_AUTOTUNE, OPT_GROUP_LANES, OPT_GROUP_COLUMNS, OPT_WARM_START, OPT_COOPERATIVE, OPT_GRAM = 6, 7, 8, 9, 10, 11
 PHASES = ("forward_transform", "jacobi", "threshold_rebuild", "inverse_transform", "warm_start")
 TRANSFORM_DOMAIN = 1
 REQ_TSVT, REQ_COMPLETE = 0, 1
@@ -30,7 +30,8 @@ REQ_TSVT, REQ_COMPLETE = 0, 1
 EXPORTED = [
     "tsvd_create", "tsvd_destroy", "tsvd_last_error", "tsvd_set_option", "tsvd_get_option", "tsvd_sync_status",
     "tsvd_get_stats", "tsvd_get_tile",
-    "tprod_dct", "tsvd_dct", "tsvt_dct", "tsvt_dct_noalloc", "complete_tensor", "tsvt_dct_batched", "tsvd_server_create",
+    "tprod_dct", "tsvd_dct", "tsvt_dct", "tsvt_dct_noalloc", "tsvt_transform", "tsvt_dft", "tnn_c", "tnn_f",
+    "complete_tensor", "tsvt_dct_batched", "tsvd_server_create",
     "tsvd_server_submit", "tsvd_server_cancel", "tsvd_server_poll", "tsvd_server_now", "tsvd_server_stats",
     "tsvd_server_destroy",
 ]
@@ -78,6 +79,10 @@ lib.tprod_dct.argtypes = [_vp, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp]
 lib.tsvd_dct.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _i32, _vp]
 lib.tsvt_dct.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _d, C.POINTER(C.c_int32), _vp]
 lib.tsvt_dct_noalloc.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _d, C.POINTER(C.c_int32), _vp]
+lib.tsvt_transform.argtypes = [_vp, _i32, _i64, _i64, _i64, C.POINTER(_d), _vp, _vp, _d, C.POINTER(C.c_int32), _vp]
+lib.tsvt_dft.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _d, C.POINTER(C.c_int32), _vp]
+lib.tnn_c.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, C.POINTER(_d), _vp]
+lib.tnn_f.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, C.POINTER(_d), _vp]
 lib.complete_tensor.argtypes = [_vp, _i32, _i64, _i64, _i64, _vp, _vp, _vp, C.POINTER(CompleteOpts),
                                 C.POINTER(CompleteInfo), _vp]
 lib.tsvt_dct_batched.argtypes = [_vp, _i32, _i32, C.POINTER(C.c_int64), C.POINTER(_vp), C.POINTER(_vp),
@@ -248,6 +253,68 @@ def tsvt_dct(Z: torch.Tensor, tau: float, Y: Optional[torch.Tensor] = None, prec
     if return_ranks:
         return Y, [int(r) for r in ranks]
     return Y
+
+
+def tsvt_transform(Z: torch.Tensor, tau: float, L, Y: Optional[torch.Tensor] = None, prec: Optional[int] = None,
+                   return_ranks: bool = False, ctx: Optional[Context] = None, stream=None):
+    """t-SVT under an invertible transform L (n3 x n3, host, row-major
+    L[k][t]) along the tubes in place of the DCT."""
+    Z = fortran(Z)
+    d = _dev(Z)
+    prec = _prec_of(Z, prec)
+    ctx = ctx or default_context(d)
+    n1, n2, n3 = Z.shape
+    Lf = [float(v) for row in L for v in row] if not hasattr(L, "ravel") else [float(v) for v in L.ravel()]
+    if len(Lf) != n3 * n3:
+        raise ValueError("L must be n3 x n3")
+    Lc = (C.c_double * (n3 * n3))(*Lf)
+    if Y is None:
+        Y = empty_f(n1, n2, n3, Z.dtype, Z.device)
+    ranks = (C.c_int32 * n3)() if return_ranks else None
+    ctx.check(lib.tsvt_transform(ctx.h, prec, n1, n2, n3, Lc, Z.data_ptr(), Y.data_ptr(), float(tau), ranks,
+                                 _stream(stream, d)))
+    if return_ranks:
+        return Y, [int(r) for r in ranks]
+    return Y
+
+
+def tsvt_dft(Z: torch.Tensor, tau: float, Y: Optional[torch.Tensor] = None, prec: Optional[int] = None,
+             return_ranks: bool = False, ctx: Optional[Context] = None, stream=None):
+    """Fourier-domain t-SVT (the prox of tau * TNN-F).  Returns Y (and the
+    rank of every Fourier slice)."""
+    Z = fortran(Z)
+    d = _dev(Z)
+    prec = _prec_of(Z, prec)
+    ctx = ctx or default_context(d)
+    n1, n2, n3 = Z.shape
+    if Y is None:
+        Y = empty_f(n1, n2, n3, Z.dtype, Z.device)
+    ranks = (C.c_int32 * n3)() if return_ranks else None
+    ctx.check(lib.tsvt_dft(ctx.h, prec, n1, n2, n3, Z.data_ptr(), Y.data_ptr(), float(tau), ranks,
+                           _stream(stream, d)))
+    if return_ranks:
+        return Y, [int(r) for r in ranks]
+    return Y
+
+
+def _tnn(fn, X, prec, ctx, stream):
+    X = fortran(X)
+    d = _dev(X)
+    prec = _prec_of(X, prec)
+    ctx = ctx or default_context(d)
+    out = C.c_double(0.0)
+    ctx.check(fn(ctx.h, prec, *X.shape, X.data_ptr(), C.byref(out), _stream(stream, d)))
+    return out.value
+
+
+def tnn_c(X: torch.Tensor, prec: Optional[int] = None, ctx: Optional[Context] = None, stream=None) -> float:
+    """TNN-C (equation (equTNN1)) of X."""
+    return _tnn(lib.tnn_c, X, prec, ctx, stream)
+
+
+def tnn_f(X: torch.Tensor, prec: Optional[int] = None, ctx: Optional[Context] = None, stream=None) -> float:
+    """TNN-F (equation (tnn)) of X."""
+    return _tnn(lib.tnn_f, X, prec, ctx, stream)
 
 
 NOALLOC_MAX_BYTES = 128 << 20

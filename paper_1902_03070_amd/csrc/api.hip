@@ -53,6 +53,11 @@ struct tsvd_ctx {
     hipStream_t own = nullptr;  // context stream (capture cannot use the legacy default stream)
     int noalloc = 0;            // inside tsvt_dct_noalloc: no tuning, no profiling events
     int coop = 0;               // 1: cooperative launches of the team kernel outside capture
+    int gram = -1;              // block-Gram kernel: 0 a tuner candidate, 1 forced, -1 excluded
+    // operands of a caller-given tube transform (tsvt_transform, the DFT path), cached by content
+    DevBuf xf;
+    std::vector<double> xf_key;
+    int xf_eng = -1;
 };
 
 // Fixed scratch of tsvt_dct_noalloc (TSVD_NOALLOC_MAX_BYTES).  Every GPU the
@@ -322,7 +327,7 @@ struct Plan {
 //           (batched plans: a team of one workgroup of kTeamMaxThreads lanes).
 // ---------------------------------------------------------------------------
 struct Tile {
-    int team = 0;
+    int team = 0;    // 0 resident, 1 multi-workgroup (column pairs), 2 multi-workgroup block-Gram
     int G = 16;
     int W = 0;
     int threads = 0;
@@ -360,6 +365,28 @@ int apply_tile(tsvd_ctx* c, Plan& P, const Tile& t, bool batched) {
         P.job.b = 0;
         P.job.nb = 0;
         P.ts = TeamSched{1, 0, nullptr};
+        return TSVD_OK;
+    }
+    if (t.team == 2) {
+        // block-Gram: blocks of kGramB columns, 256 threads, one block pair per workgroup and step
+        if (batched) return fail(c, TSVD_EINVAL, "the block-Gram kernel is a multi-workgroup kernel");
+        const int lds = jacobi_gram_lds_bytes(P.prec, P.m);
+        if (lds > kLdsBudget) return fail(c, TSVD_EINVAL, "slice too large for the block-Gram kernel");
+        int nb = (P.p + kGramBlock - 1) / kGramBlock;
+        nb += nb & 1;
+        int W = std::max(1, std::min(t.W, nb / 2));
+        const int cap = jacobi_gram_max_resident(P.prec, P.m, P.with_v);
+        if (cap < 8) return fail(c, TSVD_EINVAL, "block-Gram kernel cannot be resident with this shape");
+        W = std::min(W, cap / 8);
+        const int per_xcd = std::max(1, std::min(((int)P.n3 + 7) / 8, cap / (8 * W)));
+        P.team = 2;
+        P.lds = lds;
+        P.threads = 256;
+        P.K = 1;
+        P.ts.W = W;
+        P.ts.nwg = 8 * W * per_xcd;
+        P.job.b = kGramBlock;
+        P.job.nb = nb;
         return TSVD_OK;
     }
     P.team = 1;
@@ -463,7 +490,20 @@ Tile default_tile(const Plan& P, int team_size, int group_lanes, int group_cols,
     return t;
 }
 
-std::vector<Tile> tile_candidates(const Plan& P, bool batched) {
+// The forced block-Gram tile of a multi-workgroup plan (W from the team-size
+// option, else one workgroup per 32 columns).
+Tile gram_tile(const Plan& P, int team_size) {
+    Tile t = default_tile(P, team_size, 0, 0, false);
+    if (t.team) {
+        t.team = 2;
+        t.G = 16;
+        t.K = 1;
+        t.W = team_size > 0 ? team_size : std::max(1, (P.p + 31) / 32);
+    }
+    return t;
+}
+
+std::vector<Tile> tile_candidates(const Plan& P, bool batched, int gram) {
     std::vector<Tile> out;
     for (int G : group_widths(P.m, P.p)) {
         Tile t;
@@ -498,6 +538,17 @@ std::vector<Tile> tile_candidates(const Plan& P, bool batched) {
         t.team = 1;
         t.K = 1;
         for (int W : {2, 4, 8, 12, 16}) {
+            t.W = W;
+            out.push_back(t);
+        }
+    }
+    // and the block-Gram kernel (column blocks on the matrix cores)
+    if (!batched && gram >= 0 && !out.empty() && out.back().team) {
+        Tile t;
+        t.team = 2;
+        t.G = 16;
+        t.K = 1;
+        for (int W : {1, 2, 4, 8, 16}) {
             t.W = W;
             out.push_back(t);
         }
@@ -610,6 +661,8 @@ double time_tile(tsvd_ctx* c, const Plan& P0, const Tile& t, bool batched, char*
         else if (!P.team)
             e = launch_jacobi_resident(P.prec, J, nullptr, nullptr, nullptr, ntasks, kTuneSweeps, ctrl, P.lds,
                                        P.threads, P.with_v, s);
+        else if (P.team == 2)
+            e = launch_jacobi_gram(P.prec, J, ntasks, P.ts, kTuneSweeps, ctrl, P.with_v, c->spin_limit, c->coop, s);
         else
             e = launch_jacobi_team(P.prec, J, ntasks, P.ts, kTuneSweeps, ctrl, P.lds, P.threads, P.with_v,
                                    c->spin_limit, J.R, J.G, P.K, c->coop, s);
@@ -631,7 +684,7 @@ double time_tile(tsvd_ctx* c, const Plan& P0, const Tile& t, bool batched, char*
 }
 
 int tune_tile(tsvd_ctx* c, const Plan& P, bool batched, Tile* out, double* us_out) {
-    std::vector<Tile> cands = tile_candidates(P, batched);
+    std::vector<Tile> cands = tile_candidates(P, batched, c->gram);
     if (cands.size() < 2) return -1;
     int rc = ensure_own_stream(c);
     if (rc) return rc;
@@ -699,6 +752,11 @@ int tune_tile(tsvd_ctx* c, const Plan& P, bool batched, Tile* out, double* us_ou
 
 // The tile of a plan: forced by options, cached, autotuned, or the default.
 int pick_tile(tsvd_ctx* c, const Plan& P, bool batched, hipStream_t s, Tile* t) {
+    if (c->gram == 1 && !batched) {
+        *t = gram_tile(P, c->team_size);
+        t->source = 2;
+        return TSVD_OK;
+    }
     if (c->team_size > 0 || c->group_lanes > 0 || c->group_cols > 0) {
         *t = default_tile(P, c->team_size, c->group_lanes, c->group_cols, batched);
         t->source = 2;
@@ -800,6 +858,9 @@ int run_jacobi(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s) {
     if (!P.team)
         e = launch_jacobi_resident(P.prec, P.job, nullptr, nullptr, nullptr, (int)P.n3, clamp_sweeps(c->max_sweeps),
                                    ctrl, P.lds, P.threads, P.with_v, s);
+    else if (P.team == 2)
+        e = launch_jacobi_gram(P.prec, P.job, (int)P.n3, P.ts, clamp_sweeps(c->max_sweeps), ctrl, P.with_v,
+                               c->spin_limit, (c->capturing || !c->coop) ? 0 : 1, s);
     else
         e = launch_jacobi_team(P.prec, P.job, (int)P.n3, P.ts, clamp_sweeps(c->max_sweeps), ctrl, P.lds, P.threads,
                                P.with_v, c->spin_limit, P.job.R, P.job.G, P.K, (c->capturing || !c->coop) ? 0 : 1, s);
@@ -954,6 +1015,199 @@ int tsvt_enqueue(tsvd_ctx* c, Plan& P, char* base, const void* fwd, const void* 
     return finish_call(c, s);
 }
 
+
+// ---------------------------------------------------------------------------
+// Caller-given transforms along the tubes (the concluding remarks' other
+// transforms) and the real Fourier transform of the DFT path.
+// ---------------------------------------------------------------------------
+
+// Inverse of a row-major n x n matrix by Gauss-Jordan elimination with
+// partial pivoting, in FP64 on the host.  False when a pivot is zero or not
+// finite (singular or non-finite matrix).
+bool invert_host(int n, const double* L, std::vector<double>& inv) {
+    std::vector<double> a(L, L + (size_t)n * n);
+    inv.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(a[(size_t)r * n + col]) > fabs(a[(size_t)piv * n + col])) piv = r;
+        const double pv = a[(size_t)piv * n + col];
+        if (!(pv != 0.0) || !isfinite(pv)) return false;
+        if (piv != col)
+            for (int k = 0; k < n; ++k) {
+                std::swap(a[(size_t)piv * n + k], a[(size_t)col * n + k]);
+                std::swap(inv[(size_t)piv * n + k], inv[(size_t)col * n + k]);
+            }
+        const double rp = 1.0 / pv;
+        for (int k = 0; k < n; ++k) {
+            a[(size_t)col * n + k] *= rp;
+            inv[(size_t)col * n + k] *= rp;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            const double f = a[(size_t)r * n + col];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                a[(size_t)r * n + k] -= f * a[(size_t)col * n + k];
+                inv[(size_t)r * n + k] -= f * inv[(size_t)col * n + k];
+            }
+        }
+    }
+    for (double v : inv)
+        if (!isfinite(v)) return false;
+    return true;
+}
+
+// Real form of the unnormalized DFT along a tube of length n (rows = slots):
+// slot 0 the DC term sum_t x_t; for f = 1..h (h = (n-1)/2) slot 2f-1 the
+// real part sum_t x_t cos(2 pi f t / n) and slot 2f the imaginary part
+// -sum_t x_t sin(2 pi f t / n); for even n slot n-1 the Nyquist term
+// sum_t (-1)^t x_t.  Its inverse follows from x_t = (1/n) sum_f Xt_f
+// e^{2 pi i f t / n} with conjugate pairs combined.  Angles are reduced
+// (f t mod n) in integers.
+void real_dft_matrices(int n, std::vector<double>& R, std::vector<double>& Ri) {
+    R.assign((size_t)n * n, 0.0);
+    Ri.assign((size_t)n * n, 0.0);
+    const double pi = acos(-1.0);
+    const int h = (n - 1) / 2;
+    for (int t = 0; t < n; ++t) {
+        R[(size_t)0 * n + t] = 1.0;
+        Ri[(size_t)t * n + 0] = 1.0 / n;
+        for (int f = 1; f <= h; ++f) {
+            const double a = 2.0 * pi * (double)(((int64_t)f * t) % n) / (double)n;
+            R[(size_t)(2 * f - 1) * n + t] = cos(a);
+            R[(size_t)(2 * f) * n + t] = -sin(a);
+            Ri[(size_t)t * n + (2 * f - 1)] = 2.0 * cos(a) / n;
+            Ri[(size_t)t * n + (2 * f)] = -2.0 * sin(a) / n;
+        }
+        if (n % 2 == 0) {
+            const double sg = (t % 2) ? -1.0 : 1.0;
+            R[(size_t)(n - 1) * n + t] = sg;
+            Ri[(size_t)t * n + (n - 1)] = sg / n;
+        }
+    }
+}
+
+// Device operands (forward L, inverse Li) of a caller-given transform in the
+// form run_tube_mat takes, kept in the context and rebuilt only when L or the
+// engine changes.  Rebuilding waits for the stream (earlier calls may still
+// read the old operands).
+int get_custom_operands(tsvd_ctx* c, int prec, int n3, const double* L, const double* Li, hipStream_t s,
+                        const void** fwd, const void** inv) {
+    const int eng = tube_engine(prec);
+    const size_t nn = (size_t)n3 * n3;
+    const size_t one = align256(tube_matrix_bytes(eng, n3));
+    const bool same = c->xf_eng == eng && c->xf_key.size() == nn && memcmp(c->xf_key.data(), L, nn * 8) == 0;
+    if (!same) {
+        std::vector<unsigned char> h(2 * one, 0);
+        if (n3 <= kMaxTube) {
+            make_tube_fragments(eng, n3, L, h.data());
+            make_tube_fragments(eng, n3, Li, h.data() + one);
+        } else {
+            for (size_t e = 0; e < nn; ++e) {
+                if (prec == TSVD_FP64) {
+                    ((double*)h.data())[e] = L[e];
+                    ((double*)(h.data() + one))[e] = Li[e];
+                } else {
+                    ((float*)h.data())[e] = (float)L[e];
+                    ((float*)(h.data() + one))[e] = (float)Li[e];
+                }
+            }
+        }
+        HIPCHK(c, hipStreamSynchronize(s));
+        if (c->xf.bytes < 2 * one) {
+            if (c->xf.p) HIPCHK(c, hipFree(c->xf.p));
+            c->xf.p = nullptr;
+            c->xf.bytes = 0;
+            HIPCHK(c, hipMalloc(&c->xf.p, 2 * one));
+            c->xf.bytes = 2 * one;
+        }
+        HIPCHK(c, hipMemcpy(c->xf.p, h.data(), 2 * one, hipMemcpyHostToDevice));
+        c->xf_key.assign(L, L + nn);
+        c->xf_eng = eng;
+    }
+    *fwd = c->xf.p;
+    *inv = (const char*)c->xf.p + one;
+    return TSVD_OK;
+}
+
+// Slots of the real Fourier transform: h complex frequencies, nreal real ones.
+void dft_layout(int64_t n3, int* h, int* nreal) {
+    *h = (int)((n3 - 1) / 2);
+    *nreal = (n3 % 2 == 0) ? 2 : 1;
+}
+
+// Singular values of every slice of a planned tensor after its Jacobi launch
+// (per column, unsorted) summed on the host; synchronizes `s`.
+int sum_sigma(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s, double* out) {
+    const int dp = P.prec == TSVD_FP64 ? 0 : 1;
+    SvtPrepArgs sp{};
+    sp.A = base + P.o_A; sp.m = P.m; sp.p = P.p; sp.a_ss = (int64_t)P.m * P.p;
+    sp.F = base + P.o_F; sp.f_ss = (int64_t)P.m * P.p;
+    sp.w = (double*)(base + P.o_w); sp.w_ss = P.p;
+    sp.sig = (double*)(base + P.o_sig); sp.sig_ss = P.p;
+    sp.ranks = (int*)(base + P.o_rank); sp.pos = (int*)(base + P.o_pos); sp.n3 = (int)P.n3; sp.tau_val = 0.0;
+    sp.ctrl = ctrl;
+    hipError_t e = launch_svt_prep(dp, sp, s);
+    if (e != hipSuccess) return hip_fail(c, e, "singular values");
+    std::vector<double> h((size_t)P.p * P.n3);
+    HIPCHK(c, hipMemcpyAsync(h.data(), base + P.o_sig, h.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (double v : h) acc += v;
+    *out = acc;
+    return TSVD_OK;
+}
+
+// The DFT path's plans and workspace: the real-transform slots (N elements)
+// at o_zb, then the plan of the h complex slices in real form (2 n1 x 2 n2)
+// and the plan of the real slices.
+struct DftPlan {
+    int h = 0, nreal = 0;
+    size_t o_zb = 0;
+    Plan E, R;
+};
+
+int make_dft_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, DftPlan& D, Carve& cv, hipStream_t s) {
+    if (2 * std::max(n1, n2) > kMaxRows)
+        return fail(c, TSVD_EINVAL, "the DFT path takes frontal slices of at most 256 rows and columns");
+    dft_layout(n3, &D.h, &D.nreal);
+    D.o_zb = cv.take((size_t)n1 * n2 * n3 * esize(prec));
+    int rc;
+    if (D.h > 0 && (rc = make_plan(c, prec, 2 * n1, 2 * n2, D.h, 0, D.E, cv, s))) return rc;
+    if ((rc = make_plan(c, prec, n1, n2, D.nreal, 0, D.R, cv, s))) return rc;
+    return TSVD_OK;
+}
+
+// Forward real DFT of X into the slots and the real forms of its slices in
+// the two plans' inputs; Jacobi-ready.
+int dft_forward(tsvd_ctx* c, DftPlan& D, int prec, int64_t n1, int64_t n2, int64_t n3, const void* X,
+                const void* fwd, char* base, Ctrl* ctrl, hipStream_t s) {
+    int rc;
+    if (D.h > 0 && (rc = upload_plan(c, D.E, base))) return rc;
+    if ((rc = upload_plan(c, D.R, base))) return rc;
+    hipError_t e = hipSuccess;
+    if (D.h > 0) e = launch_fill_zero(base + D.E.o_ctr_begin, D.E.o_ctr_end - D.E.o_ctr_begin, s);
+    if (e == hipSuccess) e = launch_fill_zero(base + D.R.o_ctr_begin, D.R.o_ctr_end - D.R.o_ctr_begin, s);
+    if (e != hipSuccess) return hip_fail(c, e, "fill");
+    TubeArgs f{};
+    f.in = X; f.out = base + D.o_zb; f.N = n1 * n2; f.n3 = (int)n3; f.ctrl = ctrl; f.check_finite = 1;
+    f.beta_val = 1.0;
+    {
+        PhaseMark pm(c, 0, s);
+        if ((rc = run_tube_mat(c, prec, f, 0, fwd, s))) return rc;
+    }
+    DftEmbedArgs ea{};
+    ea.zb = base + D.o_zb;
+    ea.E = D.h > 0 ? (void*)(base + D.E.o_zbar) : nullptr;
+    ea.R = base + D.R.o_zbar;
+    ea.n1 = n1; ea.n2 = n2; ea.n3 = (int)n3; ea.h = D.h; ea.nreal = D.nreal;
+    e = launch_dft_embed(prec == TSVD_FP64 ? 0 : 1, ea, s);
+    if (e != hipSuccess) return hip_fail(c, e, "dft embed");
+    return TSVD_OK;
+}
+
 // Device addresses of the scratch array (see its definition above).
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
@@ -1020,6 +1274,7 @@ void tsvd_destroy(tsvd_ctx* c) {
         (void)hipFree(kv.second.second);
     }
     for (auto& kv : c->frag) (void)hipFree(kv.second);
+    if (c->xf.p) (void)hipFree(c->xf.p);
     if (c->ws.p) (void)hipFree(c->ws.p);
     if (c->ctrl.p) (void)hipFree(c->ctrl.p);
     if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
@@ -1066,6 +1321,10 @@ int tsvd_set_option(tsvd_ctx* c, int opt, double v) {
             c->group_lanes = (int)v;
             return TSVD_OK;
         case TSVD_OPT_COOPERATIVE: c->coop = v != 0.0; return TSVD_OK;
+        case TSVD_OPT_GRAM:
+            if (v != -1 && v != 0 && v != 1) return fail(c, TSVD_EINVAL, "gram option is -1, 0 or 1");
+            c->gram = (int)v;
+            return TSVD_OK;
     }
     return fail(c, TSVD_EINVAL, "unknown option");
 }
@@ -1084,6 +1343,7 @@ double tsvd_get_option(const tsvd_ctx* c, int opt) {
         case TSVD_OPT_WARM_START: return c->warm_start;
         case TSVD_OPT_GROUP_LANES: return c->group_lanes;
         case TSVD_OPT_COOPERATIVE: return c->coop;
+        case TSVD_OPT_GRAM: return c->gram;
     }
     return -1.0;
 }
@@ -1198,6 +1458,140 @@ int tsvt_dct_noalloc(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, 
     rc = tsvt_enqueue(c, P, sp + o_ws, sp + o_fwd, sp + o_inv, Z, Y, tau, ranks_out, s);
     c->noalloc = 0;
     return rc;
+}
+
+
+int tsvt_transform(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const double* L, const void* Z,
+                   void* Y, double tau, int32_t* ranks_out, void* stream) {
+    if (!c) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    int rc = tsvt_check(c, prec, n1, n2, n3, Z, Y, tau);
+    if (rc) return rc;
+    if (!L) return fail(c, TSVD_EINVAL, "null transform matrix");
+    std::vector<double> Li;
+    if (!invert_host((int)n3, L, Li)) return fail(c, TSVD_EINVAL, "transform matrix is singular or not finite");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const void *fwd, *inv;
+    if ((rc = get_custom_operands(c, prec, (int)n3, L, Li.data(), s, &fwd, &inv))) return rc;
+    Plan P;
+    Carve cv;
+    if ((rc = make_plan(c, prec, n1, n2, n3, 0, P, cv, s))) return rc;
+    if ((rc = ensure_ws(c, P.o_end))) return rc;
+    return tsvt_enqueue(c, P, (char*)c->ws.p, fwd, inv, Z, Y, tau, ranks_out, s);
+}
+
+int tsvt_dft(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const void* Z, void* Y, double tau,
+             int32_t* ranks_out, void* stream) {
+    if (!c) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    int rc = tsvt_check(c, prec, n1, n2, n3, Z, Y, tau);
+    if (rc) return rc;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> R, Ri;
+    real_dft_matrices((int)n3, R, Ri);
+    const void *fwd, *inv;
+    if ((rc = get_custom_operands(c, prec, (int)n3, R.data(), Ri.data(), s, &fwd, &inv))) return rc;
+    DftPlan D;
+    Carve cv;
+    if ((rc = make_dft_plan(c, prec, n1, n2, n3, D, cv, s))) return rc;
+    if ((rc = ensure_ws(c, cv.off))) return rc;
+    char* base = (char*)c->ws.p;
+    CtrlRegion cr;
+    if ((rc = ensure_ctrl(c, &cr))) return rc;
+    if ((rc = dft_forward(c, D, prec, n1, n2, n3, Z, fwd, base, cr.ctrl, s))) return rc;
+    if (D.h > 0 && (rc = enqueue_svt_core(c, D.E, base, cr.ctrl, tau, nullptr, s))) return rc;
+    if ((rc = enqueue_svt_core(c, D.R, base, cr.ctrl, tau, nullptr, s))) return rc;
+    DftEmbedArgs ea{};
+    ea.zb = base + D.o_zb;
+    ea.E = D.h > 0 ? (void*)(base + D.E.o_ybar) : nullptr;
+    ea.R = base + D.R.o_ybar;
+    ea.n1 = n1; ea.n2 = n2; ea.n3 = (int)n3; ea.h = D.h; ea.nreal = D.nreal;
+    hipError_t e = launch_dft_unembed(prec == TSVD_FP64 ? 0 : 1, ea, s);
+    if (e != hipSuccess) return hip_fail(c, e, "dft unembed");
+    TubeArgs iv{};
+    iv.in = base + D.o_zb; iv.out = Y; iv.N = n1 * n2; iv.n3 = (int)n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
+    {
+        PhaseMark pm(c, 3, s);
+        if ((rc = run_tube_mat(c, prec, iv, 1, inv, s))) return rc;
+    }
+    if (ranks_out) {
+        // a complex slice's rank is half its real form's; conjugate frequencies share it
+        std::vector<int32_t> re(D.h > 0 ? D.h : 1), rr(D.nreal);
+        if (D.h > 0) HIPCHK(c, hipMemcpyAsync(re.data(), base + D.E.o_rank, D.h * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(rr.data(), base + D.R.o_rank, D.nreal * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        ranks_out[0] = rr[0];
+        for (int f = 1; f <= D.h; ++f) ranks_out[f] = ranks_out[n3 - f] = re[f - 1] / 2;
+        if (D.nreal == 2) ranks_out[n3 / 2] = rr[1];
+        return read_status(c, s, nullptr);
+    }
+    return finish_call(c, s);
+}
+
+int tnn_c(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const void* X, double* out, void* stream) {
+    if (!c) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (bad_prec(prec)) return fail(c, TSVD_EINVAL, "unknown precision");
+    if (n1 <= 0 || n2 <= 0 || n3 <= 0) return fail(c, TSVD_EINVAL, "sizes must be positive");
+    if (!X || !out) return fail(c, TSVD_EINVAL, "null pointer");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    Plan P;
+    Carve cv;
+    int rc = make_plan(c, prec, n1, n2, n3, 0, P, cv, s);
+    if (rc) return rc;
+    if ((rc = ensure_ws(c, P.o_end))) return rc;
+    char* base = (char*)c->ws.p;
+    if ((rc = upload_plan(c, P, base))) return rc;
+    CtrlRegion cr;
+    if ((rc = ensure_ctrl(c, &cr))) return rc;
+    hipError_t e = launch_fill_zero(base + P.o_ctr_begin, P.o_ctr_end - P.o_ctr_begin, s);
+    if (e != hipSuccess) return hip_fail(c, e, "fill");
+    TubeArgs f{};
+    f.in = X; f.out = base + P.o_zbar; f.N = P.N; f.n3 = (int)n3; f.ctrl = cr.ctrl; f.check_finite = 1;
+    f.beta_val = 1.0;
+    if ((rc = run_tube(c, prec, f, 0, s))) return rc;
+    if ((rc = run_jacobi(c, P, base, cr.ctrl, s))) return rc;
+    double acc = 0.0;
+    if ((rc = sum_sigma(c, P, base, cr.ctrl, s, &acc))) return rc;
+    *out = acc / (double)n3;
+    return read_status(c, s, nullptr);
+}
+
+int tnn_f(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const void* X, double* out, void* stream) {
+    if (!c) return TSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (bad_prec(prec)) return fail(c, TSVD_EINVAL, "unknown precision");
+    if (n1 <= 0 || n2 <= 0 || n3 <= 0) return fail(c, TSVD_EINVAL, "sizes must be positive");
+    if (!X || !out) return fail(c, TSVD_EINVAL, "null pointer");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> R, Ri;
+    real_dft_matrices((int)n3, R, Ri);
+    const void *fwd, *inv;
+    int rc = get_custom_operands(c, prec, (int)n3, R.data(), Ri.data(), s, &fwd, &inv);
+    if (rc) return rc;
+    DftPlan D;
+    Carve cv;
+    if ((rc = make_dft_plan(c, prec, n1, n2, n3, D, cv, s))) return rc;
+    if ((rc = ensure_ws(c, cv.off))) return rc;
+    char* base = (char*)c->ws.p;
+    CtrlRegion cr;
+    if ((rc = ensure_ctrl(c, &cr))) return rc;
+    if ((rc = dft_forward(c, D, prec, n1, n2, n3, X, fwd, base, cr.ctrl, s))) return rc;
+    // a complex slice's real form has each of its singular values twice: the
+    // sum over the real forms is the sum over both conjugate frequencies
+    double se = 0.0, sr = 0.0;
+    if (D.h > 0) {
+        if ((rc = run_jacobi(c, D.E, base, cr.ctrl, s))) return rc;
+        if ((rc = sum_sigma(c, D.E, base, cr.ctrl, s, &se))) return rc;
+    }
+    if ((rc = run_jacobi(c, D.R, base, cr.ctrl, s))) return rc;
+    if ((rc = sum_sigma(c, D.R, base, cr.ctrl, s, &sr))) return rc;
+    *out = (se + sr) / (double)n3;
+    return read_status(c, s, nullptr);
 }
 
 int tprod_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n4, int64_t n3, const void* X, const void* Yp,
@@ -1644,7 +2038,7 @@ int tsvd_batched_shape_check(int prec, int64_t n1, int64_t n2, int with_v) {
     P.p = (int)std::min(n1, n2);
     P.with_v = with_v ? 1 : 0;
     // every candidate tile of a batched plan: one of them must hold the slice
-    for (const Tile& t : tile_candidates(P, true)) {
+    for (const Tile& t : tile_candidates(P, true, -1)) {
         Plan Q = P;
         if (apply_tile(nullptr, Q, t, true) == TSVD_OK) return TSVD_OK;
     }

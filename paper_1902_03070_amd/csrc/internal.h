@@ -121,6 +121,14 @@ hipError_t launch_jacobi_resident(int prec, const JacobiJob& job1, const JacobiJ
 hipError_t launch_jacobi_team(int prec, const JacobiJob& job, int ntasks, const TeamSched& ts, int max_sweeps,
                               Ctrl* ctrl, int lds_bytes, int threads, int with_v, int spin_limit, int R, int G, int K,
                               int coop, hipStream_t s);
+// Block-Gram multi-workgroup kernel (blocks of 16 columns, 256 threads per
+// workgroup, matrix-core Gram matrices and updates); job.b must be 16.
+// With V and job.vinit == 0 it first sets V to the identity.
+hipError_t launch_jacobi_gram(int prec, const JacobiJob& job, int ntasks, const TeamSched& ts, int max_sweeps,
+                              Ctrl* ctrl, int with_v, int spin_limit, int coop, hipStream_t s);
+int jacobi_gram_lds_bytes(int prec, int m);
+constexpr int kGramBlock = 16;  // columns per block of the block-Gram kernel
+int jacobi_gram_max_resident(int prec, int m, int with_v);
 // One persistent launch over (tensor, slice) tasks drawn from *queue (zeroed).
 // One persistent launch per row geometry (R, G) present in the batch.
 hipError_t launch_jacobi_batched(int prec, int R, int G, int with_v, const JacobiJob* jobs_dev, const int* task_job,
@@ -165,6 +173,19 @@ struct SvtPrepArgs {
     double tau_val; const double* tau_sched; Ctrl* ctrl;
 };
 hipError_t launch_svt_prep(int prec, const SvtPrepArgs& a, hipStream_t s);
+
+// DFT path: real forms of the complex Fourier slices (see ops.hip).  zb: the
+// real-transform slots (n1 x n2 x n3); E: h slices of 2 n1 x 2 n2; R: nreal
+// (1 or 2) real slices.  unembed writes back into zb.
+struct DftEmbedArgs {
+    void* zb;
+    void* E;
+    void* R;
+    int64_t n1, n2;
+    int n3, h, nreal;
+};
+hipError_t launch_dft_embed(int prec, const DftEmbedArgs& a, hipStream_t s);
+hipError_t launch_dft_unembed(int prec, const DftEmbedArgs& a, hipStream_t s);
 
 // One batched step over many tensors (used by tsvt_dct_batched and the serving
 // loop).  Per tensor: either a plain t-SVT Z -> Y, or one completion iteration

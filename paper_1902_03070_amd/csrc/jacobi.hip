@@ -1211,6 +1211,377 @@ __global__ __launch_bounds__(512) void k_jacobi_batched(const JacobiJob* __restr
 }
 
 // ---------------------------------------------------------------------------
+// Block-Gram team kernel.  The same one-sided Jacobi method and the same team
+// schedule (blocks of b = 16 columns, a round-robin tournament of block pairs
+// per sweep, point-to-point hand-over between steps, a team barrier per
+// sweep), but a workgroup treats its block pair X = [A_I A_J] (m x 32) as one
+// unit, so that the work proportional to m runs on the matrix cores:
+//   1. G = X^T X (32 x 32) on the matrix cores: BF16 hi+lo products (three,
+//      the lo*lo term dropped) for the FP32 sweeps of the mixed path, FP32
+//      products for the FP32 path, FP64 for FP64 data and for the mixed
+//      path's final sweep (FP32 values are exact in FP64);
+//   2. the step's rotations, the same pairs in the same round order as the
+//      one-sided method on X, computed from G alone: with Q the product of
+//      the rotations so far and K = G Q, the inner product of columns i and j
+//      of X Q is q_i . k_j and the rotation of a pair acts on the columns of
+//      Q and K (vectors of 32, in FP64, tracked squared norms as in the
+//      other kernels);
+//   3. X <- X Q (and V <- V Q) on the matrix cores, stored straight to the
+//      work arrays.
+// The convergence counts of a step (pairs whose cosine exceeds the rotation
+// threshold, and the larger early-exit threshold) are taken from the fresh G
+// before any rotation; every pair of the slice is a cross pair of exactly one
+// step per sweep, and the pairs inside a block are counted at the sweep's
+// first step, where they are rotated as well.  A step with nothing to rotate
+// leaves its blocks as they are (no update and no store).
+// ---------------------------------------------------------------------------
+constexpr int kGramB = kGramBlock;         // columns per block
+constexpr int kGramC = 2 * kGramB;         // columns per block pair
+constexpr int kGramThreads = 256;          // four wavefronts
+constexpr int kGramLd = kGramC + 1;        // leading dimension of G, K and Q in LDS (doubles)
+
+typedef float gram_f16v __attribute__((ext_vector_type(16)));
+typedef double gram_d4v __attribute__((ext_vector_type(4)));
+typedef __bf16 gram_bf8 __attribute__((ext_vector_type(8)));
+
+// Padded rows of a block-pair column in LDS: m rounded up to 64, plus 2
+// (FP32: the 64 lanes of an operand load that walk across the 32 columns at
+// one row then fall in distinct banks) or 1 (FP64).
+__host__ __device__ inline int gram_ldx(int m, int es) { return (m + 63) / 64 * 64 + (es == 4 ? 2 : 1); }
+
+// LDS bytes of the block-Gram kernel: the block pair, then G/K and Q, then
+// the four wavefronts' partial Gram matrices (FP64 or twice FP32 each), then
+// the tracked squared norms.
+__host__ __device__ inline int gram_lds_bytes(int m, int es) {
+    return kGramC * gram_ldx(m, es) * es + 2 * kGramC * kGramLd * 8 + 4 * kGramC * kGramC * 8 + kGramC * 8;
+}
+
+// Global column of local column c (0..31) of the pair (BI, BJ).
+__device__ __forceinline__ int gram_col(int c, int BI, int BJ) {
+    return c < kGramB ? BI * kGramB + c : BJ * kGramB + (c - kGramB);
+}
+
+// Partial Gram matrix of the wavefront's rows [r0, r0 + rows) of the block
+// pair (LDS, column-major, ld ldx) into P (32 x 32 row-major FP64), on the
+// matrix cores.  mode 0: FP64 products; 1: FP32; 2: BF16 hi + lo (three
+// products).  rows is a multiple of 16.
+template <typename T>
+__device__ void gram_partial(const T* __restrict__ Xs, int ldx, int r0, int rows, int mode, double* __restrict__ P) {
+    const int lane = threadIdx.x & 63;
+    if (mode == 0) {
+        // 16 x 16 tiles (0,0), (0,1), (1,1); K steps of 4 rows
+        gram_d4v a00 = {0.0, 0.0, 0.0, 0.0}, a01 = a00, a11 = a00;
+        const int ci = lane & 15, kq = lane >> 4;
+        for (int k0 = r0; k0 < r0 + rows; k0 += 4) {
+            const double x0 = (double)Xs[(int64_t)ci * ldx + k0 + kq];
+            const double x1 = (double)Xs[(int64_t)(16 + ci) * ldx + k0 + kq];
+            a00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x0, a00, 0, 0, 0);
+            a01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x1, a01, 0, 0, 0);
+            a11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, x1, a11, 0, 0, 0);
+        }
+        // element v of a lane: row (lane >> 4) + 4 v, column lane & 15 of the tile
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = (lane >> 4) + 4 * v, j = lane & 15;
+            P[i * kGramC + j] = a00[v];
+            P[i * kGramC + 16 + j] = a01[v];
+            P[(16 + j) * kGramC + i] = a01[v];
+            P[(16 + i) * kGramC + 16 + j] = a11[v];
+        }
+        return;
+    }
+    const int c = lane & 31, kh = lane >> 5;
+    gram_f16v acc = {}, acc2 = {};
+    if (mode == 1) {
+        for (int k0 = r0; k0 < r0 + rows; k0 += 2) {
+            const float x = (float)Xs[(int64_t)c * ldx + k0 + kh];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x, x, acc, 0, 0, 0);
+        }
+    } else {
+        // H = hi^T hi and P = hi^T lo; G = H + P + P^T
+        for (int k0 = r0; k0 < r0 + rows; k0 += 16) {
+            gram_bf8 hi, lo;
+            const T* src = Xs + (int64_t)c * ldx + k0 + 8 * kh;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float x = (float)src[e];
+                const __bf16 h = (__bf16)x;
+                hi[e] = h;
+                lo[e] = (__bf16)(x - (float)h);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi, hi, acc, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi, lo, acc2, 0, 0, 0);
+        }
+    }
+    // element v of a lane: row 8 (v / 4) + 4 (lane / 32) + v % 4, column lane % 32
+    float* Pf = (float*)P;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int i = 8 * (v >> 2) + 4 * kh + (v & 3), j = c;
+        Pf[i * kGramC + j] = acc[v];
+        Pf[kGramC * kGramC + i * kGramC + j] = mode == 2 ? acc2[v] : 0.0f;
+    }
+}
+
+// X_new = X Q for the block pair (rows [0, m)), written to the columns of the
+// work array W (column gc(i) at W + gc ld); src is X in LDS (ld ldx), or,
+// when from_global, the columns of W itself (rows < m read with L1-bypassing
+// loads; used for V).  Computed transposed, X_new^T = Q^T X^T, so that the 32
+// (FP32) or 16 (FP64) lanes of an output row of the matrix-core product walk
+// down one column of X_new (contiguous stores).  f64: FP64 products (FP32
+// data converted exactly, result rounded once).
+template <typename T>
+__device__ void gram_apply(const T* __restrict__ Xs, int ldx, bool from_global, T* __restrict__ W, int64_t ld,
+                           int m, int BI, int BJ, int p, const double* __restrict__ Qd, bool f64) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    auto xval = [&](int k, int r) -> T {
+        if (r >= m) return (T)0;
+        if (!from_global) return Xs[(int64_t)k * ldx + r];
+        const int gk = gram_col(k, BI, BJ);
+        return gk < p ? ld_team(W + (int64_t)gk * ld + r) : (T)0;
+    };
+    if (sizeof(T) == 8 || f64) {
+        // 16-row tiles, both 16-column halves of the output by the same
+        // wavefront (its reads of a row tile all precede its stores to it)
+        const int tj_n = (m + 15) / 16;
+        for (int tj = wave; tj < tj_n; tj += 4) {
+            const int j0 = tj * 16, r = j0 + (lane & 15);
+            gram_d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+            // A = Q^T tile: A[i][k] = Q[k][16 ti + i];  B[k][j] = X[j0 + j][k]
+#pragma unroll
+            for (int k0 = 0; k0 < kGramC; k0 += 4) {
+                const int k = k0 + (lane >> 4);
+                const double b = (double)xval(k, r);
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Qd[(lane & 15) * kGramLd + k], b, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Qd[(16 + (lane & 15)) * kGramLd + k], b, acc1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = (lane >> 4) + 4 * v;
+                const int g0 = gram_col(i, BI, BJ), g1 = gram_col(16 + i, BI, BJ);
+                if (r < m && g0 < p) W[(int64_t)g0 * ld + r] = (T)acc0[v];
+                if (r < m && g1 < p) W[(int64_t)g1 * ld + r] = (T)acc1[v];
+            }
+        }
+        return;
+    }
+    // FP32: 32 x 32 tiles over the rows; the Q^T operand is the same for every tile
+    float qa[kGramC / 2];
+#pragma unroll
+    for (int s = 0; s < kGramC / 2; ++s) qa[s] = (float)Qd[(lane & 31) * kGramLd + 2 * s + (lane >> 5)];
+    const int tj_n = (m + 31) / 32;
+    for (int tj = wave; tj < tj_n; tj += 4) {
+        const int j0 = tj * 32, r = j0 + (lane & 31);
+        gram_f16v acc = {};
+#pragma unroll
+        for (int s = 0; s < kGramC / 2; ++s) {
+            const float b = (float)xval(2 * s + (lane >> 5), r);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[s], b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), gi = gram_col(i, BI, BJ);
+            if (r < m && gi < p) W[(int64_t)gi * ld + r] = (T)acc[v];
+        }
+    }
+}
+
+// One slice by one team, block-Gram steps.  Returns false if a wait timed out.
+template <typename T, bool WV>
+__device__ bool gram_task(const JacobiJob& J, int k, int rank, TeamState& ts, int max_sweeps, unsigned char* lds,
+                          int* s_scratch, int* s_flag) {
+    const int m = J.m, p = J.p, nb = J.nb;
+    const int ldx = gram_ldx(m, (int)sizeof(T));
+    const int mp = (m + 63) / 64 * 64;
+    T* Xs = (T*)lds;
+    double* Kd = (double*)(lds + (size_t)kGramC * ldx * sizeof(T));
+    double* Qd = Kd + kGramC * kGramLd;
+    double* Pb = Qd + kGramC * kGramLd;
+    double* nrm = Pb + 4 * kGramC * kGramC;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int grp = tid >> 4, gl = tid & 15;  // inner phase: 16 lane groups of 16
+    const double tol = J.tol;
+    const bool refine = J.refine64 != 0;
+    int sweeps = -1, executed = 0;
+    int* rot_g = J.rot + (int64_t)k * kRotStride;
+    T* Ag = (T*)J.A + (int64_t)k * m * p;
+    T* Vg = WV ? (T*)J.V + (int64_t)k * p * p : nullptr;
+    for (int sw = 0; sw < max_sweeps + (refine ? 1 : 0); ++sw) {
+        const bool f64 = refine && sw == max_sweeps;
+        const double tl = f64 ? (double)m * Unit<double>::v : tol;
+        const int mode = (sizeof(T) == 8 || f64) ? 0 : (refine ? 2 : 1);
+        int rot = 0, big = 0;
+        ++executed;
+        for (int s = 0; s < nb - 1; ++s) {
+            const bool last = (s == nb - 2);
+            for (int q = rank; q < nb / 2; q += ts.W) {
+                int BI, BJ;
+                rr_pair(s, q, nb, BI, BJ);
+                if (s > 0 && !team_wait_blocks(ts, BI, BJ, ts.steps, s_flag)) return false;
+                const bool first = (sw == 0 && s == 0);
+                // 1. the block pair into LDS (zero rows beyond m, zero columns beyond p)
+                if (first && J.src_rs != 1) {
+                    for (int e = tid; e < kGramC * mp; e += kGramThreads) {
+                        const int r = e / kGramC, c = e - r * kGramC, gc = gram_col(c, BI, BJ);
+                        Xs[(int64_t)c * ldx + r] = (r < m && gc < p) ? src_at<T>(J, k, r, gc) : (T)0;
+                    }
+                } else {
+                    for (int e = tid; e < kGramC * mp; e += kGramThreads) {
+                        const int c = e / mp, r = e - c * mp, gc = gram_col(c, BI, BJ);
+                        T v = (T)0;
+                        if (r < m && gc < p) v = first ? src_at<T>(J, k, r, gc) : ld_team(Ag + (int64_t)gc * m + r);
+                        Xs[(int64_t)c * ldx + r] = v;
+                    }
+                }
+                __syncthreads();
+                // 2. partial Gram matrices of the four wavefronts' row quarters, then G = K
+                gram_partial<T>(Xs, ldx, wave * (mp / 4), mp / 4, mode, Pb + wave * kGramC * kGramC);
+                __syncthreads();
+                for (int e = tid; e < kGramC * kGramC; e += kGramThreads) {
+                    const int i = e / kGramC, j = e - i * kGramC;
+                    double g = 0.0;
+                    if (mode == 0) {
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) g += Pb[w * kGramC * kGramC + e];
+                    } else {
+                        const float* Pf = (const float*)Pb;
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) {
+                            const float* pw = Pf + w * 2 * kGramC * kGramC;
+                            g += (double)pw[e] + (double)pw[kGramC * kGramC + e] + (double)pw[kGramC * kGramC + j * kGramC + i];
+                        }
+                    }
+                    Kd[j * kGramLd + i] = g;
+                    Qd[j * kGramLd + i] = i == j ? 1.0 : 0.0;
+                }
+                __syncthreads();
+                if (tid < kGramC) nrm[tid] = Kd[tid * kGramLd + tid];
+                // convergence counts of this step's pairs from the fresh G (symmetrized)
+                int nrot = 0, nbig = 0;
+                for (int e = tid; e < kGramC * kGramC; e += kGramThreads) {
+                    const int i = e / kGramC, j = e - i * kGramC;
+                    if (j <= i) continue;
+                    const bool cross = (i < kGramB) != (j < kGramB);
+                    if (!cross && s != 0) continue;
+                    if (gram_col(i, BI, BJ) >= p || gram_col(j, BI, BJ) >= p) continue;
+                    const double g = 0.5 * (Kd[j * kGramLd + i] + Kd[i * kGramLd + j]);
+                    const double ab = Kd[i * kGramLd + i] * Kd[j * kGramLd + j];
+                    nrot += !(g * g <= (tl * tl) * ab);
+                    nbig += !(g * g <= J.skip2 * ab);
+                }
+                nrot = block_sum_groups(nrot, 0, s_scratch);
+                nbig = block_sum_groups(nbig, 0, s_scratch);
+                rot += (tid == 0) ? nrot : 0;
+                big += (tid == 0) ? nbig : 0;
+                // 3. the step's rotations on (Q, K): 16 lane groups, two rows of 32 per lane
+                int moved = 0;
+                if (nrot > 0) {
+                    const int nr = (s == 0) ? kGramC - 1 : kGramB;
+                    for (int r = 0; r < nr; ++r) {
+                        int i, j;
+                        if (s == 0) rr_pair(r, grp, kGramC, i, j);
+                        else { i = grp; j = kGramB + ((grp + r) & (kGramB - 1)); }
+                        double* qi = Qd + i * kGramLd;
+                        double* qj = Qd + j * kGramLd;
+                        double* ki = Kd + i * kGramLd;
+                        double* kj = Kd + j * kGramLd;
+                        const double q0 = qi[gl], q1 = qi[gl + 16], r0_ = qj[gl], r1 = qj[gl + 16];
+                        const double k0 = ki[gl], k1 = ki[gl + 16], l0 = kj[gl], l1 = kj[gl + 16];
+                        const double a = nrm[i], b = nrm[j];
+                        const double g = group_sum<16>(fma(q0, l0, q1 * l1));
+                        double c, sn, t;
+                        if (rotation(a, b, g, tl, c, sn, t)) {
+                            qi[gl] = c * q0 - sn * r0_; qj[gl] = sn * q0 + c * r0_;
+                            qi[gl + 16] = c * q1 - sn * r1; qj[gl + 16] = sn * q1 + c * r1;
+                            ki[gl] = c * k0 - sn * l0; kj[gl] = sn * k0 + c * l0;
+                            ki[gl + 16] = c * k1 - sn * l1; kj[gl + 16] = sn * k1 + c * l1;
+                            if (gl == 0) {
+                                nrm[i] = a - t * g;
+                                nrm[j] = b + t * g;
+                            }
+                            moved = 1;
+                        }
+                        __syncthreads();
+                    }
+                }
+                moved = block_sum_groups(moved, gl, s_scratch);
+                // 4. X <- X Q and V <- V Q straight to the work arrays; a first step that
+                // rotated nothing still copies the source into A
+                if (moved) {
+                    gram_apply<T>(Xs, ldx, false, Ag, m, m, BI, BJ, p, Qd, f64);
+                    if (WV) gram_apply<T>(Xs, ldx, true, Vg, p, p, BI, BJ, p, Qd, f64);
+                } else if (first) {
+                    for (int e = tid; e < kGramC * m; e += kGramThreads) {
+                        const int c = e / m, r = e - c * m, gc = gram_col(c, BI, BJ);
+                        if (gc < p) Ag[(int64_t)gc * m + r] = Xs[(int64_t)c * ldx + r];
+                    }
+                }
+                if (!last) team_release_blocks(ts, BI, BJ, ts.steps + 1);
+                else __syncthreads();
+            }
+            ts.steps += 1;
+            if (last) {
+                if (tid == 0 && rot) atomicAdd(rot_g + sw, rot);
+                if (tid == 0 && big) atomicAdd(rot_g + kMaxSweeps + sw, big);
+                if (!team_barrier(ts, s_flag)) return false;
+            }
+        }
+        if (f64) break;
+        const int total = __hip_atomic_load(rot_g + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int large = __hip_atomic_load(rot_g + kMaxSweeps + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (total == 0 || large == 0) {
+            sweeps = sw + 1;
+            if (!refine) break;
+            sw = max_sweeps - 1;
+        }
+    }
+    if (tid == 0 && rank == 0) record_slice(J, k, sweeps, executed, ts.ctrl);
+    return true;
+}
+
+template <typename T, bool WV>
+__global__ __launch_bounds__(kGramThreads) void k_jacobi_gram(JacobiJob J1, int ntasks, TeamSched sched,
+                                                             int max_sweeps, Ctrl* ctrl, int spin_limit) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_scratch, s_flag, s_team, s_rank, s_nteams;
+    const int W = sched.W;
+    int* ctl = sched.ctl;
+    if (threadIdx.x == 0) {
+        const int x = xcc_id();
+        const int slot = __hip_atomic_fetch_add(ctl + x, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(ctl + 16, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int it = 0;
+        bool ok = true;
+        while (__hip_atomic_load(ctl + 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (int)gridDim.x) {
+            if (++it > spin_limit) {
+                atomicOr(&ctrl->status, kStTimeout);
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        int before = 0, total = 0;
+        for (int xx = 0; xx < 16; ++xx) {
+            const int full = __hip_atomic_load(ctl + xx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / W;
+            if (xx < x) before += full;
+            total += full;
+        }
+        const int local = slot / W;
+        const int full_here = __hip_atomic_load(ctl + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / W;
+        s_team = (ok && local < full_here) ? before + local : -1;
+        s_rank = slot % W;
+        s_nteams = total;
+        if (ok && total == 0 && blockIdx.x == 0) atomicOr(&ctrl->status, kStTimeout);
+    }
+    __syncthreads();
+    const int team = s_team, rank = s_rank, nteams = s_nteams;
+    if (team < 0) return;
+    TeamState ts{ctl + 32 + team * W, 0, W, spin_limit, ctrl, rank, ctl + 32 + gridDim.x + team * J1.nb, 0};
+    for (int t = team; t < ntasks; t += nteams)
+        if (!gram_task<T, WV>(J1, t, rank, ts, max_sweeps, smem_raw, &s_scratch, &s_flag)) return;
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 static int elem_size(int prec) { return prec == 0 ? 8 : 4; }
@@ -1353,6 +1724,76 @@ hipError_t launch_jacobi_batched(int prec, int R, int G, int with_v, const Jacob
     void* args[] = {(void*)&jobs_dev, (void*)&task_job, (void*)&task_slice, (void*)&ntasks,
                     (void*)&queue,    (void*)&max_sweeps, (void*)&ctrl};
     return hipLaunchKernel(f, dim3(grid), dim3(kTeamMaxThreads), args, (size_t)lds_bytes, s);
+}
+
+
+// ---- block-Gram kernel ---------------------------------------------------------
+__global__ void k_identity(void* V, int p, int64_t total, int es) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = e % ((int64_t)p * p);
+        const double v = (o % p) == (o / p) ? 1.0 : 0.0;
+        if (es == 8) ((double*)V)[e] = v;
+        else ((float*)V)[e] = (float)v;
+    }
+}
+
+static const void* gram_fn(int prec, int with_v) {
+    return prec == 0 ? (with_v ? (const void*)k_jacobi_gram<double, true> : (const void*)k_jacobi_gram<double, false>)
+                     : (with_v ? (const void*)k_jacobi_gram<float, true> : (const void*)k_jacobi_gram<float, false>);
+}
+
+int jacobi_gram_lds_bytes(int prec, int m) { return gram_lds_bytes(m, elem_size(prec)); }
+
+int jacobi_gram_max_resident(int prec, int m, int with_v) {
+    const void* f = gram_fn(prec, with_v);
+    const int lds = jacobi_gram_lds_bytes(prec, m);
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kGramThreads, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, f) == hipSuccess && fa.numRegs > 0) {
+        // one wavefront per SIMD per workgroup: at most 512 / VGPRs workgroups per CU
+        const int vg = (fa.numRegs + 7) / 8 * 8;
+        nb = std::min(nb, std::min(8, 512 / vg));
+    } else {
+        (void)hipGetLastError();
+        nb = std::min(nb, 1);
+    }
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return nb * cus;
+}
+
+hipError_t launch_jacobi_gram(int prec, const JacobiJob& job, int ntasks, const TeamSched& ts_in, int max_sweeps,
+                              Ctrl* ctrl, int with_v, int spin_limit, int coop, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
+    if (job.b != kGramB) return hipErrorInvalidValue;
+    if (with_v && !job.vinit) {
+        // the kernel reads V from the work array: start it at the identity
+        const int64_t total = (int64_t)job.p * job.p * ntasks;
+        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
+        hipLaunchKernelGGL(k_identity, dim3(blocks), dim3(256), 0, s, job.V, job.p, total, elem_size(prec));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const void* f = gram_fn(prec, with_v);
+    const int lds = jacobi_gram_lds_bytes(prec, job.m);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    TeamSched ts = ts_in;
+    JacobiJob j1 = job;
+    void* args[] = {(void*)&j1, (void*)&ntasks, (void*)&ts, (void*)&max_sweeps, (void*)&ctrl, (void*)&spin_limit};
+    dim3 grid(ts.nwg), block(kGramThreads);
+    if (coop) return hipLaunchCooperativeKernel(f, grid, block, args, (unsigned)lds, s);
+    return hipLaunchKernel(f, grid, block, args, (size_t)lds, s);
 }
 
 int jacobi_team_max_resident(int prec, int lds_bytes, int threads, int with_v, int R, int G, int K) {

@@ -1,4 +1,5 @@
 // Tube transforms, batched slice GEMMs and the thresholding step.
+#include <algorithm>
 #include "internal.h"
 
 namespace tsvd {
@@ -392,6 +393,87 @@ hipError_t launch_tsvd_finish(int prec, const TsvdFinishArgs& a, hipStream_t s) 
 // ---------------------------------------------------------------------------
 // Utilities.  Zero-fill is a kernel (not a memset node) so it can sit in a
 // captured graph.
+// ---------------------------------------------------------------------------
+// DFT path: slices of the real Fourier transform as real matrices.  The real
+// transform puts the DC slice at 0, the real and imaginary parts of frequency
+// f = 1..h at slots 2f-1 and 2f, and (even n3) the Nyquist slice at n3-1.  A
+// complex slice B + iC is thresholded through its real form
+//     E = [[B, -C], [C, B]]  (2 n1 x 2 n2),
+// whose singular values are those of B + iC, each twice, and whose SVT at tau
+// is the real form of the complex slice's SVT at tau.  embed writes E_f (f =
+// 1..h, as slice f-1 of E) and the real slices (slice q of R); unembed takes
+// B' = (E11 + E22) / 2 and C' = (E21 - E12) / 2 back to the slots.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_dft_embed(DftEmbedArgs a) {
+    const int64_t n1 = a.n1, n2 = a.n2, s = n1 * n2;
+    const int64_t ne = 4 * s * a.h, total = ne + s * a.nreal;
+    const T* zb = (const T*)a.zb;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        if (e < ne) {
+            const int64_t f = e / (4 * s), o = e - f * 4 * s;
+            const int64_t c = o / (2 * n1), r = o - c * 2 * n1;
+            const int rb = r >= n1, cb = c >= n2;
+            const int64_t i = r - rb * n1, j = c - cb * n2;
+            const T* re = zb + (2 * f + 1) * s;
+            const T* im = re + s;
+            T v;
+            if (rb == cb) v = re[i + n1 * j];
+            else v = cb ? -im[i + n1 * j] : im[i + n1 * j];
+            ((T*)a.E)[e] = v;
+        } else {
+            const int64_t q = (e - ne) / s, o = (e - ne) - q * s;
+            const int64_t slot = q == 0 ? 0 : a.n3 - 1;
+            ((T*)a.R)[e - ne] = zb[slot * s + o];
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_dft_unembed(DftEmbedArgs a) {
+    const int64_t n1 = a.n1, n2 = a.n2, s = n1 * n2;
+    const int64_t ne = 2 * s * a.h, total = ne + s * a.nreal;
+    T* yb = (T*)a.zb;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        if (e < ne) {
+            const int64_t f = e / (2 * s), o = e - f * 2 * s;
+            const int part = o >= s;  // 0: real part, 1: imaginary part
+            const int64_t ij = o - part * s, j = ij / n1, i = ij - j * n1;
+            const T* E = (const T*)a.E + f * 4 * s;
+            const int64_t ld = 2 * n1;
+            T v;
+            if (!part) v = (E[i + ld * j] + E[(n1 + i) + ld * (n2 + j)]) * (T)0.5;
+            else v = (E[(n1 + i) + ld * j] - E[i + ld * (n2 + j)]) * (T)0.5;
+            yb[(2 * f + 1 + part) * s + ij] = v;
+        } else {
+            const int64_t q = (e - ne) / s, o = (e - ne) - q * s;
+            const int64_t slot = q == 0 ? 0 : a.n3 - 1;
+            yb[slot * s + o] = ((const T*)a.R)[e - ne];
+        }
+    }
+}
+
+static unsigned grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
+}
+
+hipError_t launch_dft_embed(int prec, const DftEmbedArgs& a, hipStream_t s) {
+    const int64_t total = a.n1 * a.n2 * (4 * (int64_t)a.h + a.nreal);
+    if (prec == 0) hipLaunchKernelGGL(k_dft_embed<double>, dim3(grid_for(total)), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_dft_embed<float>, dim3(grid_for(total)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dft_unembed(int prec, const DftEmbedArgs& a, hipStream_t s) {
+    const int64_t total = a.n1 * a.n2 * (2 * (int64_t)a.h + a.nreal);
+    if (prec == 0) hipLaunchKernelGGL(k_dft_unembed<double>, dim3(grid_for(total)), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_dft_unembed<float>, dim3(grid_for(total)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 __global__ void k_fill_zero(uint32_t* p, int64_t words) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
