@@ -401,6 +401,53 @@ def video_shaped(tm, torch, tprod, steps):
             "recovery_rel_err_mixed": float(np.linalg.norm(Xm - cc.T) / np.linalg.norm(cc.T))}
 
 
+def dct_vs_dft(tm, torch, reps=3):
+    """Table 2's comparison on MI355X: the DCT and DFT paths on random N(0,1)
+    tensors of the table's four shapes, FP64.  tnn_* is the t-SVD work (tube
+    transform and slice SVDs, then the singular-value sum), tsvt_* the whole
+    t-SVT (also the threshold, rebuild and inverse transform).  The DFT path
+    thresholds complex slices through their 2 n1 x 2 n2 real forms, so shapes
+    with more than 256 rows or columns are beyond it."""
+    rows = []
+    g = np.random.default_rng(synth_seed(6))
+    for n1, n2, n3 in ((100, 100, 100), (100, 100, 400), (200, 200, 100), (400, 400, 100)):
+        X = torch.from_numpy(np.asfortranarray(g.standard_normal((n1, n2, n3)))).to("cuda:0")
+        X = tm.fortran(X.permute(2, 1, 0).contiguous().permute(2, 1, 0))
+        ctx = tm.Context(0)
+        row = {"shape": [n1, n2, n3]}
+        tau = 0.5 * (np.sqrt(n1) + np.sqrt(n2))
+        calls = {"tnn_c": lambda: tm.tnn_c(X, ctx=ctx), "tsvt_dct": lambda: tm.tsvt_dct(X, tau, ctx=ctx)}
+        if max(n1, n2) <= 256:
+            calls["tnn_f"] = lambda: tm.tnn_f(X, ctx=ctx)
+            calls["tsvt_dft"] = lambda: tm.tsvt_dft(X, tau * np.sqrt(n3), ctx=ctx)
+        for name, fn in calls.items():
+            fn()  # tunes the tiles of the shape
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            row[name + "_ms"] = round(1e3 * (time.perf_counter() - t0) / reps, 3)
+        if "tnn_f_ms" in row:
+            row["dft_over_dct_tnn"] = round(row["tnn_f_ms"] / row["tnn_c_ms"], 3)
+            row["dft_over_dct_tsvt"] = round(row["tsvt_dft_ms"] / row["tsvt_dct_ms"], 3)
+        else:
+            row["dft"] = "beyond the DFT path (real forms of 800 rows)"
+        ctx.close()
+        rows.append(row)
+        log("dct vs dft:", row)
+    return {"rows": rows, "dtype": "f64", "data": "random N(0,1) tensors (Table 2's shapes)",
+            "paper_table2_s": {"100x100x100": [0.0859, 0.0481], "100x100x400": [0.3425, 0.1799],
+                               "200x200x100": [0.3817, 0.2140], "400x400x100": [1.9668, 0.9523],
+                               "note": "original (DFT) and DCT t-SVD in seconds, MATLAB on the paper's CPU"}}
+
+
+def synth_seed(i):
+    import synth
+
+    return synth.SEED_BASE + i
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -493,6 +540,7 @@ def main():
         out["batched"] = batched(tm, torch, tprod)
         log("batched:", out["batched"])
         out["beta_sweep"] = beta_sweep(tm, torch, case)
+        out["dct_vs_dft"] = dct_vs_dft(tm, torch)
         out["serving"] = serving(tm, torch, tprod, args.serving_requests,
                                  [float(x) for x in args.serving_loads.split(",")])
         log("serving:", out["serving"])
