@@ -348,25 +348,6 @@ int resident_threads(int p, int G, int halve) {
 // Fill the Jacobi part of a plan from a tile.  Fails when the tile cannot
 // hold the slice (LDS, residency, row geometry).
 int apply_tile(tsvd_ctx* c, Plan& P, const Tile& t, bool batched) {
-    int R, ldv;
-    if (jacobi_geometry_g(P.m, P.p, t.G, &R, &ldv)) return fail(c, TSVD_EINVAL, "lane group cannot hold the slice rows");
-    P.job.G = t.G;
-    P.job.R = R;
-    P.job.ldv = ldv;
-    if (t.G == 64 && (!t.team || batched || t.K == 2))
-        return fail(c, TSVD_EINVAL, "64-lane groups exist for the multi-workgroup Jacobi kernel only");
-    if (!t.team) {
-        const int rl = jacobi_resident_lds_bytes(P.prec, P.m, P.p, t.G, P.with_v);
-        if (rl > kLdsBudget) return fail(c, TSVD_EINVAL, "slice does not fit in LDS");
-        P.team = 0;
-        P.lds = rl;
-        P.threads = batched ? kTeamMaxThreads : t.threads;
-        if (P.threads < kWave || P.threads > 1024 || P.threads % t.G) return fail(c, TSVD_EINVAL, "bad workgroup size");
-        P.job.b = 0;
-        P.job.nb = 0;
-        P.ts = TeamSched{1, 0, nullptr};
-        return TSVD_OK;
-    }
     if (t.team == 2) {
         // block-Gram: blocks of kGramB columns, 256 threads, one block pair per workgroup and step
         if (batched) return fail(c, TSVD_EINVAL, "the block-Gram kernel is a multi-workgroup kernel");
@@ -387,6 +368,26 @@ int apply_tile(tsvd_ctx* c, Plan& P, const Tile& t, bool batched) {
         P.ts.nwg = 8 * W * per_xcd;
         P.job.b = kGramBlock;
         P.job.nb = nb;
+        P.job.G = 16;  // lanes per pair in its rotation phase (reported by tsvd_get_tile)
+        return TSVD_OK;
+    }
+    int R, ldv;
+    if (jacobi_geometry_g(P.m, P.p, t.G, &R, &ldv)) return fail(c, TSVD_EINVAL, "lane group cannot hold the slice rows");
+    P.job.G = t.G;
+    P.job.R = R;
+    P.job.ldv = ldv;
+    if (t.G == 64 && (!t.team || batched || t.K == 2))
+        return fail(c, TSVD_EINVAL, "64-lane groups exist for the multi-workgroup Jacobi kernel only");
+    if (!t.team) {
+        const int rl = jacobi_resident_lds_bytes(P.prec, P.m, P.p, t.G, P.with_v);
+        if (rl > kLdsBudget) return fail(c, TSVD_EINVAL, "slice does not fit in LDS");
+        P.team = 0;
+        P.lds = rl;
+        P.threads = batched ? kTeamMaxThreads : t.threads;
+        if (P.threads < kWave || P.threads > 1024 || P.threads % t.G) return fail(c, TSVD_EINVAL, "bad workgroup size");
+        P.job.b = 0;
+        P.job.nb = 0;
+        P.ts = TeamSched{1, 0, nullptr};
         return TSVD_OK;
     }
     P.team = 1;

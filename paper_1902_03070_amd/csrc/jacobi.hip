@@ -1239,21 +1239,23 @@ constexpr int kGramB = kGramBlock;         // columns per block
 constexpr int kGramC = 2 * kGramB;         // columns per block pair
 constexpr int kGramThreads = 256;          // four wavefronts
 constexpr int kGramLd = kGramC + 1;        // leading dimension of G, K and Q in LDS (doubles)
+constexpr int kGramRowsMax = kMaxRows / 64; // rows per lane when a wavefront loads one column
+constexpr int kGramPM = kGramC * kGramLd;   // one 32 x 32 matrix with leading dimension 33
 
 typedef float gram_f16v __attribute__((ext_vector_type(16)));
 typedef double gram_d4v __attribute__((ext_vector_type(4)));
 typedef __bf16 gram_bf8 __attribute__((ext_vector_type(8)));
 
-// Padded rows of a block-pair column in LDS: m rounded up to 64, plus 2
-// (FP32: the 64 lanes of an operand load that walk across the 32 columns at
-// one row then fall in distinct banks) or 1 (FP64).
-__host__ __device__ inline int gram_ldx(int m, int es) { return (m + 63) / 64 * 64 + (es == 4 ? 2 : 1); }
+// Padded rows of a block-pair column in LDS: m rounded up to 64, plus 4
+// (FP32: a column starts 16-byte aligned, and the 16-byte operand reads of
+// eight consecutive columns fall in distinct bank groups) or 1 (FP64: the
+// 8-byte reads of 16 consecutive columns at one row fall in distinct banks).
+__host__ __device__ inline int gram_ldx(int m, int es) { return (m + 63) / 64 * 64 + (es == 4 ? 4 : 1); }
 
-// LDS bytes of the block-Gram kernel: the block pair, then G/K and Q, then
-// the four wavefronts' partial Gram matrices (FP64 or twice FP32 each), then
-// the tracked squared norms.
+// LDS bytes of the block-Gram kernel: the block pair, then G/K and Q (FP64,
+// ld 33), then the tracked squared norms.
 __host__ __device__ inline int gram_lds_bytes(int m, int es) {
-    return kGramC * gram_ldx(m, es) * es + 2 * kGramC * kGramLd * 8 + 4 * kGramC * kGramC * 8 + kGramC * 8;
+    return kGramC * gram_ldx(m, es) * es + 2 * kGramPM * 8 + kGramC * 8;
 }
 
 // Global column of local column c (0..31) of the pair (BI, BJ).
@@ -1261,66 +1263,81 @@ __device__ __forceinline__ int gram_col(int c, int BI, int BJ) {
     return c < kGramB ? BI * kGramB + c : BJ * kGramB + (c - kGramB);
 }
 
-// Partial Gram matrix of the wavefront's rows [r0, r0 + rows) of the block
-// pair (LDS, column-major, ld ldx) into P (32 x 32 row-major FP64), on the
-// matrix cores.  mode 0: FP64 products; 1: FP32; 2: BF16 hi + lo (three
-// products).  rows is a multiple of 16.
+// One 16 x 16 tile (ti, tj) of G = X^T X of the block pair (rows [0, rows),
+// LDS column-major with ld ldx) on the matrix cores, written to Kd (FP64,
+// column-major, ld kGramLd).  mode 0: FP64 products; 1: FP32; 2: BF16 hi + lo
+// (hi*hi + hi*lo + lo*hi, the lo*lo term dropped).  rows is a multiple of 32.
+typedef float gram_f4v __attribute__((ext_vector_type(4)));
 template <typename T>
-__device__ void gram_partial(const T* __restrict__ Xs, int ldx, int r0, int rows, int mode, double* __restrict__ P) {
-    const int lane = threadIdx.x & 63;
+__device__ void gram_tile(const T* __restrict__ Xs, int ldx, int rows, int mode, int ti, int tj,
+                          double* __restrict__ Kd) {
+    const int lane = threadIdx.x & 63, c16 = lane & 15, kq = lane >> 4;
+    const T* xa = Xs + (int64_t)(16 * ti + c16) * ldx;
+    const T* xb = Xs + (int64_t)(16 * tj + c16) * ldx;
+    // four independent accumulators (K steps taken round robin) keep the
+    // matrix-core pipeline full; they are added in a fixed order at the end
     if (mode == 0) {
-        // 16 x 16 tiles (0,0), (0,1), (1,1); K steps of 4 rows
-        gram_d4v a00 = {0.0, 0.0, 0.0, 0.0}, a01 = a00, a11 = a00;
-        const int ci = lane & 15, kq = lane >> 4;
-        for (int k0 = r0; k0 < r0 + rows; k0 += 4) {
-            const double x0 = (double)Xs[(int64_t)ci * ldx + k0 + kq];
-            const double x1 = (double)Xs[(int64_t)(16 + ci) * ldx + k0 + kq];
-            a00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x0, a00, 0, 0, 0);
-            a01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x1, a01, 0, 0, 0);
-            a11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, x1, a11, 0, 0, 0);
+        gram_d4v a0 = {0.0, 0.0, 0.0, 0.0}, a1 = a0, a2 = a0, a3 = a0;
+        for (int k0 = 0; k0 < rows; k0 += 16) {
+            a0 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[k0 + kq], (double)xb[k0 + kq], a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[k0 + 4 + kq], (double)xb[k0 + 4 + kq], a1, 0, 0, 0);
+            a2 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[k0 + 8 + kq], (double)xb[k0 + 8 + kq], a2, 0, 0, 0);
+            a3 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[k0 + 12 + kq], (double)xb[k0 + 12 + kq], a3, 0, 0, 0);
         }
-        // element v of a lane: row (lane >> 4) + 4 v, column lane & 15 of the tile
+        // element v: row kq + 4 v, column c16
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = (lane >> 4) + 4 * v, j = lane & 15;
-            P[i * kGramC + j] = a00[v];
-            P[i * kGramC + 16 + j] = a01[v];
-            P[(16 + j) * kGramC + i] = a01[v];
-            P[(16 + i) * kGramC + 16 + j] = a11[v];
-        }
+        for (int v = 0; v < 4; ++v)
+            Kd[(16 * tj + c16) * kGramLd + 16 * ti + kq + 4 * v] = (a0[v] + a1[v]) + (a2[v] + a3[v]);
         return;
     }
-    const int c = lane & 31, kh = lane >> 5;
-    gram_f16v acc = {}, acc2 = {};
+    gram_f4v a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0, a2 = a0, a3 = a0;
     if (mode == 1) {
-        for (int k0 = r0; k0 < r0 + rows; k0 += 2) {
-            const float x = (float)Xs[(int64_t)c * ldx + k0 + kh];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x, x, acc, 0, 0, 0);
+        for (int k0 = 0; k0 < rows; k0 += 16) {
+            a0 = __builtin_amdgcn_mfma_f32_16x16x4f32((float)xa[k0 + kq], (float)xb[k0 + kq], a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f32_16x16x4f32((float)xa[k0 + 4 + kq], (float)xb[k0 + 4 + kq], a1, 0, 0, 0);
+            a2 = __builtin_amdgcn_mfma_f32_16x16x4f32((float)xa[k0 + 8 + kq], (float)xb[k0 + 8 + kq], a2, 0, 0, 0);
+            a3 = __builtin_amdgcn_mfma_f32_16x16x4f32((float)xa[k0 + 12 + kq], (float)xb[k0 + 12 + kq], a3, 0, 0, 0);
         }
     } else {
-        // H = hi^T hi and P = hi^T lo; G = H + P + P^T
-        for (int k0 = r0; k0 < r0 + rows; k0 += 16) {
-            gram_bf8 hi, lo;
-            const T* src = Xs + (int64_t)c * ldx + k0 + 8 * kh;
+        // hi*hi, hi*lo and lo*hi in three accumulators
+        for (int k0 = 0; k0 < rows; k0 += 32) {
+            gram_bf8 ah, al, bh, bl;
+            // eight consecutive rows of each column as two 16-byte reads
+            float xr[8], yr[8];
+            if constexpr (sizeof(T) == 4) {
+                const float4* pa = (const float4*)(xa + k0 + 8 * kq);
+                const float4* pb = (const float4*)(xb + k0 + 8 * kq);
+                const float4 x0 = pa[0], x1 = pa[1], y0 = pb[0], y1 = pb[1];
+                xr[0] = x0.x; xr[1] = x0.y; xr[2] = x0.z; xr[3] = x0.w;
+                xr[4] = x1.x; xr[5] = x1.y; xr[6] = x1.z; xr[7] = x1.w;
+                yr[0] = y0.x; yr[1] = y0.y; yr[2] = y0.z; yr[3] = y0.w;
+                yr[4] = y1.x; yr[5] = y1.y; yr[6] = y1.z; yr[7] = y1.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    xr[e] = (float)xa[k0 + 8 * kq + e];
+                    yr[e] = (float)xb[k0 + 8 * kq + e];
+                }
+            }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const float x = (float)src[e];
-                const __bf16 h = (__bf16)x;
-                hi[e] = h;
-                lo[e] = (__bf16)(x - (float)h);
+                const float x = xr[e], y = yr[e];
+                const __bf16 hx = (__bf16)x, hy = (__bf16)y;
+                ah[e] = hx;
+                al[e] = (__bf16)(x - (float)hx);
+                bh[e] = hy;
+                bl[e] = (__bf16)(y - (float)hy);
             }
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi, hi, acc, 0, 0, 0);
-            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi, lo, acc2, 0, 0, 0);
+            a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, a1, 0, 0, 0);
+            a2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, a2, 0, 0, 0);
         }
     }
-    // element v of a lane: row 8 (v / 4) + 4 (lane / 32) + v % 4, column lane % 32
-    float* Pf = (float*)P;
+    // element v: row 4 kq + v, column c16
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int i = 8 * (v >> 2) + 4 * kh + (v & 3), j = c;
-        Pf[i * kGramC + j] = acc[v];
-        Pf[kGramC * kGramC + i * kGramC + j] = mode == 2 ? acc2[v] : 0.0f;
-    }
+    for (int v = 0; v < 4; ++v)
+        Kd[(16 * tj + c16) * kGramLd + 16 * ti + 4 * kq + v] =
+            ((double)a0[v] + (double)a1[v]) + ((double)a2[v] + (double)a3[v]);
 }
 
 // X_new = X Q for the block pair (rows [0, m)), written to the columns of the
@@ -1346,15 +1363,22 @@ __device__ void gram_apply(const T* __restrict__ Xs, int ldx, bool from_global, 
         const int tj_n = (m + 15) / 16;
         for (int tj = wave; tj < tj_n; tj += 4) {
             const int j0 = tj * 16, r = j0 + (lane & 15);
-            gram_d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+            gram_d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
             // A = Q^T tile: A[i][k] = Q[k][16 ti + i];  B[k][j] = X[j0 + j][k]
+            double b[kGramC / 4];
 #pragma unroll
-            for (int k0 = 0; k0 < kGramC; k0 += 4) {
-                const int k = k0 + (lane >> 4);
-                const double b = (double)xval(k, r);
-                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Qd[(lane & 15) * kGramLd + k], b, acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Qd[(16 + (lane & 15)) * kGramLd + k], b, acc1, 0, 0, 0);
+            for (int q = 0; q < kGramC / 4; ++q) b[q] = (double)xval(4 * q + (lane >> 4), r);
+#pragma unroll
+            for (int q = 0; q < kGramC / 4; q += 2) {
+                const int k = 4 * q + (lane >> 4);
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Qd[(lane & 15) * kGramLd + k], b[q], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Qd[(16 + (lane & 15)) * kGramLd + k], b[q], acc1, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Qd[(lane & 15) * kGramLd + k + 4], b[q + 1], acc2, 0, 0, 0);
+                acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(Qd[(16 + (lane & 15)) * kGramLd + k + 4], b[q + 1], acc3, 0,
+                                                            0, 0);
             }
+            acc0 += acc2;
+            acc1 += acc3;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = (lane >> 4) + 4 * v;
@@ -1369,35 +1393,61 @@ __device__ void gram_apply(const T* __restrict__ Xs, int ldx, bool from_global, 
     float qa[kGramC / 2];
 #pragma unroll
     for (int s = 0; s < kGramC / 2; ++s) qa[s] = (float)Qd[(lane & 31) * kGramLd + 2 * s + (lane >> 5)];
+    // two 32-row tiles per wavefront at a time (independent accumulators); all
+    // of a tile's B operands are read before its products
     const int tj_n = (m + 31) / 32;
-    for (int tj = wave; tj < tj_n; tj += 4) {
-        const int j0 = tj * 32, r = j0 + (lane & 31);
-        gram_f16v acc = {};
+    for (int tj = wave; tj < tj_n; tj += 8) {
+        const int ra = tj * 32 + (lane & 31), rb = ra + 128;
+        const bool two = tj + 4 < tj_n;
+        float ba[kGramC / 2], bb[kGramC / 2];
 #pragma unroll
         for (int s = 0; s < kGramC / 2; ++s) {
-            const float b = (float)xval(2 * s + (lane >> 5), r);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[s], b, acc, 0, 0, 0);
+            ba[s] = (float)xval(2 * s + (lane >> 5), ra);
+            bb[s] = two ? (float)xval(2 * s + (lane >> 5), rb) : 0.0f;
         }
+        gram_f16v acc = {}, acc2 = {}, acc3 = {}, acc4 = {};
+#pragma unroll
+        for (int s = 0; s < kGramC / 2; s += 2) {
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[s], ba[s], acc, 0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[s + 1], ba[s + 1], acc3, 0, 0, 0);
+            if (two) {
+                acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[s], bb[s], acc2, 0, 0, 0);
+                acc4 = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[s + 1], bb[s + 1], acc4, 0, 0, 0);
+            }
+        }
+        acc += acc3;
+        acc2 += acc4;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), gi = gram_col(i, BI, BJ);
-            if (r < m && gi < p) W[(int64_t)gi * ld + r] = (T)acc[v];
+            if (ra < m && gi < p) W[(int64_t)gi * ld + ra] = (T)acc[v];
+            if (two && rb < m && gi < p) W[(int64_t)gi * ld + rb] = (T)acc2[v];
         }
     }
+}
+
+// Sum of one int per thread over the workgroup's four wavefronts (every
+// thread gets it): wavefront sums by lane swaps, then four LDS words.
+__device__ __forceinline__ int block_sum_waves(int v, int* s_w4) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    __syncthreads();  // earlier readers of s_w4 are done
+    if ((threadIdx.x & 63) == 0) s_w4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return s_w4[0] + s_w4[1] + s_w4[2] + s_w4[3];
 }
 
 // One slice by one team, block-Gram steps.  Returns false if a wait timed out.
 template <typename T, bool WV>
 __device__ bool gram_task(const JacobiJob& J, int k, int rank, TeamState& ts, int max_sweeps, unsigned char* lds,
-                          int* s_scratch, int* s_flag) {
+                          int* s_w4, int* s_flag) {
     const int m = J.m, p = J.p, nb = J.nb;
     const int ldx = gram_ldx(m, (int)sizeof(T));
     const int mp = (m + 63) / 64 * 64;
     T* Xs = (T*)lds;
     double* Kd = (double*)(lds + (size_t)kGramC * ldx * sizeof(T));
-    double* Qd = Kd + kGramC * kGramLd;
-    double* Pb = Qd + kGramC * kGramLd;
-    double* nrm = Pb + 4 * kGramC * kGramC;
+    double* Qd = Kd + kGramPM;
+    double* nrm = Qd + kGramPM;
     const int tid = threadIdx.x, wave = tid >> 6;
     const int grp = tid >> 4, gl = tid & 15;  // inner phase: 16 lane groups of 16
     const double tol = J.tol;
@@ -1421,66 +1471,122 @@ __device__ bool gram_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                 const bool first = (sw == 0 && s == 0);
                 // 1. the block pair into LDS (zero rows beyond m, zero columns beyond p)
                 if (first && J.src_rs != 1) {
-                    for (int e = tid; e < kGramC * mp; e += kGramThreads) {
-                        const int r = e / kGramC, c = e - r * kGramC, gc = gram_col(c, BI, BJ);
-                        Xs[(int64_t)c * ldx + r] = (r < m && gc < p) ? src_at<T>(J, k, r, gc) : (T)0;
+                    // transposed source: consecutive lanes take consecutive columns (contiguous
+                    // in memory); thread t takes column t mod 32 and rows t / 32 + 8 q, eight
+                    // loads in flight before their LDS stores
+                    const int c = tid & 31, gc = gram_col(c, BI, BJ);
+                    for (int q0 = 0; q0 < mp / 8; q0 += 8) {
+                        T v[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int r = (tid >> 5) + 8 * (q0 + q);
+                            v[q] = (r < m && gc < p) ? src_at<T>(J, k, r, gc) : (T)0;
+                        }
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) Xs[(int64_t)c * ldx + (tid >> 5) + 8 * (q0 + q)] = v[q];
                     }
                 } else {
-                    for (int e = tid; e < kGramC * mp; e += kGramThreads) {
-                        const int c = e / mp, r = e - c * mp, gc = gram_col(c, BI, BJ);
-                        T v = (T)0;
-                        if (r < m && gc < p) v = first ? src_at<T>(J, k, r, gc) : ld_team(Ag + (int64_t)gc * m + r);
-                        Xs[(int64_t)c * ldx + r] = v;
+                    // wavefront w loads columns 8 w .. 8 w + 7, lane l rows l + 64 q: all of
+                    // its loads are issued before its LDS stores
+                    const int lane = tid & 63, nq = mp / 64;
+                    T v[8][kGramRowsMax];
+#pragma unroll
+                    for (int cc = 0; cc < 8; ++cc) {
+                        const int gc = gram_col(8 * wave + cc, BI, BJ);
+#pragma unroll
+                        for (int q = 0; q < kGramRowsMax; ++q) {
+                            const int r = lane + 64 * q;
+                            T x = (T)0;
+                            if (q < nq && r < m && gc < p)
+                                x = first ? src_at<T>(J, k, r, gc) : ld_team(Ag + (int64_t)gc * m + r);
+                            v[cc][q] = x;
+                        }
+                    }
+#pragma unroll
+                    for (int cc = 0; cc < 8; ++cc) {
+#pragma unroll
+                        for (int q = 0; q < kGramRowsMax; ++q)
+                            if (q < nq) Xs[(int64_t)(8 * wave + cc) * ldx + lane + 64 * q] = v[cc][q];
                     }
                 }
                 __syncthreads();
-                // 2. partial Gram matrices of the four wavefronts' row quarters, then G = K
-                gram_partial<T>(Xs, ldx, wave * (mp / 4), mp / 4, mode, Pb + wave * kGramC * kGramC);
-                __syncthreads();
+                // 2. G = X^T X: wavefront w computes tile (w / 2, w mod 2) over all rows
+                gram_tile<T>(Xs, ldx, mp, mode, wave >> 1, wave & 1, Kd);
                 for (int e = tid; e < kGramC * kGramC; e += kGramThreads) {
-                    const int i = e / kGramC, j = e - i * kGramC;
-                    double g = 0.0;
-                    if (mode == 0) {
-#pragma unroll
-                        for (int w = 0; w < 4; ++w) g += Pb[w * kGramC * kGramC + e];
-                    } else {
-                        const float* Pf = (const float*)Pb;
-#pragma unroll
-                        for (int w = 0; w < 4; ++w) {
-                            const float* pw = Pf + w * 2 * kGramC * kGramC;
-                            g += (double)pw[e] + (double)pw[kGramC * kGramC + e] + (double)pw[kGramC * kGramC + j * kGramC + i];
-                        }
-                    }
-                    Kd[j * kGramLd + i] = g;
-                    Qd[j * kGramLd + i] = i == j ? 1.0 : 0.0;
+                    const int c = e >> 5, r = e & 31;
+                    Qd[c * kGramLd + r] = r == c ? 1.0 : 0.0;
                 }
                 __syncthreads();
                 if (tid < kGramC) nrm[tid] = Kd[tid * kGramLd + tid];
-                // convergence counts of this step's pairs from the fresh G (symmetrized)
-                int nrot = 0, nbig = 0;
-                for (int e = tid; e < kGramC * kGramC; e += kGramThreads) {
-                    const int i = e / kGramC, j = e - i * kGramC;
-                    if (j <= i) continue;
-                    const bool cross = (i < kGramB) != (j < kGramB);
+                const int cj = tid & 31;
+                // convergence counts of this step's pairs (i < j) from the fresh G
+                int cnt = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int ri = (tid >> 5) + 8 * q;
+                    if (cj <= ri) continue;
+                    const bool cross = (ri < kGramB) != (cj < kGramB);
                     if (!cross && s != 0) continue;
-                    if (gram_col(i, BI, BJ) >= p || gram_col(j, BI, BJ) >= p) continue;
-                    const double g = 0.5 * (Kd[j * kGramLd + i] + Kd[i * kGramLd + j]);
-                    const double ab = Kd[i * kGramLd + i] * Kd[j * kGramLd + j];
-                    nrot += !(g * g <= (tl * tl) * ab);
-                    nbig += !(g * g <= J.skip2 * ab);
+                    if (gram_col(ri, BI, BJ) >= p || gram_col(cj, BI, BJ) >= p) continue;
+                    const double g = Kd[cj * kGramLd + ri], ab = Kd[ri * kGramLd + ri] * Kd[cj * kGramLd + cj];
+                    cnt += !(g * g <= (tl * tl) * ab);           // would rotate (count in the low half)
+                    cnt += !(g * g <= J.skip2 * ab) ? 65536 : 0;  // large cosine (high half)
                 }
-                nrot = block_sum_groups(nrot, 0, s_scratch);
-                nbig = block_sum_groups(nbig, 0, s_scratch);
+                cnt = block_sum_waves(cnt, s_w4);
+                const int nrot = cnt & 0xFFFF, nbig = cnt >> 16;
                 rot += (tid == 0) ? nrot : 0;
                 big += (tid == 0) ? nbig : 0;
                 // 3. the step's rotations on (Q, K): 16 lane groups, two rows of 32 per lane
                 int moved = 0;
-                if (nrot > 0) {
-                    const int nr = (s == 0) ? kGramC - 1 : kGramB;
-                    for (int r = 0; r < nr; ++r) {
+                if (nrot > 0 && s != 0) {
+                    // cross rounds: group g = 4 w + u keeps I column g (its Q and K rows) in
+                    // registers; the J columns form four sub-blocks of four, and in super-round
+                    // R wavefront w owns sub-block (w + R) mod 4, whose columns pass among its
+                    // four groups (group u meets column (u + v) mod 4 in sub-round v).  LDS
+                    // accesses of one wavefront complete in program order, so only the
+                    // super-rounds end at a workgroup barrier.
+                    const int u = grp & 3, i = grp;
+                    double* qi = Qd + i * kGramLd;
+                    double* ki = Kd + i * kGramLd;
+                    double q0 = qi[gl], q1 = qi[gl + 16], k0 = ki[gl], k1 = ki[gl + 16];
+                    double a = nrm[i];
+                    for (int R = 0; R < 4; ++R) {
+                        const int sb = (wave + R) & 3;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int j = kGramB + 4 * sb + ((u + v) & 3);
+                            double* qj = Qd + j * kGramLd;
+                            double* kj = Kd + j * kGramLd;
+                            const double r0_ = qj[gl], r1 = qj[gl + 16], l0 = kj[gl], l1 = kj[gl + 16];
+                            const double b = nrm[j];
+                            const double g = group_sum<16>(fma(q0, l0, q1 * l1));
+                            double c, sn, t;
+                            if (rotation(a, b, g, tl, c, sn, t)) {
+                                qj[gl] = sn * q0 + c * r0_;
+                                qj[gl + 16] = sn * q1 + c * r1;
+                                kj[gl] = sn * k0 + c * l0;
+                                kj[gl + 16] = sn * k1 + c * l1;
+                                q0 = c * q0 - sn * r0_;
+                                q1 = c * q1 - sn * r1;
+                                k0 = c * k0 - sn * l0;
+                                k1 = c * k1 - sn * l1;
+                                if (gl == 0) nrm[j] = b + t * g;
+                                a -= t * g;
+                                moved = 1;
+                            }
+                            // keeps the next sub-round's LDS reads below this one's writes
+                            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        }
+                        __syncthreads();
+                    }
+                    qi[gl] = q0;
+                    qi[gl + 16] = q1;
+                    __syncthreads();
+                } else if (nrot > 0) {
+                    // the sweep's first step: all pairs of the 32 columns, both in LDS
+                    for (int r = 0; r < kGramC - 1; ++r) {
                         int i, j;
-                        if (s == 0) rr_pair(r, grp, kGramC, i, j);
-                        else { i = grp; j = kGramB + ((grp + r) & (kGramB - 1)); }
+                        rr_pair(r, grp, kGramC, i, j);
                         double* qi = Qd + i * kGramLd;
                         double* qj = Qd + j * kGramLd;
                         double* ki = Kd + i * kGramLd;
@@ -1504,7 +1610,7 @@ __device__ bool gram_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                         __syncthreads();
                     }
                 }
-                moved = block_sum_groups(moved, gl, s_scratch);
+                moved = block_sum_waves(moved, s_w4);
                 // 4. X <- X Q and V <- V Q straight to the work arrays; a first step that
                 // rotated nothing still copies the source into A
                 if (moved) {
@@ -1543,7 +1649,7 @@ template <typename T, bool WV>
 __global__ __launch_bounds__(kGramThreads) void k_jacobi_gram(JacobiJob J1, int ntasks, TeamSched sched,
                                                              int max_sweeps, Ctrl* ctrl, int spin_limit) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int s_scratch, s_flag, s_team, s_rank, s_nteams;
+    __shared__ int s_w4[4], s_flag, s_team, s_rank, s_nteams;
     const int W = sched.W;
     int* ctl = sched.ctl;
     if (threadIdx.x == 0) {
@@ -1578,7 +1684,7 @@ __global__ __launch_bounds__(kGramThreads) void k_jacobi_gram(JacobiJob J1, int 
     if (team < 0) return;
     TeamState ts{ctl + 32 + team * W, 0, W, spin_limit, ctrl, rank, ctl + 32 + gridDim.x + team * J1.nb, 0};
     for (int t = team; t < ntasks; t += nteams)
-        if (!gram_task<T, WV>(J1, t, rank, ts, max_sweeps, smem_raw, &s_scratch, &s_flag)) return;
+        if (!gram_task<T, WV>(J1, t, rank, ts, max_sweeps, smem_raw, s_w4, &s_flag)) return;
 }
 
 // ---------------------------------------------------------------------------
