@@ -21,6 +21,7 @@ from .oracle import (  # noqa: F401
     tprod_dct,
     jacobi_svd,
     tsvd_dct,
+    tsvd_dct_full,
     tsvt_dct,
     tnn_c,
     complete,

@@ -51,6 +51,8 @@ def _load():
     lib.or_jacobi_svd.restype = C.c_int
     lib.or_tsvd_dct.argtypes = [_i64, _i64, _i64, _dp, _dp, _dp, _dp, C.c_int]
     lib.or_tsvd_dct.restype = C.c_int
+    lib.or_tsvd_dct_full.argtypes = [_i64, _i64, _i64, _dp, _dp, _dp, _dp, C.c_int]
+    lib.or_tsvd_dct_full.restype = C.c_int
     lib.or_tsvt_dct.argtypes = [_i64, _i64, _i64, _dp, C.c_double, _dp, C.POINTER(C.c_int32), C.c_int]
     lib.or_tsvt_dct.restype = C.c_int
     lib.or_tnn_c.argtypes = [_i64, _i64, _i64, _dp, C.c_int]
@@ -223,6 +225,20 @@ def tsvd_dct(X, max_sweeps: int = MAX_SWEEPS):
     V = np.empty((n2, p, n3), order="F")
     S = np.empty((p, n3), order="F")
     sw = _load().or_tsvd_dct(n1, n2, n3, _p(X), _p(U), _p(S), _p(V), max_sweeps)
+    return U, S, V, sw
+
+
+def tsvd_dct_full(X, max_sweeps: int = MAX_SWEEPS):
+    """DCT t-SVD with full factors (Theorem 4): Ubar n1 x n1 x n3 and Vbar
+    n2 x n2 x n3 orthogonal per slice, Sbar p x n3.  The first p columns are
+    tsvd_dct's; the rest complete the longer side's basis (see the C source)."""
+    X = _as3(X)
+    n1, n2, n3 = X.shape
+    p = min(n1, n2)
+    U = np.empty((n1, n1, n3), order="F")
+    V = np.empty((n2, n2, n3), order="F")
+    S = np.empty((p, n3), order="F")
+    sw = _load().or_tsvd_dct_full(n1, n2, n3, _p(X), _p(U), _p(S), _p(V), max_sweeps)
     return U, S, V, sw
 
 

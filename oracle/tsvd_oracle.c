@@ -388,6 +388,73 @@ int or_tsvd_dct(int64_t n1, int64_t n2, int64_t n3, const double* X, double* Uba
 }
 
 /* ------------------------------------------------------------------------- */
+/* Theorem 4 with full factors: U m1 x m1, V m2 x m2 orthogonal per slice.    */
+/* The thin factors as in or_tsvd_dct; the side with more rows than p         */
+/* (U if n1 > n2, V if n2 > n1) is completed to an orthonormal basis column   */
+/* by column: candidates e_1, e_2, ... are taken in cyclic order starting     */
+/* after the last accepted one, projected out twice against every column so  */
+/* far (Gram-Schmidt), and accepted when the residual's norm exceeds 1/2; the */
+/* accepted vector is normalized and its largest-magnitude entry (first one   */
+/* on ties) made positive.  Returns the largest sweep count, or -1.           */
+/* ------------------------------------------------------------------------- */
+static void complete_columns(int64_t m, int64_t p, double* Q) {
+    double* u = (double*)malloc(sizeof(double) * m);
+    int64_t e = m - 1; /* the last accepted candidate; the search starts after it */
+    for (int64_t c = p; c < m; ++c) {
+        for (int64_t tries = 0; tries < m; ++tries) {
+            e = (e + 1) % m;
+            for (int64_t r = 0; r < m; ++r) u[r] = (r == e) ? 1.0 : 0.0;
+            for (int pass = 0; pass < 2; ++pass)
+                for (int64_t q = 0; q < c; ++q) {
+                    const double* w = Q + m * q;
+                    double d = 0.0;
+                    for (int64_t r = 0; r < m; ++r) d += w[r] * u[r];
+                    for (int64_t r = 0; r < m; ++r) u[r] -= d * w[r];
+                }
+            double nn = 0.0;
+            for (int64_t r = 0; r < m; ++r) nn += u[r] * u[r];
+            nn = sqrt(nn);
+            if (nn > 0.5) {
+                int64_t best = 0;
+                for (int64_t r = 1; r < m; ++r) if (fabs(u[r]) > fabs(u[best])) best = r;
+                const double f = (u[best] < 0.0 ? -1.0 : 1.0) / nn;
+                for (int64_t r = 0; r < m; ++r) Q[r + m * c] = f * u[r];
+                break;
+            }
+        }
+    }
+    free(u);
+}
+
+struct svdf_ctx { int64_t n1, n2, p; const double* Xb; double *U, *S, *V; int max_sweeps; int* sweeps; };
+static void svdf_range(void* a, int64_t k0, int64_t k1) {
+    const struct svdf_ctx* c = (const struct svdf_ctx*)a;
+    const int64_t n1 = c->n1, n2 = c->n2, p = c->p;
+    for (int64_t k = k0; k < k1; ++k) {
+        double* U = c->U + k * n1 * n1;
+        double* V = c->V + k * n2 * n2;
+        /* thin factors into the first p columns (leading dimensions n1 and n2) */
+        c->sweeps[k] = or_jacobi_svd(n1, n2, c->Xb + k * n1 * n2, n1, U, c->S + k * p, V, c->max_sweeps);
+        if (n1 > p) complete_columns(n1, p, U);
+        if (n2 > p) complete_columns(n2, p, V);
+    }
+}
+
+int or_tsvd_dct_full(int64_t n1, int64_t n2, int64_t n3, const double* X, double* Ubar, double* Sbar, double* Vbar,
+                     int max_sweeps) {
+    int64_t p = n1 < n2 ? n1 : n2;
+    double* Xb = (double*)malloc(sizeof(double) * n1 * n2 * n3);
+    int* sw = (int*)malloc(sizeof(int) * n3);
+    or_dct_tubes(n1, n2, n3, X, Xb);
+    struct svdf_ctx c = {n1, n2, p, Xb, Ubar, Sbar, Vbar, max_sweeps, sw};
+    parallel_for(n3, svdf_range, &c);
+    int worst = worst_sweeps(sw, n3);
+    free(Xb);
+    free(sw);
+    return worst;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Theorem 5 (tensor singular value thresholding) with Algorithm 1's loop    */
 /* body: Zbar = dct(Z); per slice SVD; Dbar = (Sbar - tau)_+; rebuild         */
 /* Ubar Dbar Vbar^T; Y = idct.  ranks[k] = #{sigma > tau} (may be NULL).      */

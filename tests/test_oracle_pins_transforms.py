@@ -245,3 +245,58 @@ def test_tnn_c_and_tnn_f_relation_constant_tubes(orc):
     nuc = np.linalg.svd(A, compute_uv=False).sum()
     assert abs(orc.tnn_f(X) - nuc) < 1e-12 * nuc
     assert abs(orc.tnn_c(X) - nuc / np.sqrt(6)) < 1e-12 * nuc
+
+
+# ----------------------------------------------------------------------------
+# Full (non-thin) t-SVD factors (Theorem 4: U is m1 x m1, V is m2 x m2)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(9, 5, 3), (5, 9, 4), (6, 6, 2), (12, 3, 4), (1, 4, 2)])
+def test_tsvd_full_orthogonal_and_reconstructs(orc, shape):
+    n1, n2, n3 = shape
+    X = rnd(100 + n1, *shape)
+    U, S, V, sw = orc.tsvd_dct_full(X)
+    p = min(n1, n2)
+    Xb = scipy.fft.dct(X, type=2, norm="ortho", axis=2)
+    for k in range(n3):
+        assert np.abs(U[:, :, k].T @ U[:, :, k] - np.eye(n1)).max() < 1e-13
+        assert np.abs(V[:, :, k].T @ V[:, :, k] - np.eye(n2)).max() < 1e-13
+        Sk = np.zeros((n1, n2))
+        Sk[:p, :p] = np.diag(S[:, k])
+        assert np.abs(U[:, :, k] @ Sk @ V[:, :, k].T - Xb[:, :, k]).max() < 1e-13
+        # the completed columns span the complement of the range (LAPACK's full factors)
+        Ul, sl, Vlt = np.linalg.svd(Xb[:, :, k])
+        if n1 > p:
+            P1 = U[:, p:, k] @ U[:, p:, k].T
+            P2 = Ul[:, p:] @ Ul[:, p:].T
+            assert np.abs(P1 - P2).max() < 1e-12
+        if n2 > p:
+            P1 = V[:, p:, k] @ V[:, p:, k].T
+            P2 = Vlt[p:, :].T @ Vlt[p:, :]
+            assert np.abs(P1 - P2).max() < 1e-12
+
+
+def test_tsvd_full_theorem4_tensor_factorization(orc):
+    # X = U * S * V^T with the DCT t-product, S the f-diagonal n1 x n2 x n3 tensor
+    n1, n2, n3 = 7, 4, 5
+    X = rnd(110, n1, n2, n3)
+    U, S, V, _ = orc.tsvd_dct_full(X)
+    Sb = np.zeros((n1, n2, n3))
+    for k in range(n3):
+        Sb[:4, :4, k] = np.diag(S[:, k])
+    Ut, St, Vt = (scipy.fft.idct(A, type=2, norm="ortho", axis=2) for A in (U, Sb, V))
+    VtT = F(np.transpose(Vt, (1, 0, 2)))
+    R = orc.tprod_dct(orc.tprod_dct(F(Ut), F(St)), VtT)
+    assert np.abs(R - X).max() < 1e-13
+
+
+def test_tsvd_full_completion_rule_closed_form(orc):
+    # slices whose range is spanned by e_1..e_p: the completion takes e_{p+1}, ..., e_m
+    n1, n2, n3 = 7, 3, 2
+    X = np.zeros((n1, n2, n3))
+    X[:3, :3, 0] = np.diag([3.0, 2.0, 1.0])  # every DCT slice: a multiple of diag(3,2,1) padded
+    X[:, :, 1] = X[:, :, 0]
+    U, S, V, _ = orc.tsvd_dct_full(F(X))
+    for k in range(n3):
+        if S[0, k] == 0.0:
+            continue
+        assert np.array_equal(np.abs(U[:, 3:, k]), np.eye(n1)[:, 3:])
