@@ -276,6 +276,34 @@ static int jacobi_tall(int64_t m, int64_t n, double* W, double* V, int max_sweep
     return -1;
 }
 
+/* Column c of Q (m rows, ld m) := a unit vector orthogonal to the columns
+ * use[0..nuse): the standard basis vector e_i with the largest part outside
+ * their span (1 - sum_q Q[i][q]^2; first i on ties), projected out twice
+ * (Gram-Schmidt, one column at a time) and normalized. */
+static void complement_column(int64_t m, double* Q, const int64_t* use, int64_t nuse, int64_t c) {
+    int64_t best = 0;
+    double bres = -1.0;
+    for (int64_t i = 0; i < m; ++i) {
+        double acc = 0.0;
+        for (int64_t t = 0; t < nuse; ++t) acc += Q[i + m * use[t]] * Q[i + m * use[t]];
+        const double res = 1.0 - acc;
+        if (res > bres) { bres = res; best = i; }
+    }
+    double* u = Q + m * c;
+    for (int64_t r = 0; r < m; ++r) u[r] = (r == best) ? 1.0 : 0.0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int64_t t = 0; t < nuse; ++t) {
+            const double* w = Q + m * use[t];
+            double d = 0.0;
+            for (int64_t r = 0; r < m; ++r) d += w[r] * u[r];
+            for (int64_t r = 0; r < m; ++r) u[r] -= d * w[r];
+        }
+    double nn = 0.0;
+    for (int64_t r = 0; r < m; ++r) nn += u[r] * u[r];
+    nn = sqrt(nn);
+    for (int64_t r = 0; r < m; ++r) u[r] /= nn;
+}
+
 int or_jacobi_svd(int64_t m, int64_t n, const double* A, int64_t lda, double* U, double* s, double* V, int max_sweeps) {
     int trans = m < n;
     int64_t mm = trans ? n : m; /* rows of the tall working matrix */
@@ -309,25 +337,18 @@ int or_jacobi_svd(int64_t m, int64_t n, const double* A, int64_t lda, double* U,
         for (int64_t r = 0; r < mm; ++r) Lt[r + mm * c] = (sv[o] > 0.0) ? W[r + mm * o] / sv[o] : 0.0;
         for (int64_t r = 0; r < p; ++r) Rt[r + p * c] = Q[r + p * o];
     }
-    /* zero singular values: complete the left vector by Gram-Schmidt (twice) */
-    for (int64_t c = 0; c < p; ++c) {
-        if (sv[ord[c]] > 0.0) continue;
-        for (int64_t e = 0; e < mm; ++e) {
-            double* u = Lt + mm * c;
-            for (int64_t r = 0; r < mm; ++r) u[r] = (r == e) ? 1.0 : 0.0;
-            for (int pass = 0; pass < 2; ++pass)
-                for (int64_t q = 0; q < p; ++q) {
-                    if (q == c || (sv[ord[q]] == 0.0 && q > c)) continue;
-                    double* w = Lt + mm * q;
-                    double d = 0.0;
-                    for (int64_t r = 0; r < mm; ++r) d += w[r] * u[r];
-                    for (int64_t r = 0; r < mm; ++r) u[r] -= d * w[r];
-                }
-            double nn = 0.0;
-            for (int64_t r = 0; r < mm; ++r) nn += u[r] * u[r];
-            nn = sqrt(nn);
-            if (nn > 0.5) { for (int64_t r = 0; r < mm; ++r) u[r] /= nn; break; }
+    /* zero singular values: complete the left vector (complement_column) against
+     * the columns with nonzero singular values and the zero ones before it */
+    {
+        int64_t* use = (int64_t*)malloc(sizeof(int64_t) * (p > 0 ? p : 1));
+        for (int64_t c = 0; c < p; ++c) {
+            if (sv[ord[c]] > 0.0) continue;
+            int64_t nuse = 0;
+            for (int64_t q = 0; q < p; ++q)
+                if (q != c && !(sv[ord[q]] == 0.0 && q > c)) use[nuse++] = q;
+            complement_column(mm, Lt, use, nuse, c);
         }
+        free(use);
     }
     /* Undo the transpose: A = Lt S Rt^T (tall) or A^T = Lt S Rt^T (wide). */
     double* Uo = trans ? Rt : Lt; int64_t ldu = trans ? p : mm;
@@ -391,39 +412,21 @@ int or_tsvd_dct(int64_t n1, int64_t n2, int64_t n3, const double* X, double* Uba
 /* Theorem 4 with full factors: U m1 x m1, V m2 x m2 orthogonal per slice.    */
 /* The thin factors as in or_tsvd_dct; the side with more rows than p         */
 /* (U if n1 > n2, V if n2 > n1) is completed to an orthonormal basis column   */
-/* by column: candidates e_1, e_2, ... are taken in cyclic order starting     */
-/* after the last accepted one, projected out twice against every column so  */
-/* far (Gram-Schmidt), and accepted when the residual's norm exceeds 1/2; the */
-/* accepted vector is normalized and its largest-magnitude entry (first one   */
-/* on ties) made positive.  Returns the largest sweep count, or -1.           */
+/* by column (complement_column against every column so far), each new       */
+/* column with its largest-magnitude entry (first one on ties) positive.      */
+/* Returns the largest sweep count, or -1.                                    */
 /* ------------------------------------------------------------------------- */
 static void complete_columns(int64_t m, int64_t p, double* Q) {
-    double* u = (double*)malloc(sizeof(double) * m);
-    int64_t e = m - 1; /* the last accepted candidate; the search starts after it */
+    int64_t* use = (int64_t*)malloc(sizeof(int64_t) * m);
     for (int64_t c = p; c < m; ++c) {
-        for (int64_t tries = 0; tries < m; ++tries) {
-            e = (e + 1) % m;
-            for (int64_t r = 0; r < m; ++r) u[r] = (r == e) ? 1.0 : 0.0;
-            for (int pass = 0; pass < 2; ++pass)
-                for (int64_t q = 0; q < c; ++q) {
-                    const double* w = Q + m * q;
-                    double d = 0.0;
-                    for (int64_t r = 0; r < m; ++r) d += w[r] * u[r];
-                    for (int64_t r = 0; r < m; ++r) u[r] -= d * w[r];
-                }
-            double nn = 0.0;
-            for (int64_t r = 0; r < m; ++r) nn += u[r] * u[r];
-            nn = sqrt(nn);
-            if (nn > 0.5) {
-                int64_t best = 0;
-                for (int64_t r = 1; r < m; ++r) if (fabs(u[r]) > fabs(u[best])) best = r;
-                const double f = (u[best] < 0.0 ? -1.0 : 1.0) / nn;
-                for (int64_t r = 0; r < m; ++r) Q[r + m * c] = f * u[r];
-                break;
-            }
-        }
+        for (int64_t q = 0; q < c; ++q) use[q] = q;
+        complement_column(m, Q, use, c, c);
+        double* u = Q + m * c;
+        int64_t best = 0;
+        for (int64_t r = 1; r < m; ++r) if (fabs(u[r]) > fabs(u[best])) best = r;
+        if (u[best] < 0.0) for (int64_t r = 0; r < m; ++r) u[r] = -u[r];
     }
-    free(u);
+    free(use);
 }
 
 struct svdf_ctx { int64_t n1, n2, p; const double* Xb; double *U, *S, *V; int max_sweeps; int* sweeps; };

@@ -300,3 +300,22 @@ def test_tsvd_full_completion_rule_closed_form(orc):
         if S[0, k] == 0.0:
             continue
         assert np.array_equal(np.abs(U[:, 3:, k]), np.eye(n1)[:, 3:])
+
+
+@pytest.mark.parametrize("shape,rank", [((30, 30, 2), 29), ((20, 12, 2), 5), ((12, 20, 2), 11), ((90, 40, 2), 40)])
+def test_tsvd_zero_sigma_and_full_completion_orthogonal(orc, shape, rank):
+    # rank-deficient square and rectangular slices, and a tall full factor whose
+    # last columns span a small complement: every completed basis is orthonormal
+    n1, n2, n3 = shape
+    g = np.random.default_rng(120 + n1)
+    Xb = np.stack([g.standard_normal((n1, rank)) @ g.standard_normal((rank, n2)) for _ in range(n3)], axis=2)
+    X = F(scipy.fft.idct(Xb, type=2, norm="ortho", axis=2))
+    for full in (False, True):
+        U, S, V, _ = (orc.tsvd_dct_full if full else orc.tsvd_dct)(X)
+        for k in range(n3):
+            assert np.abs(U[:, :, k].T @ U[:, :, k] - np.eye(U.shape[1])).max() < 1e-12
+            assert np.abs(V[:, :, k].T @ V[:, :, k] - np.eye(V.shape[1])).max() < 1e-12
+            Sk = np.zeros((U.shape[1], V.shape[1]))
+            p = min(n1, n2)
+            Sk[:p, :p] = np.diag(S[:, k])
+            assert np.abs(U[:, :, k] @ Sk @ V[:, :, k].T - Xb[:, :, k]).max() < 1e-11 * np.abs(Xb).max()
