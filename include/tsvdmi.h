@@ -166,13 +166,21 @@ int tprod_dct(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n4, int64
 /* DCT t-SVD, Theorem 4, thin form with p = min(n1,n2):
  *   U: n1 x p x n3, S: p x n3 (column k holds the singular values of the
  *   transformed slice k, descending), V: n2 x p x n3.
+ * Flag TSVD_FULL: the full factors of Theorem 4, U: n1 x n1 x n3 and
+ * V: n2 x n2 x n3, orthogonal in every transformed slice (S stays p x n3, the
+ * diagonal of the f-diagonal n1 x n2 x n3 tensor).  The first p columns are
+ * the thin ones; each of the longer side's other columns is the standard
+ * basis vector with the largest part outside the span of the columns before
+ * it (first on ties), projected out twice (Gram-Schmidt), normalized, largest
+ * entry positive.  A zero singular value's left vector is completed the same
+ * way (with the sign convention of its pair), in both forms.
  * Default: spatial-domain factors, so that X = U * S * V^T with the library's
  * tprod_dct (S expanded to the f-diagonal p x p x n3 tensor whose tubes are
  * idct of the rows of S).  Flag TSVD_TRANSFORM_DOMAIN returns Ubar, sigma,
  * Vbar instead, with S always in the transform domain.  Sign convention: in
  * each transformed slice, the largest-magnitude entry of every left singular
  * vector is positive.  U or V may be NULL when not wanted. */
-enum { TSVD_TRANSFORM_DOMAIN = 1 };
+enum { TSVD_TRANSFORM_DOMAIN = 1, TSVD_FULL = 2 };
 int tsvd_dct(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, const void* X, void* U, void* S,
              void* V, int flags, void* stream);
 

@@ -24,7 +24,7 @@ OK, WARN_NOCONV, EINVAL, ENOMEM, EHIP, ENONFINITE, EBUSY, ETIMEOUT, ECANCELED = 
 OPT_MAX_SWEEPS, OPT_SYNC_STATUS, OPT_TEAM_SIZE, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_GRAPHS = 0, 1, 2, 3, 4, 5
 OPT_AUTOTUNE, OPT_GROUP_LANES, OPT_GROUP_COLUMNS, OPT_WARM_START, OPT_COOPERATIVE, OPT_GRAM = 6, 7, 8, 9, 10, 11
 PHASES = ("forward_transform", "jacobi", "threshold_rebuild", "inverse_transform", "warm_start")
-TRANSFORM_DOMAIN = 1
+TRANSFORM_DOMAIN, FULL = 1, 2
 REQ_TSVT, REQ_COMPLETE = 0, 1
 
 EXPORTED = [
@@ -358,20 +358,22 @@ def tprod_dct(X: torch.Tensor, Yt: torch.Tensor, prec: Optional[int] = None, ctx
     return Z
 
 
-def tsvd_dct(X: torch.Tensor, prec: Optional[int] = None, transform_domain: bool = False,
+def tsvd_dct(X: torch.Tensor, prec: Optional[int] = None, transform_domain: bool = False, full: bool = False,
              ctx: Optional[Context] = None, stream=None):
-    """DCT t-SVD (Theorem 4), thin.  Returns U (n1,p,n3), S (p,n3), V (n2,p,n3)."""
+    """DCT t-SVD (Theorem 4).  Returns U (n1,p,n3), S (p,n3), V (n2,p,n3); with
+    full=True U (n1,n1,n3) and V (n2,n2,n3)."""
     X = fortran(X)
     d = _dev(X)
     prec = _prec_of(X, prec)
     ctx = ctx or default_context(d)
     n1, n2, n3 = X.shape
     p = min(n1, n2)
-    U = empty_f(n1, p, n3, X.dtype, X.device)
-    V = empty_f(n2, p, n3, X.dtype, X.device)
+    U = empty_f(n1, n1 if full else p, n3, X.dtype, X.device)
+    V = empty_f(n2, n2 if full else p, n3, X.dtype, X.device)
     S = torch.empty((n3, p), dtype=X.dtype, device=X.device).t()
+    flags = (TRANSFORM_DOMAIN if transform_domain else 0) | (FULL if full else 0)
     ctx.check(lib.tsvd_dct(ctx.h, prec, n1, n2, n3, X.data_ptr(), U.data_ptr(), S.data_ptr(), V.data_ptr(),
-                           TRANSFORM_DOMAIN if transform_domain else 0, _stream(stream, d)))
+                           flags, _stream(stream, d)))
     return U, S, V
 
 

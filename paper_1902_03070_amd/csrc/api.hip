@@ -1650,7 +1650,9 @@ int tsvd_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
     int rc = make_plan(c, prec, n1, n2, n3, 1, P, cv, s);
     if (rc) return rc;
     const size_t es = esize(prec);
-    const size_t oU = cv.take((size_t)n1 * P.p * n3 * es), oV = cv.take((size_t)n2 * P.p * n3 * es);
+    const bool full = (flags & TSVD_FULL) != 0;
+    const int64_t ucols = full ? n1 : P.p, vcols = full ? n2 : P.p;  // columns of U and V per slice
+    const size_t oU = cv.take((size_t)n1 * ucols * n3 * es), oV = cv.take((size_t)n2 * vcols * n3 * es);
     if ((rc = ensure_ws(c, cv.off))) return rc;
     char* base = (char*)c->ws.p;
     if ((rc = upload_plan(c, P, base))) return rc;
@@ -1681,17 +1683,27 @@ int tsvd_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
     fa.A = base + P.o_A; fa.m = P.m; fa.p = P.p; fa.a_ss = (int64_t)P.m * P.p;
     fa.Vj = base + P.o_V; fa.v_ss = (int64_t)P.p * P.p;
     fa.sig = (const double*)(base + P.o_sig); fa.sig_ss = P.p;
-    // tall problem: left vectors are U (n1 >= n2) or V (n1 < n2)
-    fa.Ut = P.trans ? Vo : Uo; fa.ut_ss = (int64_t)P.m * P.p;
+    // tall problem: left vectors are U (n1 >= n2) or V (n1 < n2); with full factors
+    // the tall side holds m columns per slice, the other side p = its full size
+    const int64_t tall_cols = full ? P.m : P.p;
+    fa.Ut = P.trans ? Vo : Uo; fa.ut_ss = (int64_t)P.m * tall_cols;
     fa.Vt = P.trans ? Uo : Vo; fa.vt_ss = (int64_t)P.p * P.p;
     fa.S = S; fa.s_ss = P.p; fa.n3 = (int)n3; fa.sign_from_v = P.trans;
     if ((e = launch_tsvd_finish(dp, fa, s)) != hipSuccess) return hip_fail(c, e, "tsvd finish");
+    // columns of zero singular values and the full factor's extra columns
+    TsvdCompleteArgs ca{};
+    ca.Lt = fa.Ut; ca.lt_ss = fa.ut_ss; ca.m = P.m;
+    ca.Rt = fa.Vt; ca.rt_ss = fa.vt_ss;
+    ca.Vj = base + P.o_V; ca.v_ss = (int64_t)P.p * P.p;
+    ca.sig = (const double*)(base + P.o_sig); ca.sig_ss = P.p;
+    ca.p = P.p; ca.n3 = (int)n3; ca.full = full && P.m > P.p; ca.sign_from_v = P.trans;
+    if ((e = launch_tsvd_complete(dp, ca, s)) != hipSuccess) return hip_fail(c, e, "tsvd complete");
     if (!(flags & TSVD_TRANSFORM_DOMAIN)) {
         // back to the spatial domain (in place: each workgroup owns whole tubes)
         TubeArgs iv{};
         iv.M = Ct; iv.n3 = (int)n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
-        if (U) { iv.in = U; iv.out = U; iv.N = n1 * P.p; if ((rc = run_tube(c, prec, iv, 1, s))) return rc; }
-        if (V) { iv.in = V; iv.out = V; iv.N = n2 * P.p; if ((rc = run_tube(c, prec, iv, 1, s))) return rc; }
+        if (U) { iv.in = U; iv.out = U; iv.N = n1 * ucols; if ((rc = run_tube(c, prec, iv, 1, s))) return rc; }
+        if (V) { iv.in = V; iv.out = V; iv.N = n2 * vcols; if ((rc = run_tube(c, prec, iv, 1, s))) return rc; }
         iv.in = S; iv.out = S; iv.N = P.p;
         if ((rc = run_tube(c, prec, iv, 1, s))) return rc;
     }

@@ -227,6 +227,18 @@ struct TsvdFinishArgs {
     int sign_from_v;                         // 1: the slice's left vectors are the Jacobi V (n1 < n2)
 };
 hipError_t launch_tsvd_finish(int prec, const TsvdFinishArgs& a, hipStream_t s);
+// Completion of the tall-side vectors after the finish: columns of zero
+// singular values and, with full, the columns p..m-1 of the full factor.
+struct TsvdCompleteArgs {
+    void* Lt; int64_t lt_ss; int m;          // tall-side vectors, ld m, slice stride lt_ss
+    void* Rt; int64_t rt_ss;                 // the other side (p x p): partner sign flips
+    const void* Vj; int64_t v_ss;            // Jacobi right vectors (p x p, unsorted columns)
+    const double* sig; int64_t sig_ss;       // per-column singular values (unsorted)
+    int p, n3;
+    int full;                                // 1: also columns p..m-1
+    int sign_from_v;                         // 1: wide slice (the pair's sign comes from Vj)
+};
+hipError_t launch_tsvd_complete(int prec, const TsvdCompleteArgs& a, hipStream_t s);
 
 }  // namespace tsvd
 

@@ -383,6 +383,153 @@ __global__ __launch_bounds__(256) void k_tsvd_finish(TsvdFinishArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Completion of the t-SVD's tall-side vectors (Theorem 4's full factors, and
+// the columns of zero singular values).  One workgroup per slice, FP64
+// arithmetic.  Column c is filled with the standard basis vector e_i whose
+// part outside the span of the columns before it is largest (1 - sum_q
+// Q[i][q]^2, first i on ties), projected out twice (Gram-Schmidt, each pass
+// d = Q^T u, u -= Q d) and normalized.  Zero singular values (sorted last
+// among the first p columns) get the sign convention of their pair (u_j,
+// v_j); the full factor's columns p..m-1 get their largest entry positive.
+// ---------------------------------------------------------------------------
+__device__ double block_sum_d(double v, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    return t;
+}
+
+// Load of a column this workgroup itself stored earlier in the kernel: an
+// agent-scope relaxed load, which skips the CU's L1 (a line of it may still
+// hold what was there before the store) and reads the L2.
+template <typename T>
+__device__ __forceinline__ double ld_fresh(const T* p) {
+    return (double)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Index of the largest v_r (largest |v_r| when absv; first on ties) over r < n,
+// in every thread.
+__device__ int block_argmax(const double* v, int n, bool absv, double* redv, int* redi) {
+    const int tid = threadIdx.x;
+    double best = -1e300;
+    int bi = 0x7fffffff;
+    for (int r = tid; r < n; r += blockDim.x) {
+        const double x = absv ? fabs(v[r]) : v[r];
+        if (x > best) { best = x; bi = r; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, kWave);
+        const int oi = __shfl_xor(bi, o, kWave);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) { redv[tid >> 6] = best; redi[tid >> 6] = bi; }
+    __syncthreads();
+    best = redv[0];
+    bi = redi[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+        if (redv[w] > best || (redv[w] == best && redi[w] < bi)) { best = redv[w]; bi = redi[w]; }
+    return bi;
+}
+
+// Unit vector (in u) orthogonal to columns [0, nq) of Q (m rows, ld m), from
+// the standard basis vector of largest residual.
+template <typename T>
+__device__ void complement_vector(const T* Q, int m, int nq, double* u, double* d, double* red, int* redi) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int r = tid; r < m; r += nt) {
+        double acc = 0.0;
+        for (int q = 0; q < nq; ++q) {
+            const double x = ld_fresh(Q + (int64_t)q * m + r);
+            acc = fma(x, x, acc);
+        }
+        d[r] = 1.0 - acc;
+    }
+    __syncthreads();
+    const int best = block_argmax(d, m, false, red, redi);
+    for (int r = tid; r < m; r += nt) u[r] = r == best ? 1.0 : 0.0;
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int q = tid; q < nq; q += nt) {
+            const T* w = Q + (int64_t)q * m;
+            double acc = 0.0;
+            for (int r = 0; r < m; ++r) acc = fma(ld_fresh(w + r), u[r], acc);
+            d[q] = acc;
+        }
+        __syncthreads();
+        for (int r = tid; r < m; r += nt) {
+            double acc = u[r];
+            for (int q = 0; q < nq; ++q) acc = fma(-ld_fresh(Q + (int64_t)q * m + r), d[q], acc);
+            u[r] = acc;
+        }
+        __syncthreads();
+    }
+    double nn = 0.0;
+    for (int r = tid; r < m; r += nt) nn = fma(u[r], u[r], nn);
+    const double inv = 1.0 / sqrt(block_sum_d(nn, red));
+    for (int r = tid; r < m; r += nt) u[r] *= inv;
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tsvd_complete(TsvdCompleteArgs a) {
+    __shared__ double u[kMaxRows], d[kMaxRows], red[4];
+    __shared__ int redi[4];
+    const int k = blockIdx.x, m = a.m, p = a.p, tid = threadIdx.x;
+    T* Q = (T*)a.Lt + (int64_t)k * a.lt_ss;
+    T* R = (T*)a.Rt + (int64_t)k * a.rt_ss;
+    const double* sig = a.sig + (int64_t)k * a.sig_ss;
+    // zero singular values: sorted after the nonzero ones, in column order
+    int nz = 0;
+    for (int c = 0; c < p; ++c) nz += sig[c] > 0.0 ? 1 : 0;
+    int zc = -1;  // the original column of the current zero position
+    for (int pos = nz; pos < p; ++pos) {
+        for (zc = zc + 1; zc < p && sig[zc] > 0.0; ++zc) {
+        }
+        complement_vector<T>(Q, m, pos, u, d, red, redi);
+        double f = 1.0;
+        if (!a.sign_from_v) {
+            // the pair's sign from the completed left vector itself
+            const int bi = block_argmax(u, m, true, red, redi);
+            if (u[bi] < 0.0) {
+                f = -1.0;
+                for (int r = tid; r < p; r += blockDim.x) R[(int64_t)pos * p + r] = -R[(int64_t)pos * p + r];
+            }
+        } else {
+            // the pair's sign was taken from the Jacobi right vector (the left
+            // vector of the wide slice) and already applied to it: apply it here
+            const T* vj = (const T*)a.Vj + (int64_t)k * a.v_ss + (int64_t)zc * p;
+            for (int r = tid; r < p; r += blockDim.x) d[r] = (double)vj[r];
+            __syncthreads();
+            const int bi = block_argmax(d, p, true, red, redi);
+            if (d[bi] < 0.0) f = -1.0;
+        }
+        for (int r = tid; r < m; r += blockDim.x) Q[(int64_t)pos * m + r] = (T)(f * u[r]);
+        __syncthreads();
+    }
+    if (!a.full) return;
+    for (int c = p; c < m; ++c) {
+        complement_vector<T>(Q, m, c, u, d, red, redi);
+        const int bi = block_argmax(u, m, true, red, redi);
+        const double f = u[bi] < 0.0 ? -1.0 : 1.0;
+        for (int r = tid; r < m; r += blockDim.x) Q[(int64_t)c * m + r] = (T)(f * u[r]);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_tsvd_complete(int prec, const TsvdCompleteArgs& a, hipStream_t s) {
+    if (a.n3 <= 0) return hipSuccess;
+    if (prec == 0) hipLaunchKernelGGL(k_tsvd_complete<double>, dim3(a.n3), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_tsvd_complete<float>, dim3(a.n3), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_tsvd_finish(int prec, const TsvdFinishArgs& a, hipStream_t s) {
     if (a.n3 <= 0) return hipSuccess;
     if (prec == 0) hipLaunchKernelGGL(k_tsvd_finish<double>, dim3(a.n3), dim3(256), 0, s, a);
