@@ -65,12 +65,18 @@ static void parallel_for(int64_t n, range_fn fn, void* ctx) {
 /* The paper writes dct(X,[],3), MATLAB's orthonormal DCT-II, and never       */
 /* prints the matrix; this is the standard orthonormal DCT-II matrix:         */
 /*   C[k][t] = s_k cos(pi (2t+1) k / (2n)),  s_0 = sqrt(1/n), s_k = sqrt(2/n). */
+/* The integer (2t+1) k is reduced modulo 4n (the cosine's period in these    */
+/* units) before the cosine, so the argument stays below 2 pi and is rounded  */
+/* once, whatever n.                                                          */
 /* ------------------------------------------------------------------------- */
 void or_dct_matrix(int n, double* C) {
     const double pi = acos(-1.0);
     for (int k = 0; k < n; ++k) {
         double s = (k == 0) ? sqrt(1.0 / n) : sqrt(2.0 / n);
-        for (int t = 0; t < n; ++t) C[(int64_t)k * n + t] = s * cos(pi * (2.0 * t + 1.0) * k / (2.0 * n));
+        for (int t = 0; t < n; ++t) {
+            const int64_t q = ((2 * (int64_t)t + 1) * k) % (4 * (int64_t)n);
+            C[(int64_t)k * n + t] = s * cos(pi * (double)q / (2.0 * n));
+        }
     }
 }
 
