@@ -24,6 +24,13 @@
  *     call says it synchronizes.
  *   - A context owns its device workspace, the DCT matrices, captured graphs
  *     and tuning results.  One context per host thread, or external locking.
+ *   - Tube length n3 (the transform along the tubes): n3 <= 128 runs on the
+ *     matrix cores; 128 < n3 <= 512 (DCT and Fourier paths) on the fast
+ *     O(n3 log n3) transform in FP64 arithmetic (Makhoul's reordering,
+ *     Bluestein's chirp, radix-2 FFTs); other tubes longer than 128 (caller-
+ *     given transforms, tsvt_dct_noalloc, n3 > 512) on the dense vector-ALU
+ *     kernel, which holds at most 304 (double data) or 608 (float data):
+ *     beyond that a call returns TSVD_EINVAL.
  *   - Return value: TSVD_OK, a positive warning (outputs written), or a
  *     negative error (outputs undefined).  Errors found on the device
  *     (non-finite input, Jacobi not converged, a wait that timed out) are
@@ -176,8 +183,9 @@ int tprod_dct(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n4, int64
  * way (with the sign convention of its pair), in both forms.
  * Default: spatial-domain factors, so that X = U * S * V^T with the library's
  * tprod_dct (S expanded to the f-diagonal p x p x n3 tensor whose tubes are
- * idct of the rows of S).  Flag TSVD_TRANSFORM_DOMAIN returns Ubar, sigma,
- * Vbar instead, with S always in the transform domain.  Sign convention: in
+ * idct of the rows of S: S itself is returned in the spatial domain).  Flag
+ * TSVD_TRANSFORM_DOMAIN returns Ubar, the singular values sigma and Vbar
+ * instead.  Sign convention: in
  * each transformed slice, the largest-magnitude entry of every left singular
  * vector is positive.  U or V may be NULL when not wanted. */
 enum { TSVD_TRANSFORM_DOMAIN = 1, TSVD_FULL = 2 };

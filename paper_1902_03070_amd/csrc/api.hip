@@ -37,6 +37,8 @@ struct tsvd_ctx {
     std::map<std::pair<int, int>, std::pair<void*, void*>> dct;
     // matrix-core fragments: (n3, engine, inverse) -> device buffer
     std::map<std::tuple<int, int, int>, void*> frag;
+    // fast-transform tables of long tubes: n3 -> device buffer
+    std::map<int, void*> fft;
     DevBuf ws;                 // main workspace
     DevBuf ctrl;               // Ctrl + norms + history (persistent)
     Ctrl* h_ctrl = nullptr;    // pinned host mirror
@@ -163,6 +165,8 @@ int run_tube_mat(tsvd_ctx* c, int prec, TubeArgs a, int inverse, const void* mat
     if (a.n3 <= kMaxTube) {
         e = launch_tube_mfma(tube_engine(prec), a, mat, s);
     } else {
+        if (dense_tube_lds(prec, a.n3) > kLdsBudget)
+            return fail(c, TSVD_EINVAL, "tubes too long for the dense transform kernel");
         a.M = mat;
         e = launch_tube_transform(prec == TSVD_FP64 ? 0 : 1, a, s);
     }
@@ -170,8 +174,47 @@ int run_tube_mat(tsvd_ctx* c, int prec, TubeArgs a, int inverse, const void* mat
     return TSVD_OK;
 }
 
+// Tables of the fast transform for tubes of length n3 (built once per context).
+int get_fft_tables(tsvd_ctx* c, int n3, const void** out) {
+    auto it = c->fft.find(n3);
+    if (it == c->fft.end()) {
+        const size_t bytes = fft_table_bytes(n3);
+        std::vector<unsigned char> h(bytes);
+        make_fft_tables(n3, h.data());
+        void* d = nullptr;
+        HIPCHK(c, hipMalloc(&d, bytes));
+        HIPCHK(c, hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
+        it = c->fft.emplace(n3, d).first;
+    }
+    *out = it->second;
+    return TSVD_OK;
+}
+
+// The fast transform of long tubes (mode: kFftDct* or kFftDft*).
+int run_tube_fft(tsvd_ctx* c, int prec, const TubeArgs& a, int mode, hipStream_t s) {
+    const void* tab;
+    int rc = get_fft_tables(c, a.n3, &tab);
+    if (rc) return rc;
+    const hipError_t e = launch_tube_fft(prec == TSVD_FP64 ? 0 : 1, a, tab, mode, s);
+    if (e != hipSuccess) return hip_fail(c, e, (mode & 1) ? "inverse fast tube transform" : "fast tube transform");
+    return TSVD_OK;
+}
+
+// Transform operands run_tube uses (fast-transform tables, fragments or the dense
+// matrices), built now: before a graph capture, which cannot allocate.
+int prepare_tube(tsvd_ctx* c, int n3, int prec) {
+    const void *a, *b;
+    if (fft_fits(n3)) return get_fft_tables(c, n3, &a);
+    if (n3 <= kMaxTube) {
+        int rc = get_frag(c, n3, prec, 0, &a);
+        return rc ? rc : get_frag(c, n3, prec, 1, &b);
+    }
+    return get_dct(c, n3, prec, &a, &b);
+}
+
 int run_tube(tsvd_ctx* c, int prec, TubeArgs a, int inverse, hipStream_t s) {
     const void* mat;
+    if (fft_fits(a.n3)) return run_tube_fft(c, prec, a, inverse ? kFftDctInverse : kFftDctForward, s);
     if (a.n3 <= kMaxTube) {
         int rc = get_frag(c, a.n3, prec, inverse, &mat);
         if (rc) return rc;
@@ -1197,7 +1240,8 @@ int dft_forward(tsvd_ctx* c, DftPlan& D, int prec, int64_t n1, int64_t n2, int64
     f.beta_val = 1.0;
     {
         PhaseMark pm(c, 0, s);
-        if ((rc = run_tube_mat(c, prec, f, 0, fwd, s))) return rc;
+        rc = fwd ? run_tube_mat(c, prec, f, 0, fwd, s) : run_tube_fft(c, prec, f, kFftDftForward, s);
+        if (rc) return rc;
     }
     DftEmbedArgs ea{};
     ea.zb = base + D.o_zb;
@@ -1275,6 +1319,7 @@ void tsvd_destroy(tsvd_ctx* c) {
         (void)hipFree(kv.second.second);
     }
     for (auto& kv : c->frag) (void)hipFree(kv.second);
+    for (auto& kv : c->fft) (void)hipFree(kv.second);
     if (c->xf.p) (void)hipFree(c->xf.p);
     if (c->ws.p) (void)hipFree(c->ws.p);
     if (c->ctrl.p) (void)hipFree(c->ctrl.p);
@@ -1490,10 +1535,12 @@ int tsvt_dft(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
     if (rc) return rc;
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
-    std::vector<double> R, Ri;
-    real_dft_matrices((int)n3, R, Ri);
-    const void *fwd, *inv;
-    if ((rc = get_custom_operands(c, prec, (int)n3, R.data(), Ri.data(), s, &fwd, &inv))) return rc;
+    const void *fwd = nullptr, *inv = nullptr;  // null: the fast transform (long tubes)
+    if (!fft_fits((int)n3)) {
+        std::vector<double> R, Ri;
+        real_dft_matrices((int)n3, R, Ri);
+        if ((rc = get_custom_operands(c, prec, (int)n3, R.data(), Ri.data(), s, &fwd, &inv))) return rc;
+    }
     DftPlan D;
     Carve cv;
     if ((rc = make_dft_plan(c, prec, n1, n2, n3, D, cv, s))) return rc;
@@ -1515,7 +1562,8 @@ int tsvt_dft(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
     iv.in = base + D.o_zb; iv.out = Y; iv.N = n1 * n2; iv.n3 = (int)n3; iv.ctrl = cr.ctrl; iv.beta_val = 1.0;
     {
         PhaseMark pm(c, 3, s);
-        if ((rc = run_tube_mat(c, prec, iv, 1, inv, s))) return rc;
+        rc = inv ? run_tube_mat(c, prec, iv, 1, inv, s) : run_tube_fft(c, prec, iv, kFftDftInverse, s);
+        if (rc) return rc;
     }
     if (ranks_out) {
         // a complex slice's rank is half its real form's; conjugate frequencies share it
@@ -1569,11 +1617,13 @@ int tnn_f(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const void*
     if (!X || !out) return fail(c, TSVD_EINVAL, "null pointer");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
-    std::vector<double> R, Ri;
-    real_dft_matrices((int)n3, R, Ri);
-    const void *fwd, *inv;
-    int rc = get_custom_operands(c, prec, (int)n3, R.data(), Ri.data(), s, &fwd, &inv);
-    if (rc) return rc;
+    const void *fwd = nullptr, *inv = nullptr;  // null: the fast transform (long tubes)
+    int rc;
+    if (!fft_fits((int)n3)) {
+        std::vector<double> R, Ri;
+        real_dft_matrices((int)n3, R, Ri);
+        if ((rc = get_custom_operands(c, prec, (int)n3, R.data(), Ri.data(), s, &fwd, &inv))) return rc;
+    }
     DftPlan D;
     Carve cv;
     if ((rc = make_dft_plan(c, prec, n1, n2, n3, D, cv, s))) return rc;
@@ -1814,10 +1864,7 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
     hipStream_t run = s;
     if (c->use_graphs && !c->prof) {
         // everything the iteration allocates lazily must exist before capture
-        const void* tmp;
-        if (n3 <= kMaxTube) {
-            if ((rc = get_frag(c, (int)n3, prec, 0, &tmp)) || (rc = get_frag(c, (int)n3, prec, 1, &tmp))) return rc;
-        }
+        if ((rc = prepare_tube(c, (int)n3, prec))) return rc;
         if (!c->own) HIPCHK(c, hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
         HIPCHK(c, hipStreamSynchronize(s));
         run = c->own;

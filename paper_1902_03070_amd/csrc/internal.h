@@ -95,6 +95,9 @@ struct TubeArgs {
     int check_finite;      // 1: flag non-finite inputs in ctrl->status
 };
 hipError_t launch_tube_transform(int prec, const TubeArgs& a, hipStream_t s);
+constexpr int kTubeTile = 64;  // tubes per workgroup of launch_tube_transform
+// Dynamic LDS of launch_tube_transform (prec: 0 FP64, else FP32 data).
+inline int dense_tube_lds(int prec, int n3) { return n3 * kTubeTile * (prec == 0 ? 8 : 4); }
 
 // The same transform on the matrix cores for tubes of length n3 <= kMaxTube.
 // eng: 0 FP64, 1 FP32, 2 BF16 hi+lo (FP32 data).  frag: M in fragment order,
@@ -104,6 +107,21 @@ int tube_ks(int eng, int n3);
 size_t tube_fragment_bytes(int eng, int n3);
 void make_tube_fragments(int eng, int n3, const double* M, void* out);
 hipError_t launch_tube_mfma(int eng, const TubeArgs& a, const void* frag, hipStream_t s);
+// Fast tube transforms (dct_fft.hip) for tubes longer than kMaxTube, in
+// O(n3 log n3) by Bluestein's chirp with radix-2 FFTs, FP64 arithmetic: the
+// orthonormal DCT-II and its inverse (Makhoul's reordering), and the real form
+// of the DFT and its inverse (rows: Re V0, (Re Vf, Im Vf) for 1 <= f <= (n3-1)/2,
+// Re V(n3/2) for even n3).  Tables built on the host by make_fft_tables
+// (fft_table_bytes(n3) bytes).  Fails (hipErrorInvalidValue) when
+// fft_lds_bytes(n3) exceeds the LDS budget (n3 > 512).
+enum { kFftDctForward = 0, kFftDctInverse = 1, kFftDftForward = 2, kFftDftInverse = 3 };
+int fft_size(int n);
+size_t fft_table_bytes(int n);
+void make_fft_tables(int n, void* out);
+int fft_lds_bytes(int n);
+bool fft_fits(int n3);  // n3 > kMaxTube and the kernel's LDS fits
+hipError_t launch_tube_fft(int prec, const TubeArgs& a, const void* tables, int mode, hipStream_t s);
+
 // The operand of the tube transform built on the device (no host copy): the
 // fragments of engine eng for n3 <= kMaxTube, else the dense row-major matrix
 // (FP64 for eng 0, FP32 otherwise).  tube_matrix_bytes gives its size.

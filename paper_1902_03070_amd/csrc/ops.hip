@@ -15,7 +15,6 @@ namespace tsvd {
 //   Xn = mask ? B : y + Mlt/beta;  Mlt += beta (y - Xn);  X = Xn
 // with FP64 partial sums of ||Xn - X||^2 and ||X||^2.
 // ---------------------------------------------------------------------------
-constexpr int kTubeTile = 64;
 constexpr int kTubeKB = 8;
 
 __device__ __forceinline__ double beta_of(const TubeArgs& a) {
@@ -115,13 +114,10 @@ __global__ __launch_bounds__(256) void k_tube(TubeArgs a) {
 hipError_t launch_tube_transform(int prec, const TubeArgs& a, hipStream_t s) {
     if (a.N <= 0) return hipSuccess;
     dim3 grid((unsigned)((a.N + kTubeTile - 1) / kTubeTile)), block(256);
-    if (prec == 0) {
-        const int lds = a.n3 * kTubeTile * 8;
-        hipLaunchKernelGGL(k_tube<double>, grid, block, lds, s, a);
-    } else {
-        const int lds = a.n3 * kTubeTile * 4;
-        hipLaunchKernelGGL(k_tube<float>, grid, block, lds, s, a);
-    }
+    const int lds = dense_tube_lds(prec, a.n3);
+    if (lds > kLdsBudget) return hipErrorInvalidValue;
+    if (prec == 0) hipLaunchKernelGGL(k_tube<double>, grid, block, lds, s, a);
+    else hipLaunchKernelGGL(k_tube<float>, grid, block, lds, s, a);
     return hipGetLastError();
 }
 
