@@ -442,6 +442,52 @@ def dct_vs_dft(tm, torch, reps=3):
                                "note": "original (DFT) and DCT t-SVD in seconds, MATLAB on the paper's CPU"}}
 
 
+def long_tubes(tm, torch, reps=5):
+    """Tubes longer than 128: the fast O(n3 log n3) transform (Bluestein's chirp
+    with register FFTs) against the dense vector-ALU product, forward-transform
+    launch time from the HIP events of a profiled t-SVT on N(0,1) tensors.
+    Roofline of the fast kernel: algorithmic bytes = read and write every
+    element once (2 N n3 es)."""
+    rows = []
+    g = np.random.default_rng(synth_seed(7))
+    for n1, n2, n3 in ((256, 256, 200), (256, 256, 400)):
+        for name, prec in (("mixed", tm.MIXED), ("fp64", tm.FP64)):
+            dt = torch.float64 if prec == tm.FP64 else torch.float32
+            X = torch.from_numpy(np.asfortranarray(g.standard_normal((n1, n2, n3)))).to(dt).to("cuda:0")
+            X = tm.fortran(X.permute(2, 1, 0).contiguous().permute(2, 1, 0))
+            row = {"shape": [n1, n2, n3], "path": name}
+            for kind, dense in (("fast", 0), ("dense", 1)):
+                if dense and n3 * 64 * (8 if prec == tm.FP64 else 4) > (160 - 8) * 1024:
+                    row[kind] = "not run: a 64-tube tile of this length exceeds the LDS"
+                    continue
+                ctx = tm.Context(0)
+                try:
+                    ctx.set_option(tm.OPT_LONG_TUBES, dense)
+                    ctx.set_option(tm.OPT_PROFILE, 1)
+                    tm.tsvt_dct(X, 1.0, prec=prec, ctx=ctx)
+                    torch.cuda.synchronize()
+                    ctx.stats(reset=True)
+                    for _ in range(reps):
+                        tm.tsvt_dct(X, 1.0, prec=prec, ctx=ctx)
+                    torch.cuda.synchronize()
+                    st = ctx.stats(reset=True)
+                    row[kind + "_forward_us"] = round(1e3 * st["ms"]["forward_transform"] / reps, 1)
+                    row[kind + "_inverse_us"] = round(1e3 * st["ms"]["inverse_transform"] / reps, 1)
+                except tm.TsvdError as e:
+                    row[kind] = "not run: %s" % e
+                finally:
+                    ctx.close()
+            if "fast_forward_us" in row:
+                nbytes = 2.0 * n1 * n2 * n3 * (8 if prec == tm.FP64 else 4)
+                gbs = nbytes / (row["fast_forward_us"] * 1e-6) / 1e9
+                row["fast_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_GBs"],
+                                        "unit": "GB/s", "frac": round(gbs / PEAK["hbm_GBs"], 4)}
+            rows.append(row)
+            log("long tubes:", row)
+    return {"rows": rows, "data": "random N(0,1) tensors",
+            "note": "dense = the vector-ALU product; FP64 tubes beyond 304 have only the fast kernel"}
+
+
 def synth_seed(i):
     import synth
 
@@ -541,6 +587,7 @@ def main():
         log("batched:", out["batched"])
         out["beta_sweep"] = beta_sweep(tm, torch, case)
         out["dct_vs_dft"] = dct_vs_dft(tm, torch)
+        out["long_tubes"] = long_tubes(tm, torch)
         out["serving"] = serving(tm, torch, tprod, args.serving_requests,
                                  [float(x) for x in args.serving_loads.split(",")])
         log("serving:", out["serving"])

@@ -114,11 +114,14 @@ enum {
                                   segmentation fault at exit under rocprofv3, one that made only
                                   ordinary launches did not.  The environment variable
                                   TSVDMI_COOPERATIVE=1 sets 1 at context creation. */
-    TSVD_OPT_GRAM = 11         /* block-Gram Jacobi kernel for slices that need several workgroups
+    TSVD_OPT_GRAM = 11,        /* block-Gram Jacobi kernel for slices that need several workgroups
                                   (column blocks of 16: Gram matrices and the accumulated rotations
                                   applied on the matrix cores): 0 a candidate of the tuner, 1
                                   forced (team size from TSVD_OPT_TEAM_SIZE, else one workgroup
                                   per 32 columns), -1 (default) never used */
+    TSVD_OPT_LONG_TUBES = 12   /* DCT tubes of 129..512: 0 (default) the fast O(n3 log n3)
+                                  transform, 1 the dense vector-ALU product where its LDS tile
+                                  fits (n3 <= 304 for double data, 608 for float) */
 };
 int tsvd_set_option(tsvd_ctx* ctx, int option, double value);
 double tsvd_get_option(const tsvd_ctx* ctx, int option);

@@ -39,6 +39,7 @@ struct tsvd_ctx {
     std::map<std::tuple<int, int, int>, void*> frag;
     // fast-transform tables of long tubes: n3 -> device buffer
     std::map<int, void*> fft;
+    int dense_long = 0;  // 1: DCT tubes of 129..512 on the dense kernel where it fits
     DevBuf ws;                 // main workspace
     DevBuf ctrl;               // Ctrl + norms + history (persistent)
     Ctrl* h_ctrl = nullptr;    // pinned host mirror
@@ -200,11 +201,17 @@ int run_tube_fft(tsvd_ctx* c, int prec, const TubeArgs& a, int mode, hipStream_t
     return TSVD_OK;
 }
 
+// Whether DCT tubes of length n3 take the fast transform.
+bool use_fft(const tsvd_ctx* c, int prec, int n3) {
+    if (!fft_fits(n3)) return false;
+    return !(c->dense_long && dense_tube_lds(prec, n3) <= kLdsBudget);
+}
+
 // Transform operands run_tube uses (fast-transform tables, fragments or the dense
 // matrices), built now: before a graph capture, which cannot allocate.
 int prepare_tube(tsvd_ctx* c, int n3, int prec) {
     const void *a, *b;
-    if (fft_fits(n3)) return get_fft_tables(c, n3, &a);
+    if (use_fft(c, prec, n3)) return get_fft_tables(c, n3, &a);
     if (n3 <= kMaxTube) {
         int rc = get_frag(c, n3, prec, 0, &a);
         return rc ? rc : get_frag(c, n3, prec, 1, &b);
@@ -214,7 +221,7 @@ int prepare_tube(tsvd_ctx* c, int n3, int prec) {
 
 int run_tube(tsvd_ctx* c, int prec, TubeArgs a, int inverse, hipStream_t s) {
     const void* mat;
-    if (fft_fits(a.n3)) return run_tube_fft(c, prec, a, inverse ? kFftDctInverse : kFftDctForward, s);
+    if (use_fft(c, prec, a.n3)) return run_tube_fft(c, prec, a, inverse ? kFftDctInverse : kFftDctForward, s);
     if (a.n3 <= kMaxTube) {
         int rc = get_frag(c, a.n3, prec, inverse, &mat);
         if (rc) return rc;
@@ -1367,6 +1374,10 @@ int tsvd_set_option(tsvd_ctx* c, int opt, double v) {
             c->group_lanes = (int)v;
             return TSVD_OK;
         case TSVD_OPT_COOPERATIVE: c->coop = v != 0.0; return TSVD_OK;
+        case TSVD_OPT_LONG_TUBES:
+            if (v != 0.0 && v != 1.0) return fail(c, TSVD_EINVAL, "long-tube kernel must be 0 or 1");
+            c->dense_long = (int)v;
+            return TSVD_OK;
         case TSVD_OPT_GRAM:
             if (v != -1 && v != 0 && v != 1) return fail(c, TSVD_EINVAL, "gram option is -1, 0 or 1");
             c->gram = (int)v;
@@ -1390,6 +1401,7 @@ double tsvd_get_option(const tsvd_ctx* c, int opt) {
         case TSVD_OPT_GROUP_LANES: return c->group_lanes;
         case TSVD_OPT_COOPERATIVE: return c->coop;
         case TSVD_OPT_GRAM: return c->gram;
+        case TSVD_OPT_LONG_TUBES: return c->dense_long;
     }
     return -1.0;
 }

@@ -1,35 +1,43 @@
 // Fast tube transforms for long tubes: the orthonormal DCT-II along every
-// tube (Section 3, dct(.,[],3)) and its inverse in O(n3 log n3) work, for
+// tube (Section 3, dct(.,[],3)) and its inverse, and the real form of the DFT
+// along the tubes (Section 2) and its inverse, in O(n3 log n3) work, for
 // tubes longer than the matrix-core kernel's limit.
 //
-// Forward (Makhoul's reordering): with v[t] = x[2t] for t < ceil(n/2) and
+// DCT-II by Makhoul's reordering: with v[t] = x[2t] for t < ceil(n/2) and
 // v[n-1-t] = x[2t+1] for t < floor(n/2), the unnormalized DCT-II is
 //     y[k] = sum_t x[t] cos(pi (2t+1) k / (2n)) = Re(e^{-i pi k/(2n)} V[k]),
 // V = DFT_n(v), and X[k] = s_k y[k] (s_0 = sqrt(1/n), s_k = sqrt(2/n)).
 // Inverse: y[k] = X[k] / s_k, V[k] = e^{i pi k/(2n)} (y[k] - i y[n-k])
 // (y[n] = 0), v = IDFT_n(V) (real), x[2t] = v[t], x[2t+1] = v[n-1-t].
 //
+// Real form of the DFT (the Fourier path's tube transform): row 0 = Re V[0],
+// rows 2f - 1 and 2f = Re V[f] and Im V[f] for 1 <= f <= (n - 1) / 2, and
+// for even n row n - 1 = V[n/2] (real), V = DFT_n(x); the inverse rebuilds the
+// Hermitian spectrum and returns IDFT_n (real).
+//
+// Two real tubes per complex transform: the DFT of u = v1 + i v2 gives
+// V1[k] = (W[k] + conj W[n-k]) / 2 and V2[k] = (W[k] - conj W[n-k]) / (2i);
+// the inverse DFT of V1 + i V2 is v1 + i v2 when both are real.
+//
 // DFT_n of any length by Bluestein's chirp: with c[j] = e^{-i pi j^2 / n},
 // DFT_n(u)[k] = c[k] sum_j (u[j] c[j]) conj(c[k-j]), a linear convolution
-// done as a cyclic one of length M (a power of two >= 2n - 1): a forward
-// radix-2 FFT of the chirped input (decimation in frequency: natural order
-// in, bit-reversed order out), a product with the transformed conjugate chirp
-// (stored bit-reversed on the host), and an inverse radix-2 FFT (decimation
-// in time: bit-reversed order in, natural order out), so that no explicit
-// permutation is needed.  The inverse DFT is conj(DFT_n(conj(V))) / n.
+// done as a cyclic one of length M = 64 R (a power of two >= 2n - 1): an FFT
+// of the chirped input, a product with the FFT of the wrapped conjugate chirp
+// (a table), and an inverse FFT taken as conj(FFT(conj .)).  An inverse DFT is
+// conj(DFT(conj .)) / n.
+//
+// FFT of M points by one wavefront, Stockham autosort (natural order in and
+// out, no bit reversal): lane l holds x[l + 64 s], s < R, in registers; each
+// pass of radix r applies the twiddles and r-point DFTs in registers and
+// exchanges through LDS (three passes: 8 x 8 x 8 for M = 512, 16 x 16 x 4 for
+// M = 1024).
 //
 // Workgroup: 16 consecutive tubes (each row of the mode-3 unfolding read and
-// written as 16-element runs), staged in LDS; each of the 4 wavefronts takes
-// tubes w, w+4, w+8, w+12 in turn, with an M-point complex FP64 buffer of its
-// own.  The completion prologue and epilogue are applied as in the dense
-// kernels.  All arithmetic is FP64; tables (twiddles, chirps, the transformed
-// chirp, the DCT phases) are FP64 and built on the host.
-//
-// The same kernel computes the real form of the DFT along the tubes (the
-// Fourier-domain t-SVD of Section 2): row 0 = Re V[0], rows 2f - 1 and 2f =
-// Re V[f] and Im V[f] for 1 <= f <= (n - 1) / 2, and for even n row n - 1 =
-// V[n/2] (real), V = DFT_n(x); its inverse rebuilds the Hermitian spectrum and
-// returns Re IDFT_n.
+// written as 16-element runs), staged in LDS in the data type; each of the 4
+// wavefronts transforms tube pairs w and w + 4 with an M-point complex FP64
+// exchange buffer of its own.  The completion prologue and epilogue are
+// applied as in the dense kernels.  All arithmetic is FP64; tables
+// (twiddles, chirp, transformed chirp, DCT phases) are FP64, built on the host.
 #include <math.h>
 
 #include <complex>
@@ -40,7 +48,15 @@
 namespace tsvd {
 
 constexpr int kFftTubes = 16;
-constexpr int kFftLd = kFftTubes + 1;  // LDS row pitch of the tube tile (odd: no bank conflicts down a tube)
+constexpr int kFftLd = kFftTubes + 1;  // LDS row pitch of the tube tile (odd: fewer bank conflicts down a tube)
+
+struct FftTables {
+    const double2* tw;     // M: e^{-2 pi i t / M}
+    const double2* chirp;  // M: c[j] = e^{-i pi j^2 / n} for j < n, then zeros
+    const double2* bhat;   // M: FFT_M of the wrapped conjugate chirp
+    const double2* phase;  // M/2: e^{-i pi k / (2n)} for k < n, then zeros
+    int n;
+};
 
 // Orders the LDS accesses of one wavefront (the hardware keeps them in order;
 // this keeps the compiler from moving them across).
@@ -50,77 +66,148 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-struct FftTables {
-    const double2* tw;     // M/2: e^{-2 pi i j / M}
-    const double2* chirp;  // n: c[j] = e^{-i pi j^2 / n}
-    const double2* bhat;   // M: FFT_M of the wrapped conjugate chirp, bit-reversed order
-    const double2* phase;  // n: e^{-i pi k / (2n)}
-    int n, M, logM;
-};
+// Tile bytes (data type es), rounded up to 16 so that the buffers after it are aligned.
+__host__ __device__ __forceinline__ int fft_tile_bytes(int n, int es) { return (n * kFftLd * es + 15) & ~15; }
+// Exchange buffer index: one pad slot per 16 entries against bank conflicts.
+__host__ __device__ __forceinline__ int fpad(int i) { return i + (i >> 4); }
+__host__ __device__ __forceinline__ int fft_buf_entries(int M) { return fpad(M - 1) + 1; }
 
-// Bytes of the tube tile, rounded up to 16 so that the FFT buffers after it are aligned.
-__host__ __device__ __forceinline__ int fft_tile_bytes(int n) { return (n * kFftLd * 8 + 15) & ~15; }
-
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
-// In-place radix-2 FFT of M points in LDS by one wavefront.  dif: forward
-// decimation in frequency (natural in, bit-reversed out, twiddles e^{-}); else
-// decimation in time with conjugate twiddles (bit-reversed in, natural out):
-// the unscaled inverse.  LDS accesses of one wavefront complete in program
-// order, so the stages need no workgroup barrier.
-__device__ void fft_wave(double2* buf, const FftTables& t, bool dif) {
-    const int lane = threadIdx.x & 63, M = t.M;
-    for (int s = 0; s < t.logM; ++s) {
-        const int h = dif ? (M >> (s + 1)) : (1 << s);  // half-size of the butterflies
-        const int stride = M / (2 * h);                  // twiddle stride in tw
-        for (int b = lane; b < M / 2; b += 64) {
-            const int grp = b / h, j = b - grp * h;
-            const int i0 = grp * 2 * h + j, i1 = i0 + h;
-            double2 w = t.tw[j * stride];
-            const double2 x0 = buf[i0], x1 = buf[i1];
-            if (dif) {
-                buf[i0] = make_double2(x0.x + x1.x, x0.y + x1.y);
-                buf[i1] = cmul(make_double2(x0.x - x1.x, x0.y - x1.y), w);
-            } else {
-                w = cconj(w);
-                const double2 y = cmul(x1, w);
-                buf[i0] = make_double2(x0.x + y.x, x0.y + y.y);
-                buf[i1] = make_double2(x0.x - y.x, x0.y - y.y);
+// cos and sin of 2 pi m / 16
+constexpr double kC1 = 0.92387953251128675613;  // cos(pi/8)
+constexpr double kS1 = 0.38268343236508977173;  // sin(pi/8)
+constexpr double kH = 0.70710678118654752440;   // sqrt(1/2)
+
+// a * e^{-2 pi i m / 16}; m is a constant after unrolling, so the branches fold.
+__device__ __forceinline__ double2 rot16(double2 a, int m) {
+    double c, s;
+    switch (m & 15) {
+        case 0: return a;
+        case 4: return make_double2(a.y, -a.x);
+        case 8: return make_double2(-a.x, -a.y);
+        case 12: return make_double2(-a.y, a.x);
+        case 1: c = kC1; s = kS1; break;
+        case 2: c = kH; s = kH; break;
+        case 3: c = kS1; s = kC1; break;
+        case 5: c = -kS1; s = kC1; break;
+        case 6: c = -kH; s = kH; break;
+        case 7: c = -kC1; s = kS1; break;
+        case 9: c = -kC1; s = -kS1; break;
+        case 10: c = -kH; s = -kH; break;
+        case 11: c = -kS1; s = -kC1; break;
+        case 13: c = kS1; s = -kC1; break;
+        case 14: c = kH; s = -kH; break;
+        default: c = kC1; s = -kS1; break;
+    }
+    return make_double2(a.x * c + a.y * s, a.y * c - a.x * s);
+}
+
+__host__ __device__ constexpr int bit_rev(int q, int r) {
+    int y = 0;
+    for (int b = 1; b < r; b <<= 1) {
+        y = (y << 1) | (q & 1);
+        q >>= 1;
+    }
+    return y;
+}
+
+// r-point DFT in registers (r = 4, 8, 16): radix-2 decimation in frequency,
+// result in bit-reversed order.
+template <int r>
+__device__ __forceinline__ void dft_small(double2 (&v)[r]) {
+#pragma unroll
+    for (int h = r / 2; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int g = 0; g < r; g += 2 * h) {
+#pragma unroll
+            for (int j = 0; j < h; ++j) {
+                const double2 a = v[g + j], b = v[g + j + h];
+                v[g + j] = cadd(a, b);
+                v[g + j + h] = rot16(csub(a, b), j * (16 / (2 * h)));
             }
         }
-        wave_sync();
     }
 }
 
-// DFT_n of u (n values in buf[0..n)) into buf[0..n), by the chirp.
-__device__ void dft_bluestein(double2* buf, const FftTables& t) {
-    const int lane = threadIdx.x & 63;
-    for (int j = lane; j < t.M; j += 64) buf[j] = j < t.n ? cmul(buf[j], t.chirp[j]) : make_double2(0.0, 0.0);
-    wave_sync();
-    fft_wave(buf, t, true);
-    for (int j = lane; j < t.M; j += 64) buf[j] = cmul(buf[j], t.bhat[j]);
-    wave_sync();
-    fft_wave(buf, t, false);
-    const double inv = 1.0 / t.M;
-    for (int k = lane; k < t.n; k += 64) {
-        const double2 v = cmul(buf[k], t.chirp[k]);
-        buf[k] = make_double2(v.x * inv, v.y * inv);
+// One Stockham pass of radix r (sub-transform length Ls before the pass) on
+// the register layout x[s] = X[lane + 64 s]; the exchange goes through buf,
+// the twiddles (tw[t] = e^{-2 pi i t / M}) are read through the caches.
+template <int R, int r, int Ls>
+__device__ __forceinline__ void fft_pass(double2 (&x)[R], double2* buf, const double2* __restrict__ tw, int lane) {
+    constexpr int B = R / r;               // butterflies per lane
+    constexpr int M = 64 * R;
+    constexpr int span = M / (Ls * r);     // twiddle stride in tw
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+        const int b = lane + 64 * t;
+        const int j = b % Ls, k = b / Ls;
+        double2 v[r];
+#pragma unroll
+        for (int i = 0; i < r; ++i) v[i] = x[t + i * B];
+        if (Ls > 1) {
+#pragma unroll
+            for (int i = 1; i < r; ++i) v[i] = cmul(v[i], tw[j * i * span]);
+        }
+        dft_small<r>(v);
+        const int base = k * Ls * r + j;
+#pragma unroll
+        for (int q = 0; q < r; ++q) buf[fpad(base + q * Ls)] = v[bit_rev(q, r)];
     }
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < R; ++s) x[s] = buf[fpad(lane + 64 * s)];
     wave_sync();
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_tube_fft(TubeArgs a, FftTables t, int mode) {
+template <int R>
+__device__ __forceinline__ void fft_wave(double2 (&x)[R], double2* buf, const double2* __restrict__ tw, int lane) {
+    if constexpr (R == 8) {
+        fft_pass<8, 8, 1>(x, buf, tw, lane);
+        fft_pass<8, 8, 8>(x, buf, tw, lane);
+        fft_pass<8, 8, 64>(x, buf, tw, lane);
+    } else {
+        static_assert(R == 16, "M = 512 or 1024");
+        fft_pass<16, 16, 1>(x, buf, tw, lane);
+        fft_pass<16, 16, 16>(x, buf, tw, lane);
+        fft_pass<16, 4, 256>(x, buf, tw, lane);
+    }
+}
+
+// Bluestein: x[s] holds a[lane + 64 s] = u[j] c[j] (0 for j >= n); returns
+// with x[s] = W[j] = DFT_n(u)[j] for j = lane + 64 s < n.  The table loads
+// are issued one FFT ahead of their use.
+template <int R>
+__device__ __forceinline__ void bluestein(double2 (&x)[R], double2* buf, const FftTables& t, int lane) {
+    double2 pre[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) pre[s] = t.bhat[lane + 64 * s];
+    fft_wave<R>(x, buf, t.tw, lane);
+#pragma unroll
+    for (int s = 0; s < R; ++s) x[s] = cconj(cmul(x[s], pre[s]));
+#pragma unroll
+    for (int s = 0; s < R; ++s) pre[s] = t.chirp[lane + 64 * s];
+    fft_wave<R>(x, buf, t.tw, lane);
+    const double inv = 1.0 / (64 * R);
+#pragma unroll
+    for (int s = 0; s < R; ++s) x[s] = cscale(cmul(cconj(x[s]), pre[s]), inv);
+}
+
+template <typename T, int R, int mode>
+__global__ __launch_bounds__(256) void k_tube_fft(TubeArgs a, FftTables t) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double s_red[2][4];
-    const int n = a.n3, M = t.M;
+    const int n = a.n3;
     const int64_t N = a.N;
-    double* tile = (double*)smem_raw;                              // n rows of 16 tubes, pitch kFftLd
-    double2* bufs = (double2*)(smem_raw + fft_tile_bytes(n));      // 4 x M
+    T* tile = (T*)smem_raw;  // n rows of 16 tubes, pitch kFftLd
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double2* buf = (double2*)(smem_raw + fft_tile_bytes(n, (int)sizeof(T))) + wave * fft_buf_entries(64 * R);
     const int64_t r0 = (int64_t)blockIdx.x * kFftTubes;
     double beta = 1.0;
     if (a.pX || a.eX) beta = a.beta_sched ? a.beta_sched[a.ctrl->iter] : a.beta_val;
@@ -130,78 +217,120 @@ __global__ __launch_bounds__(256) void k_tube_fft(TubeArgs a, FftTables t, int m
     for (int e = tid; e < n * kFftTubes; e += 256) {
         const int k = e / kFftTubes, q = e - k * kFftTubes;
         const int64_t r = r0 + q;
-        double v = 0.0;
+        T v = (T)0;
         if (r < N) {
             const int64_t g = r + N * k;
-            if (a.pX) v = (double)((const T*)a.pX)[g] - (double)((const T*)a.pM)[g] / beta;
-            else v = (double)((const T*)a.in)[g];
-            v = (double)(T)v;  // the value the dense kernels see
-            if (a.check_finite && !isfinite(v)) bad = 1;
+            if (a.pX) v = (T)((double)((const T*)a.pX)[g] - (double)((const T*)a.pM)[g] / beta);
+            else v = ((const T*)a.in)[g];
+            if (a.check_finite && !isfinite((double)v)) bad = 1;
         }
         tile[k * kFftLd + q] = v;
     }
     if (a.check_finite && bad) atomicOr(&a.ctrl->status, kStNonFinite);
     __syncthreads();
 
-    double2* buf = bufs + (size_t)wave * M;
     const double s0 = sqrt(1.0 / n), s1 = sqrt(2.0 / n);
-    for (int q = wave; q < kFftTubes; q += 4) {
-        if (r0 + q >= N) break;
-        if (mode == kFftDftForward) {
-            for (int j = lane; j < n; j += 64) buf[j] = make_double2(tile[j * kFftLd + q], 0.0);
-            wave_sync();
-            dft_bluestein(buf, t);
-            for (int k = lane; k < n; k += 64) {
-                double y;
-                if (k == 0) y = buf[0].x;
-                else if ((n & 1) == 0 && k == n - 1) y = buf[n / 2].x;
-                else y = (k & 1) ? buf[(k + 1) / 2].x : buf[k / 2].y;
-                tile[k * kFftLd + q] = y;
-            }
-        } else if (mode == kFftDftInverse) {
-            // conj(V) of the Hermitian spectrum; x = Re DFT(conj V) / n
-            const int h = (n - 1) / 2;
-            for (int k = lane; k < n; k += 64) {
-                double re, im;
-                if (k == 0) { re = tile[q]; im = 0.0; }
-                else if ((n & 1) == 0 && k == n / 2) { re = tile[(n - 1) * kFftLd + q]; im = 0.0; }
-                else if (k <= h) { re = tile[(2 * k - 1) * kFftLd + q]; im = tile[2 * k * kFftLd + q]; }
-                else { re = tile[(2 * (n - k) - 1) * kFftLd + q]; im = -tile[2 * (n - k) * kFftLd + q]; }
-                buf[k] = make_double2(re, -im);
-            }
-            wave_sync();
-            dft_bluestein(buf, t);
-            for (int j = lane; j < n; j += 64) tile[j * kFftLd + q] = buf[j].x / n;
-        } else if (mode == kFftDctForward) {
-            // v[t] = x[2t], v[n-1-t] = x[2t+1]
-            for (int j = lane; j < n; j += 64) {
-                const int src = (2 * j < n) ? 2 * j : 2 * (n - 1 - j) + 1;
-                buf[j] = make_double2(tile[src * kFftLd + q], 0.0);
-            }
-            wave_sync();
-            dft_bluestein(buf, t);
-            for (int k = lane; k < n; k += 64) {
-                const double2 z = cmul(t.phase[k], buf[k]);
-                tile[k * kFftLd + q] = (k == 0 ? s0 : s1) * z.x;
-            }
-        } else {
-            // V[k] = e^{i pi k/(2n)} (y[k] - i y[n-k]), y = X / s; the inverse DFT as
-            // conj(DFT(conj(V))) / n, so the input is conj(V)
-            for (int k = lane; k < n; k += 64) {
-                const double yk = tile[k * kFftLd + q] / (k == 0 ? s0 : s1);
-                const double ynk = k == 0 ? 0.0 : tile[(n - k) * kFftLd + q] / s1;
-                const double2 v = cmul(cconj(t.phase[k]), make_double2(yk, -ynk));
-                buf[k] = cconj(v);
-            }
-            wave_sync();
-            dft_bluestein(buf, t);
-            // x[2t] = v[t], x[2t+1] = v[n-1-t] with v = conj(DFT(...)) / n (real part)
-            for (int j = lane; j < n; j += 64) {
-                const int dst = (2 * j < n) ? 2 * j : 2 * (n - 1 - j) + 1;
-                tile[dst * kFftLd + q] = buf[j].x / n;
-            }
+    const int h = (n - 1) / 2;
+    for (int pr = wave; pr < kFftTubes / 2; pr += 4) {
+        const int q1 = 2 * pr, q2 = q1 + 1;
+        if (r0 + q1 >= N) break;
+        double2 x[R], cj[R], ph[R / 2];
+        // table loads first, in one batch (the tables are zero-padded: no branches)
+#pragma unroll
+        for (int s = 0; s < R; ++s) cj[s] = t.chirp[lane + 64 * s];
+        if constexpr (mode == kFftDctForward || mode == kFftDctInverse) {
+#pragma unroll
+            for (int s = 0; s < R / 2; ++s) ph[s] = t.phase[lane + 64 * s];
         }
-        wave_sync();
+        // chirped input a[j] = u[j] c[j]
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int j = lane + 64 * s;
+            double2 u = make_double2(0.0, 0.0);
+            if (j < n) {
+                if constexpr (mode == kFftDctForward) {
+                    const int src = (2 * j < n) ? 2 * j : 2 * (n - 1 - j) + 1;
+                    u = make_double2((double)tile[src * kFftLd + q1], (double)tile[src * kFftLd + q2]);
+                } else if constexpr (mode == kFftDftForward) {
+                    u = make_double2((double)tile[j * kFftLd + q1], (double)tile[j * kFftLd + q2]);
+                } else {
+                    // U = V1 + i V2 from the coefficients; the input is conj(U)
+                    double2 V1, V2;
+                    if constexpr (mode == kFftDctInverse) {
+                        const double sj = j == 0 ? s0 : s1;
+                        const double2 w = cconj(ph[s < R / 2 ? s : 0]);  // j < n <= M/2: s < R/2
+                        const double y1 = (double)tile[j * kFftLd + q1] / sj, y2 = (double)tile[j * kFftLd + q2] / sj;
+                        const double z1 = j == 0 ? 0.0 : (double)tile[(n - j) * kFftLd + q1] / s1;
+                        const double z2 = j == 0 ? 0.0 : (double)tile[(n - j) * kFftLd + q2] / s1;
+                        V1 = cmul(w, make_double2(y1, -z1));
+                        V2 = cmul(w, make_double2(y2, -z2));
+                    } else {
+                        int ir, ii;  // rows of Re and Im (-1: zero); isg: sign of Im
+                        double isg = 1.0;
+                        if (j == 0) { ir = 0; ii = -1; }
+                        else if ((n & 1) == 0 && j == n / 2) { ir = n - 1; ii = -1; }
+                        else if (j <= h) { ir = 2 * j - 1; ii = 2 * j; }
+                        else { ir = 2 * (n - j) - 1; ii = 2 * (n - j); isg = -1.0; }
+                        V1 = make_double2((double)tile[ir * kFftLd + q1],
+                                          ii < 0 ? 0.0 : isg * (double)tile[ii * kFftLd + q1]);
+                        V2 = make_double2((double)tile[ir * kFftLd + q2],
+                                          ii < 0 ? 0.0 : isg * (double)tile[ii * kFftLd + q2]);
+                    }
+                    u = make_double2(V1.x - V2.y, -(V1.y + V2.x));
+                }
+            }
+            x[s] = cmul(u, cj[s]);
+        }
+        bluestein<R>(x, buf, t, lane);
+        if constexpr (mode == kFftDctForward || mode == kFftDftForward) {
+            // separate the two tubes' spectra: needs W[n - k], from the exchange buffer
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+                const int j = lane + 64 * s;
+                if (j < n) buf[fpad(j)] = x[s];
+            }
+            wave_sync();
+#pragma unroll
+            for (int s = 0; s < R / 2; ++s) {
+                const int k = lane + 64 * s;
+                if (k >= n) break;
+                if constexpr (mode == kFftDctForward) {
+                    const double2 Wk = buf[fpad(k)], Wn = cconj(buf[fpad(k == 0 ? 0 : n - k)]);
+                    const double2 V1 = cscale(cadd(Wk, Wn), 0.5);
+                    const double2 d = csub(Wk, Wn);
+                    const double2 V2 = make_double2(0.5 * d.y, -0.5 * d.x);
+                    const double2 p = ph[s];
+                    const double sk = k == 0 ? s0 : s1;
+                    tile[k * kFftLd + q1] = (T)(sk * (p.x * V1.x - p.y * V1.y));
+                    tile[k * kFftLd + q2] = (T)(sk * (p.x * V2.x - p.y * V2.y));
+                } else {
+                    int f, im;
+                    if (k == 0) { f = 0; im = 0; }
+                    else if ((n & 1) == 0 && k == n - 1) { f = n / 2; im = 0; }
+                    else { f = (k + 1) / 2; im = (k & 1) ? 0 : 1; }
+                    const double2 Wk = buf[fpad(f)], Wn = cconj(buf[fpad(f == 0 ? 0 : n - f)]);
+                    const double2 V1 = cscale(cadd(Wk, Wn), 0.5);
+                    const double2 d = csub(Wk, Wn);
+                    const double2 V2 = make_double2(0.5 * d.y, -0.5 * d.x);
+                    tile[k * kFftLd + q1] = (T)(im ? V1.y : V1.x);
+                    tile[k * kFftLd + q2] = (T)(im ? V2.y : V2.x);
+                }
+            }
+            wave_sync();
+        } else {
+            // v1 + i v2 = conj(W) / n
+            const double invn = 1.0 / n;
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+                const int j = lane + 64 * s;
+                if (j < n) {
+                    const int dst = (mode == kFftDftInverse) ? j : ((2 * j < n) ? 2 * j : 2 * (n - 1 - j) + 1);
+                    tile[dst * kFftLd + q1] = (T)(x[s].x * invn);
+                    tile[dst * kFftLd + q2] = (T)(-x[s].y * invn);
+                }
+            }
+            wave_sync();
+        }
     }
     __syncthreads();
 
@@ -212,7 +341,7 @@ __global__ __launch_bounds__(256) void k_tube_fft(TubeArgs a, FftTables t, int m
         const int64_t r = r0 + q;
         if (r >= N) continue;
         const int64_t g = r + N * k;
-        const T y = (T)tile[k * kFftLd + q];
+        const T y = tile[k * kFftLd + q];
         if (a.out) ((T*)a.out)[g] = y;
         if (a.eX) {
             T* X = (T*)a.eX;
@@ -251,41 +380,36 @@ __global__ __launch_bounds__(256) void k_tube_fft(TubeArgs a, FftTables t, int m
 // ---- host side ------------------------------------------------------------------
 
 int fft_size(int n) {
-    int M = 1;
+    int M = 512;
     while (M < 2 * n - 1) M <<= 1;
     return M;
 }
 
 size_t fft_table_bytes(int n) {
     const int M = fft_size(n);
-    return sizeof(double) * 2 * ((size_t)M / 2 + n + M + n);
+    return sizeof(double) * 2 * ((size_t)M + M + M + M / 2);
 }
 
-static int bit_reverse(int x, int bits) {
-    int y = 0;
-    for (int b = 0; b < bits; ++b) y |= ((x >> b) & 1) << (bits - 1 - b);
-    return y;
-}
-
-// Tables in FP64: twiddles e^{-2 pi i j/M}; chirp c[j] = e^{-i pi (j^2 mod 2n)/n};
-// the transformed wrapped conjugate chirp (an O(M^2) DFT in long double, once
-// per length), stored bit-reversed; DCT phases e^{-i pi k/(2n)}.
+// Tables in FP64 (computed in long double): twiddles e^{-2 pi i t/M}; chirp
+// c[j] = e^{-i pi (j^2 mod 2n)/n} (zero-padded to M); the FFT of the wrapped conjugate chirp (a
+// direct O(M^2) DFT over the twiddles, once per length); DCT phases
+// e^{-i pi k/(2n)} (zero-padded to M/2).
 void make_fft_tables(int n, void* out) {
     const int M = fft_size(n);
-    int logM = 0;
-    while ((1 << logM) < M) ++logM;
     const long double pi = acosl(-1.0L);
-    double* p = (double*)out;
-    double* tw = p;
-    double* ch = tw + M;       // M/2 complex
-    double* bh = ch + 2 * n;   // n complex
-    double* ph = bh + 2 * M;   // M complex
-    for (int j = 0; j < M / 2; ++j) {
+    double* tw = (double*)out;  // M complex
+    double* ch = tw + 2 * M;    // M complex (n values, then zeros)
+    double* bh = ch + 2 * M;    // M complex
+    double* ph = bh + 2 * M;    // M/2 complex (n values, then zeros)
+    for (int j = 2 * n; j < 2 * M; ++j) ch[j] = 0.0;
+    for (int j = 2 * n; j < M; ++j) ph[j] = 0.0;
+    std::vector<std::complex<long double>> root(M), c(n), b(M, 0.0L);
+    for (int j = 0; j < M; ++j) {
         const long double ang = -2.0L * pi * j / M;
-        tw[2 * j] = (double)cosl(ang);
-        tw[2 * j + 1] = (double)sinl(ang);
+        root[j] = std::complex<long double>(cosl(ang), sinl(ang));
+        tw[2 * j] = (double)root[j].real();
+        tw[2 * j + 1] = (double)root[j].imag();
     }
-    std::vector<std::complex<long double>> c(n), b(M, 0.0L);
     for (int j = 0; j < n; ++j) {
         const long long q = ((long long)j * j) % (2LL * n);
         const long double ang = -pi * (long double)q / n;
@@ -301,14 +425,11 @@ void make_fft_tables(int n, void* out) {
     for (int k = 0; k < M; ++k) {
         std::complex<long double> acc = 0.0L;
         for (int m = 0; m < M; ++m) {
-            if (b[m] == std::complex<long double>(0.0L, 0.0L)) continue;
-            const long long q = ((long long)k * m) % M;
-            const long double ang = -2.0L * pi * (long double)q / M;
-            acc += b[m] * std::complex<long double>(cosl(ang), sinl(ang));
+            if (m >= n && m <= M - n) continue;  // zero entries
+            acc += b[m] * root[((long long)k * m) % M];
         }
-        const int kr = bit_reverse(k, logM);
-        bh[2 * kr] = (double)acc.real();
-        bh[2 * kr + 1] = (double)acc.imag();
+        bh[2 * k] = (double)acc.real();
+        bh[2 * k + 1] = (double)acc.imag();
     }
     for (int k = 0; k < n; ++k) {
         const long double ang = -pi * k / (2.0L * n);
@@ -317,32 +438,51 @@ void make_fft_tables(int n, void* out) {
     }
 }
 
-int fft_lds_bytes(int n) { return fft_tile_bytes(n) + 4 * fft_size(n) * 16; }
+int fft_lds_bytes(int n, int prec) {
+    const int M = fft_size(n);
+    return fft_tile_bytes(n, prec == 0 ? 8 : 4) + 4 * fft_buf_entries(M) * 16;
+}
 
-bool fft_fits(int n3) { return n3 > kMaxTube && fft_lds_bytes(n3) <= kLdsBudget; }
+bool fft_fits(int n3) { return n3 > kMaxTube && fft_size(n3) <= 1024 && fft_lds_bytes(n3, 0) <= kLdsBudget; }
+
+template <typename T, int R, int mode>
+static hipError_t launch_fft(const TubeArgs& a, const FftTables& t, int lds, dim3 grid, hipStream_t s) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_tube_fft<T, R, mode>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_tube_fft<T, R, mode>), grid, dim3(256), lds, s, a, t);
+    return hipGetLastError();
+}
+
+template <typename T, int R>
+static hipError_t launch_fft_mode(const TubeArgs& a, const FftTables& t, int mode, int lds, dim3 grid,
+                                  hipStream_t s) {
+    switch (mode) {
+        case kFftDctForward: return launch_fft<T, R, kFftDctForward>(a, t, lds, grid, s);
+        case kFftDctInverse: return launch_fft<T, R, kFftDctInverse>(a, t, lds, grid, s);
+        case kFftDftForward: return launch_fft<T, R, kFftDftForward>(a, t, lds, grid, s);
+        case kFftDftInverse: return launch_fft<T, R, kFftDftInverse>(a, t, lds, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_tube_fft(int prec, const TubeArgs& a, const void* tables, int mode, hipStream_t s) {
     if (a.N <= 0) return hipSuccess;
     const int n = a.n3, M = fft_size(n);
-    if (fft_lds_bytes(n) > kLdsBudget) return hipErrorInvalidValue;
+    if (!fft_fits(n)) return hipErrorInvalidValue;
     FftTables t;
     const double* p = (const double*)tables;
     t.tw = (const double2*)p;
-    t.chirp = (const double2*)(p + M);
-    t.bhat = (const double2*)(p + M + 2 * n);
-    t.phase = (const double2*)(p + M + 2 * n + 2 * M);
+    t.chirp = (const double2*)(p + 2 * M);
+    t.bhat = (const double2*)(p + 4 * M);
+    t.phase = (const double2*)(p + 6 * M);
     t.n = n;
-    t.M = M;
-    t.logM = 0;
-    while ((1 << t.logM) < M) ++t.logM;
-    const int lds = fft_lds_bytes(n);
-    const dim3 grid((unsigned)((a.N + kFftTubes - 1) / kFftTubes)), block(256);
-    const void* f = prec == 0 ? (const void*)k_tube_fft<double> : (const void*)k_tube_fft<float>;
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    if (prec == 0) hipLaunchKernelGGL(k_tube_fft<double>, grid, block, lds, s, a, t, mode);
-    else hipLaunchKernelGGL(k_tube_fft<float>, grid, block, lds, s, a, t, mode);
-    return hipGetLastError();
+    const int lds = fft_lds_bytes(n, prec);
+    const dim3 grid((unsigned)((a.N + kFftTubes - 1) / kFftTubes));
+    if (prec == 0) return M == 512 ? launch_fft_mode<double, 8>(a, t, mode, lds, grid, s)
+                                   : launch_fft_mode<double, 16>(a, t, mode, lds, grid, s);
+    return M == 512 ? launch_fft_mode<float, 8>(a, t, mode, lds, grid, s)
+                    : launch_fft_mode<float, 16>(a, t, mode, lds, grid, s);
 }
 
 }  // namespace tsvd
