@@ -382,6 +382,7 @@ struct Tile {
     int W = 0;
     int threads = 0;
     int K = 1;       // team: lane-group columns (2: two I columns per group, no V)
+    int slots = 0;   // team: slices in flight per XCD (0: as many as residency and n3 allow)
     int source = 0;  // 0 default heuristic, 1 autotuned, 2 forced by options
 };
 
@@ -475,7 +476,8 @@ int apply_tile(tsvd_ctx* c, Plan& P, const Tile& t, bool batched) {
         const int cap = jacobi_team_max_resident(P.prec, P.lds, P.threads, 0, R, t.G, 2);
         if (cap < 8) return fail(c, TSVD_EINVAL, "Jacobi team kernel cannot be resident with this shape");
         W = std::min(W, cap / 8);
-        const int per_xcd = std::max(1, std::min(((int)P.n3 + 7) / 8, cap / (8 * W)));
+        int per_xcd = std::max(1, std::min(((int)P.n3 + 7) / 8, cap / (8 * W)));
+        if (t.slots > 0) per_xcd = std::min(per_xcd, t.slots);
         P.ts.W = W;
         P.ts.nwg = 8 * W * per_xcd;
         P.job.b = B;
@@ -502,13 +504,17 @@ int apply_tile(tsvd_ctx* c, Plan& P, const Tile& t, bool batched) {
     if (cap < 8) return fail(c, TSVD_EINVAL, "Jacobi team kernel cannot be resident with this shape");
     // whole teams on every XCD: the grid is a multiple of 8 W workgroups
     W = std::min(W, cap / 8);
-    const int per_xcd = std::max(1, std::min(((int)P.n3 + 7) / 8, cap / (8 * W)));
+    int per_xcd = std::max(1, std::min(((int)P.n3 + 7) / 8, cap / (8 * W)));
+    if (t.slots > 0) per_xcd = std::min(per_xcd, t.slots);
     P.ts.W = W;
     P.ts.nwg = 8 * W * per_xcd;
     P.job.b = b;
     P.job.nb = nb;
     return TSVD_OK;
 }
+
+// Of an XCD's 4 MiB L2, what the slices in flight on it may hold (3.5 MiB).
+constexpr size_t kL2PerXcdBudget = (size_t)7 << 19;
 
 // Lane-group widths worth trying: those with the fewest padded rows R G.
 std::vector<int> group_widths(int m, int p) {
@@ -593,6 +599,23 @@ std::vector<Tile> tile_candidates(const Plan& P, bool batched, int gram) {
             out.push_back(t);
         }
     }
+    // Slices whose A (and V) overflow an XCD's L2 when every team of the XCD
+    // holds one: also try fewer slices in flight per XCD (teams then take
+    // several slices in turn), with the larger team sizes to keep the CUs busy.
+    if (!batched && !out.empty() && out.back().team) {
+        const size_t es = P.prec == TSVD_FP64 ? 8 : 4;
+        const size_t slice_bytes = ((size_t)P.m * P.p + (P.with_v ? (size_t)P.p * P.p : 0)) * es;
+        const int fit = (int)(kL2PerXcdBudget / slice_bytes);
+        if (fit >= 1 && fit < ((int)P.n3 + 7) / 8) {
+            const size_t n0 = out.size();
+            for (size_t i = 0; i < n0; ++i) {
+                if (out[i].team != 1 || out[i].K != 1 || out[i].W < 8) continue;
+                Tile t = out[i];
+                t.slots = fit;
+                out.push_back(t);
+            }
+        }
+    }
     // and the block-Gram kernel (column blocks on the matrix cores)
     if (!batched && gram >= 0 && !out.empty() && out.back().team) {
         Tile t;
@@ -611,7 +634,7 @@ std::vector<Tile> tile_candidates(const Plan& P, bool batched, int gram) {
 // Key: (batched, prec, m, p, n3, with_v); batched plans ignore n3.  When the
 // environment variable TSVDMI_TILE_CACHE names a file, it is read at first
 // use and every newly tuned tile is appended to it, one line per tile:
-//   tile <batched> <prec> <m> <p> <n3> <with_v> <team> <G> <W> <threads> <K> <microseconds>
+//   tile <batched> <prec> <m> <p> <n3> <with_v> <team> <G> <W> <threads> <K> <microseconds> [<slots>]
 typedef std::tuple<int, int, int, int, int, int> TileKey;
 std::mutex g_tile_mu;
 std::map<TileKey, Tile> g_tiles;
@@ -626,13 +649,14 @@ void tile_cache_load_locked() {
     if (!f) return;
     char line[256];
     while (fgets(line, sizeof line, f)) {
-        int k[6], team, G, W, th, K;
+        int k[6], team, G, W, th, K, slots = 0;
         double us;
-        if (sscanf(line, "tile %d %d %d %d %d %d %d %d %d %d %d %lf", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &team,
-                   &G, &W, &th, &K, &us) != 12)
+        if (sscanf(line, "tile %d %d %d %d %d %d %d %d %d %d %d %lf %d", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &team,
+                   &G, &W, &th, &K, &us, &slots) < 12)
             continue;
         Tile t;
-        t.team = team; t.G = G; t.W = W; t.threads = th; t.K = K == 2 ? 2 : 1; t.source = 1;
+        t.team = team; t.G = G; t.W = W; t.threads = th; t.K = K == 2 ? 2 : 1; t.slots = std::max(0, slots);
+        t.source = 1;
         g_tiles[TileKey(k[0], k[1], k[2], k[3], k[4], k[5])] = t;
     }
     fclose(f);
@@ -655,8 +679,8 @@ void tile_cache_put(const TileKey& k, const Tile& t, double us) {
     if (!path || !*path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "tile %d %d %d %d %d %d %d %d %d %d %d %.1f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
-            std::get<3>(k), std::get<4>(k), std::get<5>(k), t.team, t.G, t.W, t.threads, t.K, us);
+    fprintf(f, "tile %d %d %d %d %d %d %d %d %d %d %d %.1f %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+            std::get<3>(k), std::get<4>(k), std::get<5>(k), t.team, t.G, t.W, t.threads, t.K, us, t.slots);
     fclose(f);
 }
 
@@ -778,9 +802,11 @@ int tune_tile(tsvd_ctx* c, const Plan& P, bool batched, Tile* out, double* us_ou
         const double us = time_tile(c, P, cands[i], batched, tb, o_src, o_A, o_V, o_cnt, cnt_bytes, o_jobs, o_tj, o_tk,
                                     ntasks, e0, e1);
         if (getenv("TSVDMI_TUNE_LOG"))
-            fprintf(stderr, "tsvdmi tune prec %d m %d p %d n3 %lld v %d: team %d G %d W %d threads %d K %d: %.1f us\n",
+            fprintf(stderr,
+                    "tsvdmi tune prec %d m %d p %d n3 %lld v %d: team %d G %d W %d threads %d K %d slots %d grid %d: "
+                    "%.1f us\n",
                     P.prec, P.m, P.p, (long long)P.n3, P.with_v, cands[i].team, cands[i].G, cands[i].W, Q.threads,
-                    cands[i].K, us);
+                    cands[i].K, cands[i].slots, Q.ts.nwg, us);
         // a later candidate must be 2% faster to replace an earlier one, so that
         // near-ties resolve the same way from run to run
         if (us > 0.0 && (best_us < 0.0 || us < 0.98 * best_us)) {
