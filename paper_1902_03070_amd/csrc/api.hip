@@ -37,7 +37,7 @@ struct tsvd_ctx {
     std::map<std::pair<int, int>, std::pair<void*, void*>> dct;
     // matrix-core fragments: (n3, engine, inverse) -> device buffer
     std::map<std::tuple<int, int, int>, void*> frag;
-    // fast-transform tables of long tubes: n3 -> device buffer
+    // fast-transform tables of long tubes: 2 n3 + (float data) -> device buffer
     std::map<int, void*> fft;
     int dense_long = 0;  // 1: DCT tubes of 129..512 on the dense kernel where it fits
     DevBuf ws;                 // main workspace
@@ -175,17 +175,20 @@ int run_tube_mat(tsvd_ctx* c, int prec, TubeArgs a, int inverse, const void* mat
     return TSVD_OK;
 }
 
-// Tables of the fast transform for tubes of length n3 (built once per context).
-int get_fft_tables(tsvd_ctx* c, int n3, const void** out) {
-    auto it = c->fft.find(n3);
+// Tables of the fast transform for tubes of length n3 in the precision of the
+// data (FP64 for double, FP32 for float), built once per context.
+int get_fft_tables(tsvd_ctx* c, int n3, int prec, const void** out) {
+    const int tp = prec == TSVD_FP64 ? 0 : 1;
+    const int key = 2 * n3 + tp;
+    auto it = c->fft.find(key);
     if (it == c->fft.end()) {
-        const size_t bytes = fft_table_bytes(n3);
+        const size_t bytes = fft_table_bytes(n3, tp);
         std::vector<unsigned char> h(bytes);
-        make_fft_tables(n3, h.data());
+        make_fft_tables(n3, tp, h.data());
         void* d = nullptr;
         HIPCHK(c, hipMalloc(&d, bytes));
         HIPCHK(c, hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
-        it = c->fft.emplace(n3, d).first;
+        it = c->fft.emplace(key, d).first;
     }
     *out = it->second;
     return TSVD_OK;
@@ -194,7 +197,7 @@ int get_fft_tables(tsvd_ctx* c, int n3, const void** out) {
 // The fast transform of long tubes (mode: kFftDct* or kFftDft*).
 int run_tube_fft(tsvd_ctx* c, int prec, const TubeArgs& a, int mode, hipStream_t s) {
     const void* tab;
-    int rc = get_fft_tables(c, a.n3, &tab);
+    int rc = get_fft_tables(c, a.n3, prec, &tab);
     if (rc) return rc;
     const hipError_t e = launch_tube_fft(prec == TSVD_FP64 ? 0 : 1, a, tab, mode, s);
     if (e != hipSuccess) return hip_fail(c, e, (mode & 1) ? "inverse fast tube transform" : "fast tube transform");
@@ -211,7 +214,7 @@ bool use_fft(const tsvd_ctx* c, int prec, int n3) {
 // matrices), built now: before a graph capture, which cannot allocate.
 int prepare_tube(tsvd_ctx* c, int n3, int prec) {
     const void *a, *b;
-    if (use_fft(c, prec, n3)) return get_fft_tables(c, n3, &a);
+    if (use_fft(c, prec, n3)) return get_fft_tables(c, n3, prec, &a);
     if (n3 <= kMaxTube) {
         int rc = get_frag(c, n3, prec, 0, &a);
         return rc ? rc : get_frag(c, n3, prec, 1, &b);

@@ -34,10 +34,11 @@
 //
 // Workgroup: 16 consecutive tubes (each row of the mode-3 unfolding read and
 // written as 16-element runs), staged in LDS in the data type; each of the 4
-// wavefronts transforms tube pairs w and w + 4 with an M-point complex FP64
+// wavefronts transforms tube pairs w and w + 4 with an M-point complex
 // exchange buffer of its own.  The completion prologue and epilogue are
-// applied as in the dense kernels.  All arithmetic is FP64; tables
-// (twiddles, chirp, transformed chirp, DCT phases) are FP64, built on the host.
+// applied as in the dense kernels.  The arithmetic and the tables (twiddles,
+// chirp, transformed chirp, DCT phases; built on the host in long double) are
+// FP64 for double data and FP32 for float data.
 #include <math.h>
 
 #include <complex>
@@ -50,11 +51,19 @@ namespace tsvd {
 constexpr int kFftTubes = 16;
 constexpr int kFftLd = kFftTubes + 1;  // LDS row pitch of the tube tile (odd: fewer bank conflicts down a tube)
 
+// Complex value of the compute type C (double or float), aligned so that LDS
+// and table accesses are single wide loads and stores.
+template <typename C>
+struct __align__(2 * sizeof(C)) cx {
+    C x, y;
+};
+
+template <typename C>
 struct FftTables {
-    const double2* tw;     // M: e^{-2 pi i t / M}
-    const double2* chirp;  // M: c[j] = e^{-i pi j^2 / n} for j < n, then zeros
-    const double2* bhat;   // M: FFT_M of the wrapped conjugate chirp
-    const double2* phase;  // M/2: e^{-i pi k / (2n)} for k < n, then zeros
+    const cx<C>* tw;     // M: e^{-2 pi i t / M}
+    const cx<C>* chirp;  // M: c[j] = e^{-i pi j^2 / n} for j < n, then zeros
+    const cx<C>* bhat;   // M: FFT_M of the wrapped conjugate chirp
+    const cx<C>* phase;  // M/2: e^{-i pi k / (2n)} for k < n, then zeros
     int n;
 };
 
@@ -72,13 +81,25 @@ __host__ __device__ __forceinline__ int fft_tile_bytes(int n, int es) { return (
 __host__ __device__ __forceinline__ int fpad(int i) { return i + (i >> 4); }
 __host__ __device__ __forceinline__ int fft_buf_entries(int M) { return fpad(M - 1) + 1; }
 
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+template <typename C>
+__device__ __forceinline__ cx<C> mkc(C x, C y) {
+    cx<C> r;
+    r.x = x;
+    r.y = y;
+    return r;
 }
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+template <typename C>
+__device__ __forceinline__ cx<C> cadd(cx<C> a, cx<C> b) { return mkc<C>(a.x + b.x, a.y + b.y); }
+template <typename C>
+__device__ __forceinline__ cx<C> csub(cx<C> a, cx<C> b) { return mkc<C>(a.x - b.x, a.y - b.y); }
+template <typename C>
+__device__ __forceinline__ cx<C> cmul(cx<C> a, cx<C> b) {
+    return mkc<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename C>
+__device__ __forceinline__ cx<C> cconj(cx<C> a) { return mkc<C>(a.x, -a.y); }
+template <typename C>
+__device__ __forceinline__ cx<C> cscale(cx<C> a, C s) { return mkc<C>(a.x * s, a.y * s); }
 
 // cos and sin of 2 pi m / 16
 constexpr double kC1 = 0.92387953251128675613;  // cos(pi/8)
@@ -86,13 +107,14 @@ constexpr double kS1 = 0.38268343236508977173;  // sin(pi/8)
 constexpr double kH = 0.70710678118654752440;   // sqrt(1/2)
 
 // a * e^{-2 pi i m / 16}; m is a constant after unrolling, so the branches fold.
-__device__ __forceinline__ double2 rot16(double2 a, int m) {
+template <typename C>
+__device__ __forceinline__ cx<C> rot16(cx<C> a, int m) {
     double c, s;
     switch (m & 15) {
         case 0: return a;
-        case 4: return make_double2(a.y, -a.x);
-        case 8: return make_double2(-a.x, -a.y);
-        case 12: return make_double2(-a.y, a.x);
+        case 4: return mkc<C>(a.y, -a.x);
+        case 8: return mkc<C>(-a.x, -a.y);
+        case 12: return mkc<C>(-a.y, a.x);
         case 1: c = kC1; s = kS1; break;
         case 2: c = kH; s = kH; break;
         case 3: c = kS1; s = kC1; break;
@@ -106,7 +128,8 @@ __device__ __forceinline__ double2 rot16(double2 a, int m) {
         case 14: c = kH; s = -kH; break;
         default: c = kC1; s = -kS1; break;
     }
-    return make_double2(a.x * c + a.y * s, a.y * c - a.x * s);
+    const C cc = (C)c, ss = (C)s;
+    return mkc<C>(a.x * cc + a.y * ss, a.y * cc - a.x * ss);
 }
 
 __host__ __device__ constexpr int bit_rev(int q, int r) {
@@ -120,15 +143,15 @@ __host__ __device__ constexpr int bit_rev(int q, int r) {
 
 // r-point DFT in registers (r = 4, 8, 16): radix-2 decimation in frequency,
 // result in bit-reversed order.
-template <int r>
-__device__ __forceinline__ void dft_small(double2 (&v)[r]) {
+template <typename C, int r>
+__device__ __forceinline__ void dft_small(cx<C> (&v)[r]) {
 #pragma unroll
     for (int h = r / 2; h >= 1; h >>= 1) {
 #pragma unroll
         for (int g = 0; g < r; g += 2 * h) {
 #pragma unroll
             for (int j = 0; j < h; ++j) {
-                const double2 a = v[g + j], b = v[g + j + h];
+                const cx<C> a = v[g + j], b = v[g + j + h];
                 v[g + j] = cadd(a, b);
                 v[g + j + h] = rot16(csub(a, b), j * (16 / (2 * h)));
             }
@@ -139,8 +162,8 @@ __device__ __forceinline__ void dft_small(double2 (&v)[r]) {
 // One Stockham pass of radix r (sub-transform length Ls before the pass) on
 // the register layout x[s] = X[lane + 64 s]; the exchange goes through buf,
 // the twiddles (tw[t] = e^{-2 pi i t / M}) are read through the caches.
-template <int R, int r, int Ls>
-__device__ __forceinline__ void fft_pass(double2 (&x)[R], double2* buf, const double2* __restrict__ tw, int lane) {
+template <typename C, int R, int r, int Ls>
+__device__ __forceinline__ void fft_pass(cx<C> (&x)[R], cx<C>* buf, const cx<C>* __restrict__ tw, int lane) {
     constexpr int B = R / r;               // butterflies per lane
     constexpr int M = 64 * R;
     constexpr int span = M / (Ls * r);     // twiddle stride in tw
@@ -148,14 +171,14 @@ __device__ __forceinline__ void fft_pass(double2 (&x)[R], double2* buf, const do
     for (int t = 0; t < B; ++t) {
         const int b = lane + 64 * t;
         const int j = b % Ls, k = b / Ls;
-        double2 v[r];
+        cx<C> v[r];
 #pragma unroll
         for (int i = 0; i < r; ++i) v[i] = x[t + i * B];
         if (Ls > 1) {
 #pragma unroll
             for (int i = 1; i < r; ++i) v[i] = cmul(v[i], tw[j * i * span]);
         }
-        dft_small<r>(v);
+        dft_small<C, r>(v);
         const int base = k * Ls * r + j;
 #pragma unroll
         for (int q = 0; q < r; ++q) buf[fpad(base + q * Ls)] = v[bit_rev(q, r)];
@@ -166,48 +189,49 @@ __device__ __forceinline__ void fft_pass(double2 (&x)[R], double2* buf, const do
     wave_sync();
 }
 
-template <int R>
-__device__ __forceinline__ void fft_wave(double2 (&x)[R], double2* buf, const double2* __restrict__ tw, int lane) {
+template <typename C, int R>
+__device__ __forceinline__ void fft_wave(cx<C> (&x)[R], cx<C>* buf, const cx<C>* __restrict__ tw, int lane) {
     if constexpr (R == 8) {
-        fft_pass<8, 8, 1>(x, buf, tw, lane);
-        fft_pass<8, 8, 8>(x, buf, tw, lane);
-        fft_pass<8, 8, 64>(x, buf, tw, lane);
+        fft_pass<C, 8, 8, 1>(x, buf, tw, lane);
+        fft_pass<C, 8, 8, 8>(x, buf, tw, lane);
+        fft_pass<C, 8, 8, 64>(x, buf, tw, lane);
     } else {
         static_assert(R == 16, "M = 512 or 1024");
-        fft_pass<16, 16, 1>(x, buf, tw, lane);
-        fft_pass<16, 16, 16>(x, buf, tw, lane);
-        fft_pass<16, 4, 256>(x, buf, tw, lane);
+        fft_pass<C, 16, 16, 1>(x, buf, tw, lane);
+        fft_pass<C, 16, 16, 16>(x, buf, tw, lane);
+        fft_pass<C, 16, 4, 256>(x, buf, tw, lane);
     }
 }
 
 // Bluestein: x[s] holds a[lane + 64 s] = u[j] c[j] (0 for j >= n); returns
 // with x[s] = W[j] = DFT_n(u)[j] for j = lane + 64 s < n.  The table loads
 // are issued one FFT ahead of their use.
-template <int R>
-__device__ __forceinline__ void bluestein(double2 (&x)[R], double2* buf, const FftTables& t, int lane) {
-    double2 pre[R];
+template <typename C, int R>
+__device__ __forceinline__ void bluestein(cx<C> (&x)[R], cx<C>* buf, const FftTables<C>& t, int lane) {
+    cx<C> pre[R];
 #pragma unroll
     for (int s = 0; s < R; ++s) pre[s] = t.bhat[lane + 64 * s];
-    fft_wave<R>(x, buf, t.tw, lane);
+    fft_wave<C, R>(x, buf, t.tw, lane);
 #pragma unroll
     for (int s = 0; s < R; ++s) x[s] = cconj(cmul(x[s], pre[s]));
 #pragma unroll
     for (int s = 0; s < R; ++s) pre[s] = t.chirp[lane + 64 * s];
-    fft_wave<R>(x, buf, t.tw, lane);
-    const double inv = 1.0 / (64 * R);
+    fft_wave<C, R>(x, buf, t.tw, lane);
+    const C inv = (C)(1.0 / (64 * R));
 #pragma unroll
     for (int s = 0; s < R; ++s) x[s] = cscale(cmul(cconj(x[s]), pre[s]), inv);
 }
 
-template <typename T, int R, int mode>
-__global__ __launch_bounds__(256) void k_tube_fft(TubeArgs a, FftTables t) {
+template <typename T, typename C, int R, int mode>
+__global__ __launch_bounds__(256, (sizeof(C) == 4 || R == 8) ? 2 : 1) void k_tube_fft(TubeArgs a, FftTables<C> t) {
+    using V = cx<C>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double s_red[2][4];
     const int n = a.n3;
     const int64_t N = a.N;
     T* tile = (T*)smem_raw;  // n rows of 16 tubes, pitch kFftLd
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double2* buf = (double2*)(smem_raw + fft_tile_bytes(n, (int)sizeof(T))) + wave * fft_buf_entries(64 * R);
+    V* buf = (V*)(smem_raw + fft_tile_bytes(n, (int)sizeof(T))) + wave * fft_buf_entries(64 * R);
     const int64_t r0 = (int64_t)blockIdx.x * kFftTubes;
     double beta = 1.0;
     if (a.pX || a.eX) beta = a.beta_sched ? a.beta_sched[a.ctrl->iter] : a.beta_val;
@@ -229,12 +253,12 @@ __global__ __launch_bounds__(256) void k_tube_fft(TubeArgs a, FftTables t) {
     if (a.check_finite && bad) atomicOr(&a.ctrl->status, kStNonFinite);
     __syncthreads();
 
-    const double s0 = sqrt(1.0 / n), s1 = sqrt(2.0 / n);
+    const C s0 = (C)sqrt(1.0 / n), s1 = (C)sqrt(2.0 / n);
     const int h = (n - 1) / 2;
     for (int pr = wave; pr < kFftTubes / 2; pr += 4) {
         const int q1 = 2 * pr, q2 = q1 + 1;
         if (r0 + q1 >= N) break;
-        double2 x[R], cj[R], ph[R / 2];
+        V x[R], cj[R], ph[R / 2];
         // table loads first, in one batch (the tables are zero-padded: no branches)
 #pragma unroll
         for (int s = 0; s < R; ++s) cj[s] = t.chirp[lane + 64 * s];
@@ -246,42 +270,42 @@ __global__ __launch_bounds__(256) void k_tube_fft(TubeArgs a, FftTables t) {
 #pragma unroll
         for (int s = 0; s < R; ++s) {
             const int j = lane + 64 * s;
-            double2 u = make_double2(0.0, 0.0);
+            V u = mkc<C>((C)0, (C)0);
             if (j < n) {
                 if constexpr (mode == kFftDctForward) {
                     const int src = (2 * j < n) ? 2 * j : 2 * (n - 1 - j) + 1;
-                    u = make_double2((double)tile[src * kFftLd + q1], (double)tile[src * kFftLd + q2]);
+                    u = mkc<C>((C)tile[src * kFftLd + q1], (C)tile[src * kFftLd + q2]);
                 } else if constexpr (mode == kFftDftForward) {
-                    u = make_double2((double)tile[j * kFftLd + q1], (double)tile[j * kFftLd + q2]);
+                    u = mkc<C>((C)tile[j * kFftLd + q1], (C)tile[j * kFftLd + q2]);
                 } else {
                     // U = V1 + i V2 from the coefficients; the input is conj(U)
-                    double2 V1, V2;
+                    V V1, V2;
                     if constexpr (mode == kFftDctInverse) {
-                        const double sj = j == 0 ? s0 : s1;
-                        const double2 w = cconj(ph[s < R / 2 ? s : 0]);  // j < n <= M/2: s < R/2
-                        const double y1 = (double)tile[j * kFftLd + q1] / sj, y2 = (double)tile[j * kFftLd + q2] / sj;
-                        const double z1 = j == 0 ? 0.0 : (double)tile[(n - j) * kFftLd + q1] / s1;
-                        const double z2 = j == 0 ? 0.0 : (double)tile[(n - j) * kFftLd + q2] / s1;
-                        V1 = cmul(w, make_double2(y1, -z1));
-                        V2 = cmul(w, make_double2(y2, -z2));
+                        const C sj = j == 0 ? s0 : s1;
+                        const V w = cconj(ph[s < R / 2 ? s : 0]);  // j < n <= M/2: s < R/2
+                        const C y1 = (C)tile[j * kFftLd + q1] / sj, y2 = (C)tile[j * kFftLd + q2] / sj;
+                        const C z1 = j == 0 ? (C)0 : (C)tile[(n - j) * kFftLd + q1] / s1;
+                        const C z2 = j == 0 ? (C)0 : (C)tile[(n - j) * kFftLd + q2] / s1;
+                        V1 = cmul(w, mkc<C>(y1, -z1));
+                        V2 = cmul(w, mkc<C>(y2, -z2));
                     } else {
                         int ir, ii;  // rows of Re and Im (-1: zero); isg: sign of Im
-                        double isg = 1.0;
+                        C isg = (C)1;
                         if (j == 0) { ir = 0; ii = -1; }
                         else if ((n & 1) == 0 && j == n / 2) { ir = n - 1; ii = -1; }
                         else if (j <= h) { ir = 2 * j - 1; ii = 2 * j; }
-                        else { ir = 2 * (n - j) - 1; ii = 2 * (n - j); isg = -1.0; }
-                        V1 = make_double2((double)tile[ir * kFftLd + q1],
-                                          ii < 0 ? 0.0 : isg * (double)tile[ii * kFftLd + q1]);
-                        V2 = make_double2((double)tile[ir * kFftLd + q2],
-                                          ii < 0 ? 0.0 : isg * (double)tile[ii * kFftLd + q2]);
+                        else { ir = 2 * (n - j) - 1; ii = 2 * (n - j); isg = (C)-1; }
+                        V1 = mkc<C>((C)tile[ir * kFftLd + q1],
+                                          ii < 0 ? (C)0 : isg * (C)tile[ii * kFftLd + q1]);
+                        V2 = mkc<C>((C)tile[ir * kFftLd + q2],
+                                          ii < 0 ? (C)0 : isg * (C)tile[ii * kFftLd + q2]);
                     }
-                    u = make_double2(V1.x - V2.y, -(V1.y + V2.x));
+                    u = mkc<C>(V1.x - V2.y, -(V1.y + V2.x));
                 }
             }
             x[s] = cmul(u, cj[s]);
         }
-        bluestein<R>(x, buf, t, lane);
+        bluestein<C, R>(x, buf, t, lane);
         if constexpr (mode == kFftDctForward || mode == kFftDftForward) {
             // separate the two tubes' spectra: needs W[n - k], from the exchange buffer
 #pragma unroll
@@ -295,12 +319,12 @@ __global__ __launch_bounds__(256) void k_tube_fft(TubeArgs a, FftTables t) {
                 const int k = lane + 64 * s;
                 if (k >= n) break;
                 if constexpr (mode == kFftDctForward) {
-                    const double2 Wk = buf[fpad(k)], Wn = cconj(buf[fpad(k == 0 ? 0 : n - k)]);
-                    const double2 V1 = cscale(cadd(Wk, Wn), 0.5);
-                    const double2 d = csub(Wk, Wn);
-                    const double2 V2 = make_double2(0.5 * d.y, -0.5 * d.x);
-                    const double2 p = ph[s];
-                    const double sk = k == 0 ? s0 : s1;
+                    const V Wk = buf[fpad(k)], Wn = cconj(buf[fpad(k == 0 ? 0 : n - k)]);
+                    const V V1 = cscale(cadd(Wk, Wn), (C)0.5);
+                    const V d = csub(Wk, Wn);
+                    const V V2 = mkc<C>((C)0.5 * d.y, (C)-0.5 * d.x);
+                    const V p = ph[s];
+                    const C sk = k == 0 ? s0 : s1;
                     tile[k * kFftLd + q1] = (T)(sk * (p.x * V1.x - p.y * V1.y));
                     tile[k * kFftLd + q2] = (T)(sk * (p.x * V2.x - p.y * V2.y));
                 } else {
@@ -308,10 +332,10 @@ __global__ __launch_bounds__(256) void k_tube_fft(TubeArgs a, FftTables t) {
                     if (k == 0) { f = 0; im = 0; }
                     else if ((n & 1) == 0 && k == n - 1) { f = n / 2; im = 0; }
                     else { f = (k + 1) / 2; im = (k & 1) ? 0 : 1; }
-                    const double2 Wk = buf[fpad(f)], Wn = cconj(buf[fpad(f == 0 ? 0 : n - f)]);
-                    const double2 V1 = cscale(cadd(Wk, Wn), 0.5);
-                    const double2 d = csub(Wk, Wn);
-                    const double2 V2 = make_double2(0.5 * d.y, -0.5 * d.x);
+                    const V Wk = buf[fpad(f)], Wn = cconj(buf[fpad(f == 0 ? 0 : n - f)]);
+                    const V V1 = cscale(cadd(Wk, Wn), (C)0.5);
+                    const V d = csub(Wk, Wn);
+                    const V V2 = mkc<C>((C)0.5 * d.y, (C)-0.5 * d.x);
                     tile[k * kFftLd + q1] = (T)(im ? V1.y : V1.x);
                     tile[k * kFftLd + q2] = (T)(im ? V2.y : V2.x);
                 }
@@ -319,7 +343,7 @@ __global__ __launch_bounds__(256) void k_tube_fft(TubeArgs a, FftTables t) {
             wave_sync();
         } else {
             // v1 + i v2 = conj(W) / n
-            const double invn = 1.0 / n;
+            const C invn = (C)(1.0 / n);
 #pragma unroll
             for (int s = 0; s < R; ++s) {
                 const int j = lane + 64 * s;
@@ -385,37 +409,35 @@ int fft_size(int n) {
     return M;
 }
 
-size_t fft_table_bytes(int n) {
+// prec: 0 FP64 tables (double data), else FP32 tables (float data).
+size_t fft_table_bytes(int n, int prec) {
     const int M = fft_size(n);
-    return sizeof(double) * 2 * ((size_t)M + M + M + M / 2);
+    return (prec == 0 ? sizeof(double) : sizeof(float)) * 2 * ((size_t)M + M + M + M / 2);
 }
 
-// Tables in FP64 (computed in long double): twiddles e^{-2 pi i t/M}; chirp
-// c[j] = e^{-i pi (j^2 mod 2n)/n} (zero-padded to M); the FFT of the wrapped conjugate chirp (a
-// direct O(M^2) DFT over the twiddles, once per length); DCT phases
-// e^{-i pi k/(2n)} (zero-padded to M/2).
-void make_fft_tables(int n, void* out) {
+template <typename C>
+static void write_tables(int n, C* out) {
     const int M = fft_size(n);
     const long double pi = acosl(-1.0L);
-    double* tw = (double*)out;  // M complex
-    double* ch = tw + 2 * M;    // M complex (n values, then zeros)
-    double* bh = ch + 2 * M;    // M complex
-    double* ph = bh + 2 * M;    // M/2 complex (n values, then zeros)
-    for (int j = 2 * n; j < 2 * M; ++j) ch[j] = 0.0;
-    for (int j = 2 * n; j < M; ++j) ph[j] = 0.0;
+    C* tw = out;          // M complex
+    C* ch = tw + 2 * M;   // M complex (n values, then zeros)
+    C* bh = ch + 2 * M;   // M complex
+    C* ph = bh + 2 * M;   // M/2 complex (n values, then zeros)
+    for (int j = 2 * n; j < 2 * M; ++j) ch[j] = (C)0;
+    for (int j = 2 * n; j < M; ++j) ph[j] = (C)0;
     std::vector<std::complex<long double>> root(M), c(n), b(M, 0.0L);
     for (int j = 0; j < M; ++j) {
         const long double ang = -2.0L * pi * j / M;
         root[j] = std::complex<long double>(cosl(ang), sinl(ang));
-        tw[2 * j] = (double)root[j].real();
-        tw[2 * j + 1] = (double)root[j].imag();
+        tw[2 * j] = (C)root[j].real();
+        tw[2 * j + 1] = (C)root[j].imag();
     }
     for (int j = 0; j < n; ++j) {
         const long long q = ((long long)j * j) % (2LL * n);
         const long double ang = -pi * (long double)q / n;
         c[j] = std::complex<long double>(cosl(ang), sinl(ang));
-        ch[2 * j] = (double)c[j].real();
-        ch[2 * j + 1] = (double)c[j].imag();
+        ch[2 * j] = (C)c[j].real();
+        ch[2 * j + 1] = (C)c[j].imag();
     }
     // wrapped conj(c): b[m] = conj(c[m]) for m < n, b[M - m] = conj(c[m]) for 0 < m < n
     for (int m = 0; m < n; ++m) {
@@ -428,61 +450,74 @@ void make_fft_tables(int n, void* out) {
             if (m >= n && m <= M - n) continue;  // zero entries
             acc += b[m] * root[((long long)k * m) % M];
         }
-        bh[2 * k] = (double)acc.real();
-        bh[2 * k + 1] = (double)acc.imag();
+        bh[2 * k] = (C)acc.real();
+        bh[2 * k + 1] = (C)acc.imag();
     }
     for (int k = 0; k < n; ++k) {
         const long double ang = -pi * k / (2.0L * n);
-        ph[2 * k] = (double)cosl(ang);
-        ph[2 * k + 1] = (double)sinl(ang);
+        ph[2 * k] = (C)cosl(ang);
+        ph[2 * k + 1] = (C)sinl(ang);
     }
 }
 
+// Tables (computed in long double, stored in FP64 or FP32): twiddles
+// e^{-2 pi i t/M}; chirp c[j] = e^{-i pi (j^2 mod 2n)/n} (zero-padded to M);
+// the FFT of the wrapped conjugate chirp (a direct O(M^2) DFT over the
+// twiddles, once per length); DCT phases e^{-i pi k/(2n)} (zero-padded to M/2).
+void make_fft_tables(int n, int prec, void* out) {
+    if (prec == 0) write_tables<double>(n, (double*)out);
+    else write_tables<float>(n, (float*)out);
+}
+
 int fft_lds_bytes(int n, int prec) {
-    const int M = fft_size(n);
-    return fft_tile_bytes(n, prec == 0 ? 8 : 4) + 4 * fft_buf_entries(M) * 16;
+    const int es = prec == 0 ? 8 : 4;
+    return fft_tile_bytes(n, es) + 4 * fft_buf_entries(fft_size(n)) * 2 * es;
 }
 
 bool fft_fits(int n3) { return n3 > kMaxTube && fft_size(n3) <= 1024 && fft_lds_bytes(n3, 0) <= kLdsBudget; }
 
-template <typename T, int R, int mode>
-static hipError_t launch_fft(const TubeArgs& a, const FftTables& t, int lds, dim3 grid, hipStream_t s) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_tube_fft<T, R, mode>,
+template <typename T, typename C, int R, int mode>
+static hipError_t launch_fft(const TubeArgs& a, const FftTables<C>& t, int lds, dim3 grid, hipStream_t s) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_tube_fft<T, C, R, mode>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_tube_fft<T, R, mode>), grid, dim3(256), lds, s, a, t);
+    hipLaunchKernelGGL((k_tube_fft<T, C, R, mode>), grid, dim3(256), lds, s, a, t);
     return hipGetLastError();
 }
 
-template <typename T, int R>
-static hipError_t launch_fft_mode(const TubeArgs& a, const FftTables& t, int mode, int lds, dim3 grid,
+template <typename T, typename C, int R>
+static hipError_t launch_fft_mode(const TubeArgs& a, const FftTables<C>& t, int mode, int lds, dim3 grid,
                                   hipStream_t s) {
     switch (mode) {
-        case kFftDctForward: return launch_fft<T, R, kFftDctForward>(a, t, lds, grid, s);
-        case kFftDctInverse: return launch_fft<T, R, kFftDctInverse>(a, t, lds, grid, s);
-        case kFftDftForward: return launch_fft<T, R, kFftDftForward>(a, t, lds, grid, s);
-        case kFftDftInverse: return launch_fft<T, R, kFftDftInverse>(a, t, lds, grid, s);
+        case kFftDctForward: return launch_fft<T, C, R, kFftDctForward>(a, t, lds, grid, s);
+        case kFftDctInverse: return launch_fft<T, C, R, kFftDctInverse>(a, t, lds, grid, s);
+        case kFftDftForward: return launch_fft<T, C, R, kFftDftForward>(a, t, lds, grid, s);
+        case kFftDftInverse: return launch_fft<T, C, R, kFftDftInverse>(a, t, lds, grid, s);
         default: return hipErrorInvalidValue;
     }
 }
 
+template <typename T, typename C>
+static hipError_t launch_fft_typed(const TubeArgs& a, const void* tables, int mode, hipStream_t s) {
+    const int n = a.n3, M = fft_size(n);
+    FftTables<C> t;
+    const cx<C>* p = (const cx<C>*)tables;
+    t.tw = p;
+    t.chirp = p + M;
+    t.bhat = p + 2 * M;
+    t.phase = p + 3 * M;
+    t.n = n;
+    const int lds = fft_lds_bytes(n, sizeof(C) == 8 ? 0 : 1);
+    const dim3 grid((unsigned)((a.N + kFftTubes - 1) / kFftTubes));
+    return M == 512 ? launch_fft_mode<T, C, 8>(a, t, mode, lds, grid, s)
+                    : launch_fft_mode<T, C, 16>(a, t, mode, lds, grid, s);
+}
+
 hipError_t launch_tube_fft(int prec, const TubeArgs& a, const void* tables, int mode, hipStream_t s) {
     if (a.N <= 0) return hipSuccess;
-    const int n = a.n3, M = fft_size(n);
-    if (!fft_fits(n)) return hipErrorInvalidValue;
-    FftTables t;
-    const double* p = (const double*)tables;
-    t.tw = (const double2*)p;
-    t.chirp = (const double2*)(p + 2 * M);
-    t.bhat = (const double2*)(p + 4 * M);
-    t.phase = (const double2*)(p + 6 * M);
-    t.n = n;
-    const int lds = fft_lds_bytes(n, prec);
-    const dim3 grid((unsigned)((a.N + kFftTubes - 1) / kFftTubes));
-    if (prec == 0) return M == 512 ? launch_fft_mode<double, 8>(a, t, mode, lds, grid, s)
-                                   : launch_fft_mode<double, 16>(a, t, mode, lds, grid, s);
-    return M == 512 ? launch_fft_mode<float, 8>(a, t, mode, lds, grid, s)
-                    : launch_fft_mode<float, 16>(a, t, mode, lds, grid, s);
+    if (!fft_fits(a.n3)) return hipErrorInvalidValue;
+    return prec == 0 ? launch_fft_typed<double, double>(a, tables, mode, s)
+                     : launch_fft_typed<float, float>(a, tables, mode, s);
 }
 
 }  // namespace tsvd

@@ -109,16 +109,16 @@ void make_tube_fragments(int eng, int n3, const double* M, void* out);
 hipError_t launch_tube_mfma(int eng, const TubeArgs& a, const void* frag, hipStream_t s);
 // Fast tube transforms (dct_fft.hip) for tubes of 129..512, in O(n3 log n3)
 // by Bluestein's chirp with register-resident Stockham FFTs of 512 or 1024
-// points, two real tubes per complex transform, FP64 arithmetic: the
-// orthonormal DCT-II and its inverse (Makhoul's reordering), and the real form
-// of the DFT and its inverse (rows: Re V0, (Re Vf, Im Vf) for 1 <= f <=
-// (n3-1)/2, Re V(n3/2) for even n3).  Tables built on the host by
-// make_fft_tables (fft_table_bytes(n3) bytes).  launch_tube_fft's prec: 0
-// double data, 1 float data; hipErrorInvalidValue unless fft_fits(n3).
+// points, two real tubes per complex transform, in FP64 arithmetic for double
+// data (prec 0) and FP32 for float data (prec 1): the orthonormal DCT-II and
+// its inverse (Makhoul's reordering), and the real form of the DFT and its
+// inverse (rows: Re V0, (Re Vf, Im Vf) for 1 <= f <= (n3-1)/2, Re V(n3/2) for
+// even n3).  Tables built on the host by make_fft_tables (fft_table_bytes
+// bytes, per precision).  hipErrorInvalidValue unless fft_fits(n3).
 enum { kFftDctForward = 0, kFftDctInverse = 1, kFftDftForward = 2, kFftDftInverse = 3 };
 int fft_size(int n);
-size_t fft_table_bytes(int n);
-void make_fft_tables(int n, void* out);
+size_t fft_table_bytes(int n, int prec);
+void make_fft_tables(int n, int prec, void* out);
 int fft_lds_bytes(int n, int prec);
 bool fft_fits(int n3);  // 128 < n3 <= 512
 hipError_t launch_tube_fft(int prec, const TubeArgs& a, const void* tables, int mode, hipStream_t s);

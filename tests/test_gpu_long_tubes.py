@@ -161,3 +161,36 @@ def test_dense_kernel_limits(tm):
     cr = ratio(to_np(Y), oracle.tsvt_dct(Zf, c.tau), Zf, 1)
     print("dense FP32 n3 600: c = %.3f" % cr)
     assert cr <= C_PATH[1]
+
+
+@pytest.mark.parametrize("shape", [(7, 5, 300), (1, 1, 129), (3, 1, 512), (17, 1, 200)])
+def test_tsvt_long_tubes_odd_and_tiny_tube_counts(tm, shape):
+    # an odd number of tubes leaves the last pair of a workgroup half empty;
+    # fewer than 16 tubes leave most of the only workgroup empty
+    announce("tsvt_long_odd", shape=shape)
+    c = tsvt_case(shape, 66, r=1)
+    Y, ranks = tm.tsvt_dct(to_dev(c.Z), c.tau, return_ranks=True)
+    Yo, ro, _ = oracle.tsvt_dct(c.Z, c.tau, return_ranks=True)
+    assert rel(to_np(Y), Yo) <= FP64_TOL
+    assert ranks == [int(x) for x in ro]
+    Yd = tm.tsvt_dft(to_dev(c.Z), c.tau * np.sqrt(shape[2]))
+    assert rel(to_np(Yd), oracle.tsvt_dft(c.Z, c.tau * np.sqrt(shape[2]))) <= FP64_TOL
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_complete_long_tubes_reduced(tm, prec):
+    # FP32 / MIXED completion on the fast transform against the oracle's iterates
+    # on the float-rounded input, within the per-iteration bound
+    from bounds import U_EFF, oracle_iterates
+
+    announce("complete_long_reduced", prec=prec)
+    L = 6
+    cc = synth.completion_case(oracle.tprod_dct, 20, 18, 300, 3, 0.5, L, 91, tau0=1.0, tau1=0.01)
+    Bf = cc.B.astype(np.float32).astype(np.float64)
+    Xo, _, zmax = oracle_iterates(Bf, cc.mask, cc.taus, L)
+    X, info = tm.complete_tensor(to_dev(Bf, torch.float32), to_dev(cc.mask, torch.uint8), max_iter=L, tol=0.0,
+                                 tau_schedule=cc.taus, prec=prec)
+    assert info["status"] == 0
+    cr = np.linalg.norm(to_np(X) - Xo) / (U_EFF[prec] * zmax)
+    print("completion long tubes prec %d: c per iteration %.3f" % (prec, cr / L))
+    assert cr <= L * C_PATH[prec]
