@@ -26,8 +26,9 @@
  *     and tuning results.  One context per host thread, or external locking.
  *   - Tube length n3 (the transform along the tubes): n3 <= 128 runs on the
  *     matrix cores; 128 < n3 <= 512 (DCT and Fourier paths) on the fast
- *     O(n3 log n3) transform in FP64 arithmetic (Makhoul's reordering,
- *     Bluestein's chirp, radix-2 FFTs); other tubes longer than 128 (caller-
+ *     O(n3 log n3) transform (Makhoul's reordering, Bluestein's chirp,
+ *     radix-8/16 FFTs) in FP64 arithmetic for double data and FP32 for float
+ *     data; other tubes longer than 128 (caller-
  *     given transforms, tsvt_dct_noalloc, n3 > 512) on the dense vector-ALU
  *     kernel, which holds at most 304 (double data) or 608 (float data):
  *     beyond that a call returns TSVD_EINVAL.
