@@ -124,9 +124,10 @@ def dct_roofline(st, prec_name, launches_per_step=1):
 
 
 def kernel_source_md5():
-    """Hash of the Jacobi kernel's sources (the counters are tied to them)."""
+    """Hash of the Jacobi kernel's sources, jacobi.hip then jacobi.h (the
+    counters are tied to them)."""
     h = hashlib.md5()
-    for f in ("jacobi.hip", "internal.h"):
+    for f in ("jacobi.hip", "jacobi.h"):
         with open(os.path.join(ROOT, "paper_1902_03070_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

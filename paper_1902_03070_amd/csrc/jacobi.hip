@@ -38,7 +38,7 @@
 //    a timeout instead of hanging.
 #include <algorithm>
 
-#include "internal.h"
+#include "jacobi.h"
 
 namespace tsvd {
 
