@@ -120,9 +120,13 @@ enum {
                                   applied on the matrix cores): 0 a candidate of the tuner, 1
                                   forced (team size from TSVD_OPT_TEAM_SIZE, else one workgroup
                                   per 32 columns), -1 (default) never used */
-    TSVD_OPT_LONG_TUBES = 12   /* DCT tubes of 129..512: 0 (default) the fast O(n3 log n3)
+    TSVD_OPT_LONG_TUBES = 12,  /* DCT tubes of 129..512: 0 (default) the fast O(n3 log n3)
                                   transform, 1 the dense vector-ALU product where its LDS tile
                                   fits (n3 <= 304 for double data, 608 for float) */
+    TSVD_OPT_TEAM_SLOTS = 13   /* 0: automatic; N > 0: at most N slices in flight per XCD in the
+                                  multi-workgroup Jacobi kernel (teams then take several slices
+                                  in turn; the tuner also tries the count whose A and V fit an
+                                  XCD's L2).  A forced setting, like TEAM_SIZE, disables tuning. */
 };
 int tsvd_set_option(tsvd_ctx* ctx, int option, double value);
 double tsvd_get_option(const tsvd_ctx* ctx, int option);

@@ -24,6 +24,7 @@ OK, WARN_NOCONV, EINVAL, ENOMEM, EHIP, ENONFINITE, EBUSY, ETIMEOUT, ECANCELED = 
 OPT_MAX_SWEEPS, OPT_SYNC_STATUS, OPT_TEAM_SIZE, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_GRAPHS = 0, 1, 2, 3, 4, 5
 OPT_AUTOTUNE, OPT_GROUP_LANES, OPT_GROUP_COLUMNS, OPT_WARM_START, OPT_COOPERATIVE, OPT_GRAM = 6, 7, 8, 9, 10, 11
 OPT_LONG_TUBES = 12
+OPT_TEAM_SLOTS = 13
 PHASES = ("forward_transform", "jacobi", "threshold_rebuild", "inverse_transform", "warm_start")
 TRANSFORM_DOMAIN, FULL = 1, 2
 REQ_TSVT, REQ_COMPLETE = 0, 1

@@ -27,6 +27,7 @@ struct tsvd_ctx {
     int max_sweeps = 30;
     int sync_status = 1;
     int team_size = 0;
+    int team_slots = 0;  // > 0: slices in flight per XCD of the multi-workgroup kernel (forced)
     int group_lanes = 0;
     int group_cols = 0;
     int autotune = 1;
@@ -837,8 +838,9 @@ int pick_tile(tsvd_ctx* c, const Plan& P, bool batched, hipStream_t s, Tile* t) 
         t->source = 2;
         return TSVD_OK;
     }
-    if (c->team_size > 0 || c->group_lanes > 0 || c->group_cols > 0) {
+    if (c->team_size > 0 || c->group_lanes > 0 || c->group_cols > 0 || c->team_slots > 0) {
         *t = default_tile(P, c->team_size, c->group_lanes, c->group_cols, batched);
+        if (t->team == 1 && !batched) t->slots = c->team_slots;
         t->source = 2;
         return TSVD_OK;
     }
@@ -1411,6 +1413,10 @@ int tsvd_set_option(tsvd_ctx* c, int opt, double v) {
             if (v != -1 && v != 0 && v != 1) return fail(c, TSVD_EINVAL, "gram option is -1, 0 or 1");
             c->gram = (int)v;
             return TSVD_OK;
+        case TSVD_OPT_TEAM_SLOTS:
+            if (v < 0 || v > 64) return fail(c, TSVD_EINVAL, "team slots out of range 0..64");
+            c->team_slots = (int)v;
+            return TSVD_OK;
     }
     return fail(c, TSVD_EINVAL, "unknown option");
 }
@@ -1428,6 +1434,7 @@ double tsvd_get_option(const tsvd_ctx* c, int opt) {
         case TSVD_OPT_GROUP_COLUMNS: return c->group_cols;
         case TSVD_OPT_WARM_START: return c->warm_start;
         case TSVD_OPT_GROUP_LANES: return c->group_lanes;
+        case TSVD_OPT_TEAM_SLOTS: return c->team_slots;
         case TSVD_OPT_COOPERATIVE: return c->coop;
         case TSVD_OPT_GRAM: return c->gram;
         case TSVD_OPT_LONG_TUBES: return c->dense_long;

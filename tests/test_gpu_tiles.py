@@ -126,3 +126,29 @@ def test_team_residency_with_six_wavefront_workgroups(tm):
     ctx.close()
     assert info["status"] == 0
     assert within_completion(to_np(X), Xo, zmax, 1, 2)
+
+
+@pytest.mark.parametrize("slots,W", [(1, 8), (3, 16), (2, 4)])
+def test_team_slots_forced_completion_fp64(tm, slots, W):
+    # fewer slices in flight per XCD than the tensor has slices per XCD: teams
+    # take several slices in turn (the tuner's L2-fitting candidates).  FP64
+    # completion with V at 256 x 256 x 31 against the oracle's iterates.
+    announce("team_slots", slots=slots, W=W)
+    cc = synth.completion_case(oracle.tprod_dct, 256, 256, 31, 10, 0.3, 3, synth.SEED_BASE + 2)
+    oracle.set_threads(min(16, oracle.host_threads()))
+    Xo, _, _ = oracle_iterates(cc.B, cc.mask, cc.taus, 3)
+    ctx = tm.Context(0)
+    try:
+        ctx.set_option(tm.OPT_TEAM_SLOTS, slots)
+        ctx.set_option(tm.OPT_TEAM_SIZE, W)
+        assert ctx.get_option(tm.OPT_TEAM_SLOTS) == slots
+        t = ctx.tile(0, 256, 256, 31, with_v=True)
+        assert t["team"] == 1 and t["source"] == 2
+        X, info = tm.complete_tensor(to_dev(cc.B), to_dev(cc.mask, torch.uint8), max_iter=3, tol=0.0,
+                                     tau_schedule=cc.taus, ctx=ctx)
+    finally:
+        ctx.close()
+    assert info["status"] == 0
+    err = rel(to_np(X), Xo)
+    print("slots %d W %d: rel err %.3e" % (slots, W, err))
+    assert err <= FP64_TOL
