@@ -124,11 +124,12 @@ class Context:
             lib.tsvd_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no HIP call while the interpreter shuts down: contexts still open
         # then were closed by the exit hook below, before the runtime's own
-        # teardown; anything left is reclaimed by the process exit
-        if sys.is_finalizing():
+        # teardown; anything left is reclaimed by the process exit (the check
+        # is bound at definition time: module globals may already be gone)
+        if _finalizing():
             return
         try:
             self.close()
@@ -531,8 +532,8 @@ class Server:
             self.ctx.close()
             self.ctx = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
