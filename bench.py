@@ -57,6 +57,12 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip completion, batch and serving measurements")
     ap.add_argument("--serving-requests", type=int, default=60)
     ap.add_argument("--serving-loads", default="0.5,0.8", help="fractions of the measured saturation throughput")
+    ap.add_argument("--serving-stream", type=int, default=0,
+                    help="only the long serving stream: this many requests per load after the warm-up")
+    ap.add_argument("--serving-warmup", type=int, default=200)
+    ap.add_argument("--serving-pool", type=int, default=200, help="distinct requests the stream cycles through")
+    ap.add_argument("--serving-saturation", type=float, default=0.0,
+                    help="saturation throughput (req/s) for the stream's loads; 0 measures it on the pool")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (hardware-counter scale for profiling runs)")
     return ap.parse_args()
@@ -313,11 +319,12 @@ def batched(tm, torch, tprod):
             "recipe": "n1,n2 ~ U{32..512}, n3 ~ U{8..128}, rank min(n1,n2)/10, t-product + N(0,0.01)"}
 
 
-def serving(tm, torch, tprod, nreq, loads):
+def serving_requests(tprod, n, seed_offset=5):
+    """n requests of the serving mix: shapes as the batch configuration,
+    alternately a t-SVT and a 50-iteration completion (30% observed)."""
     import synth
 
-    g = np.random.default_rng(synth.SEED_BASE + 5)
-    shapes = synth.batch_shapes(nreq, synth.SEED_BASE + 5, cfg_index=5)
+    shapes = synth.batch_shapes(n, synth.SEED_BASE + seed_offset, cfg_index=5)
     reqs = []
     for j, s in enumerate(shapes):
         if j % 2 == 0:
@@ -326,61 +333,110 @@ def serving(tm, torch, tprod, nreq, loads):
         else:
             cc = synth.completion_case(tprod, s.n1, s.n2, s.n3, s.r, 0.3, 50, s.seed)
             reqs.append(("complete", cc.B.astype(np.float32), cc.mask))
-    budget = 64 << 30
+    return reqs
 
-    def submit(srv, r):
-        if r[0] == "tsvt":
-            return srv.submit_tsvt(r[1], r[2])
-        return srv.submit_complete(r[1], r[2], 50, 10.0, 0.1)
 
-    def drain(srv, ids):
-        got = {}
-        while len(got) < len(ids):
-            for i in ids:
-                if i not in got:
-                    r = srv.poll(i)
-                    if r is not None:
-                        got[i] = r[1]
-            time.sleep(0.0005)
-        return got
+def _submit(srv, r):
+    if r[0] == "tsvt":
+        return srv.submit_tsvt(r[1], r[2])
+    return srv.submit_complete(r[1], r[2], 50, 10.0, 0.1)
 
-    # saturation: all requests submitted at once
-    srv = tm.Server(budget_bytes=budget, max_active=16)
+
+def _drain(srv, ids):
+    got = {}
+    while len(got) < len(ids):
+        for i in ids:
+            if i not in got:
+                r = srv.poll(i)
+                if r is not None:
+                    got[i] = r[1]
+        time.sleep(0.0005)
+    return got
+
+
+def serving_saturation(tm, reqs, budget, max_active=16):
+    """Requests per second with every request submitted at once."""
+    srv = tm.Server(budget_bytes=budget, max_active=max_active)
     t0 = time.perf_counter()
-    ids = [submit(srv, r) for r in reqs]
-    drain(srv, ids)
+    _drain(srv, [_submit(srv, r) for r in reqs])
     sat = len(reqs) / (time.perf_counter() - t0)
     srv.close()
-    log("serving saturation %.2f req/s" % sat)
-    out = {"requests": len(reqs), "mix": "50% t-SVT / 50% completion (50 iterations, tau 10->0.1), 30% observed",
-           "shapes": "n1,n2 ~ U{32..512}, n3 ~ U{8..128}", "saturation_req_per_s": round(sat, 3),
-           "budget_bytes": budget, "max_active": 16, "loads": {}}
-    # fixed request rates: Poisson arrivals at a fraction of saturation
-    for load in loads:
-        qps = load * sat
-        arrivals = synth.poisson_arrivals(g, qps, len(reqs))
-        srv = tm.Server(budget_bytes=budget, max_active=16)
-        t0 = time.perf_counter()
-        ids = []
-        for a, r in zip(arrivals, reqs):
-            while time.perf_counter() - t0 < a:
-                time.sleep(0.0002)
-            ids.append(submit(srv, r))
-        got = drain(srv, ids)
-        wall = time.perf_counter() - t0
-        st = srv.stats()
-        srv.close()
-        lat = np.array([got[i][2] - got[i][0] for i in ids]) * 1e3
-        kinds = [r[0] for r in reqs]
-        lt = np.array([lat[k] for k in range(len(ids)) if kinds[k] == "tsvt"])
-        lc = np.array([lat[k] for k in range(len(ids)) if kinds[k] == "complete"])
-        pc = lambda a, q: round(float(np.percentile(a, q)), 2)  # noqa: E731
-        out["loads"][str(load)] = {
-            "qps": round(qps, 3), "p50_ms": pc(lat, 50), "p99_ms": pc(lat, 99),
+    return sat
+
+
+def serving_load(tm, reqs, kinds, qps, g, budget, skip=0, max_active=16):
+    """Poisson arrivals at qps; latency percentiles over the requests after the
+    first `skip` (warm-up).  reqs[k] is submitted as request k."""
+    import synth
+
+    arrivals = synth.poisson_arrivals(g, qps, len(reqs))
+    srv = tm.Server(budget_bytes=budget, max_active=max_active)
+    t0 = time.perf_counter()
+    ids = []
+    for a, r in zip(arrivals, reqs):
+        while time.perf_counter() - t0 < a:
+            time.sleep(0.0002)
+        ids.append(_submit(srv, r))
+        if len(ids) % 200 == 0:
+            log("serving: %d of %d requests submitted, %.0f s" % (len(ids), len(reqs), time.perf_counter() - t0))
+    got = _drain(srv, ids)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = np.array([got[i][2] - got[i][0] for i in ids]) * 1e3
+    keep = range(skip, len(ids))
+    la = np.array([lat[k] for k in keep])
+    lt = np.array([lat[k] for k in keep if kinds[k] == "tsvt"])
+    lc = np.array([lat[k] for k in keep if kinds[k] == "complete"])
+    pc = lambda a, q: round(float(np.percentile(a, q)), 2)  # noqa: E731
+    return {"qps": round(qps, 3), "p50_ms": pc(la, 50), "p99_ms": pc(la, 99),
             "p50_ms_tsvt": pc(lt, 50), "p99_ms_tsvt": pc(lt, 99),
             "p50_ms_complete": pc(lc, 50), "p99_ms_complete": pc(lc, 99),
             "throughput_req_per_s": round(len(ids) / wall, 3), "ticks": st["ticks"], "peak_bytes": st["peak_bytes"]}
+
+
+SERVING_MIX = "50% t-SVT / 50% completion (50 iterations, tau 10->0.1), 30% observed"
+SERVING_SHAPES = "n1,n2 ~ U{32..512}, n3 ~ U{8..128}"
+
+
+def serving(tm, torch, tprod, nreq, loads):
+    import synth
+
+    g = np.random.default_rng(synth.SEED_BASE + 5)
+    reqs = serving_requests(tprod, nreq)
+    kinds = [r[0] for r in reqs]
+    budget = 64 << 30
+    sat = serving_saturation(tm, reqs, budget)
+    log("serving saturation %.2f req/s" % sat)
+    out = {"requests": len(reqs), "mix": SERVING_MIX, "shapes": SERVING_SHAPES, "saturation_req_per_s": round(sat, 3),
+           "budget_bytes": budget, "max_active": 16, "loads": {}}
+    # fixed request rates: Poisson arrivals at a fraction of saturation
+    for load in loads:
+        out["loads"][str(load)] = serving_load(tm, reqs, kinds, load * sat, g, budget)
         log("serving load %.2f: %s" % (load, out["loads"][str(load)]))
+    return out
+
+
+def serving_stream(tm, torch, tprod, nreq, warmup, loads, pool, saturation):
+    """The long serving stream: warmup + nreq requests per load, drawn in turn
+    from a pool of `pool` generated requests (request k is pool[k mod pool]);
+    percentiles over the nreq requests after the warm-up.  Saturation is
+    given, or measured on the pool."""
+    import synth
+
+    g = np.random.default_rng(synth.SEED_BASE + 8)
+    base = serving_requests(tprod, pool)
+    budget = 64 << 30
+    sat = saturation if saturation > 0 else serving_saturation(tm, base, budget)
+    total = warmup + nreq
+    reqs = [base[k % pool] for k in range(total)]
+    kinds = [r[0] for r in reqs]
+    out = {"requests": nreq, "warmup_requests": warmup, "pool": pool, "mix": SERVING_MIX, "shapes": SERVING_SHAPES,
+           "saturation_req_per_s": round(sat, 3), "saturation_given": saturation > 0, "budget_bytes": budget,
+           "max_active": 16, "loads": {}}
+    for load in loads:
+        out["loads"][str(load)] = serving_load(tm, reqs, kinds, load * sat, g, budget, skip=warmup)
+        log("serving stream load %.2f: %s" % (load, out["loads"][str(load)]))
     return out
 
 
@@ -544,6 +600,13 @@ def main():
 
     assert torch.cuda.is_available(), "needs a ROCm GPU"
     tprod = gpu_tprod_factory(tm, torch)
+    if args.serving_stream > 0:
+        out = {"serving_stream": serving_stream(tm, torch, tprod, args.serving_stream, args.serving_warmup,
+                                                [float(x) for x in args.serving_loads.split(",")],
+                                                args.serving_pool, args.serving_saturation)}
+        tm.close_all()
+        print(json.dumps(out), flush=True)
+        return
     case = synth.completion_case(tprod, N1, N2, N3, RANK, SR, L_FULL, synth.SEED_BASE + 2)
     Z0 = tm.fortran(torch.from_numpy(case.B).to("cuda:0"))
     Z99, cap = capture_last_iterate(tm, torch, case)
