@@ -188,7 +188,11 @@ int get_fft_tables(tsvd_ctx* c, int n3, int prec, const void** out) {
         make_fft_tables(n3, tp, h.data());
         void* d = nullptr;
         HIPCHK(c, hipMalloc(&d, bytes));
-        HIPCHK(c, hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice));
+        const hipError_t e = hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return hip_fail(c, e, "fast-transform tables");
+        }
         it = c->fft.emplace(key, d).first;
     }
     *out = it->second;
