@@ -499,6 +499,39 @@ def dct_vs_dft(tm, torch, reps=3):
                                "note": "original (DFT) and DCT t-SVD in seconds, MATLAB on the paper's CPU"}}
 
 
+def other_transforms(tm, torch, Z0, tau, reps=10):
+    """The t-SVT under caller-given transforms (the concluding remarks' other
+    transforms) against the DCT one on the same input (Z_0 at 256x256x31):
+    a random orthogonal L and a random well-conditioned non-orthogonal L
+    (I + 0.2 N(0,1)/sqrt(n3)), same kernels, host-given matrices."""
+    g = np.random.default_rng(synth_seed(9))
+    n3 = Z0.shape[2]
+    Lo, _ = np.linalg.qr(g.standard_normal((n3, n3)))
+    Lg = np.eye(n3) + 0.2 * g.standard_normal((n3, n3)) / np.sqrt(n3)
+    rows = []
+    for name, prec in (("mixed", tm.MIXED), ("fp64", tm.FP64)):
+        dt = torch.float64 if prec == tm.FP64 else torch.float32
+        Z = tm.fortran(Z0.to(dt).permute(2, 1, 0).contiguous().permute(2, 1, 0))
+        ctx = tm.Context(0)
+        calls = {"dct": lambda: tm.tsvt_dct(Z, tau, prec=prec, ctx=ctx),
+                 "orthogonal_L": lambda: tm.tsvt_transform(Z, tau, Lo, prec=prec, ctx=ctx),
+                 "general_L": lambda: tm.tsvt_transform(Z, tau, Lg, prec=prec, ctx=ctx)}
+        row = {"path": name}
+        for k, fn in calls.items():
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            row[k + "_ms"] = round(1e3 * (time.perf_counter() - t0) / reps, 4)
+        ctx.close()
+        rows.append(row)
+        log("other transforms:", row)
+    return {"shape": list(Z0.shape), "tau": float(tau), "rows": rows,
+            "note": "cold t-SVTs of Z_0; the transform matrix changes the slices, so sweeps differ"}
+
+
 def long_tubes(tm, torch, reps=5):
     """Tubes longer than 128: the fast O(n3 log n3) transform (Bluestein's chirp
     with register FFTs) against the dense vector-ALU product, forward-transform
@@ -659,6 +692,7 @@ def main():
         out["beta_sweep"] = beta_sweep(tm, torch, case)
         out["dct_vs_dft"] = dct_vs_dft(tm, torch)
         out["long_tubes"] = long_tubes(tm, torch)
+        out["other_transforms"] = other_transforms(tm, torch, inputs[0][0], inputs[0][1])
         out["serving"] = serving(tm, torch, tprod, args.serving_requests,
                                  [float(x) for x in args.serving_loads.split(",")])
         log("serving:", out["serving"])
