@@ -194,3 +194,18 @@ def test_complete_long_tubes_reduced(tm, prec):
     cr = np.linalg.norm(to_np(X) - Xo) / (U_EFF[prec] * zmax)
     print("completion long tubes prec %d: c per iteration %.3f" % (prec, cr / L))
     assert cr <= L * C_PATH[prec]
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_tsvt_dft_long_tubes_reduced(tm, prec):
+    # the FP32 fast transform on the Fourier path; the real DFT has condition
+    # number sqrt(2) relative to an orthogonal transform, so the bound is twice
+    # the DCT path's
+    announce("tsvt_dft_long_reduced", prec=prec)
+    n1, n2, n3 = 48, 36, 300
+    c = synth.tsvt_case(oracle.tprod_dct, n1, n2, n3, 3, 0.01, 0.15 * (np.sqrt(n1) + np.sqrt(n2)) * np.sqrt(n3), 67)
+    Zf = c.Z.astype(np.float32).astype(np.float64)
+    Y = tm.tsvt_dft(to_dev(Zf, torch.float32), c.tau, prec=prec)
+    cr = ratio(to_np(Y), oracle.tsvt_dft(Zf, c.tau), Zf, prec)
+    print("tsvt_dft long prec %d: c = %.3f" % (prec, cr))
+    assert cr <= 2 * C_PATH[prec]
