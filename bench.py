@@ -96,16 +96,22 @@ def capture_last_iterate(tm, torch, case):
 
 
 def jacobi_roofline(st, prec_name, with_v, n3_total):
-    """Roofline of the Jacobi kernel from the device's slice-sweep count and the
-    HIP events around its launches.  One-sided Jacobi with tracked norms: per
+    """Roofline of the Jacobi kernel from the device's counts and the HIP
+    events around its launches.  One-sided Jacobi with tracked norms: per
     column pair an inner product (2m flops) and the rotation of two length-m
     columns (6m), plus the rotation of two length-p columns of V when V is
-    carried (6p); p(p-1)/2 pairs per sweep."""
+    carried (6p).  The full iteration takes p(p-1)/2 pairs per sweep; the
+    kept-column mode counts the pairs it evaluates (the others cost no flop)."""
     m, p = max(N1, N2), min(N1, N2)
-    flops_per_slice_sweep = (8.0 * m + (6.0 * p if with_v else 0.0)) * p * (p - 1) / 2.0
+    flops_per_pair = 8.0 * m + (6.0 * p if with_v else 0.0)
+    flops_per_slice_sweep = flops_per_pair * p * (p - 1) / 2.0
     launches = max(1, st["launches"]["jacobi"])
     avg_ms = st["ms"]["jacobi"] / launches
-    flops_per_launch = flops_per_slice_sweep * st["slice_sweeps"] / launches
+    pairs = st.get("pairs", 0)
+    if pairs > 0:
+        flops_per_launch = flops_per_pair * pairs / launches
+    else:
+        flops_per_launch = flops_per_slice_sweep * st["slice_sweeps"] / launches
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     peak = PEAK["fp64_alu"] if prec_name == "fp64" else PEAK["fp32_alu"]
     return {"kernel": "k_jacobi_team", "bound": "alu", "achieved": round(achieved, 3), "peak": peak,
@@ -113,7 +119,9 @@ def jacobi_roofline(st, prec_name, with_v, n3_total):
             "traffic": traffic_for("jacobi_tsvt" if not with_v else "jacobi", prec_name),
             "avg_launch_ms": round(avg_ms, 4), "launches": launches,
             "slice_sweeps": st["slice_sweeps"], "sweeps_per_slice": round(st["slice_sweeps"] / (launches * n3_total), 3),
-            "flops_per_slice_sweep": flops_per_slice_sweep, "flops_per_launch": flops_per_launch}
+            "pairs_per_launch": round(pairs / launches, 1), "fallback_slices": st.get("fallback_slices", 0),
+            "flops_per_pair": flops_per_pair, "flops_per_slice_sweep": flops_per_slice_sweep,
+            "flops_per_launch": flops_per_launch}
 
 
 def dct_roofline(st, prec_name, launches_per_step=1):
@@ -154,15 +162,18 @@ def traffic_for(kernel, prec_name):
     return None
 
 
-def timed_tsvt(tm, torch, inputs, prec, steps, warmup):
+def timed_tsvt(tm, torch, inputs, prec, steps, warmup, kept=1, phases=True):
     """The timed loop: `steps` cold t-SVTs, step i on inputs[i % len(inputs)],
     asynchronous calls on one stream with HIP events around the Jacobi
-    launches (the device status is checked after the loop)."""
+    launches (the device status is checked after the loop).  kept: the
+    kept-column Jacobi with its threshold certificate (1, the library's
+    default) or the full iteration (0)."""
     dt = torch.float64 if prec == tm.FP64 else torch.float32
     Zs = [(Z.to(dt), float(tau)) for Z, tau in inputs]
     Zs = [(tm.fortran(Z.permute(2, 1, 0).contiguous().permute(2, 1, 0)), tau) for Z, tau in Zs]
     Ys = [tm.empty_f(N1, N2, N3, dt, "cuda:0") for _ in Zs]
     ctx = tm.Context(0)
+    ctx.set_option(tm.OPT_KEPT_COLUMNS, kept)
     for i in range(max(warmup, len(Zs))):  # the first calls tune the Jacobi tile
         Z, tau = Zs[i % len(Zs)]
         tm.tsvt_dct(Z, tau, Y=Ys[i % len(Zs)], prec=prec, ctx=ctx)
@@ -192,9 +203,22 @@ def timed_tsvt(tm, torch, inputs, prec, steps, warmup):
         torch.cuda.synchronize()
         per.append((time.perf_counter() - a) / reps)
     ctx.sync_status()
+    phase_ms = None
+    if phases:
+        # events around every phase (they add a few microseconds each): where a step goes
+        ctx.set_option(tm.OPT_PROFILE, 1)
+        ctx.stats(reset=True)
+        reps = 2 * len(Zs) * 5
+        for i in range(reps):
+            Z, tau = Zs[i % len(Zs)]
+            tm.tsvt_dct(Z, tau, Y=Ys[i % len(Zs)], prec=prec, ctx=ctx)
+        ph = ctx.stats(reset=True)
+        phase_ms = {k: round(v / reps, 4) for k, v in ph["ms"].items()}
+        ctx.set_option(tm.OPT_PROFILE, 0)
+    ctx.sync_status()
     ctx.close()
     return {"seconds": t1 - t0, "stats": st, "status": status, "max_sweeps": max_sweeps, "tile": tile,
-            "per_input_ms": [round(1e3 * x, 4) for x in per]}
+            "per_input_ms": [round(1e3 * x, 4) for x in per], "phase_ms_per_step": phase_ms}
 
 
 def run_completion(tm, torch, case, prec, steps, warmup, profile, warm_period=-1):
@@ -680,9 +704,18 @@ def main():
             "ms_per_step": round(1e3 * rr["seconds"] / args.steps, 4),
             "per_input_ms": {"Z_0": rr["per_input_ms"][0], "Z_99": rr["per_input_ms"][1]},
             "jacobi_roofline": jacobi_roofline(rr["stats"], name, False, N3),
-            "status": rr["status"], "max_sweeps": rr["max_sweeps"], "jacobi_tile": rr["tile"]}
+            "status": rr["status"], "max_sweeps": rr["max_sweeps"], "jacobi_tile": rr["tile"],
+            "phase_ms_per_step": rr["phase_ms_per_step"]}
     if "fp64" in results and head != "fp64":
         out["speedup_vs_fp64"] = round(results["fp64"]["seconds"] / r["seconds"], 3)
+    # the same loop with the full Jacobi iteration on every slice (the kept-column
+    # mode and its threshold certificate switched off)
+    fr = timed_tsvt(tm, torch, inputs, precs[head], args.steps, args.warmup, kept=0, phases=False)
+    out["full_iteration"] = {"t_svt_per_s": round(args.steps / fr["seconds"], 3),
+                             "ms_per_step": round(1e3 * fr["seconds"] / args.steps, 4),
+                             "per_input_ms": {"Z_0": fr["per_input_ms"][0], "Z_99": fr["per_input_ms"][1]},
+                             "jacobi_roofline": jacobi_roofline(fr["stats"], head, False, N3), "status": fr["status"]}
+    log("%s, full iteration: %.4f ms/step" % (head, out["full_iteration"]["ms_per_step"]))
     if not args.no_extras:
         out["completion_in_situ"] = completion_in_situ(tm, torch, case)
         out["video_shaped"] = video_shaped(tm, torch, tprod, 100)

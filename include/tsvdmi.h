@@ -123,10 +123,20 @@ enum {
     TSVD_OPT_LONG_TUBES = 12,  /* DCT tubes of 129..512: 0 (default) the fast O(n3 log n3)
                                   transform, 1 the dense vector-ALU product where its LDS tile
                                   fits (n3 <= 304 for double data, 608 for float) */
-    TSVD_OPT_TEAM_SLOTS = 13   /* 0: automatic; N > 0: at most N slices in flight per XCD in the
+    TSVD_OPT_TEAM_SLOTS = 13,  /* 0: automatic; N > 0: at most N slices in flight per XCD in the
                                   multi-workgroup Jacobi kernel (teams then take several slices
                                   in turn; the tuner also tries the count whose A and V fit an
                                   XCD's L2).  A forced setting, like TEAM_SIZE, disables tuning. */
+    TSVD_OPT_KEPT_COLUMNS = 14 /* tsvd_tsvt_dct and tsvd_tsvt_transform with tau > 0, when the
+                                  multi-workgroup kernel with one column per lane group runs the
+                                  SVDs: 1 (default) each slice's Jacobi iteration works only on
+                                  the column pairs that touch a column of norm > tau and stops
+                                  once those columns are orthogonal to all others (Theorem 5
+                                  needs no more); the slice is then certified -- the remaining
+                                  columns of spectral norm <= tau -- or run through the full
+                                  iteration.  A slice with a remaining column of norm above
+                                  tau / sqrt(2) (no gap below tau) turns into the full
+                                  iteration at once.  0: the full iteration for every slice */
 };
 int tsvd_set_option(tsvd_ctx* ctx, int option, double value);
 double tsvd_get_option(const tsvd_ctx* ctx, int option);
@@ -161,14 +171,19 @@ int tsvd_get_tile(tsvd_ctx* ctx, int prec, int64_t n1, int64_t n2, int64_t n3, i
 /* Counters since the last reset.  Phases: 0 forward transform (with the
  * completion prologue), 1 Jacobi SVD, 2 thresholding and rebuild, 3 inverse
  * transform (with the completion epilogue), 4 warm start of the completion's
- * Jacobi (reset of V and the product Zbar V).  ms/launches are filled only
- * while TSVD_OPT_PROFILE is 1 (event pairs on the launch stream).
- * slice_sweeps counts Jacobi sweeps summed over all slices processed, always.
+ * Jacobi (reset of V and the product Zbar V), 5 threshold certificate of the
+ * kept-column mode (TSVD_OPT_KEPT_COLUMNS) with the full iteration of the
+ * slices it rejects.  ms/launches are filled only while TSVD_OPT_PROFILE is 1
+ * (event pairs on the launch stream).  Always counted: slice_sweeps, Jacobi
+ * sweeps summed over all slices processed; pairs, column pairs evaluated by
+ * the kept-column mode; fallback_slices, slices its certificate rejected.
  * Synchronizes `stream`. */
 typedef struct {
     int64_t slice_sweeps;
-    double ms[5];
-    int64_t launches[5];
+    double ms[6];
+    int64_t launches[6];
+    int64_t pairs;
+    int64_t fallback_slices;
 } tsvd_stats;
 int tsvd_get_stats(tsvd_ctx* ctx, void* stream, tsvd_stats* out, int reset);
 

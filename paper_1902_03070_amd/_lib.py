@@ -25,7 +25,8 @@ OPT_MAX_SWEEPS, OPT_SYNC_STATUS, OPT_TEAM_SIZE, OPT_SPIN_LIMIT, OPT_PROFILE, OPT
 OPT_AUTOTUNE, OPT_GROUP_LANES, OPT_GROUP_COLUMNS, OPT_WARM_START, OPT_COOPERATIVE, OPT_GRAM = 6, 7, 8, 9, 10, 11
 OPT_LONG_TUBES = 12
 OPT_TEAM_SLOTS = 13
-PHASES = ("forward_transform", "jacobi", "threshold_rebuild", "inverse_transform", "warm_start")
+OPT_KEPT_COLUMNS = 14
+PHASES = ("forward_transform", "jacobi", "threshold_rebuild", "inverse_transform", "warm_start", "certificate")
 TRANSFORM_DOMAIN, FULL = 1, 2
 REQ_TSVT, REQ_COMPLETE = 0, 1
 
@@ -57,7 +58,8 @@ class CompleteInfo(C.Structure):
 
 
 class Stats(C.Structure):
-    _fields_ = [("slice_sweeps", C.c_int64), ("ms", C.c_double * 5), ("launches", C.c_int64 * 5)]
+    _fields_ = [("slice_sweeps", C.c_int64), ("ms", C.c_double * 6), ("launches", C.c_int64 * 6),
+                ("pairs", C.c_int64), ("fallback_slices", C.c_int64)]
 
 
 class Request(C.Structure):
@@ -151,8 +153,9 @@ class Context:
         st = Stats()
         self.check(lib.tsvd_get_stats(self.h, _stream(stream, self.device), C.byref(st), int(reset)))
         return {"slice_sweeps": st.slice_sweeps,
-                "ms": {PHASES[i]: st.ms[i] for i in range(5)},
-                "launches": {PHASES[i]: st.launches[i] for i in range(5)}}
+                "pairs": st.pairs, "fallback_slices": st.fallback_slices,
+                "ms": {PHASES[i]: st.ms[i] for i in range(6)},
+                "launches": {PHASES[i]: st.launches[i] for i in range(6)}}
 
     def tile(self, prec: int, n1: int, n2: int, n3: int, batched: bool = False, with_v: bool = False) -> dict:
         """Jacobi tile this context uses for the shape (tunes it if needed)."""

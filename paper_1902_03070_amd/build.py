@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtsvdmi.so")
-SOURCES = ["api.hip", "jacobi.hip", "ops.hip", "dct_mfma.hip", "dct_fft.hip", "server.cpp"]
+SOURCES = ["api.hip", "jacobi.hip", "ops.hip", "dct_mfma.hip", "dct_fft.hip", "certify.hip", "server.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code.

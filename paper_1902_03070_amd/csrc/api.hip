@@ -58,6 +58,7 @@ struct tsvd_ctx {
     int noalloc = 0;            // inside tsvt_dct_noalloc: no tuning, no profiling events
     int coop = 0;               // 1: cooperative launches of the team kernel outside capture
     int gram = -1;              // block-Gram kernel: 0 a tuner candidate, 1 forced, -1 excluded
+    int kept_cols = 1;          // 1: plain t-SVTs run the kept-column Jacobi with the threshold certificate
     // operands of a caller-given tube transform (tsvt_transform, the DFT path), cached by content
     DevBuf xf;
     std::vector<double> xf_key;
@@ -375,6 +376,9 @@ struct Plan {
     // workspace offsets
     size_t o_zbar, o_A, o_F, o_G, o_w, o_sig, o_ybar, o_V, o_rot, o_sw, o_bar, o_rank, o_pos, o_end;
     size_t o_ctr_begin, o_ctr_end;  // region zeroed per call (counters)
+    // kept-column Jacobi and its threshold certificate (plan_kept_columns)
+    int keep = 0;
+    size_t o_full = 0, o_sums = 0, o_rot2 = 0, o_bar2 = 0, o_flags = 0, o_nrm2 = 0, o_As = 0, o_H = 0, o_H2 = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -904,6 +908,33 @@ int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int wit
     return TSVD_OK;
 }
 
+// Kept-column Jacobi for a plain t-SVT (cold SVDs, no V): the team kernel with
+// one column per lane group iterates only on the pairs that touch a column
+// above the threshold (a slice without a gap below it turns into the full
+// iteration), the threshold certificate checks each slice, and the full
+// iteration runs for the slices it rejects.  Adds the mode's counters to
+// the plan's zeroed region (right after the others) and its buffers after
+// them.  Leaves the plan unchanged when the option is off or the tile is
+// another kernel.
+void plan_kept_columns(tsvd_ctx* c, Plan& P, Carve& cv) {
+    P.keep = 0;
+    if (!c->kept_cols || c->noalloc || P.team != 1 || P.K != 1 || P.with_v || P.m > kMaxRows) return;
+    if (P.o_ctr_end != cv.off) return;  // the zeroed region must stay contiguous
+    const size_t n3 = (size_t)P.n3, m = (size_t)P.m, p = (size_t)P.p;
+    P.o_full = cv.take(n3 * 4);
+    P.o_sums = cv.take(n3 * 8);
+    P.o_rot2 = cv.take(n3 * kRotStride * 4);
+    P.o_bar2 = cv.take((size_t)(kTeamCtlInts + (size_t)std::max(1, P.ts.nwg) * (1 + std::max(1, P.job.nb))) * 4);
+    P.o_ctr_end = cv.off;
+    P.o_flags = cv.take(n3 * 4);
+    P.o_nrm2 = cv.take(n3 * p * 8);
+    P.o_As = cv.take(n3 * m * p * 4);
+    P.o_H = cv.take(n3 * p * p * 4);
+    P.o_H2 = cv.take(n3 * p * p * 4);
+    P.o_end = cv.off;
+    P.keep = 1;
+}
+
 // Point the plan's Jacobi descriptor at its workspace regions.
 void bind_plan(Plan& P, char* base) {
     JacobiJob& J = P.job;
@@ -961,6 +992,43 @@ int enqueue_after_jacobi(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double ta
 
 int enqueue_warm_start(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t s);
 
+// Threshold certificate after the kept-column iteration, then the full
+// iteration (in place, from A') for the slices it rejects; the others are
+// left alone by that launch.
+int enqueue_certificate(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau, hipStream_t s) {
+    const int prec = P.prec == TSVD_FP64 ? 0 : 1;
+    CertArgs a{};
+    a.A = base + P.o_A;
+    a.m = P.m; a.p = P.p; a.n3 = (int)P.n3;
+    a.tau = tau;
+    a.nrm2 = (double*)(base + P.o_nrm2);
+    a.As = (float*)(base + P.o_As);
+    a.H = (float*)(base + P.o_H);
+    a.H2 = (float*)(base + P.o_H2);
+    a.sums = (double*)(base + P.o_sums);
+    a.sweeps = P.job.sweeps;
+    a.full = (const int*)(base + P.o_full);
+    a.flags = (int*)(base + P.o_flags);
+    a.ctrl = ctrl;
+    hipError_t e = launch_threshold_certificate(prec, a, s);
+    if (e != hipSuccess) return hip_fail(c, e, "threshold certificate");
+    JacobiJob J = P.job;
+    J.keep = 0;
+    J.keep2 = 0.0;
+    J.skip = a.flags;
+    J.src = base + P.o_A;
+    J.src_ss = (int64_t)P.m * P.p;
+    J.src_rs = 1;
+    J.src_cs = P.m;
+    J.rot = (int*)(base + P.o_rot2);
+    TeamSched ts = P.ts;
+    ts.ctl = (int*)(base + P.o_bar2);
+    e = launch_jacobi_team(P.prec, J, (int)P.n3, ts, clamp_sweeps(c->max_sweeps), ctrl, P.lds, P.threads, 0,
+                           c->spin_limit, J.R, J.G, 1, (c->capturing || !c->coop) ? 0 : 1, s);
+    if (e != hipSuccess) return hip_fail(c, e, "jacobi launch");
+    return TSVD_OK;
+}
+
 int enqueue_svt_core(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau_val, const double* tau_sched,
                      hipStream_t s) {
     if (P.warm) {
@@ -968,9 +1036,20 @@ int enqueue_svt_core(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau_va
         int rc = enqueue_warm_start(c, P, base, ctrl, s);
         if (rc) return rc;
     }
+    // the kept-column mode needs the threshold on the host (not a schedule) and tau > 0
+    const bool keep = P.keep && !tau_sched && tau_val > 0.0 && isfinite(tau_val);
+    P.job.keep = keep ? 1 : 0;
+    P.job.keep2 = keep ? tau_val * tau_val : 0.0;
+    P.job.skip = nullptr;
+    P.job.full = keep ? (int*)(base + P.o_full) : nullptr;
     {
         PhaseMark pm(c, 1, s);
         int rc = run_jacobi(c, P, base, ctrl, s);
+        if (rc) return rc;
+    }
+    if (keep) {
+        PhaseMark pm(c, 5, s);
+        int rc = enqueue_certificate(c, P, base, ctrl, tau_val, s);
         if (rc) return rc;
     }
     return enqueue_after_jacobi(c, P, base, ctrl, tau_val, tau_sched, s);
@@ -1421,6 +1500,10 @@ int tsvd_set_option(tsvd_ctx* c, int opt, double v) {
             if (v < 0 || v > 64) return fail(c, TSVD_EINVAL, "team slots out of range 0..64");
             c->team_slots = (int)v;
             return TSVD_OK;
+        case TSVD_OPT_KEPT_COLUMNS:
+            if (v != 0.0 && v != 1.0) return fail(c, TSVD_EINVAL, "kept-column option must be 0 or 1");
+            c->kept_cols = (int)v;
+            return TSVD_OK;
     }
     return fail(c, TSVD_EINVAL, "unknown option");
 }
@@ -1442,6 +1525,7 @@ double tsvd_get_option(const tsvd_ctx* c, int opt) {
         case TSVD_OPT_COOPERATIVE: return c->coop;
         case TSVD_OPT_GRAM: return c->gram;
         case TSVD_OPT_LONG_TUBES: return c->dense_long;
+        case TSVD_OPT_KEPT_COLUMNS: return c->kept_cols;
     }
     return -1.0;
 }
@@ -1492,10 +1576,14 @@ int tsvd_get_stats(tsvd_ctx* c, void* stream, tsvd_stats* out, int reset) {
     Ctrl h;
     HIPCHK(c, hipMemcpy(&h, cr.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
     out->slice_sweeps = (int64_t)h.slice_sweeps;
+    out->pairs = (int64_t)h.pairs;
+    out->fallback_slices = h.fallback;
     if (reset) {
         c->marks.clear();
         c->ev_used = 0;
         h.slice_sweeps = 0;
+        h.pairs = 0;
+        h.fallback = 0;
         HIPCHK(c, hipMemcpy(cr.ctrl, &h, sizeof(Ctrl), hipMemcpyHostToDevice));
     }
     return TSVD_OK;
@@ -1512,6 +1600,7 @@ int tsvt_dct(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
     Plan P;
     Carve cv;
     if ((rc = make_plan(c, prec, n1, n2, n3, 0, P, cv, s))) return rc;
+    plan_kept_columns(c, P, cv);
     if ((rc = ensure_ws(c, P.o_end))) return rc;
     return tsvt_enqueue(c, P, (char*)c->ws.p, nullptr, nullptr, Z, Y, tau, ranks_out, s);
 }
@@ -1575,6 +1664,7 @@ int tsvt_transform(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, co
     Plan P;
     Carve cv;
     if ((rc = make_plan(c, prec, n1, n2, n3, 0, P, cv, s))) return rc;
+    plan_kept_columns(c, P, cv);
     if ((rc = ensure_ws(c, P.o_end))) return rc;
     return tsvt_enqueue(c, P, (char*)c->ws.p, fwd, inv, Z, Y, tau, ranks_out, s);
 }

@@ -114,6 +114,29 @@ struct DftEmbedArgs {
 hipError_t launch_dft_embed(int prec, const DftEmbedArgs& a, hipStream_t s);
 hipError_t launch_dft_unembed(int prec, const DftEmbedArgs& a, hipStream_t s);
 
+// Threshold certificate of the kept-column Jacobi mode (certify.hip): per
+// slice, after the kept-column iteration, flags[k] = 1 when the iteration
+// converged and the columns of A' with squared norm <= tau^2 have spectral
+// norm <= tau (bound ||H^4||_F^2 with H their Gram matrix / tau^2, FP32 with
+// a rounding margin), or when the slice converged as the full iteration;
+// else 0, and ctrl->fallback += 1.  hipErrorInvalidValue when m > kMaxRows
+// or tau <= 0.
+struct CertArgs {
+    const void* A;      // A' (tall, m x p per slice, ld m, slice stride m p), FP64 for prec 0 else FP32
+    int m, p, n3;
+    double tau;
+    double* nrm2;       // [n3 p] squared column norms (written)
+    float* As;          // [n3 m p] A' / tau in FP32 (written)
+    float* H;           // [n3 p p] Gram matrix, then H^4 (written)
+    float* H2;          // [n3 p p] H^2 (written)
+    double* sums;       // [n3] zero before the launch; ||H^4||_F^2
+    const int* sweeps;  // [n3] sweeps of the kept-column iteration (-1: did not converge)
+    const int* full;    // [n3] 1: the slice converged as the full iteration (no certificate needed)
+    int* flags;         // [n3] result
+    Ctrl* ctrl;
+};
+hipError_t launch_threshold_certificate(int prec, CertArgs a, hipStream_t s);
+
 // One batched step over many tensors (used by tsvt_dct_batched and the serving
 // loop).  Per tensor: either a plain t-SVT Z -> Y, or one completion iteration
 // with the fused prologue Z = X - M/beta and epilogue (X, M updated in place).

@@ -9,7 +9,8 @@
 namespace tsvd {
 
 constexpr int kMaxSweeps = 64;       // hard cap on Jacobi sweeps (per-sweep counters are sized by it)
-constexpr int kRotStride = 2 * kMaxSweeps;  // per slice: rotations per sweep, then large-angle pairs per sweep
+constexpr int kRotStride = 3 * kMaxSweeps;  // per slice: rotations per sweep, large-angle pairs per sweep, then
+                                            // (kept-column mode) pairs evaluated per sweep
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kMaxEpl = 8;           // rows per lane in the Jacobi kernels: m <= 512
 constexpr int kMaxRows = kWave * kMaxEpl;
@@ -27,8 +28,9 @@ struct Ctrl {
     int status;      // kSt* bits
     int max_sweeps;  // largest sweep count seen (atomicMax)
     int iter;        // completion iteration counter (graph-captured loops)
-    int pad;
+    int fallback;    // slices the threshold certificate sent back to a full Jacobi SVD (statistics)
     unsigned long long slice_sweeps;  // sweeps executed, summed over slices (statistics)
+    unsigned long long pairs;         // column pairs evaluated in the kept-column mode (statistics)
 };
 
 // One Jacobi problem set: all frontal slices of one tensor, in "tall" form.
@@ -55,6 +57,23 @@ struct JacobiJob {
     double skip2;      // a sweep whose pairs all have (x.y)^2 <= skip2 |x|^2 |y|^2 ends the iteration
                        // (the next sweep would rotate by angles far below tol: no check sweep)
     Ctrl* ctrl;        // per-job status and counters (batched steps), or nullptr: the launch's block
+    // Kept-column mode (team kernel with one column per lane group, no V): only
+    // the pairs with a column of squared norm above keep2 (tau^2 of a t-SVT)
+    // are evaluated and count towards convergence; a pair of two columns at or
+    // below it (a "rest" pair) is skipped.  The iteration ends once the columns
+    // above the threshold are orthogonal to all others -- all a singular value
+    // thresholding needs, provided the remaining columns have spectral norm
+    // <= tau, which the threshold certificate checks afterwards (a slice that
+    // fails goes through the full iteration).  One last sweep on the kept pairs
+    // (FP64 arithmetic for the mixed path) follows convergence.  A sweep after
+    // the first that still evaluates over half of all pairs (a large kept set)
+    // turns the slice into the full iteration for good, and a slice that
+    // converges that way is marked in full[] (it needs no certificate).  A slice that does not converge in this
+    // mode is not flagged TSVD_WARN_NOCONV here: the certificate sends it back.
+    int keep;          // 0: every pair, to full convergence; 1: kept-column mode
+    double keep2;      // the mode's squared threshold (> 0)
+    int* full;         // [n3] (kept-column mode) set to 1 for a slice that converged as the full iteration
+    const int* skip;   // [n3] or nullptr: nonzero = the slice is done, the launch leaves it untouched
 };
 
 struct TeamSched {

@@ -309,16 +309,22 @@ __device__ __forceinline__ int gpair_lds(T* __restrict__ x, T* __restrict__ y, d
 // (row gl + G q), the others (RT > R when V is accumulated) the rows of V
 // (row gl + G (q - R)).  Inner products and norms use the A rows; rotations
 // act on the whole column, so V follows every rotation of A.
+//
+// Kept-column mode (keep2 >= 0): a pair whose two squared norms are both
+// <= keep2 (a "rest" pair) is skipped before any load or product.  ev counts
+// the pairs evaluated.
 template <typename T, int R, int RT, int G>
 __device__ __forceinline__ int tpair_lds(T* __restrict__ x, T* __restrict__ y, double* na, double* nb, int gl,
-                                         double tol, bool f64, double th2, int& big) {
+                                         double tol, bool f64, double th2, double keep2, int& big, int& ev) {
+    const double a = *na, b = *nb;
+    if (a <= keep2 && b <= keep2) return 0;  // (a NaN norm makes a kept pair)
+    ++ev;
     T xr[RT], yr[RT];
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
         xr[q] = x[gl + G * q];
         yr[q] = y[gl + G * q];
     }
-    const double a = *na, b = *nb;
     const double g = group_dot<T, R, G>(xr, yr, f64);
     big += !(g * g <= th2 * (a * b));  // a NaN counts as large: never converged
     double c, s, t;
@@ -337,14 +343,17 @@ __device__ __forceinline__ int tpair_lds(T* __restrict__ x, T* __restrict__ y, d
 }
 
 // Pair with x in registers (squared norm na, uniform in the group) and y in LDS.
+// keep2 and ev as for tpair_lds.
 template <typename T, int R, int RT, int G>
 __device__ __forceinline__ int tpair_reg(T (&xr)[RT], double& na, T* __restrict__ y, double* nb, int gl,
-                                         double tol, bool f64, double th2, int& big) {
+                                         double tol, bool f64, double th2, double keep2, int& big, int& ev) {
     const double b = *nb;
+    const double a = na;
+    if (a <= keep2 && b <= keep2) return 0;
+    ++ev;
     T yr[RT];
 #pragma unroll
     for (int q = 0; q < RT; ++q) yr[q] = y[gl + G * q];
-    const double a = na;
     const double g = group_dot<T, R, G>(xr, yr, f64);
     big += !(g * g <= th2 * (a * b));  // a NaN counts as large: never converged
     double c, s, t;
@@ -414,8 +423,11 @@ __device__ __forceinline__ int block_sum_groups(int v, int gl, int* s_scratch) {
 
 __device__ __forceinline__ void record_slice(const JacobiJob& J, int k, int sweeps, int executed, Ctrl* ctrl) {
     J.sweeps[k] = sweeps;
-    if (sweeps < 0) atomicOr(&ctrl->status, kStNoConv);
-    else atomicMax(&ctrl->max_sweeps, sweeps);
+    if (sweeps < 0) {
+        if (!J.keep) atomicOr(&ctrl->status, kStNoConv);  // kept-column mode: the certificate decides
+    } else {
+        atomicMax(&ctrl->max_sweeps, sweeps);
+    }
     atomicAdd(&ctrl->slice_sweeps, (unsigned long long)executed);
 }
 
@@ -828,10 +840,18 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
     int* rot_g = J.rot + (int64_t)k * kRotStride;
     T* Ag = (T*)J.A + (int64_t)k * m * p;
     T* Vg = WV ? (T*)J.V + (int64_t)k * p * p : nullptr;
-    for (int sw = 0; sw < max_sweeps + (refine ? 1 : 0); ++sw) {
-        const bool f64 = refine && sw == max_sweeps;
+    // a slice already done (uniform over the team: every member reads the same flag)
+    if (J.skip && J.skip[k]) return true;
+    // kept-column mode, until the slice turns into the full iteration (uniform
+    // over the team: decided from the slice's counters after a team barrier)
+    int keep = J.keep;
+    const bool final_sweep = refine || keep;
+    for (int sw = 0; sw < max_sweeps + (final_sweep ? 1 : 0); ++sw) {
+        const bool fin = final_sweep && sw == max_sweeps;
+        const bool f64 = refine && fin;
+        const double keep2 = keep ? J.keep2 : -1.0;
         const double tl = f64 ? (double)m * Unit<double>::v : tol;
-        int rot = 0, big = 0;
+        int rot = 0, big = 0, ev = 0;
         ++executed;
         for (int s = 0; s < nb - 1; ++s) {
             const bool last = (s == nb - 2);
@@ -883,7 +903,7 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                         double* nb_ = half ? nJ : nI;
                         if (blk * b + j < p)
                             rot += tpair_lds<T, R, RT, G>(base + i * ldl, base + j * ldl, nb_ + i, nb_ + j, gl, tl,
-                                                          f64, J.skip2, big);
+                                                          f64, J.skip2, keep2, big, ev);
                         __syncthreads();
                     }
 #pragma unroll
@@ -908,7 +928,7 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                             const int j = sb * gw + ((u + v) & (gw - 1));
                             if (ci < p && BJ * b + j < p)
                                 rot += tpair_reg<T, R, RT, G>(xr, na, Js + j * ldl, nJ + j, gl, tl, f64, J.skip2,
-                                                              big);
+                                                              keep2, big, ev);
                             // keeps the compiler from moving the next sub-round's LDS reads
                             // above this one's writes (no instruction is emitted)
                             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -936,19 +956,43 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                 const int btot = block_sum_groups(big, gl, s_scratch);
                 if (tid == 0 && tot) atomicAdd(rot_g + sw, tot);
                 if (tid == 0 && btot) atomicAdd(rot_g + kMaxSweeps + sw, btot);
+                if (keep) {
+                    const int etot = block_sum_groups(ev, gl, s_scratch);
+                    if (tid == 0 && etot) {
+                        atomicAdd(&ts.ctrl->pairs, (unsigned long long)etot);
+                        atomicAdd(rot_g + 2 * kMaxSweeps + sw, etot);
+                    }
+                }
                 if (!team_barrier(ts, s_flag)) return false;
             }
         }
-        if (f64) break;
+        if (fin) break;
         const int total = __hip_atomic_load(rot_g + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int large = __hip_atomic_load(rot_g + kMaxSweeps + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (keep && sw >= 1) {
+            // past the first sweep (which starts from the input's columns), a sweep
+            // that still evaluated over half of all pairs has a large kept set:
+            // the mode saves little there, and the few columns left below tau tend
+            // to sit near it, beyond what the certificate can clear.  The slice
+            // continues as the full iteration (this sweep's counts covered the
+            // kept pairs only, so they decide nothing).
+            const int evs = __hip_atomic_load(rot_g + 2 * kMaxSweeps + sw, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+            if (2.0 * evs > 0.5 * (double)p * (p - 1)) {
+                keep = 0;
+                continue;
+            }
+        }
         if (total == 0 || large == 0) {
             sweeps = sw + 1;
-            if (!refine) break;
+            if (!final_sweep || (!keep && !refine)) break;
             sw = max_sweeps - 1;
         }
     }
-    if (tid == 0 && rank == 0) record_slice(J, k, sweeps, executed, ts.ctrl);
+    if (tid == 0 && rank == 0) {
+        if (J.keep && !keep && sweeps >= 0) J.full[k] = 1;
+        record_slice(J, k, sweeps, executed, ts.ctrl);
+    }
     return true;
 }
 
