@@ -378,7 +378,7 @@ struct Plan {
     size_t o_ctr_begin, o_ctr_end;  // region zeroed per call (counters)
     // kept-column Jacobi and its threshold certificate (plan_kept_columns)
     int keep = 0;
-    size_t o_full = 0, o_sums = 0, o_rot2 = 0, o_bar2 = 0, o_flags = 0, o_nrm2 = 0, o_As = 0, o_H = 0, o_H2 = 0;
+    size_t o_full = 0, o_ncols = 0, o_sums = 0, o_rot2 = 0, o_bar2 = 0, o_flags = 0, o_nrm2 = 0, o_As = 0, o_H = 0, o_H2 = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -927,6 +927,7 @@ void plan_kept_columns(tsvd_ctx* c, Plan& P, Carve& cv) {
     P.o_bar2 = cv.take((size_t)(kTeamCtlInts + (size_t)std::max(1, P.ts.nwg) * (1 + std::max(1, P.job.nb))) * 4);
     P.o_ctr_end = cv.off;
     P.o_flags = cv.take(n3 * 4);
+    P.o_ncols = cv.take(n3 * 4);
     P.o_nrm2 = cv.take(n3 * p * 8);
     P.o_As = cv.take(n3 * m * p * 4);
     P.o_H = cv.take(n3 * p * p * 4);
@@ -1008,6 +1009,7 @@ int enqueue_certificate(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau
     a.sums = (double*)(base + P.o_sums);
     a.sweeps = P.job.sweeps;
     a.full = (const int*)(base + P.o_full);
+    a.ncols = (int*)(base + P.o_ncols);
     a.flags = (int*)(base + P.o_flags);
     a.ctrl = ctrl;
     hipError_t e = launch_threshold_certificate(prec, a, s);

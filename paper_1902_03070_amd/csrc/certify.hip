@@ -43,12 +43,17 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 }
 
 // One wavefront per column: its squared norm in FP64, and the column scaled
-// by 1/tau as FP32 (the Gram operand).
+// by 1/tau as FP32 (the Gram operand).  Slices that converged as the full
+// iteration are skipped (their GEMM column count is set to 0).
 template <typename T>
 __global__ __launch_bounds__(kCertThreads) void k_cert_scan(CertArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t col = (int64_t)blockIdx.x * (kCertThreads / kWave) + wave;
     if (col >= (int64_t)a.n3 * a.p) return;
+    const int k = (int)(col / a.p);
+    const bool skip = a.full[k] != 0;
+    if (lane == 0 && col - (int64_t)k * a.p == 0) a.ncols[k] = skip ? 0 : a.p;
+    if (skip) return;
     const T* x = (const T*)a.A + col * a.m;
     float* y = a.As + col * a.m;
     const double inv = 1.0 / a.tau;
@@ -70,6 +75,7 @@ __global__ __launch_bounds__(kCertThreads) void k_cert_mask(CertArgs a) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t k = e / pp, o = e - k * pp;
+        if (a.full[k]) continue;
         const int i = (int)(o % a.p), j = (int)(o / a.p);
         const double* nk = a.nrm2 + k * a.p;
         if (nk[i] > t2 || nk[j] > t2) a.H[e] = 0.0f;
@@ -81,6 +87,7 @@ __global__ __launch_bounds__(kCertThreads) void k_cert_mask(CertArgs a) {
 __global__ __launch_bounds__(kCertThreads) void k_cert_sumsq(CertArgs a) {
     __shared__ double s_part[kCertThreads / kWave];
     const int k = blockIdx.y, tid = threadIdx.x;
+    if (a.full[k]) return;  // (the same for the whole workgroup)
     const int64_t pp = (int64_t)a.p * a.p;
     const float* H4 = a.H + (int64_t)k * pp;
     double s = 0.0;
@@ -105,6 +112,10 @@ __global__ __launch_bounds__(kCertThreads) void k_cert_sumsq(CertArgs a) {
 __global__ __launch_bounds__(kCertThreads) void k_cert_final(CertArgs a) {
     __shared__ double s_part[kCertThreads / kWave];
     const int k = blockIdx.x, tid = threadIdx.x;
+    if (a.full[k]) {
+        if (tid == 0) a.flags[k] = 1;
+        return;
+    }
     const double* nk = a.nrm2 + (int64_t)k * a.p;
     const double t2 = a.tau * a.tau;
     double tr = 0.0;
@@ -119,7 +130,7 @@ __global__ __launch_bounds__(kCertThreads) void k_cert_final(CertArgs a) {
         const double S = a.sums[k];
         const double delta = 2.0 * (a.m + 2.0 * a.p) * 0x1p-24 * TR + 0x1p-8;
         const double b = 1.0 - delta, b2 = b * b, b4 = b2 * b2;
-        const bool ok = a.full[k] != 0 || (a.sweeps[k] >= 0 && delta < 1.0 && S <= b4 * b4);
+        const bool ok = a.sweeps[k] >= 0 && delta < 1.0 && S <= b4 * b4;
         a.flags[k] = ok ? 1 : 0;
         if (!ok) atomicAdd(&a.ctrl->fallback, 1);
     }
@@ -143,6 +154,7 @@ hipError_t launch_threshold_certificate(int prec, CertArgs a, hipStream_t s) {
     g.B = a.As; g.b_rs = 1; g.b_cs = a.m; g.b_bs = (int64_t)a.m * a.p;
     g.C = a.H; g.c_rs = 1; g.c_cs = a.p; g.c_bs = pp;
     g.M = a.p; g.Nn = a.p; g.K = a.m; g.batch = a.n3;
+    g.Ndev = a.ncols;
     if ((e = launch_gemm(1, g, s)) != hipSuccess) return e;
     const int64_t total = pp * a.n3;
     const unsigned gm = (unsigned)std::min<int64_t>((total + kCertThreads - 1) / kCertThreads, 4096);
@@ -154,6 +166,7 @@ hipError_t launch_threshold_certificate(int prec, CertArgs a, hipStream_t s) {
     q.b_rs = 1; q.b_cs = a.p; q.b_bs = pp;
     q.c_rs = 1; q.c_cs = a.p; q.c_bs = pp;
     q.M = a.p; q.Nn = a.p; q.K = a.p; q.batch = a.n3;
+    q.Ndev = a.ncols;
     q.A = a.H; q.B = a.H; q.C = a.H2;
     if ((e = launch_gemm(1, q, s)) != hipSuccess) return e;
     q.A = a.H2; q.B = a.H2; q.C = a.H;

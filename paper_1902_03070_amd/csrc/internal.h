@@ -132,6 +132,8 @@ struct CertArgs {
     double* sums;       // [n3] zero before the launch; ||H^4||_F^2
     const int* sweeps;  // [n3] sweeps of the kept-column iteration (-1: did not converge)
     const int* full;    // [n3] 1: the slice converged as the full iteration (no certificate needed)
+    int* ncols;         // [n3] (written) p for a slice to certify, 0 for one that converged as the full
+                        // iteration: the column count of its GEMMs, which then skip it
     int* flags;         // [n3] result
     Ctrl* ctrl;
 };

@@ -9,8 +9,10 @@
 namespace tsvd {
 
 constexpr int kMaxSweeps = 64;       // hard cap on Jacobi sweeps (per-sweep counters are sized by it)
-constexpr int kRotStride = 3 * kMaxSweeps;  // per slice: rotations per sweep, large-angle pairs per sweep, then
-                                            // (kept-column mode) pairs evaluated per sweep
+constexpr int kRotStride = 4 * kMaxSweeps;  // per slice: rotations per sweep, large-angle pairs per sweep, then
+                                            // (kept-column mode) pairs evaluated and pairs with cosine > 1e-2
+constexpr int kKeepMaxSweeps = 10;   // kept-column sweeps before a slice that has not converged turns into
+                                     // the full iteration
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kMaxEpl = 8;           // rows per lane in the Jacobi kernels: m <= 512
 constexpr int kMaxRows = kWave * kMaxEpl;
@@ -65,10 +67,14 @@ struct JacobiJob {
     // thresholding needs, provided the remaining columns have spectral norm
     // <= tau, which the threshold certificate checks afterwards (a slice that
     // fails goes through the full iteration).  One last sweep on the kept pairs
-    // (FP64 arithmetic for the mixed path) follows convergence.  A sweep after
-    // the first that still evaluates over half of all pairs (a large kept set)
-    // turns the slice into the full iteration for good, and a slice that
-    // converges that way is marked in full[] (it needs no certificate).  A slice that does not converge in this
+    // (FP64 arithmetic for the mixed path) follows convergence.  The kept
+    // columns settle fast when the singular values have a gap below tau and
+    // slowly when they do not, so the slice turns into the full iteration for
+    // good after a sweep (past the first) that evaluated over 40% of all pairs,
+    // after a sweep with an unchanged kept set in which the pairs with cosine
+    // > 1e-2 fell by less than a factor 0.5 (or two in a row by less than
+    // 0.35), or after kKeepMaxSweeps sweeps; a slice that converges that way is
+    // marked in full[] (it needs no certificate).  A slice that does not converge in this
     // mode is not flagged TSVD_WARN_NOCONV here: the certificate sends it back.
     int keep;          // 0: every pair, to full convergence; 1: kept-column mode
     double keep2;      // the mode's squared threshold (> 0)

@@ -312,10 +312,12 @@ __device__ __forceinline__ int gpair_lds(T* __restrict__ x, T* __restrict__ y, d
 //
 // Kept-column mode (keep2 >= 0): a pair whose two squared norms are both
 // <= keep2 (a "rest" pair) is skipped before any load or product.  ev counts
-// the pairs evaluated.
+// the pairs evaluated, prog those with cosine > 1e-2 (the mode's measure of
+// progress).
 template <typename T, int R, int RT, int G>
 __device__ __forceinline__ int tpair_lds(T* __restrict__ x, T* __restrict__ y, double* na, double* nb, int gl,
-                                         double tol, bool f64, double th2, double keep2, int& big, int& ev) {
+                                         double tol, bool f64, double th2, double keep2, int& big, int& ev,
+                                         int& prog) {
     const double a = *na, b = *nb;
     if (a <= keep2 && b <= keep2) return 0;  // (a NaN norm makes a kept pair)
     ++ev;
@@ -327,6 +329,7 @@ __device__ __forceinline__ int tpair_lds(T* __restrict__ x, T* __restrict__ y, d
     }
     const double g = group_dot<T, R, G>(xr, yr, f64);
     big += !(g * g <= th2 * (a * b));  // a NaN counts as large: never converged
+    prog += !(g * g <= 1e-4 * (a * b));
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
     rotate_regs<T, RT>(xr, yr, c, s);
@@ -343,10 +346,11 @@ __device__ __forceinline__ int tpair_lds(T* __restrict__ x, T* __restrict__ y, d
 }
 
 // Pair with x in registers (squared norm na, uniform in the group) and y in LDS.
-// keep2 and ev as for tpair_lds.
+// keep2, ev and prog as for tpair_lds.
 template <typename T, int R, int RT, int G>
 __device__ __forceinline__ int tpair_reg(T (&xr)[RT], double& na, T* __restrict__ y, double* nb, int gl,
-                                         double tol, bool f64, double th2, double keep2, int& big, int& ev) {
+                                         double tol, bool f64, double th2, double keep2, int& big, int& ev,
+                                         int& prog) {
     const double b = *nb;
     const double a = na;
     if (a <= keep2 && b <= keep2) return 0;
@@ -356,6 +360,7 @@ __device__ __forceinline__ int tpair_reg(T (&xr)[RT], double& na, T* __restrict_
     for (int q = 0; q < RT; ++q) yr[q] = y[gl + G * q];
     const double g = group_dot<T, R, G>(xr, yr, f64);
     big += !(g * g <= th2 * (a * b));  // a NaN counts as large: never converged
+    prog += !(g * g <= 1e-4 * (a * b));
     double c, s, t;
     if (!rotation(a, b, g, tol, c, s, t)) return 0;
     rotate_regs<T, RT>(xr, yr, c, s);
@@ -845,13 +850,14 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
     // kept-column mode, until the slice turns into the full iteration (uniform
     // over the team: decided from the slice's counters after a team barrier)
     int keep = J.keep;
+    int slow = 0;  // consecutive kept-column sweeps of slow progress
     const bool final_sweep = refine || keep;
     for (int sw = 0; sw < max_sweeps + (final_sweep ? 1 : 0); ++sw) {
         const bool fin = final_sweep && sw == max_sweeps;
         const bool f64 = refine && fin;
         const double keep2 = keep ? J.keep2 : -1.0;
         const double tl = f64 ? (double)m * Unit<double>::v : tol;
-        int rot = 0, big = 0, ev = 0;
+        int rot = 0, big = 0, ev = 0, prog = 0;
         ++executed;
         for (int s = 0; s < nb - 1; ++s) {
             const bool last = (s == nb - 2);
@@ -903,7 +909,7 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                         double* nb_ = half ? nJ : nI;
                         if (blk * b + j < p)
                             rot += tpair_lds<T, R, RT, G>(base + i * ldl, base + j * ldl, nb_ + i, nb_ + j, gl, tl,
-                                                          f64, J.skip2, keep2, big, ev);
+                                                          f64, J.skip2, keep2, big, ev, prog);
                         __syncthreads();
                     }
 #pragma unroll
@@ -928,7 +934,7 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                             const int j = sb * gw + ((u + v) & (gw - 1));
                             if (ci < p && BJ * b + j < p)
                                 rot += tpair_reg<T, R, RT, G>(xr, na, Js + j * ldl, nJ + j, gl, tl, f64, J.skip2,
-                                                              keep2, big, ev);
+                                                              keep2, big, ev, prog);
                             // keeps the compiler from moving the next sub-round's LDS reads
                             // above this one's writes (no instruction is emitted)
                             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -958,10 +964,12 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
                 if (tid == 0 && btot) atomicAdd(rot_g + kMaxSweeps + sw, btot);
                 if (keep) {
                     const int etot = block_sum_groups(ev, gl, s_scratch);
+                    const int ptot = block_sum_groups(prog, gl, s_scratch);
                     if (tid == 0 && etot) {
                         atomicAdd(&ts.ctrl->pairs, (unsigned long long)etot);
                         atomicAdd(rot_g + 2 * kMaxSweeps + sw, etot);
                     }
+                    if (tid == 0 && ptot) atomicAdd(rot_g + 3 * kMaxSweeps + sw, ptot);
                 }
                 if (!team_barrier(ts, s_flag)) return false;
             }
@@ -969,16 +977,25 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
         if (fin) break;
         const int total = __hip_atomic_load(rot_g + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int large = __hip_atomic_load(rot_g + kMaxSweeps + sw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (keep && sw >= 1) {
-            // past the first sweep (which starts from the input's columns), a sweep
-            // that still evaluated over half of all pairs has a large kept set:
-            // the mode saves little there, and the few columns left below tau tend
-            // to sit near it, beyond what the certificate can clear.  The slice
-            // continues as the full iteration (this sweep's counts covered the
-            // kept pairs only, so they decide nothing).
-            const int evs = __hip_atomic_load(rot_g + 2 * kMaxSweeps + sw, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-            if (2.0 * evs > 0.5 * (double)p * (p - 1)) {
+        if (keep && sw >= 1 && !(total == 0 || large == 0)) {
+            // Signs that the kept columns will not settle soon, or that the columns
+            // left below tau sit near it, beyond what the certificate can clear
+            // (past the first sweep, which starts from the input's columns): a
+            // sweep that still evaluated over 40% of all pairs (a large kept set);
+            // a sweep with an unchanged kept set (the same number of pairs
+            // evaluated as the one before) whose pairs with cosine > 1e-2 fell by
+            // less than a factor 0.5, or two in a row by less than 0.35 (a
+            // continuous spectrum through tau); the sweep limit of the mode.  The
+            // slice then continues as the full iteration (this sweep's counts
+            // covered the kept pairs only, so they decide nothing).
+            auto ld = [&](int seg, int w) {
+                return __hip_atomic_load(rot_g + seg * kMaxSweeps + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            };
+            const int evs = ld(2, sw), evp = ld(2, sw - 1), pg = ld(3, sw), pgp = ld(3, sw - 1);
+            const bool stable = evs == evp && pg > 0;
+            slow = (stable && pg > 0.35 * pgp) ? slow + 1 : 0;
+            if (2.0 * evs > 0.4 * (double)p * (p - 1) || (stable && pg > 0.5 * pgp) || slow >= 2 ||
+                sw + 1 >= kKeepMaxSweeps) {
                 keep = 0;
                 continue;
             }
