@@ -127,16 +127,18 @@ enum {
                                   multi-workgroup Jacobi kernel (teams then take several slices
                                   in turn; the tuner also tries the count whose A and V fit an
                                   XCD's L2).  A forced setting, like TEAM_SIZE, disables tuning. */
-    TSVD_OPT_KEPT_COLUMNS = 14 /* tsvd_tsvt_dct and tsvd_tsvt_transform with tau > 0, when the
-                                  multi-workgroup kernel with one column per lane group runs the
-                                  SVDs: 1 (default) each slice's Jacobi iteration works only on
-                                  the column pairs that touch a column of norm > tau and stops
-                                  once those columns are orthogonal to all others (Theorem 5
-                                  needs no more); the slice is then certified -- the remaining
-                                  columns of spectral norm <= tau -- or run through the full
-                                  iteration.  A slice with a remaining column of norm above
-                                  tau / sqrt(2) (no gap below tau) turns into the full
-                                  iteration at once.  0: the full iteration for every slice */
+    TSVD_OPT_KEPT_COLUMNS = 14 /* tsvt_dct, tsvt_transform and tsvt_dft with tau > 0, when the
+                                  multi-workgroup Jacobi kernel with one column per lane group
+                                  runs the SVDs: 1 (default) each slice's iteration evaluates
+                                  only the column pairs that touch a column of norm > tau and
+                                  stops once those columns are orthogonal to all others
+                                  (Theorem 5 needs no more); the slice is then certified (the
+                                  remaining columns of spectral norm <= tau) or run through the
+                                  full iteration.  A slice whose kept set is large or settles
+                                  slowly (no gap below tau) turns into the full iteration after
+                                  its second or third sweep.  0: the full iteration for every
+                                  slice.  tsvd_stats counts the pairs evaluated and the slices
+                                  the certificate rejected. */
 };
 int tsvd_set_option(tsvd_ctx* ctx, int option, double value);
 double tsvd_get_option(const tsvd_ctx* ctx, int option);

@@ -1336,14 +1336,21 @@ struct DftPlan {
     Plan E, R;
 };
 
-int make_dft_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, DftPlan& D, Carve& cv, hipStream_t s) {
+// kept: a t-SVT (the kept-column Jacobi where its tile allows; a TNN needs
+// every singular value).
+int make_dft_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, DftPlan& D, Carve& cv, hipStream_t s,
+                  bool kept = false) {
     if (2 * std::max(n1, n2) > kMaxRows)
         return fail(c, TSVD_EINVAL, "the DFT path takes frontal slices of at most 256 rows and columns");
     dft_layout(n3, &D.h, &D.nreal);
     D.o_zb = cv.take((size_t)n1 * n2 * n3 * esize(prec));
     int rc;
-    if (D.h > 0 && (rc = make_plan(c, prec, 2 * n1, 2 * n2, D.h, 0, D.E, cv, s))) return rc;
+    if (D.h > 0) {
+        if ((rc = make_plan(c, prec, 2 * n1, 2 * n2, D.h, 0, D.E, cv, s))) return rc;
+        if (kept) plan_kept_columns(c, D.E, cv);
+    }
     if ((rc = make_plan(c, prec, n1, n2, D.nreal, 0, D.R, cv, s))) return rc;
+    if (kept) plan_kept_columns(c, D.R, cv);
     return TSVD_OK;
 }
 
@@ -1687,7 +1694,7 @@ int tsvt_dft(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, const vo
     }
     DftPlan D;
     Carve cv;
-    if ((rc = make_dft_plan(c, prec, n1, n2, n3, D, cv, s))) return rc;
+    if ((rc = make_dft_plan(c, prec, n1, n2, n3, D, cv, s, true))) return rc;
     if ((rc = ensure_ws(c, cv.off))) return rc;
     char* base = (char*)c->ws.p;
     CtrlRegion cr;

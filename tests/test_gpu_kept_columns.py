@@ -217,3 +217,56 @@ def test_kept_columns_against_full_iteration(tm, prec):
         assert rel(out[1][0], out[0][0]) <= FP64_TOL
     else:
         assert ratio(out[1][0], out[0][0], Zn, prec) <= 2 * C_PATH[prec]
+
+
+def test_kept_columns_transform(tm):
+    # the t-SVT under a caller-given orthogonal transform along the tubes
+    announce("kept_transform")
+    n1, n2, n3 = 200, 150, 4
+    c = case((n1, n2, n3), 76)
+    L, _ = np.linalg.qr(np.random.default_rng(77).standard_normal((n3, n3)))
+    ctx = team_ctx(tm, 4)
+    try:
+        ctx.stats(reset=True)
+        Y, ranks = tm.tsvt_transform(to_dev(c.Z), c.tau, L, return_ranks=True, ctx=ctx)
+        st = ctx.stats(reset=True)
+    finally:
+        ctx.close()
+    Yo, ro, _ = oracle.tsvt_transform(c.Z, c.tau, L, return_ranks=True)
+    err = rel(to_np(Y), Yo)
+    print("kept transform: rel err %.3e, ranks %s, pairs %d, fallback %d" % (err, list(ranks), st["pairs"],
+                                                                           st["fallback_slices"]))
+    assert list(ranks) == [int(x) for x in ro]
+    assert err <= FP64_TOL
+    assert st["pairs"] > 0
+    assert st["fallback_slices"] == 0
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_kept_columns_dft(tm, prec):
+    # the Fourier path: complex slices thresholded through their 2 n1 x 2 n2 real
+    # forms (every singular value twice), real slices as they are; its slices
+    # carry sqrt(n3) times the orthonormal transform's scale
+    announce("kept_dft", prec=prec)
+    n1, n2, n3 = 120, 100, 5
+    c = case((n1, n2, n3), 78)
+    tau = c.tau * np.sqrt(n3)
+    Z = c.Z if prec == 0 else c.Z.astype(np.float32).astype(np.float64)
+    ctx = team_ctx(tm, 4)
+    try:
+        ctx.stats(reset=True)
+        Y, ranks = tm.tsvt_dft(to_dev(Z, torch.float32 if prec else torch.float64), tau, prec=prec,
+                               return_ranks=True, ctx=ctx)
+        st = ctx.stats(reset=True)
+    finally:
+        ctx.close()
+    Yo, ro, _ = oracle.tsvt_dft(Z, tau, return_ranks=True)
+    print("kept dft prec %d: ranks %s (oracle %s), pairs %d, fallback %d" % (
+        prec, list(ranks), [int(x) for x in ro], st["pairs"], st["fallback_slices"]))
+    assert list(ranks) == [int(x) for x in ro]
+    assert st["pairs"] > 0
+    assert st["fallback_slices"] == 0
+    if prec == 0:
+        assert rel(to_np(Y), Yo) <= FP64_TOL
+    else:
+        assert ratio(to_np(Y), Yo, Z, prec) <= 2 * C_PATH[prec]
