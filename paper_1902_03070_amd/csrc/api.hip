@@ -378,7 +378,7 @@ struct Plan {
     size_t o_ctr_begin, o_ctr_end;  // region zeroed per call (counters)
     // kept-column Jacobi and its threshold certificate (plan_kept_columns)
     int keep = 0;
-    size_t o_full = 0, o_ncols = 0, o_sums = 0, o_rot2 = 0, o_bar2 = 0, o_flags = 0, o_nrm2 = 0, o_As = 0, o_H = 0, o_H2 = 0;
+    size_t o_full = 0, o_ncols = 0, o_sums = 0, o_done = 0, o_rot2 = 0, o_bar2 = 0, o_flags = 0, o_nrm2 = 0, o_As = 0, o_H = 0, o_H2 = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -923,6 +923,7 @@ void plan_kept_columns(tsvd_ctx* c, Plan& P, Carve& cv) {
     const size_t n3 = (size_t)P.n3, m = (size_t)P.m, p = (size_t)P.p;
     P.o_full = cv.take(n3 * 4);
     P.o_sums = cv.take(n3 * 8);
+    P.o_done = cv.take(n3 * 4);
     P.o_rot2 = cv.take(n3 * kRotStride * 4);
     P.o_bar2 = cv.take((size_t)(kTeamCtlInts + (size_t)std::max(1, P.ts.nwg) * (1 + std::max(1, P.job.nb))) * 4);
     P.o_ctr_end = cv.off;
@@ -1007,6 +1008,7 @@ int enqueue_certificate(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau
     a.H = (float*)(base + P.o_H);
     a.H2 = (float*)(base + P.o_H2);
     a.sums = (double*)(base + P.o_sums);
+    a.done = (int*)(base + P.o_done);
     a.sweeps = P.job.sweeps;
     a.full = (const int*)(base + P.o_full);
     a.ncols = (int*)(base + P.o_ncols);

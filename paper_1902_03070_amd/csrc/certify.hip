@@ -35,6 +35,7 @@ namespace tsvd {
 namespace {
 
 constexpr int kCertThreads = 256;  // four wavefronts, one column each
+constexpr int kCertRows = kMaxRows / kWave;  // rows per lane (m <= kMaxRows)
 
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
@@ -43,8 +44,10 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 }
 
 // One wavefront per column: its squared norm in FP64, and the column scaled
-// by 1/tau as FP32 (the Gram operand).  Slices that converged as the full
-// iteration are skipped (their GEMM column count is set to 0).
+// by 1/tau as FP32 (the Gram operand), or zero for a kept column (squared
+// norm > tau^2), so that the Gram matrix is H with the kept columns' rows and
+// columns zero.  Slices that converged as the full iteration are skipped
+// (GEMM column count 0, verdict 1).
 template <typename T>
 __global__ __launch_bounds__(kCertThreads) void k_cert_scan(CertArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -52,42 +55,43 @@ __global__ __launch_bounds__(kCertThreads) void k_cert_scan(CertArgs a) {
     if (col >= (int64_t)a.n3 * a.p) return;
     const int k = (int)(col / a.p);
     const bool skip = a.full[k] != 0;
-    if (lane == 0 && col - (int64_t)k * a.p == 0) a.ncols[k] = skip ? 0 : a.p;
+    if (lane == 0 && col - (int64_t)k * a.p == 0) {
+        a.ncols[k] = skip ? 0 : a.p;
+        a.flags[k] = skip ? 1 : 0;
+    }
     if (skip) return;
     const T* x = (const T*)a.A + col * a.m;
     float* y = a.As + col * a.m;
-    const double inv = 1.0 / a.tau;
+    double v[kCertRows];
     double acc = 0.0;
-    for (int r = lane; r < a.m; r += kWave) {
-        const double v = (double)x[r];
-        acc = fma(v, v, acc);
-        y[r] = (float)(v * inv);
+#pragma unroll
+    for (int q = 0; q < kCertRows; ++q) {
+        const int r = lane + kWave * q;
+        v[q] = r < a.m ? (double)x[r] : 0.0;
+        acc = fma(v[q], v[q], acc);
     }
     acc = wave_sum_d(acc);
     if (lane == 0) a.nrm2[col] = acc;
-}
-
-// H = R^T R / tau^2: the Gram matrix of A' / tau with the rows and columns of
-// the kept columns set to zero (in place).
-__global__ __launch_bounds__(kCertThreads) void k_cert_mask(CertArgs a) {
-    const int64_t pp = (int64_t)a.p * a.p, total = pp * a.n3;
-    const double t2 = a.tau * a.tau;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = e / pp, o = e - k * pp;
-        if (a.full[k]) continue;
-        const int i = (int)(o % a.p), j = (int)(o / a.p);
-        const double* nk = a.nrm2 + k * a.p;
-        if (nk[i] > t2 || nk[j] > t2) a.H[e] = 0.0f;
+    const bool kept = acc > a.tau * a.tau;  // (a NaN norm stays in H and fails the test)
+    const double inv = 1.0 / a.tau;
+#pragma unroll
+    for (int q = 0; q < kCertRows; ++q) {
+        const int r = lane + kWave * q;
+        if (r < a.m) y[r] = kept ? 0.0f : (float)(v[q] * inv);
     }
 }
 
-// ||H^4||_F^2 per slice: grid (chunks, slices), FP64 partial sums added to
-// sums[k] (zero before the launch).
-__global__ __launch_bounds__(kCertThreads) void k_cert_sumsq(CertArgs a) {
+// ||H^4||_F^2 per slice and the verdict: grid (chunks, slices); each
+// workgroup adds its FP64 partial sum to sums[k] (zero before the launch),
+// and the last one of a slice to finish decides.  The margin covers the FP32
+// Gram matrix (entrywise error <= gamma_m |R|^T |R| / tau^2, whose spectral
+// norm is at most gamma_m trace(H)) and the two squarings:
+//   delta = 2 (m + 2 p) u32 trace(H) + 2^-8,  pass iff ||H^4||_F^2 <= (1 - delta)^8.
+__global__ __launch_bounds__(kCertThreads) void k_cert_verdict(CertArgs a) {
     __shared__ double s_part[kCertThreads / kWave];
+    __shared__ int s_last;
     const int k = blockIdx.y, tid = threadIdx.x;
-    if (a.full[k]) return;  // (the same for the whole workgroup)
+    if (a.full[k]) return;  // (the same for the whole workgroup; the scan set its verdict)
     const int64_t pp = (int64_t)a.p * a.p;
     const float* H4 = a.H + (int64_t)k * pp;
     double s = 0.0;
@@ -102,32 +106,25 @@ __global__ __launch_bounds__(kCertThreads) void k_cert_sumsq(CertArgs a) {
         double S = 0.0;
         for (int w = 0; w < kCertThreads / kWave; ++w) S += s_part[w];
         atomicAdd(a.sums + k, S);
+        __threadfence();
+        s_last = atomicAdd(a.done + k, 1) == (int)gridDim.x - 1;
     }
-}
-
-// Condition (2) and the verdict, one workgroup per slice.  The margin covers
-// the FP32 Gram matrix (entrywise error <= gamma_m |R|^T |R| / tau^2, whose
-// spectral norm is at most gamma_m trace(H)) and the two squarings:
-//   delta = 2 (m + 2 p) u32 trace(H) + 2^-8,  pass iff ||H^4||_F^2 <= (1 - delta)^8.
-__global__ __launch_bounds__(kCertThreads) void k_cert_final(CertArgs a) {
-    __shared__ double s_part[kCertThreads / kWave];
-    const int k = blockIdx.x, tid = threadIdx.x;
-    if (a.full[k]) {
-        if (tid == 0) a.flags[k] = 1;
-        return;
-    }
+    __syncthreads();
+    if (!s_last) return;
+    // the slice's last workgroup: every partial sum is in sums[k]
     const double* nk = a.nrm2 + (int64_t)k * a.p;
     const double t2 = a.tau * a.tau;
     double tr = 0.0;
     for (int c = tid; c < a.p; c += kCertThreads)
         if (!(nk[c] > t2)) tr += nk[c] / t2;
     tr = wave_sum_d(tr);
+    __syncthreads();  // s_part is reused
     if ((tid & 63) == 0) s_part[tid >> 6] = tr;
     __syncthreads();
     if (tid == 0) {
         double TR = 0.0;
         for (int w = 0; w < kCertThreads / kWave; ++w) TR += s_part[w];
-        const double S = a.sums[k];
+        const double S = __hip_atomic_load(a.sums + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double delta = 2.0 * (a.m + 2.0 * a.p) * 0x1p-24 * TR + 0x1p-8;
         const double b = 1.0 - delta, b2 = b * b, b4 = b2 * b2;
         const bool ok = a.sweeps[k] >= 0 && delta < 1.0 && S <= b4 * b4;
@@ -156,10 +153,6 @@ hipError_t launch_threshold_certificate(int prec, CertArgs a, hipStream_t s) {
     g.M = a.p; g.Nn = a.p; g.K = a.m; g.batch = a.n3;
     g.Ndev = a.ncols;
     if ((e = launch_gemm(1, g, s)) != hipSuccess) return e;
-    const int64_t total = pp * a.n3;
-    const unsigned gm = (unsigned)std::min<int64_t>((total + kCertThreads - 1) / kCertThreads, 4096);
-    hipLaunchKernelGGL(k_cert_mask, dim3(gm), blk, 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     // H^2 into H2, then H^4 back into H
     GemmArgs q{};
     q.a_rs = 1; q.a_cs = a.p; q.a_bs = pp;
@@ -172,9 +165,7 @@ hipError_t launch_threshold_certificate(int prec, CertArgs a, hipStream_t s) {
     q.A = a.H2; q.B = a.H2; q.C = a.H;
     if ((e = launch_gemm(1, q, s)) != hipSuccess) return e;
     const unsigned chunks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(16, pp / (8 * kCertThreads)));
-    hipLaunchKernelGGL(k_cert_sumsq, dim3(chunks, (unsigned)a.n3), blk, 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cert_final, dim3(a.n3), blk, 0, s, a);
+    hipLaunchKernelGGL(k_cert_verdict, dim3(chunks, (unsigned)a.n3), blk, 0, s, a);
     return hipGetLastError();
 }
 

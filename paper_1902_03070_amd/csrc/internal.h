@@ -130,6 +130,7 @@ struct CertArgs {
     float* H;           // [n3 p p] Gram matrix, then H^4 (written)
     float* H2;          // [n3 p p] H^2 (written)
     double* sums;       // [n3] zero before the launch; ||H^4||_F^2
+    int* done;          // [n3] zero before the launch; workgroups of the slice's sum that finished
     const int* sweeps;  // [n3] sweeps of the kept-column iteration (-1: did not converge)
     const int* full;    // [n3] 1: the slice converged as the full iteration (no certificate needed)
     int* ncols;         // [n3] (written) p for a slice to certify, 0 for one that converged as the full
