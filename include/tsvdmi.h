@@ -82,7 +82,9 @@ const char* tsvd_last_error(const tsvd_ctx* ctx);
 
 /* Options (set before use; values are doubles for a uniform interface). */
 enum {
-    TSVD_OPT_MAX_SWEEPS = 0,   /* Jacobi sweep limit, 1..64 (default 30) */
+    TSVD_OPT_MAX_SWEEPS = 0,   /* Jacobi sweep limit, 1..63 (default 30); with TSVD_OPT_KEPT_COLUMNS
+                                  the kept-column iteration and the full iteration it may fall
+                                  back to each have this limit */
     TSVD_OPT_SYNC_STATUS = 1,  /* 1: each call synchronizes and returns device status (default);
                                   0: calls are asynchronous, status via tsvd_sync_status */
     TSVD_OPT_TEAM_SIZE = 2,    /* 0: automatic; >0: workgroups per frontal slice in the Jacobi
