@@ -3,6 +3,8 @@
 256 x 256 x 31 (multispectral-shaped; tubal rank 10, [0, 1], 30% observed):
   * the isolated t-SVT, every slice, FP64 (<= 1e-10) and MIXED (stated bound),
     at the schedule's first and last thresholds;
+  * the isolated t-SVT of a late iterate of the schedule (the oracle's 30th),
+    where the kept-column Jacobi certifies every slice, every slice checked;
   * the completion (Algorithm 1) on the path the benchmark times: the
     multi-workgroup Jacobi kernel carrying V (warm start), FP64 and MIXED,
     whole tensor, against the oracle's iterations;
@@ -67,6 +69,51 @@ def test_tsvt_fullsize_every_slice_reduced(tm, cc, prec, which):
           "vs FP64 input %.3e" % (prec, tau, c, ck, rel(Y, Yo), rel(Y, oracle.tsvt_dct(cc.B, tau))))
     assert c <= C_PATH[prec]
     assert ck <= C_PATH[prec]
+
+
+@pytest.fixture(scope="module")
+def late_iterate(cc):
+    # a late t-SVT input of the benchmark's schedule, Z_L = X_L - M_L / beta_L,
+    # from L iterations of the oracle's Algorithm 1 (a rank-10 part far above
+    # tau_L, the rest well below: the kept-column mode's fast path)
+    L = 30
+    X, M, _, _ = oracle.complete(cc.B, cc.mask, cc.betas[:L], cc.taus[:L])
+    return np.asfortranarray(X - M / cc.betas[L]), float(cc.taus[L])
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_tsvt_fullsize_late_iterate_kept_columns(tm, late_iterate, prec):
+    Z, tau = late_iterate
+    announce("tsvt_full_late", prec=prec, tau=tau)
+    Zi = Z if prec == 0 else Z.astype(np.float32).astype(np.float64)
+    Yo, ro, _ = oracle.tsvt_dct(Zi, tau, return_ranks=True)
+    ctx = tm.Context(0)
+    try:
+        ctx.stats(reset=True)
+        Y, ranks = tm.tsvt_dct(to_dev(Zi, torch.float32 if prec else torch.float64), tau, prec=prec,
+                               return_ranks=True, ctx=ctx)
+        st = ctx.stats(reset=True)
+    finally:
+        ctx.close()
+    Y = to_np(Y)
+    print("late iterate prec %d tau %.3g: ranks %s, pairs %d, fallback %d, sweeps per slice %.2f" % (
+        prec, tau, list(ranks), st["pairs"], st["fallback_slices"], st["slice_sweeps"] / N3))
+    assert list(ranks) == [int(r) for r in ro]
+    assert st["pairs"] > 0 and st["fallback_slices"] == 0
+    if prec == 0:
+        Yb, Yob = oracle.dct_tubes(Y), oracle.dct_tubes(Yo)
+        worst = max(np.linalg.norm(Yb[:, :, k] - Yob[:, :, k]) / max(np.linalg.norm(Yob[:, :, k]), 1e-300)
+                    for k in range(N3) if ro[k] > 0)
+        print("  FP64 rel err %.3e, worst kept slice %.3e" % (rel(Y, Yo), worst))
+        assert rel(Y, Yo) <= FP64_TOL
+        assert worst <= FP64_TOL
+    else:
+        Yb, Yob, Zb = oracle.dct_tubes(Y), oracle.dct_tubes(Yo), oracle.dct_tubes(Zi)
+        ck = max(np.linalg.norm(Yb[:, :, k] - Yob[:, :, k]) / (U_EFF[prec] * np.linalg.norm(Zb[:, :, k]))
+                 for k in range(N3))
+        c = ratio(Y, Yo, Zi, prec)
+        print("  MIXED c = %.3f, worst slice c = %.3f" % (c, ck))
+        assert c <= C_PATH[prec] and ck <= C_PATH[prec]
 
 
 def test_complete_fullsize_fp64_bench_path(tm, cc):
