@@ -11,7 +11,7 @@ namespace tsvd {
 constexpr int kMaxSweeps = 64;       // hard cap on Jacobi sweeps (per-sweep counters are sized by it)
 constexpr int kRotStride = 4 * kMaxSweeps;  // per slice: rotations per sweep, large-angle pairs per sweep, then
                                             // (kept-column mode) pairs evaluated and pairs with cosine > 1e-2
-constexpr int kKeepMaxSweeps = 10;   // kept-column sweeps before a slice that has not converged turns into
+constexpr int kKeepMaxSweeps = 16;   // kept-column sweeps before a slice that has not converged turns into
                                      // the full iteration
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kMaxEpl = 8;           // rows per lane in the Jacobi kernels: m <= 512

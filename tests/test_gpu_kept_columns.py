@@ -270,3 +270,40 @@ def test_kept_columns_dft(tm, prec):
         assert rel(to_np(Y), Yo) <= FP64_TOL
     else:
         assert ratio(to_np(Y), Yo, Z, prec) <= 2 * C_PATH[prec]
+
+
+def test_kept_columns_graph_replays(tm):
+    # a kept-column t-SVT captured in a HIP graph (the library's workspace and
+    # tile already set up by an eager call): every replay, with other eager
+    # work on the same workspace between replays, gives the eager result bitwise
+    announce("kept_graph")
+    n1, n2, n3 = 200, 150, 4
+    c = case((n1, n2, n3), 79)
+    ctx = team_ctx(tm, 4)
+    ctx.set_option(tm.OPT_SYNC_STATUS, 0)  # no host synchronization inside the capture
+    try:
+        Z, Z2 = to_dev(c.Z), to_dev(2.0 * c.Z)
+        Y, Y2 = tm.empty_f(n1, n2, n3, torch.float64, "cuda:0"), tm.empty_f(n1, n2, n3, torch.float64, "cuda:0")
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            tm.tsvt_dct(Z, c.tau, Y=Y, ctx=ctx, stream=s)
+        torch.cuda.synchronize()
+        ref = Y.clone()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+            tm.tsvt_dct(Z, c.tau, Y=Y, ctx=ctx, stream=s)
+        torch.cuda.synchronize()
+        for rep in range(3):
+            tm.tsvt_dct(Z2, c.tau, Y=Y2, ctx=ctx)  # eager work on the same workspace
+            Y.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(Y, ref), "replay %d differs from the eager result" % rep
+        status, _ = ctx.sync_status()
+        st = ctx.stats(reset=True)
+    finally:
+        ctx.close()
+    assert status == 0
+    assert st["pairs"] > 0
+    assert rel(to_np(ref), oracle.tsvt_dct(c.Z, c.tau)) <= FP64_TOL
