@@ -307,3 +307,24 @@ def test_kept_columns_graph_replays(tm):
     assert status == 0
     assert st["pairs"] > 0
     assert rel(to_np(ref), oracle.tsvt_dct(c.Z, c.tau)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_kept_columns_nonfinite_input(tm, prec):
+    # a NaN in a slice that the kept-column mode would take: every sweep limit
+    # still ends the iteration, the certificate rejects the slice, and the call
+    # reports the input as non-finite
+    announce("kept_nan", prec=prec)
+    c = case((200, 150, 4), 80)
+    Z = c.Z.copy()
+    Z[17, 33, 2] = np.nan
+    ctx = team_ctx(tm, 4)
+    try:
+        with pytest.raises(tm.TsvdError) as ei:
+            tm.tsvt_dct(to_dev(Z, torch.float32 if prec else torch.float64), c.tau, prec=prec, ctx=ctx)
+        assert ei.value.code == tm.ENONFINITE
+        # the context stays usable
+        Y = tm.tsvt_dct(to_dev(c.Z), c.tau, ctx=ctx)
+    finally:
+        ctx.close()
+    assert rel(to_np(Y), oracle.tsvt_dct(c.Z, c.tau)) <= FP64_TOL
