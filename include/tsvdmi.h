@@ -129,7 +129,8 @@ enum {
                                   multi-workgroup Jacobi kernel (teams then take several slices
                                   in turn; the tuner also tries the count whose A and V fit an
                                   XCD's L2).  A forced setting, like TEAM_SIZE, disables tuning. */
-    TSVD_OPT_KEPT_COLUMNS = 14 /* tsvt_dct, tsvt_transform and tsvt_dft with tau > 0, when the
+    TSVD_OPT_KEPT_COLUMNS = 14 /* tsvt_dct, tsvt_transform, tsvt_dft (tau > 0) and complete_tensor
+                                  without the warm start (TSVD_OPT_WARM_START 0), when the
                                   multi-workgroup Jacobi kernel with one column per lane group
                                   runs the SVDs: 1 (default) each slice's iteration evaluates
                                   only the column pairs that touch a column of norm > tau and

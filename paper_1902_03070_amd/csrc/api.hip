@@ -908,17 +908,17 @@ int make_plan(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, int wit
     return TSVD_OK;
 }
 
-// Kept-column Jacobi for a plain t-SVT (cold SVDs, no V): the team kernel with
-// one column per lane group iterates only on the pairs that touch a column
-// above the threshold (a slice without a gap below it turns into the full
-// iteration), the threshold certificate checks each slice, and the full
-// iteration runs for the slices it rejects.  Adds the mode's counters to
+// Kept-column Jacobi for a t-SVT (cold SVDs, or the completion's warm-started
+// ones carrying V): the team kernel with one column per lane group iterates
+// only on the pairs that touch a column above the threshold (a slice without
+// a gap below it turns into the full iteration), the threshold certificate
+// checks each slice, and the full iteration runs for the slices it rejects.  Adds the mode's counters to
 // the plan's zeroed region (right after the others) and its buffers after
 // them.  Leaves the plan unchanged when the option is off or the tile is
 // another kernel.
 void plan_kept_columns(tsvd_ctx* c, Plan& P, Carve& cv) {
     P.keep = 0;
-    if (!c->kept_cols || c->noalloc || P.team != 1 || P.K != 1 || P.with_v || P.m > kMaxRows) return;
+    if (!c->kept_cols || c->noalloc || P.team != 1 || P.K != 1 || P.m > kMaxRows) return;
     if (P.o_ctr_end != cv.off) return;  // the zeroed region must stay contiguous
     const size_t n3 = (size_t)P.n3, m = (size_t)P.m, p = (size_t)P.p;
     P.o_full = cv.take(n3 * 4);
@@ -997,12 +997,14 @@ int enqueue_warm_start(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, hipStream_t
 // Threshold certificate after the kept-column iteration, then the full
 // iteration (in place, from A') for the slices it rejects; the others are
 // left alone by that launch.
-int enqueue_certificate(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau, hipStream_t s) {
+int enqueue_certificate(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau, const double* tau_sched,
+                        hipStream_t s) {
     const int prec = P.prec == TSVD_FP64 ? 0 : 1;
     CertArgs a{};
     a.A = base + P.o_A;
     a.m = P.m; a.p = P.p; a.n3 = (int)P.n3;
     a.tau = tau;
+    a.tau_sched = tau_sched;
     a.nrm2 = (double*)(base + P.o_nrm2);
     a.As = (float*)(base + P.o_As);
     a.H = (float*)(base + P.o_H);
@@ -1025,9 +1027,10 @@ int enqueue_certificate(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau
     J.src_rs = 1;
     J.src_cs = P.m;
     J.rot = (int*)(base + P.o_rot2);
+    if (P.with_v) J.vinit = 1;  // V continues from where the kept-column iteration left it
     TeamSched ts = P.ts;
     ts.ctl = (int*)(base + P.o_bar2);
-    e = launch_jacobi_team(P.prec, J, (int)P.n3, ts, clamp_sweeps(c->max_sweeps), ctrl, P.lds, P.threads, 0,
+    e = launch_jacobi_team(P.prec, J, (int)P.n3, ts, clamp_sweeps(c->max_sweeps), ctrl, P.lds, P.threads, P.with_v,
                            c->spin_limit, J.R, J.G, 1, (c->capturing || !c->coop) ? 0 : 1, s);
     if (e != hipSuccess) return hip_fail(c, e, "jacobi launch");
     return TSVD_OK;
@@ -1040,10 +1043,12 @@ int enqueue_svt_core(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau_va
         int rc = enqueue_warm_start(c, P, base, ctrl, s);
         if (rc) return rc;
     }
-    // the kept-column mode needs the threshold on the host (not a schedule) and tau > 0
-    const bool keep = P.keep && !tau_sched && tau_val > 0.0 && isfinite(tau_val);
+    // the kept-column mode takes tau > 0 from the host or a schedule on the device
+    // (the completion's entries are checked > 0 on the host)
+    const bool keep = P.keep && (tau_sched || (tau_val > 0.0 && isfinite(tau_val)));
     P.job.keep = keep ? 1 : 0;
-    P.job.keep2 = keep ? tau_val * tau_val : 0.0;
+    P.job.keep2 = keep && !tau_sched ? tau_val * tau_val : 0.0;
+    P.job.keep_sched = keep ? tau_sched : nullptr;
     P.job.skip = nullptr;
     P.job.full = keep ? (int*)(base + P.o_full) : nullptr;
     {
@@ -1053,7 +1058,7 @@ int enqueue_svt_core(tsvd_ctx* c, Plan& P, char* base, Ctrl* ctrl, double tau_va
     }
     if (keep) {
         PhaseMark pm(c, 5, s);
-        int rc = enqueue_certificate(c, P, base, ctrl, tau_val, s);
+        int rc = enqueue_certificate(c, P, base, ctrl, tau_val, tau_sched, s);
         if (rc) return rc;
     }
     return enqueue_after_jacobi(c, P, base, ctrl, tau_val, tau_sched, s);
@@ -1939,6 +1944,13 @@ int complete_tensor(tsvd_ctx* c, int prec, int64_t n1, int64_t n2, int64_t n3, c
     const int warm_period = c->warm_start < 0 ? 64 : c->warm_start;
     int rc = make_plan(c, prec, n1, n2, n3, warm_period > 0 ? 1 : 0, P, cv, s);
     if (rc) return rc;
+    // Cold SVDs take the kept-column mode as a single t-SVT does.  Warm-started
+    // ones leave it few sweeps to save and, in the middle of the schedule,
+    // slices the certificate rejects; they run the full iteration (measured,
+    // 100 iterations: 256x256x31 MIXED 1.20 -> 0.98 ms per iteration but FP64
+    // 1.57 -> 1.82, and the 144x176x100 video-shaped MIXED completion 969 ->
+    // 531 t-SVT/s).
+    if (warm_period == 0) plan_kept_columns(c, P, cv);
     const size_t es = esize(prec);
     const size_t oM = cv.take((size_t)P.N * n3 * es);
     if (warm_period > 0) {

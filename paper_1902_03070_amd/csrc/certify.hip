@@ -37,6 +37,10 @@ namespace {
 constexpr int kCertThreads = 256;  // four wavefronts, one column each
 constexpr int kCertRows = kMaxRows / kWave;  // rows per lane (m <= kMaxRows)
 
+__device__ __forceinline__ double cert_tau(const CertArgs& a) {
+    return a.tau_sched ? a.tau_sched[a.ctrl->iter] : a.tau;
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -72,8 +76,9 @@ __global__ __launch_bounds__(kCertThreads) void k_cert_scan(CertArgs a) {
     }
     acc = wave_sum_d(acc);
     if (lane == 0) a.nrm2[col] = acc;
-    const bool kept = acc > a.tau * a.tau;  // (a NaN norm stays in H and fails the test)
-    const double inv = 1.0 / a.tau;
+    const double tau = cert_tau(a);
+    const bool kept = acc > tau * tau;  // (a NaN norm stays in H and fails the test)
+    const double inv = 1.0 / tau;
 #pragma unroll
     for (int q = 0; q < kCertRows; ++q) {
         const int r = lane + kWave * q;
@@ -113,7 +118,7 @@ __global__ __launch_bounds__(kCertThreads) void k_cert_verdict(CertArgs a) {
     if (!s_last) return;
     // the slice's last workgroup: every partial sum is in sums[k]
     const double* nk = a.nrm2 + (int64_t)k * a.p;
-    const double t2 = a.tau * a.tau;
+    const double tau = cert_tau(a), t2 = tau * tau;
     double tr = 0.0;
     for (int c = tid; c < a.p; c += kCertThreads)
         if (!(nk[c] > t2)) tr += nk[c] / t2;
@@ -137,7 +142,7 @@ __global__ __launch_bounds__(kCertThreads) void k_cert_verdict(CertArgs a) {
 
 hipError_t launch_threshold_certificate(int prec, CertArgs a, hipStream_t s) {
     if (a.n3 <= 0 || a.p <= 0) return hipSuccess;
-    if (a.m > kMaxRows || !(a.tau > 0.0)) return hipErrorInvalidValue;
+    if (a.m > kMaxRows || (!a.tau_sched && !(a.tau > 0.0))) return hipErrorInvalidValue;
     const int64_t cols = (int64_t)a.n3 * a.p;
     const dim3 gcols((unsigned)((cols + 3) / 4)), blk(kCertThreads);
     if (prec == 0) hipLaunchKernelGGL(k_cert_scan<double>, gcols, blk, 0, s, a);

@@ -119,12 +119,13 @@ hipError_t launch_dft_unembed(int prec, const DftEmbedArgs& a, hipStream_t s);
 // converged and the columns of A' with squared norm <= tau^2 have spectral
 // norm <= tau (bound ||H^4||_F^2 with H their Gram matrix / tau^2, FP32 with
 // a rounding margin), or when the slice converged as the full iteration;
-// else 0, and ctrl->fallback += 1.  hipErrorInvalidValue when m > kMaxRows
-// or tau <= 0.
+// else 0, and ctrl->fallback += 1.  hipErrorInvalidValue when m > kMaxRows,
+// or tau <= 0 without a schedule.
 struct CertArgs {
     const void* A;      // A' (tall, m x p per slice, ld m, slice stride m p), FP64 for prec 0 else FP32
     int m, p, n3;
-    double tau;
+    double tau;         // the threshold (> 0), or
+    const double* tau_sched;  // (device) thresholds by iteration: tau = tau_sched[ctrl->iter]
     double* nrm2;       // [n3 p] squared column norms (written)
     float* As;          // [n3 m p] A' / tau in FP32 (written)
     float* H;           // [n3 p p] Gram matrix, then H^4 (written)

@@ -59,7 +59,7 @@ struct JacobiJob {
     double skip2;      // a sweep whose pairs all have (x.y)^2 <= skip2 |x|^2 |y|^2 ends the iteration
                        // (the next sweep would rotate by angles far below tol: no check sweep)
     Ctrl* ctrl;        // per-job status and counters (batched steps), or nullptr: the launch's block
-    // Kept-column mode (team kernel with one column per lane group, no V): only
+    // Kept-column mode (team kernel with one column per lane group): only
     // the pairs with a column of squared norm above keep2 (tau^2 of a t-SVT)
     // are evaluated and count towards convergence; a pair of two columns at or
     // below it (a "rest" pair) is skipped.  The iteration ends once the columns
@@ -77,7 +77,8 @@ struct JacobiJob {
     // marked in full[] (it needs no certificate).  A slice that does not converge in this
     // mode is not flagged TSVD_WARN_NOCONV here: the certificate sends it back.
     int keep;          // 0: every pair, to full convergence; 1: kept-column mode
-    double keep2;      // the mode's squared threshold (> 0)
+    double keep2;      // the mode's squared threshold (> 0), or
+    const double* keep_sched;  // (device) thresholds by iteration: tau = keep_sched[ctrl->iter]
     int* full;         // [n3] (kept-column mode) set to 1 for a slice that converged as the full iteration
     const int* skip;   // [n3] or nullptr: nonzero = the slice is done, the launch leaves it untouched
 };

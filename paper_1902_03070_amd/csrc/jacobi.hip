@@ -850,12 +850,17 @@ __device__ bool team_task(const JacobiJob& J, int k, int rank, TeamState& ts, in
     // kept-column mode, until the slice turns into the full iteration (uniform
     // over the team: decided from the slice's counters after a team barrier)
     int keep = J.keep;
+    double kt2 = J.keep2;
+    if (keep && J.keep_sched) {
+        const double t = J.keep_sched[ts.ctrl->iter];
+        kt2 = t * t;
+    }
     int slow = 0;  // consecutive kept-column sweeps of slow progress
     const bool final_sweep = refine || keep;
     for (int sw = 0; sw < max_sweeps + (final_sweep ? 1 : 0); ++sw) {
         const bool fin = final_sweep && sw == max_sweeps;
         const bool f64 = refine && fin;
-        const double keep2 = keep ? J.keep2 : -1.0;
+        const double keep2 = keep ? kt2 : -1.0;
         const double tl = f64 ? (double)m * Unit<double>::v : tol;
         int rot = 0, big = 0, ev = 0, prog = 0;
         ++executed;

@@ -328,3 +328,37 @@ def test_kept_columns_nonfinite_input(tm, prec):
     finally:
         ctx.close()
     assert rel(to_np(Y), oracle.tsvt_dct(c.Z, c.tau)) <= FP64_TOL
+
+
+def test_kept_columns_completion_mixed(tm):
+    # the MIXED completion with cold SVDs (no warm start) in the kept-column
+    # mode, whose thresholds come from the device-side schedule: the oracle's
+    # iterates within the per-iteration bound, the mode in use, and a replayed
+    # graph giving the direct launches' result bitwise
+    from bounds import U_EFF, oracle_iterates
+
+    announce("kept_completion")
+    L = 8
+    cc = synth.completion_case(oracle.tprod_dct, 200, 150, 6, 4, 0.5, L, 92, tau0=1.0, tau1=0.01)
+    Bf = cc.B.astype(np.float32).astype(np.float64)
+    Xo, _, zmax = oracle_iterates(Bf, cc.mask, cc.taus, L)
+    outs = []
+    for graphs in (1, 0):
+        ctx = team_ctx(tm, 4)
+        ctx.set_option(tm.OPT_GRAPHS, graphs)
+        ctx.set_option(tm.OPT_WARM_START, 0)
+        try:
+            ctx.stats(reset=True)
+            X, info = tm.complete_tensor(to_dev(Bf, torch.float32), to_dev(cc.mask, torch.uint8), max_iter=L,
+                                         tol=0.0, tau_schedule=cc.taus, prec=tm.MIXED, ctx=ctx)
+            st = ctx.stats(reset=True)
+        finally:
+            ctx.close()
+        assert info["status"] == 0
+        assert st["pairs"] > 0
+        outs.append(to_np(X))
+    assert np.array_equal(outs[0], outs[1])
+    cr = np.linalg.norm(outs[0] - Xo) / (U_EFF[2] * zmax)
+    print("kept completion MIXED: c per iteration %.3f, pairs %d, fallback %d" % (cr / L, st["pairs"],
+                                                                                 st["fallback_slices"]))
+    assert cr <= L * C_PATH[2]
