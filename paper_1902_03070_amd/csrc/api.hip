@@ -58,7 +58,7 @@ struct tsvd_ctx {
     int noalloc = 0;            // inside tsvt_dct_noalloc: no tuning, no profiling events
     int coop = 0;               // 1: cooperative launches of the team kernel outside capture
     int gram = -1;              // block-Gram kernel: 0 a tuner candidate, 1 forced, -1 excluded
-    int kept_cols = 1;          // 1: plain t-SVTs run the kept-column Jacobi with the threshold certificate
+    int kept_cols = 1;          // 1: t-SVTs with cold SVDs (single calls, cold completions) run the kept-column Jacobi
     // operands of a caller-given tube transform (tsvt_transform, the DFT path), cached by content
     DevBuf xf;
     std::vector<double> xf_key;
